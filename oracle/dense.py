@@ -1,0 +1,393 @@
+"""Dense MPS algebra for the two-site TDVP hot path.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Everything works on full tensors in the Jordan-Wigner basis of
+``oracle.fermions``: site tensors ``M[chi_left, 4, chi_right]``, two-site
+tensors ``Th[chi_left, 4, 4, chi_right]``, and environments stored per channel
+as ``{w: E[chi, n_kappa, chi]}`` (w = 0 'H', 1 'D+', 2 'D-'; n_kappa = 1, 2, 2),
+the same layout ``oracle.reduced.expand_env`` produces.
+
+Definitions (supplementary section S2.2: TDVP merges one or two sites,
+exponentiates the effective Hamiltonian of that block with a Krylov method
+and sweeps; section S2.3: the dominant work is the environment updates and
+the Krylov exponentials):
+
+* Left environment at bond k (block of sites 1..k with basis |Phi>):
+     'H'  : <Phi'| H_block |Phi>        (H restricted to sites 1..k)
+     'D+' : <Phi'| O^{D+}_kappa |Phi>,  'D-' likewise,
+  with the edge operators of ``left_channel_ops(k)`` acting on site k.
+* Right environment at bond k (block of sites k+1..L with basis |Psi>):
+     'H'  : <Psi'| H_block |Psi>,  'D+'/'D-': <Psi'| Q^{w}_kappa |Psi>
+  with the operators of ``right_channel_ops(k+1)`` acting on site k+1.
+* The hopping across a bond (k, k+1) of Eq. (1) equals
+     (-1)^k sum_kappa [ O^{D+}_kappa(k) Q^{D+}_kappa(k+1) - O^{D-}_kappa(k) Q^{D-}_kappa(k+1) ]
+  (checked against the Jordan-Wigner operators in the tests).
+* The effective Hamiltonian of sites (i, i+1) acting on Th is the projection
+  P^dag H P with P = |Phi_{i-1}> x 1 x 1 x |Psi_{i+1}>; written with the
+  environments it is the sum of the terms in ``heff2``.
+
+The interaction is the particle-hole symmetric U (n_up - 1/2)(n_dn - 1/2),
+the form for which the pseudospin SU(2) of section S2.1 is exact.
+"""
+import numpy as np
+import scipy.linalg
+
+from .fermions import A_UP, A_DN, PARITY, N_UP, N_DN, EYE4, hubbard
+
+TJ_W = [0, 1, 1]
+
+
+def left_channel_ops(k):
+    """Edge operators of a left block whose last site is k (1-based):
+    {w: [op_kappa=+1/2, op_kappa=-1/2]} (w = 1 'D+', 2 'D-').
+    They are the pseudospin doublets D+ = (c+_up, (-1)^k c_dn) and
+    D- = (c+_dn, -(-1)^k c_up) of site k times the site parity."""
+    sg = (-1.0) ** k
+    return {1: [A_UP.T @ PARITY, sg * A_DN @ PARITY],
+            2: [A_DN.T @ PARITY, -sg * A_UP @ PARITY]}
+
+
+def right_channel_ops(k):
+    """Partner operators on site k for a hopping that enters from the left:
+    Q^{D+}_kappa = eps(kappa) [D-]_{-kappa},  Q^{D-}_kappa = eps(kappa) [D+]_{-kappa},
+    eps(+1/2) = +1, eps(-1/2) = -1, with the doublets of site k."""
+    sg = (-1.0) ** k
+    return {1: [-sg * A_UP, -A_DN.T],
+            2: [sg * A_DN, -A_UP.T]}
+
+
+def onsite(U):
+    """U (n_up - 1/2)(n_dn - 1/2) on one site."""
+    return U * (N_UP - 0.5 * EYE4) @ (N_DN - 0.5 * EYE4)
+
+
+def two_site_hop(t):
+    """-t sum_s (c+_1s c_2s + h.c.) on a two-site chain, as a 16x16 matrix in
+    the local basis (site 1 slow).  Taken from the Jordan-Wigner Hamiltonian
+    of a two-site chain with U = 0."""
+    return hubbard(2, t=t, U=0.0).toarray()
+
+
+# ----------------------------------------------------------------------------
+# MPS <-> state vector, explicit block bases
+# ----------------------------------------------------------------------------
+def mps_state(mps):
+    """Contract a dense MPS [M_1 .. M_L] (boundary bonds of dimension 1) to a
+    state vector of length 4^L."""
+    v = mps[0]
+    for M in mps[1:]:
+        v = np.tensordot(v, M, axes=([v.ndim - 1], [0]))
+    return v.reshape(-1)
+
+
+def left_block_basis(sites):
+    """Matrix Phi[(s_1..s_k), b] of the left block states defined by the
+    tensors of sites 1..k (first bond of dimension 1)."""
+    v = sites[0][0]                      # [4, chi_1]
+    for M in sites[1:]:
+        v = np.tensordot(v, M, axes=([v.ndim - 1], [0]))
+    return v.reshape(-1, v.shape[-1])
+
+
+def right_block_basis(sites):
+    """Matrix Psi[b, (s_{k+1}..s_L)] of the right block states defined by the
+    tensors of sites k+1..L (last bond of dimension 1)."""
+    v = sites[-1][..., 0]                # [chi, 4]
+    for M in reversed(sites[:-1]):
+        v = np.tensordot(M, v, axes=([2], [0]))
+    return v.reshape(v.shape[0], -1)
+
+
+def block_hamiltonian(n, t, U):
+    """Hubbard Hamiltonian (symmetric interaction) of an isolated block of n
+    sites, dense."""
+    if n == 0:
+        return np.zeros((1, 1))
+    return hubbard(n, t=t, U=U, symmetric=True).toarray()
+
+
+def _embed(op, pos, n):
+    """Operator acting on the pos-th (1-based) site of an n-site block."""
+    return np.kron(np.kron(np.eye(4 ** (pos - 1)), op), np.eye(4 ** (n - pos)))
+
+
+def left_env_explicit(sites, k, t, U):
+    """Left environment at bond k computed from the explicit block basis
+    (sites = tensors of sites 1..k, k >= 1)."""
+    Phi = left_block_basis(sites)
+    Hb = block_hamiltonian(k, t, U)
+    env = {0: (Phi.conj().T @ Hb @ Phi)[:, None, :]}
+    ops = left_channel_ops(k)
+    for w in (1, 2):
+        env[w] = np.stack([Phi.conj().T @ _embed(op, k, k) @ Phi for op in ops[w]], axis=1)
+    return env
+
+
+def right_env_explicit(sites, k, L, t, U):
+    """Right environment at bond k (block of sites k+1..L) from the explicit
+    block basis (sites = tensors of sites k+1..L)."""
+    Psi = right_block_basis(sites)
+    n = L - k
+    Hb = block_hamiltonian(n, t, U)
+    env = {0: (Psi.conj() @ Hb @ Psi.T)[:, None, :]}
+    ops = right_channel_ops(k + 1)
+    for w in (1, 2):
+        env[w] = np.stack([Psi.conj() @ _embed(op, 1, n) @ Psi.T for op in ops[w]], axis=1)
+    return env
+
+
+def empty_env():
+    """Environment of an empty block (bond of dimension 1)."""
+    return {0: np.zeros((1, 1, 1), complex), 1: np.zeros((1, 2, 1), complex),
+            2: np.zeros((1, 2, 1), complex)}
+
+
+# ----------------------------------------------------------------------------
+# environment updates (recursive definition)
+# ----------------------------------------------------------------------------
+def left_env_update(env, A, k, t, U):
+    """Left environment at bond k from the one at bond k-1 and the
+    left-canonical tensor A of site k:
+      H'   = A^dag (H x 1 + 1 x onsite_k + hop(k-1, k)) A
+      D'_w = A^dag (1 x O^w_kappa(k)) A
+    where hop(k-1,k) couples the old edge operators to the partners on site k."""
+    Ac = A.conj()
+    # H part: old block Hamiltonian carried through
+    X = np.einsum("xy,ysb->xsb", env[0][:, 0, :], A)
+    Hn = np.einsum("xsc,xsb->cb", Ac, X)
+    # on-site term of site k
+    Hn = Hn + np.einsum("xsc,st,xtb->cb", Ac, onsite(U), A)
+    # hopping across (k-1, k)
+    if k > 1:
+        sg = (-1.0) ** (k - 1)
+        qops = right_channel_ops(k)
+        for w, sign in ((1, 1.0), (2, -1.0)):
+            for kap in range(2):
+                Y = np.einsum("xy,st,ytb->xsb", env[w][:, kap, :], qops[w][kap], A)
+                Hn = Hn + (-t) * sg * sign * np.einsum("xsc,xsb->cb", Ac, Y)
+    out = {0: Hn[:, None, :]}
+    ops = left_channel_ops(k)
+    for w in (1, 2):
+        out[w] = np.stack([np.einsum("xsc,st,xtb->cb", Ac, op, A) for op in ops[w]], axis=1)
+    return out
+
+
+def right_env_update(env, B, k, t, U):
+    """Right environment at bond k-1 from the one at bond k and the
+    right-canonical tensor B of site k (B[chi_{k-1}, 4, chi_k]):
+      H'   = B (H x 1 + onsite_k x 1 + hop(k, k+1)) B^dag
+      D'_w = B (Q^w_kappa(k) x 1) B^dag
+    written with <Psi'| . |Psi> ordering: E'[x', x] = sum conj(B[x',..]) (.) B[x,..]."""
+    Bc = B.conj()
+    X = np.einsum("xsb,yb->xsy", B, env[0][:, 0, :])        # [x, s, b']
+    Hn = np.einsum("zsy,xsy->zx", Bc, X)
+    Hn = Hn + np.einsum("zsb,st,xtb->zx", Bc, onsite(U), B)
+    sg = (-1.0) ** k
+    oops = left_channel_ops(k)
+    for w, sign in ((1, 1.0), (2, -1.0)):
+        for kap in range(2):
+            Y = np.einsum("st,xtb,yb->xsy", oops[w][kap], B, env[w][:, kap, :])
+            Hn = Hn + (-t) * sg * sign * np.einsum("zsy,xsy->zx", Bc, Y)
+    out = {0: Hn[:, None, :]}
+    qops = right_channel_ops(k)
+    for w in (1, 2):
+        out[w] = np.stack([np.einsum("zsb,st,xtb->zx", Bc, op, B) for op in qops[w]], axis=1)
+    return out
+
+
+# ----------------------------------------------------------------------------
+# effective Hamiltonians
+# ----------------------------------------------------------------------------
+def heff2(Lenv, Renv, Th, i, t, U):
+    """Effective Hamiltonian of sites (i, i+1) applied to Th[a, s1, s2, b].
+    Lenv: left environment at bond i-1; Renv: right environment at bond i+1."""
+    out = np.einsum("xy,ystb->xstb", Lenv[0][:, 0, :], Th)
+    out += np.einsum("zb,xstb->xstz", Renv[0][:, 0, :], Th)
+    hU = onsite(U)
+    out += np.einsum("su,xutb->xstb", hU, Th)
+    out += np.einsum("tu,xsub->xstb", hU, Th)
+    h2 = two_site_hop(t).reshape(4, 4, 4, 4)
+    out += np.einsum("stuv,xuvb->xstb", h2, Th)
+    # hopping across (i-1, i): left edge operators x partners on site i
+    sgl = (-1.0) ** (i - 1)
+    q = right_channel_ops(i)
+    for w, sign in ((1, 1.0), (2, -1.0)):
+        for kap in range(2):
+            out += (-t) * sgl * sign * np.einsum("xy,su,yutb->xstb", Lenv[w][:, kap, :],
+                                                 q[w][kap], Th)
+    # hopping across (i+1, i+2): operators on site i+1 x right edge partners
+    sgr = (-1.0) ** (i + 1)
+    o = left_channel_ops(i + 1)
+    for w, sign in ((1, 1.0), (2, -1.0)):
+        for kap in range(2):
+            out += (-t) * sgr * sign * np.einsum("tu,zb,xsub->xstz", o[w][kap],
+                                                 Renv[w][:, kap, :], Th)
+    return out
+
+
+def heff1(Lenv, Renv, C, k, t, U):
+    """Effective Hamiltonian of site k applied to C[a, s, b].
+    Lenv: left environment at bond k-1; Renv: right environment at bond k."""
+    out = np.einsum("xy,ysb->xsb", Lenv[0][:, 0, :], C)
+    out += np.einsum("zb,xsb->xsz", Renv[0][:, 0, :], C)
+    out += np.einsum("su,xub->xsb", onsite(U), C)
+    sgl = (-1.0) ** (k - 1)
+    q = right_channel_ops(k)
+    for w, sign in ((1, 1.0), (2, -1.0)):
+        for kap in range(2):
+            out += (-t) * sgl * sign * np.einsum("xy,su,yub->xsb", Lenv[w][:, kap, :], q[w][kap], C)
+    sgr = (-1.0) ** k
+    o = left_channel_ops(k)
+    for w, sign in ((1, 1.0), (2, -1.0)):
+        for kap in range(2):
+            out += (-t) * sgr * sign * np.einsum("su,zb,xub->xsz", o[w][kap], Renv[w][:, kap, :], C)
+    return out
+
+
+def heff2_projected(H, Phi, Psi, Th):
+    """Plain definition P^dag H P Th with P = Phi x 1 x 1 x Psi^T
+    (Phi: left block basis [4^(i-1), chi], Psi: right block basis [chi, 4^(L-i-1)])."""
+    nl, a = Phi.shape
+    b, nr = Psi.shape
+    P = np.kron(np.kron(Phi, np.eye(16)), Psi.T)          # [4^L, a*16*b]
+    return (P.conj().T @ (H @ (P @ Th.reshape(-1)))).reshape(Th.shape)
+
+
+# ----------------------------------------------------------------------------
+# Krylov exponential
+# ----------------------------------------------------------------------------
+def expm_dense(apply, v, tau):
+    """exp(tau H) v by building the dense matrix of ``apply`` column by
+    column and calling scipy.linalg.expm (small problems only)."""
+    shape = v.shape
+    n = v.size
+    Hm = np.empty((n, n), dtype=np.complex128)
+    e = np.zeros(n, dtype=np.complex128)
+    for j in range(n):
+        e[j] = 1.0
+        Hm[:, j] = apply(e.reshape(shape)).reshape(-1)
+        e[j] = 0.0
+    return (scipy.linalg.expm(tau * Hm) @ v.reshape(-1)).reshape(shape)
+
+
+def lanczos_expm(apply, v, tau, tol=1e-12, maxdim=40):
+    """exp(tau H) v for Hermitian H given as ``apply``.
+
+    Lanczos with full re-orthogonalisation (two classical Gram-Schmidt
+    passes).  After each new vector the Krylov approximation
+    y = |v| exp(tau T_m) e_1 is formed and the iteration stops when the
+    a-posteriori estimate beta_m |y_m| <= tol |v| (the adaptive-dimension rule
+    cited by the paper in section S2.2), on a happy breakdown, or at maxdim.
+    Returns (w, info) with info = {'iters', 'err', 'converged'}."""
+    shape = v.shape
+    nrm = np.linalg.norm(v)
+    if nrm == 0.0:
+        return v.copy(), {"iters": 0, "err": 0.0, "converged": True}
+    V = [v.reshape(-1) / nrm]
+    alpha, beta = [], []
+    err = np.inf
+    for m in range(1, maxdim + 1):
+        w = apply(V[-1].reshape(shape)).reshape(-1)
+        a = np.vdot(V[-1], w).real
+        alpha.append(a)
+        w = w - a * V[-1] - (beta[-1] * V[-2] if m > 1 else 0.0)
+        for _ in range(2):
+            Vm = np.array(V)
+            w = w - Vm.T @ (Vm.conj() @ w)
+        b = np.linalg.norm(w)
+        T = np.diag(alpha) + np.diag(beta, 1) + np.diag(beta, -1)
+        y = scipy.linalg.expm(tau * T)[:, 0] * nrm
+        err = b * abs(y[-1])
+        if b < 1e-14 * nrm or err <= tol * nrm or m == maxdim:
+            out = np.array(V).T @ y
+            return out.reshape(shape), {"iters": m, "err": float(err),
+                                        "converged": bool(b < 1e-14 * nrm or err <= tol * nrm)}
+        beta.append(b)
+        V.append(w / b)
+
+
+# ----------------------------------------------------------------------------
+# complete MPS and the two-site TDVP sweep
+# ----------------------------------------------------------------------------
+def complete_right_canonical(psi, L):
+    """Right-canonical MPS [C_1, B_2, ..., B_L] of a state vector with every
+    bond at its maximal dimension min(4^k, 4^(L-k)): every singular value is
+    kept, zero ones included, so the bases are complete."""
+    mps = [None] * L
+    rest = psi.reshape(-1, 1)            # [4^L, 1]
+    chi_r = 1
+    for k in range(L, 1, -1):
+        M = rest.reshape(-1, 4 * chi_r)  # [4^(k-1), 4 chi_r]
+        U_, S, Vh = np.linalg.svd(M, full_matrices=False)
+        chi = S.size
+        mps[k - 1] = Vh.reshape(chi, 4, chi_r)
+        rest = U_ * S
+        chi_r = chi
+    mps[0] = rest.reshape(1, 4, chi_r)
+    return mps
+
+
+def _svd_split(M, keep_all, eps_tol, chi_cap):
+    U_, S, Vh = np.linalg.svd(M, full_matrices=False)
+    if keep_all:
+        return U_, S, Vh, 0.0
+    w = S ** 2
+    tot = w.sum()
+    keep = S.size
+    disc = 0.0
+    while keep > 1 and (disc + w[keep - 1] <= eps_tol * tot or keep > chi_cap):
+        disc += w[keep - 1]
+        keep -= 1
+    S = S[:keep] / np.sqrt(1.0 - disc / tot) if tot > 0 else S[:keep]
+    return U_[:, :keep], S, Vh[:keep], disc / tot if tot > 0 else 0.0
+
+
+def tdvp2_sweep(mps, dt, t, U, tol=1e-12, maxdim=40, keep_all=True, eps_tol=0.0,
+                chi_cap=10 ** 9, use_dense_expm=False):
+    """One time step dt of symmetric second-order two-site TDVP.
+
+    Input: right-canonical MPS [C_1, B_2, ..., B_L] (centre on site 1).
+    Left-to-right with tau = dt/2: for i = 1..L-1, Th = C_i B_{i+1};
+    Th <- exp(-i tau H2_eff) Th; SVD Th = U S V^dag; A_i = U; C_{i+1} = S V^dag;
+    update the left environment; if i < L-1, C_{i+1} <- exp(+i tau H1_eff) C_{i+1}.
+    Then right-to-left, mirrored, with tau = dt/2, ending with the centre on
+    site 1.  Returns the new MPS (same form) and the discarded weights."""
+    L = len(mps)
+    tau = dt / 2.0
+    expm = (lambda f, v, z: expm_dense(f, v, z)) if use_dense_expm else \
+        (lambda f, v, z: lanczos_expm(f, v, z, tol=tol, maxdim=maxdim)[0])
+    # right environments from the right-canonical tensors
+    R = [None] * (L + 1)
+    R[L] = empty_env()
+    for k in range(L, 1, -1):
+        R[k - 1] = right_env_update(R[k], mps[k - 1], k, t, U)
+    Lf = [None] * (L + 1)
+    Lf[0] = empty_env()
+    mps = list(mps)
+    disc = []
+    C = mps[0]
+    for i in range(1, L):
+        Th = np.tensordot(C, mps[i], axes=([2], [0]))
+        Th = expm(lambda x: heff2(Lf[i - 1], R[i + 1], x, i, t, U), Th, -1j * tau)
+        a, s1, s2, b = Th.shape
+        Um, S, Vh, d = _svd_split(Th.reshape(a * 4, 4 * b), keep_all, eps_tol, chi_cap)
+        disc.append(d)
+        mps[i - 1] = Um.reshape(a, 4, -1)
+        C = (S[:, None] * Vh).reshape(-1, 4, b)
+        Lf[i] = left_env_update(Lf[i - 1], mps[i - 1], i, t, U)
+        if i < L - 1:
+            C = expm(lambda x: heff1(Lf[i], R[i + 1], x, i + 1, t, U), C, +1j * tau)
+    for i in range(L - 1, 0, -1):
+        Th = np.tensordot(mps[i - 1], C, axes=([2], [0]))
+        Th = expm(lambda x: heff2(Lf[i - 1], R[i + 1], x, i, t, U), Th, -1j * tau)
+        a, s1, s2, b = Th.shape
+        Um, S, Vh, d = _svd_split(Th.reshape(a * 4, 4 * b), keep_all, eps_tol, chi_cap)
+        disc.append(d)
+        mps[i] = Vh.reshape(-1, 4, b)
+        C = (Um * S).reshape(a, 4, -1)
+        R[i] = right_env_update(R[i + 1], mps[i], i + 1, t, U)
+        if i > 1:
+            C = expm(lambda x: heff1(Lf[i - 1], R[i], x, i, t, U), C, +1j * tau)
+    mps[0] = C
+    return mps, disc
