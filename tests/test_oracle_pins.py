@@ -1,0 +1,346 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: closed
+forms, an independent library, invariants, brute force, or a value printed
+in the paper.  A plausible slip anywhere in the oracle (a dropped term, a
+wrong sign or index, a transposed operand) breaks at least one of them.
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import cg as CG
+from oracle import dense as D
+from oracle import fermions as F
+from oracle import reduced as R
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------
+# Clebsch-Gordan coefficients
+# --------------------------------------------------------------------------
+def test_cg_matches_sympy():
+    from sympy import S
+    from sympy.physics.wigner import clebsch_gordan
+    worst = 0.0
+    for tj1 in range(0, 6):
+        for tj2 in range(0, 5):
+            for tJ in range(abs(tj1 - tj2), tj1 + tj2 + 1, 2):
+                for tm1 in range(-tj1, tj1 + 1, 2):
+                    for tm2 in range(-tj2, tj2 + 1, 2):
+                        tM = tm1 + tm2
+                        if abs(tM) > tJ:
+                            continue
+                        ref = float(clebsch_gordan(S(tj1) / 2, S(tj2) / 2, S(tJ) / 2,
+                                                   S(tm1) / 2, S(tm2) / 2, S(tM) / 2))
+                        worst = max(worst, abs(CG.cg2(tj1, tm1, tj2, tm2, tJ, tM) - ref))
+    assert worst < 1e-15
+
+
+def test_cg_closed_forms_and_orthonormality():
+    # coupling to a singlet: <j m; j -m | 0 0> = (-1)^(j-m) / sqrt(2j+1)
+    for tj in range(0, 9):
+        for tm in range(-tj, tj + 1, 2):
+            ref = (-1) ** ((tj - tm) // 2) / np.sqrt(tj + 1)
+            assert abs(CG.cg2(tj, tm, tj, -tm, 0, 0) - ref) < 1e-15
+    # stretched state <j1 j1; j2 j2 | j1+j2 j1+j2> = 1
+    for tj1 in range(0, 7):
+        for tj2 in range(0, 7):
+            assert abs(CG.cg2(tj1, tj1, tj2, tj2, tj1 + tj2, tj1 + tj2) - 1.0) < 1e-15
+    # unitarity of the coupling transformation
+    for tj1 in range(0, 6):
+        for tj2 in range(0, 4):
+            rows = []
+            for tJ in range(abs(tj1 - tj2), tj1 + tj2 + 1, 2):
+                rows.append(CG.cg_tensor(tj1, tj2, tJ).reshape(-1, tJ + 1))
+            Umat = np.concatenate(rows, axis=1)
+            assert np.allclose(Umat.T @ Umat, np.eye(Umat.shape[1]), atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Fermions, Hamiltonian, pseudospin
+# --------------------------------------------------------------------------
+def test_jordan_wigner_anticommutation():
+    L = 3
+    c = [F.annihilator(i, s, L) for i in range(1, L + 1) for s in (0, 1)]
+    eye = np.eye(4 ** L)
+    for p in range(len(c)):
+        for q in range(len(c)):
+            ac = (c[p] @ c[q].T + c[q].T @ c[p]).toarray()
+            assert np.allclose(ac, eye * (p == q))
+            aa = (c[p] @ c[q] + c[q] @ c[p]).toarray()
+            assert np.allclose(aa, 0.0)
+
+
+def test_pseudospin_algebra_and_symmetry_of_h():
+    """Supplementary S2.1: [T+,T-] = 2Tz, [Tz,T+-] = +-T+-; the symmetric
+    interaction commutes with T+, Eq. (1)'s n_up n_dn gives [H,T+] = U T+."""
+    L = 4
+    U = 3.0
+    Tp, Tm, Tz = F.pseudospin(L)
+    assert abs(Tp @ Tm - Tm @ Tp - 2 * Tz).max() < 1e-12
+    assert abs(Tz @ Tp - Tp @ Tz - Tp).max() < 1e-12
+    assert abs(Tz @ Tm - Tm @ Tz + Tm).max() < 1e-12
+    Hs = F.hubbard(L, 1.0, U, symmetric=True)
+    He = F.hubbard(L, 1.0, U, symmetric=False)
+    assert abs(Hs @ Tp - Tp @ Hs).max() < 1e-12
+    assert abs(He @ Tp - Tp @ He - U * Tp).max() < 1e-12
+
+
+def test_neel_quantum_numbers():
+    L = 6
+    psi = F.neel_state(L)
+    Tp, Tm, Tz = F.pseudospin(L)
+    T2 = Tp @ Tm + Tz @ Tz - Tz
+    assert abs(np.vdot(psi, T2 @ psi)) < 1e-14
+    nu, nd, _ = F.local_expectations(psi, L)
+    assert np.allclose(nu, [1, 0, 1, 0, 1, 0]) and np.allclose(nd, 1 - nu)
+    He = F.hubbard(L, 1.0, 4.0)
+    Hs = F.hubbard(L, 1.0, 4.0, symmetric=True)
+    assert abs(np.vdot(psi, He @ psi)) < 1e-14                      # E_Eq1(Neel) = 0
+    assert abs(np.vdot(psi, Hs @ psi).real + 4.0 * L / 4) < 1e-12  # E_sym = -UL/4
+
+
+def test_free_fermion_closed_form():
+    """U = 0: each spin species evolves as free fermions on the open chain."""
+    L = 6
+    H = F.hubbard(L, 1.0, 0.0)
+    psi0 = F.neel_state(L)
+    times = np.linspace(0.0, 2.0, 5)
+    traj = F.evolve(H, psi0, times)
+    n0u = np.array([1.0 if i % 2 == 0 else 0.0 for i in range(L)])
+    ref = F.free_fermion_density(L, 1.0, times, n0u)
+    for k in range(len(times)):
+        nu, nd, _ = F.local_expectations(traj[k], L)
+        assert np.abs(nu - ref[k]).max() < 1e-12
+        assert np.abs(nd - F.free_fermion_density(L, 1.0, [times[k]], 1 - n0u)[0]).max() < 1e-12
+
+
+def test_short_time_expansion():
+    """<n_i,up(t)> = n0 + (1 - 2 n0) z_i t^2 + O(t^4), independent of U."""
+    L = 6
+    for U in (0.0, 4.0):
+        H = F.hubbard(L, 1.0, U)
+        psi = F.evolve(H, F.neel_state(L), [0.0, 0.02])[1]
+        nu, _, _ = F.local_expectations(psi, L)
+        n0 = np.array([1.0 if i % 2 == 0 else 0.0 for i in range(L)])
+        z = np.array([1] + [2] * (L - 2) + [1])
+        ref = n0 + (1 - 2 * n0) * z * 0.02 ** 2
+        assert np.abs(nu - ref).max() < 5e-6
+
+
+def test_exact_invariants():
+    L = 6
+    U = 4.0
+    H = F.hubbard(L, 1.0, U)
+    traj = F.evolve(H, F.neel_state(L), [0.0, 0.5, 1.5])
+    for psi in traj:
+        nu, nd, dd = F.local_expectations(psi, L)
+        assert np.abs(nu + nd - 1).max() < 1e-12                # <n_i> = 1
+        assert np.abs(dd - (1 - nu - nd + dd)).max() < 1e-12    # doublon = holon
+        assert np.abs(nu - nd[::-1]).max() < 1e-12              # reflection x spin flip
+        assert abs(np.vdot(psi, H @ psi)) < 1e-12               # E_Eq1 conserved (= 0)
+        assert abs(np.linalg.norm(psi) - 1) < 1e-12
+
+
+def test_zero_hopping_is_static():
+    L = 4
+    H = F.hubbard(L, 0.0, 4.0)
+    psi = F.evolve(H, F.neel_state(L), [0.0, 3.0])[1]
+    nu, _, _ = F.local_expectations(psi, L)
+    assert np.allclose(nu, [1, 0, 1, 0], atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Reduced-tensor conventions
+# --------------------------------------------------------------------------
+def _expand_mps(bonds, sites, center):
+    full = []
+    for k in range(1, len(sites) + 1):
+        kind = "A" if k < center else ("C" if k == center else "B")
+        full.append(R.expand_site(kind, sites[k - 1], bonds[k - 1], bonds[k], k))
+    return full
+
+
+def test_reduced_expansion_isometries_and_singlet():
+    L = 6
+    bonds, sites = synth.random_mps(L, 24, seed=3, center=3)
+    full = _expand_mps(bonds, sites, 3)
+    for k in (1, 2):
+        A = full[k - 1].reshape(-1, full[k - 1].shape[2])
+        assert np.allclose(A.conj().T @ A, np.eye(A.shape[1]), atol=1e-13)
+    for k in (4, 5, 6):
+        B = full[k - 1].reshape(full[k - 1].shape[0], -1)
+        assert np.allclose(B @ B.conj().T, np.eye(B.shape[0]), atol=1e-13)
+    psi = D.mps_state(full)
+    flat = np.sqrt(sum(np.sum(np.abs(v) ** 2) for v in sites[2].values()))
+    assert abs(np.linalg.norm(psi) - flat) < 1e-13
+    Tp, Tm, Tz = F.pseudospin(L)
+    assert abs(np.vdot(psi, (Tp @ Tm + Tz @ Tz - Tz) @ psi)) < 1e-13
+    nu, nd, _ = F.local_expectations(psi / np.linalg.norm(psi), L)
+    assert abs(np.sum(nu - nd)) < 1e-13                          # S^z = 0
+
+
+def test_theta_expansion_norm():
+    bonds, sites = synth.random_mps(6, 30, seed=5, center=3)
+    left, right = bonds[2], bonds[4]
+    keys = []
+    for ia, (qa, tja, da) in enumerate(left):
+        for s1, (q1, t1) in enumerate(R.MULTIPLETS):
+            for tjx in range(abs(tja - t1), tja + t1 + 1, 2):
+                for s2, (q2, t2) in enumerate(R.MULTIPLETS):
+                    for ib, (qb, tjb, db) in enumerate(right):
+                        if qa + q1 + q2 == qb and abs(tjx - t2) <= tjb <= tjx + t2:
+                            keys.append((ia, s1, tjx, s2, ib))
+    blocks = synth.block_data(keys, [(left[k[0]][2], right[k[4]][2]) for k in keys], seed=1)
+    Th = R.expand_theta(blocks, left, right, 3)
+    flat = np.sqrt(sum(np.sum(np.abs(v) ** 2) for v in blocks.values()))
+    assert abs(np.linalg.norm(Th) - flat) < 1e-12
+
+
+def _project_env(E, bond):
+    offs, _ = R.bond_offsets(bond)
+    resid = 0.0
+    for io, (qo, tjo, do) in enumerate(bond):
+        for ii, (qi, tji, di) in enumerate(bond):
+            for w, (qw, tjw) in enumerate(R.CHANNELS):
+                sub = E[w][offs[io]:offs[io] + do * (tjo + 1), :, offs[ii]:offs[ii] + di * (tji + 1)]
+                sub = sub.reshape(do, tjo + 1, tjw + 1, di, tji + 1)
+                if qo != qi + qw or not (abs(tji - tjw) <= tjo <= tji + tjw):
+                    resid = max(resid, np.abs(sub).max())
+                    continue
+                mt = np.transpose(CG.cg_tensor(tji, tjw, tjo), (2, 1, 0))
+                blk = np.einsum("xakyb,akb->xy", sub, mt) / np.sum(mt ** 2)
+                resid = max(resid, np.abs(np.einsum("xy,akb->xakyb", blk, mt) - sub).max())
+    return resid
+
+
+def test_environment_wigner_eckart_form():
+    """Dense environments of an expanded symmetric MPS have exactly the
+    documented reduced form E_red x C(j_in m; j_w kappa | j_out m')."""
+    L = 6
+    t, U = 1.0, 4.0
+    bonds, sites = synth.random_mps(L, 24, seed=11, center=L)
+    full = _expand_mps(bonds, sites, L)
+    env = D.empty_env()
+    for k in range(1, L):
+        env = D.left_env_update(env, full[k - 1], k, t, U)
+        assert _project_env(env, bonds[k]) < 1e-12
+    bonds, sites = synth.random_mps(L, 24, seed=12, center=1)
+    full = _expand_mps(bonds, sites, 1)
+    env = D.empty_env()
+    for k in range(L, 1, -1):
+        env = D.right_env_update(env, full[k - 1], k, t, U)
+        assert _project_env(env, bonds[k - 1]) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# Dense MPS algebra and TDVP
+# --------------------------------------------------------------------------
+def test_bond_hopping_decomposition():
+    for k in (1, 2, 5):
+        o = D.left_channel_ops(k)
+        q = D.right_channel_ops(k + 1)
+        h = sum(sg * np.kron(o[w][kap], q[w][kap]) for w, sg in ((1, 1), (2, -1)) for kap in range(2))
+        assert np.abs((-1) ** k * h + D.two_site_hop(1.0)).max() < 1e-15
+
+
+def _left_complete(psi, L):
+    mps, rest, chi = [None] * L, psi.reshape(1, -1), 1
+    for k in range(1, L):
+        U_, S, Vh = np.linalg.svd(rest.reshape(chi * 4, -1), full_matrices=False)
+        mps[k - 1] = U_.reshape(chi, 4, -1)
+        rest, chi = S[:, None] * Vh, S.size
+    mps[L - 1] = rest.reshape(chi, 4, 1)
+    return mps
+
+
+def test_environments_recursive_vs_explicit_and_heff_vs_projection():
+    L, t, U = 5, 1.0, 4.0
+    rng = np.random.default_rng(0)
+    psi = rng.normal(size=4 ** L) + 1j * rng.normal(size=4 ** L)
+    psi /= np.linalg.norm(psi)
+    right = D.complete_right_canonical(psi, L)
+    left = _left_complete(psi, L)
+    Rv = [None] * (L + 1)
+    Rv[L] = D.empty_env()
+    for k in range(L, 1, -1):
+        Rv[k - 1] = D.right_env_update(Rv[k], right[k - 1], k, t, U)
+        ex = D.right_env_explicit(right[k - 1:], k - 1, L, t, U)
+        assert max(np.abs(ex[w] - Rv[k - 1][w]).max() for w in range(3)) < 1e-12
+    Lv = [D.empty_env()]
+    for k in range(1, L):
+        Lv.append(D.left_env_update(Lv[-1], left[k - 1], k, t, U))
+        ex = D.left_env_explicit(left[:k], k, t, U)
+        assert max(np.abs(ex[w] - Lv[k][w]).max() for w in range(3)) < 1e-12
+    H = F.hubbard(L, t, U, symmetric=True)
+    for i in range(1, L):
+        Phi = D.left_block_basis(left[:i - 1]) if i > 1 else np.ones((1, 1))
+        Psi = D.right_block_basis(right[i + 1:]) if i + 1 < L else np.ones((1, 1))
+        Th = rng.normal(size=(Phi.shape[1], 4, 4, Psi.shape[0])) + 0j
+        a = D.heff2(Lv[i - 1], Rv[i + 1], Th, i, t, U)
+        b = D.heff2_projected(H, Phi, Psi, Th)
+        assert np.abs(a - b).max() < 1e-12 * max(1.0, np.abs(b).max())
+
+
+def test_lanczos_expm_matches_scipy():
+    rng = np.random.default_rng(2)
+    n = 60
+    M = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+    Hm = (M + M.conj().T) / 2
+    v = rng.normal(size=n) + 1j * rng.normal(size=n)
+    for tau in (-0.05j, 0.05j, -0.3j):
+        w, info = D.lanczos_expm(lambda x: Hm @ x, v, tau, tol=1e-13, maxdim=40)
+        ref = scipy.linalg.expm(tau * Hm) @ v
+        assert info["converged"]
+        assert np.abs(w - ref).max() < 1e-11 * np.linalg.norm(v)
+
+
+@pytest.mark.parametrize("L,nsteps", [(4, 3), (6, 1)])
+def test_complete_basis_tdvp_equals_exact_evolution(L, nsteps):
+    t, U, dt = 1.0, 4.0, 0.05
+    psi0 = F.neel_state(L)
+    mps = D.complete_right_canonical(psi0, L)
+    H = F.hubbard(L, t, U, symmetric=True)
+    exact = F.evolve(H, psi0, np.arange(nsteps + 1) * dt)
+    for n in range(nsteps):
+        mps, _ = D.tdvp2_sweep(mps, dt, t, U, tol=1e-13)
+        v = D.mps_state(mps)
+        assert abs(abs(np.vdot(exact[n + 1], v)) - 1) < 1e-12
+        assert np.abs(F.local_expectations(v, L)[0] - F.local_expectations(exact[n + 1], L)[0]).max() < 1e-12
+
+
+def test_complete_basis_time_reversal():
+    L, t, U = 4, 1.0, 4.0
+    rng = np.random.default_rng(4)
+    psi = rng.normal(size=4 ** L) + 1j * rng.normal(size=4 ** L)
+    psi /= np.linalg.norm(psi)
+    mps = D.complete_right_canonical(psi, L)
+    mps, _ = D.tdvp2_sweep(mps, 0.1, t, U, tol=1e-13)
+    mps, _ = D.tdvp2_sweep(mps, -0.1, t, U, tol=1e-13)
+    assert abs(abs(np.vdot(psi, D.mps_state(mps))) - 1) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# Paper-printed values
+# --------------------------------------------------------------------------
+def test_table_s2_bond_dimension_bookkeeping():
+    """Supplementary Table S2: sum d = chi_SU(2) = 12288, and the full-state
+    dimension sum d (2j+1) = 30842 (the paper's chi ~ 30 000)."""
+    rows = np.loadtxt(os.path.join(GOLDEN, "table_s2.txt"), dtype=int)
+    assert rows.shape == (32, 3)
+    assert rows[:, 2].sum() == 12288
+    assert int(np.sum(rows[:, 2] * (rows[:, 1] + 1))) == 30842
+    assert np.all((rows[:, 0] - rows[:, 1]) % 2 == 0)      # even left block: q = 2j mod 2
+    assert rows[:, 2].max() == 1735                          # d_max
+
+
+def test_synthetic_profile_shape():
+    p = synth.sector_profile(4096, 0)
+    assert synth.chi_full(p) == 4096
+    ratio = synth.chi_full(p) / synth.chi_su2(p)
+    assert 2.3 < ratio < 2.6                                 # the paper's chi ~ 2.4 chi_SU(2)
