@@ -1,0 +1,272 @@
+/*
+ * tdvp.h -- C ABI of the MI355X (gfx950) two-site TDVP hot path for the
+ * U(1)_spin x SU(2)_charge symmetric 1D Fermi-Hubbard chain.
+ *
+ * Paper: two-site TDVP of a U(1)xSU(2)-reduced MPS; each sweep step merges
+ * two sites, exponentiates the local effective Hamiltonian with an adaptive
+ * Krylov method, splits by SVD and updates the environments (supplementary
+ * sections S2.1-S2.3).  This library computes those steps on one GPU.
+ *
+ * ---------------------------------------------------------------------------
+ * Conventions (shared with the CPU oracle by this text only)
+ * ---------------------------------------------------------------------------
+ * Hamiltonian.  Eq. (1) on an open chain of L sites, with the interaction in
+ * its particle-hole symmetric form U (n_up - 1/2)(n_dn - 1/2): that form
+ * commutes with the eta-pairing pseudospin of section S2.1, Eq. (1)'s own
+ * U n_up n_dn does not ([H, T+] = U T+).  At half filling the two differ by
+ * the constant U L / 4, i.e. a global phase.  Sites are numbered 1..L.
+ *
+ * Labels.  A bond sector is (q, tj): q = 2 S^z and tj = 2T (pseudospin) of
+ * everything left of the bond; its degeneracy is dim.  The local multiplets
+ * of site k are s = 0: (q=0, tj=1) with components m=+1/2 -> |up dn>,
+ * m=-1/2 -> (-1)^k |0>; s = 1: (q=+1, tj=0) = |up>; s = 2: (q=-1, tj=0) = |dn>
+ * (Jordan-Wigner mode order 1up, 1dn, 2up, ...; |up dn> = c+_up c+_dn |0>).
+ *
+ * Reduced tensors (Wigner-Eckart, section S2.1 bond decomposition), with
+ * Condon-Shortley coefficients C(j1 m1; j2 m2 | J M):
+ *   one-site key (ia, s, ib), block d_a x d_b:
+ *     A  (left-canonical):  A_full = A C(ja ma; js mu | jb mb)
+ *     B  (right-canonical): B_full = B C(..) sqrt((2ja+1)/(2jb+1))
+ *     C1 (one-site centre): C_full = C C(..) / sqrt(2jb+1)
+ *   two-site key (ia, s1, tjx, s2, ib), block d_a x d_b, tree ((a s1)->x) s2->b:
+ *     Th_full = Th sum_mx C(ja ma; js1 mu1 | jx mx) C(jx mx; js2 mu2 | jb mb) / sqrt(2jb+1)
+ *   With A left and B right of the centre, the flat Frobenius inner product of
+ *   centre tensors equals the inner product of the states.
+ *   environment key (iout, w, iin), block d_out x d_in, channel w = 0 'H'
+ *   (scalar), 1 'D+' (tj=1, q=+1), 2 'D-' (tj=1, q=-1):
+ *     E_full[(out m'), kappa, (in m)] = E C(j_in m; j_w kappa | j_out m')
+ *   Left environment at bond k: <Phi'| O |Phi> over the block of sites 1..k,
+ *   O = block Hamiltonian ('H'), or the edge doublets of site k times the site
+ *   parity: D+ = (c+_up P, (-1)^k c_dn P), D- = (c+_dn P, -(-1)^k c_up P).
+ *   Right environment at bond k: <Psi'| Q |Psi> over sites k+1..L, Q = block
+ *   Hamiltonian, or on site k+1: Q^{D+}_kappa = eps(kappa) [D-]_{-kappa},
+ *   Q^{D-}_kappa = eps(kappa) [D+]_{-kappa}, eps(+1/2) = 1, eps(-1/2) = -1.
+ *   The identity channels are implicit (canonical gauge).
+ *
+ * Memory.  Block data is complex128, interleaved (re, im), each block
+ * column-major with leading dimension = its row count, at the element
+ * offset given for it.  Data pointers passed to compute calls are DEVICE
+ * pointers owned by the caller; descriptor arrays are HOST pointers read
+ * during the call only.  Block order is free, but keys must be unique and
+ * offsets must not overlap; the *_layout queries give a canonical layout.
+ *
+ * Errors.  Every call returns TDVP_OK or a negative code and never throws;
+ * tdvp_last_error() gives a message.  Work is enqueued on the context stream;
+ * heff_apply and env_update do not synchronise.  krylov_expm and sweep
+ * synchronise (they need the Lanczos scalars on the host) and report earlier
+ * asynchronous device faults as TDVP_E_HIP.  A context is not thread-safe.
+ */
+#ifndef TDVP_H
+#define TDVP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  TDVP_OK = 0,
+  TDVP_E_INVALID = -1,   /* bad argument (null pointer, bad site, bad enum) */
+  TDVP_E_SHAPE = -2,     /* block dims / offsets inconsistent with the bonds */
+  TDVP_E_SECTOR = -3,    /* a block key violates the fusion rules or repeats */
+  TDVP_E_NOMEM = -4,     /* device or workspace allocation failed */
+  TDVP_E_HIP = -5,       /* HIP runtime error (including earlier async faults) */
+  TDVP_E_NOCONV = -6,    /* Krylov did not reach the tolerance within maxdim */
+  TDVP_E_NONFINITE = -7  /* NaN or Inf met in the data */
+};
+
+/* Arithmetic of the block contractions.  Lanczos scalars, reorthogonalisation,
+ * the small exponential and the SVD stay in FP64 in every mode. */
+enum { TDVP_FP64 = 0, TDVP_FP32 = 1 };
+
+typedef struct tdvp_ctx tdvp_ctx;
+typedef struct tdvp_mps tdvp_mps;
+
+/* Fermi-Hubbard chain: hopping t (Eq. (1)'s t_h), interaction U, L sites. */
+typedef struct {
+  double t;
+  double U;
+  int32_t L;
+} tdvp_model;
+
+/* One bond: n sectors (q[i], tj[i]) of degeneracy dim[i] (host arrays). */
+typedef struct {
+  int32_t n;
+  const int32_t* q;
+  const int32_t* tj;
+  const int64_t* dim;
+} tdvp_bond;
+
+/* Block-sparse reduced tensor: nblocks keys (3 or 5 ints each, host),
+ * element offsets (host), device data of `size` complex128 elements. */
+typedef struct {
+  int32_t nblocks;
+  const int32_t* keys;
+  const int64_t* offsets;
+  void* data;
+  int64_t size;
+} tdvp_blocks;
+
+typedef struct {
+  int32_t iters;        /* Krylov dimension used */
+  int32_t converged;    /* 1 if the error estimate met tol (or breakdown) */
+  double err_est;       /* beta_m |[exp(tau T_m)]_{m,1}| |x| */
+  double norm_in;       /* |x| on entry */
+  double alpha[64];     /* Lanczos diagonal (first min(iters,64)) */
+  double beta[64];      /* Lanczos off-diagonal */
+} tdvp_krylov_info;
+
+typedef struct {
+  double eps_tol;        /* discarded weight tolerance (relative), e.g. 1e-4 */
+  int64_t chi_cap;       /* cap on sum_kept (2j+1) d per bond (full-state units) */
+  int32_t keep_all;      /* 1: keep every singular value, zero ones included */
+  double krylov_tol;     /* Lanczos tolerance, relative to |x| */
+  int32_t krylov_maxdim; /* maximal Krylov dimension (<= 64) */
+} tdvp_trunc;
+
+typedef struct {
+  double max_discarded;   /* largest discarded weight of one bond update */
+  double sum_discarded;   /* sum over the sweep */
+  int64_t max_chi;        /* largest full-state bond dimension after the sweep */
+  int64_t max_chi_su2;    /* largest sum of degeneracies */
+  int32_t krylov_iters;   /* total Lanczos iterations (two- and one-site) */
+  int32_t krylov_max;     /* largest Krylov dimension used */
+  int32_t nonconverged;   /* exponentials that hit maxdim */
+  double heff_flops;      /* algorithmic flops of all H_eff applies */
+  double env_flops;       /* algorithmic flops of all environment updates */
+  double seconds;         /* host wall time of the call */
+  double t_heff, t_lanczos, t_svd, t_env;  /* seconds per phase (device events) */
+} tdvp_sweep_info;
+
+/* Plan of one H_eff apply, exported for host-side inspection and tests.
+ * kind 0: y[out] += coef * E[env] . x[in]   (left-environment term)
+ * kind 1: y[out] += coef * x[in] . E[env]^T (right-environment term)
+ * kind 2: y[out] += coef * x[in]            (local term)               */
+typedef struct {
+  int32_t kind;
+  int32_t out;
+  int32_t in;
+  int32_t env;
+  double coef;
+} tdvp_term;
+
+/* Plan of one environment update (host inspection):
+ * kind 0: out[o] += coef * op(bra[b])^ . E[env] . op(ket[k])
+ * kind 1: out[o] += coef * op(bra[b])^ . op(ket[k])    (identity channel)
+ * For direction +1 op(bra)^ = A^dag, op(ket) = A; for -1 op(bra)^ = conj(B),
+ * op(ket) = B^T. */
+typedef struct {
+  int32_t kind;
+  int32_t out;
+  int32_t bra;
+  int32_t ket;
+  int32_t env;
+  double coef;
+} tdvp_env_term;
+
+/* ---- context -------------------------------------------------------------
+ * device: HIP device ordinal; hip_stream: hipStream_t or NULL (the library
+ * then creates its own default-priority stream); precision: TDVP_FP64/FP32. */
+int tdvp_ctx_create(tdvp_ctx** out, int32_t device, void* hip_stream, int32_t precision);
+void tdvp_ctx_destroy(tdvp_ctx* ctx);
+int tdvp_ctx_set_precision(tdvp_ctx* ctx, int32_t precision);
+int tdvp_ctx_synchronize(tdvp_ctx* ctx);
+/* Last error message of ctx, or of the calling thread when ctx is NULL. */
+const char* tdvp_last_error(const tdvp_ctx* ctx);
+
+/* ---- layouts (host only, no GPU needed) ----------------------------------
+ * Canonical block list of a centre tensor between bonds left and right:
+ * nsites = 2 -> keys (ia, s1, tjx, s2, ib); nsites = 1 -> keys (ia, s, ib).
+ * Two-call pattern: pass keys = offsets = NULL to get *nblocks and *total. */
+int tdvp_center_layout(const tdvp_bond* left, const tdvp_bond* right, int32_t nsites,
+                       int32_t* nblocks, int32_t* keys, int64_t* offsets, int64_t* total);
+/* Canonical block list of an environment on `bond`: all (iout, w, iin)
+ * allowed by the selection rules of channel w. */
+int tdvp_env_layout(const tdvp_bond* bond, int32_t* nblocks, int32_t* keys, int64_t* offsets,
+                    int64_t* total);
+
+/* ---- effective Hamiltonian -----------------------------------------------
+ * y = H_eff x for the block of sites site..site+nsites-1 (nsites 1 or 2):
+ * left = bond site-1, right = bond site+nsites-1, Lenv = left environment at
+ * bond site-1, Renv = right environment at bond site+nsites-1.  x and y must
+ * list the same keys (offsets may differ); y is overwritten.
+ * The left-environment block products, the local two-site terms with their
+ * recoupling coefficients and the right-environment block products are fused
+ * in one grouped-GEMM launch. */
+int tdvp_heff_apply(tdvp_ctx* ctx, const tdvp_model* model, int32_t site, int32_t nsites,
+                    const tdvp_bond* left, const tdvp_bond* right, const tdvp_blocks* Lenv,
+                    const tdvp_blocks* Renv, const tdvp_blocks* x, tdvp_blocks* y);
+
+/* Host-side plan of the same apply (no GPU): fills up to *nterms terms and
+ * sets *nterms to the count (terms may be NULL) and *flops to the algorithmic
+ * flop count (8 per complex multiply-add of every block product). */
+int tdvp_heff_plan(const tdvp_model* model, int32_t site, int32_t nsites, const tdvp_bond* left,
+                   const tdvp_bond* right, const tdvp_blocks* Lenv, const tdvp_blocks* Renv,
+                   const tdvp_blocks* x, int64_t* nterms, tdvp_term* terms, double* flops);
+
+/* ---- Krylov exponential --------------------------------------------------
+ * x <- exp(tau H_eff) x, tau = tau_re + i tau_im (TDVP uses tau = -i dt/2
+ * forward and +i dt/2 for the one-site backward step).  Lanczos with full
+ * FP64 classical Gram-Schmidt re-orthogonalisation (two passes); stops when
+ * beta_m |[exp(tau T_m)]_{m,1}| <= tol |x|, on breakdown, or at maxdim
+ * (then TDVP_E_NOCONV with the best iterate left in x). */
+int tdvp_krylov_expm(tdvp_ctx* ctx, const tdvp_model* model, int32_t site, int32_t nsites,
+                     const tdvp_bond* left, const tdvp_bond* right, const tdvp_blocks* Lenv,
+                     const tdvp_blocks* Renv, tdvp_blocks* x, double tau_re, double tau_im,
+                     double tol, int32_t maxdim, tdvp_krylov_info* info);
+
+/* Host helper used by krylov_expm, exported for tests: y = nrm exp(tau T) e_1
+ * for the real symmetric tridiagonal T with diagonal alpha[0..n) and
+ * off-diagonal beta[0..n-1); y is n complex numbers, interleaved. */
+int tdvp_tridiag_expm(int32_t n, const double* alpha, const double* beta, double tau_re, double tau_im,
+                      double nrm, double* y);
+
+/* ---- environment update ----------------------------------------------------
+ * direction +1: env_in = left environment at bond site-1 (bond_in), tensor =
+ *   left-canonical A of `site` with keys (ia on bond_in, s, ib on bond_out);
+ *   env_out = left environment at bond site (bond_out).
+ * direction -1: env_in = right environment at bond site (bond_in), tensor =
+ *   right-canonical B of `site` with keys (ia on bond_out, s, ib on bond_in);
+ *   env_out = right environment at bond site-1 (bond_out).
+ * env_out keys must be those of tdvp_env_layout(bond_out); it is overwritten. */
+int tdvp_env_update(tdvp_ctx* ctx, const tdvp_model* model, int32_t site, int32_t direction,
+                    const tdvp_bond* bond_in, const tdvp_bond* bond_out, const tdvp_blocks* env_in,
+                    const tdvp_blocks* tensor, tdvp_blocks* env_out);
+int tdvp_env_plan(const tdvp_model* model, int32_t site, int32_t direction, const tdvp_bond* bond_in,
+                  const tdvp_bond* bond_out, const tdvp_blocks* env_in, const tdvp_blocks* tensor,
+                  const tdvp_blocks* env_out, int64_t* nterms, tdvp_env_term* terms, double* flops);
+
+/* ---- MPS and sweep ----------------------------------------------------------
+ * tdvp_mps_create copies a right-canonical MPS (centre C1 on site 1, B on
+ * sites 2..L; bonds[0..L], sites[0..L-1] with keys (ia, s, ib) on
+ * bonds[k-1], bonds[k]; device data) into library-owned memory and builds the
+ * right environments.  tdvp_mps_create_neel builds the Neel state of Eq. (2)
+ * (up on odd sites); complete = 1 pads every bond to its full symmetric
+ * dimension (zero-weight directions), which makes two-site TDVP exact. */
+int tdvp_mps_create(tdvp_ctx* ctx, const tdvp_model* model, const tdvp_bond* bonds,
+                    const tdvp_blocks* sites, tdvp_mps** out);
+int tdvp_mps_create_neel(tdvp_ctx* ctx, const tdvp_model* model, int32_t complete, tdvp_mps** out);
+void tdvp_mps_destroy(tdvp_mps* mps);
+/* bond k in 0..L: sector count, and (if arrays non-NULL) the sectors. */
+int tdvp_mps_bond(const tdvp_mps* mps, int32_t k, int32_t* n, int32_t* q, int32_t* tj, int64_t* dim);
+/* site tensor k in 1..L: layout query (two-call pattern) and host copy. */
+int tdvp_mps_site_layout(const tdvp_mps* mps, int32_t k, int32_t* nblocks, int32_t* keys,
+                         int64_t* offsets, int64_t* total);
+int tdvp_mps_site_read(tdvp_ctx* ctx, const tdvp_mps* mps, int32_t k, void* host_dst);
+/* One time step dt of symmetric second-order two-site TDVP: left-to-right
+ * then right-to-left with tau = dt/2 each, every bond merged, evolved by
+ * exp(-i tau H2), split by per-sector SVD (truncation: whole multiplets by
+ * descending singular value while the discarded weight stays within
+ * eps_tol of the total and the kept full dimension within chi_cap; kept
+ * values renormalised), environments updated and the one-site centre evolved
+ * back by exp(+i tau H1).  The MPS returns to right-canonical form. */
+int tdvp_sweep(tdvp_ctx* ctx, tdvp_mps* mps, double dt, const tdvp_trunc* trunc,
+               tdvp_sweep_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TDVP_H */

@@ -1,0 +1,280 @@
+"""MI355X (gfx950) two-site TDVP hot path for the U(1)xSU(2) Hubbard chain.
+
+Thin ctypes binding of ``libtdvp.so`` (C ABI declared in include/tdvp.h).
+It only marshals arguments: every step of the computation runs in the HIP
+library.  Device buffers are passed as raw pointers (e.g. from torch
+tensors); the binding allocates nothing on the device itself.
+
+Loading fails loudly if the library has not been built
+(``python -m paper_2606_04771_amd.build``): there is no fallback.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtdvp.so")
+
+TDVP_OK = 0
+ERRORS = {-1: "INVALID", -2: "SHAPE", -3: "SECTOR", -4: "NOMEM", -5: "HIP", -6: "NOCONV", -7: "NONFINITE"}
+FP64, FP32 = 0, 1
+
+
+class TdvpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"tdvp error {code} ({ERRORS.get(code, '?')}): {msg}")
+        self.code = code
+
+
+class _Model(C.Structure):
+    _fields_ = [("t", C.c_double), ("U", C.c_double), ("L", C.c_int32)]
+
+
+class _Bond(C.Structure):
+    _fields_ = [("n", C.c_int32), ("q", C.POINTER(C.c_int32)), ("tj", C.POINTER(C.c_int32)),
+                ("dim", C.POINTER(C.c_int64))]
+
+
+class _Blocks(C.Structure):
+    _fields_ = [("nblocks", C.c_int32), ("keys", C.POINTER(C.c_int32)), ("offsets", C.POINTER(C.c_int64)),
+                ("data", C.c_void_p), ("size", C.c_int64)]
+
+
+class _KrylovInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("err_est", C.c_double),
+                ("norm_in", C.c_double), ("alpha", C.c_double * 64), ("beta", C.c_double * 64)]
+
+
+class _Trunc(C.Structure):
+    _fields_ = [("eps_tol", C.c_double), ("chi_cap", C.c_int64), ("keep_all", C.c_int32),
+                ("krylov_tol", C.c_double), ("krylov_maxdim", C.c_int32)]
+
+
+class _SweepInfo(C.Structure):
+    _fields_ = [("max_discarded", C.c_double), ("sum_discarded", C.c_double), ("max_chi", C.c_int64),
+                ("max_chi_su2", C.c_int64), ("krylov_iters", C.c_int32), ("krylov_max", C.c_int32),
+                ("nonconverged", C.c_int32), ("heff_flops", C.c_double), ("env_flops", C.c_double),
+                ("seconds", C.c_double), ("t_heff", C.c_double), ("t_lanczos", C.c_double),
+                ("t_svd", C.c_double), ("t_env", C.c_double)]
+
+
+class _Term(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("out", C.c_int32), ("in_", C.c_int32), ("env", C.c_int32),
+                ("coef", C.c_double)]
+
+
+class _EnvTerm(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("out", C.c_int32), ("bra", C.c_int32), ("ket", C.c_int32),
+                ("env", C.c_int32), ("coef", C.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2606_04771_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "tdvp_ctx_create": [C.POINTER(C.c_void_p), I32, P, I32],
+        "tdvp_ctx_destroy": [P],
+        "tdvp_ctx_set_precision": [P, I32],
+        "tdvp_ctx_synchronize": [P],
+        "tdvp_last_error": [P],
+        "tdvp_center_layout": [P, P, I32, P, P, P, P],
+        "tdvp_env_layout": [P, P, P, P, P],
+        "tdvp_heff_apply": [P, P, I32, I32, P, P, P, P, P, P],
+        "tdvp_heff_plan": [P, I32, I32, P, P, P, P, P, P, P, P],
+        "tdvp_krylov_expm": [P, P, I32, I32, P, P, P, P, P, D, D, D, I32, P],
+        "tdvp_tridiag_expm": [I32, P, P, D, D, D, P],
+        "tdvp_env_update": [P, P, I32, I32, P, P, P, P, P],
+        "tdvp_env_plan": [P, I32, I32, P, P, P, P, P, P, P, P],
+        "tdvp_mps_create": [P, P, P, P, P],
+        "tdvp_mps_create_neel": [P, P, I32, P],
+        "tdvp_mps_destroy": [P],
+        "tdvp_mps_bond": [P, I32, P, P, P, P],
+        "tdvp_mps_site_layout": [P, I32, P, P, P, P],
+        "tdvp_mps_site_read": [P, P, I32, P],
+        "tdvp_sweep": [P, P, D, P, P],
+    }
+    for name, args in sig.items():
+        if not hasattr(lib, name):
+            continue
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_char_p if name == "tdvp_last_error" else (None if name.endswith("destroy") else C.c_int)
+    return lib
+
+
+lib = _load()
+
+
+def _check(rc, ctx=None):
+    if rc != TDVP_OK:
+        msg = lib.tdvp_last_error(ctx)
+        raise TdvpError(rc, msg.decode() if msg else "")
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Model:
+    def __init__(self, L, t=1.0, U=4.0):
+        self.L, self.t, self.U = int(L), float(t), float(U)
+        self._s = _Model(self.t, self.U, self.L)
+
+    @property
+    def ref(self):
+        return C.byref(self._s)
+
+
+class Bond:
+    """A bond as sectors [(q, tj, d), ...]."""
+
+    def __init__(self, sectors):
+        self.sectors = [(int(q), int(tj), int(d)) for q, tj, d in sectors]
+        n = len(self.sectors)
+        self.q = np.array([s[0] for s in self.sectors], np.int32)
+        self.tj = np.array([s[1] for s in self.sectors], np.int32)
+        self.d = np.array([s[2] for s in self.sectors], np.int64)
+        self._s = _Bond(n, self.q.ctypes.data_as(C.POINTER(C.c_int32)),
+                        self.tj.ctypes.data_as(C.POINTER(C.c_int32)),
+                        self.d.ctypes.data_as(C.POINTER(C.c_int64)))
+
+    @property
+    def ref(self):
+        return C.byref(self._s)
+
+    def __len__(self):
+        return len(self.sectors)
+
+
+class Blocks:
+    """Block descriptor: keys (n x keylen int32), offsets (int64), device
+    data pointer (int) and size in complex elements."""
+
+    def __init__(self, keys, offsets, data_ptr=0, size=None, dims=None):
+        self.keys = np.ascontiguousarray(np.asarray(keys, np.int32).reshape(len(offsets), -1))
+        self.offsets = np.ascontiguousarray(np.asarray(offsets, np.int64))
+        self.dims = dims
+        if size is None:
+            size = int(max((o + r * c for o, (r, c) in zip(self.offsets, dims)), default=0)) if dims else 0
+        self.size = int(size)
+        self.set_data(data_ptr)
+
+    def set_data(self, data_ptr):
+        self.data_ptr = int(data_ptr)
+        self._s = _Blocks(len(self.offsets), self.keys.ctypes.data_as(C.POINTER(C.c_int32)),
+                          self.offsets.ctypes.data_as(C.POINTER(C.c_int64)), C.c_void_p(self.data_ptr or None),
+                          self.size)
+        return self
+
+    @property
+    def ref(self):
+        return C.byref(self._s)
+
+    def __len__(self):
+        return len(self.offsets)
+
+
+def center_layout(left, right, nsites):
+    """Canonical blocks of a centre tensor: (keys, offsets, total, dims)."""
+    n = C.c_int32()
+    tot = C.c_int64()
+    _check(lib.tdvp_center_layout(left.ref, right.ref, nsites, C.byref(n), None, None, C.byref(tot)))
+    kl = 5 if nsites == 2 else 3
+    keys = np.zeros((n.value, kl), np.int32)
+    offs = np.zeros(n.value, np.int64)
+    _check(lib.tdvp_center_layout(left.ref, right.ref, nsites, C.byref(n), _ptr(keys), _ptr(offs), C.byref(tot)))
+    dims = [(left.sectors[k[0]][2], right.sectors[k[-1]][2]) for k in keys]
+    return keys, offs, tot.value, dims
+
+
+def env_layout(bond):
+    n = C.c_int32()
+    tot = C.c_int64()
+    _check(lib.tdvp_env_layout(bond.ref, C.byref(n), None, None, C.byref(tot)))
+    keys = np.zeros((n.value, 3), np.int32)
+    offs = np.zeros(n.value, np.int64)
+    _check(lib.tdvp_env_layout(bond.ref, C.byref(n), _ptr(keys), _ptr(offs), C.byref(tot)))
+    dims = [(bond.sectors[k[0]][2], bond.sectors[k[2]][2]) for k in keys]
+    return keys, offs, tot.value, dims
+
+
+def heff_plan(model, site, nsites, left, right, Lenv, Renv, x):
+    """Host-side term list of one H_eff apply: structured array with fields
+    kind, out, in_, env, coef; and the algorithmic flop count."""
+    nt = C.c_int64(0)
+    fl = C.c_double()
+    _check(lib.tdvp_heff_plan(model.ref, site, nsites, left.ref, right.ref, Lenv.ref, Renv.ref, x.ref,
+                              C.byref(nt), None, C.byref(fl)))
+    arr = (_Term * nt.value)()
+    _check(lib.tdvp_heff_plan(model.ref, site, nsites, left.ref, right.ref, Lenv.ref, Renv.ref, x.ref,
+                              C.byref(nt), arr, C.byref(fl)))
+    return [(t.kind, t.out, t.in_, t.env, t.coef) for t in arr], fl.value
+
+
+def env_plan(model, site, direction, bond_in, bond_out, env_in, tensor, env_out):
+    nt = C.c_int64(0)
+    fl = C.c_double()
+    _check(lib.tdvp_env_plan(model.ref, site, direction, bond_in.ref, bond_out.ref, env_in.ref, tensor.ref,
+                             env_out.ref, C.byref(nt), None, C.byref(fl)))
+    arr = (_EnvTerm * nt.value)()
+    _check(lib.tdvp_env_plan(model.ref, site, direction, bond_in.ref, bond_out.ref, env_in.ref, tensor.ref,
+                             env_out.ref, C.byref(nt), arr, C.byref(fl)))
+    return [(t.kind, t.out, t.bra, t.ket, t.env, t.coef) for t in arr], fl.value
+
+
+def tridiag_expm(alpha, beta, tau, nrm=1.0):
+    a = np.ascontiguousarray(alpha, np.float64)
+    b = np.ascontiguousarray(beta if len(beta) else [0.0], np.float64)
+    y = np.zeros(2 * len(a))
+    _check(lib.tdvp_tridiag_expm(len(a), _ptr(a), _ptr(b), float(np.real(tau)), float(np.imag(tau)),
+                                 float(nrm), _ptr(y)))
+    return y[0::2] + 1j * y[1::2]
+
+
+class Context:
+    """A library context on one HIP device and stream."""
+
+    def __init__(self, device=0, stream=None, precision=FP64):
+        h = C.c_void_p()
+        _check(lib.tdvp_ctx_create(C.byref(h), int(device), C.c_void_p(stream), int(precision)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib.tdvp_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_precision(self, p):
+        _check(lib.tdvp_ctx_set_precision(self.h, int(p)), self.h)
+
+    def synchronize(self):
+        _check(lib.tdvp_ctx_synchronize(self.h), self.h)
+
+    def heff_apply(self, model, site, nsites, left, right, Lenv, Renv, x, y):
+        _check(lib.tdvp_heff_apply(self.h, model.ref, site, nsites, left.ref, right.ref, Lenv.ref, Renv.ref,
+                                   x.ref, y.ref), self.h)
+
+    def krylov_expm(self, model, site, nsites, left, right, Lenv, Renv, x, tau, tol=1e-12, maxdim=40,
+                    check=True):
+        info = _KrylovInfo()
+        rc = lib.tdvp_krylov_expm(self.h, model.ref, site, nsites, left.ref, right.ref, Lenv.ref, Renv.ref,
+                                  x.ref, float(np.real(tau)), float(np.imag(tau)), float(tol), int(maxdim),
+                                  C.byref(info))
+        if check:
+            _check(rc, self.h)
+        return rc, {"iters": info.iters, "converged": bool(info.converged), "err": info.err_est,
+                    "norm": info.norm_in, "alpha": list(info.alpha[:info.iters]),
+                    "beta": list(info.beta[:info.iters])}
+
+    def env_update(self, model, site, direction, bond_in, bond_out, env_in, tensor, env_out):
+        _check(lib.tdvp_env_update(self.h, model.ref, site, direction, bond_in.ref, bond_out.ref, env_in.ref,
+                                   tensor.ref, env_out.ref), self.h)

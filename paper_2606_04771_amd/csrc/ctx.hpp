@@ -1,0 +1,119 @@
+// Device context: stream, grow-only workspaces, cached device programs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <list>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/tdvp.h"
+
+namespace tdvp {
+
+// One term of an output-stationary grouped GEMM:
+//   C[m][n] += coef * sum_k opA(A)[m][k] * opB(B)[k][n]
+// ops bits: 0 transpose A, 1 conjugate A, 2 transpose B, 3 conjugate B.
+// Element (r, c) of an untransposed operand sits at off + r + c * ld
+// (complex128, column-major).  Direct terms (K = 0): C[m][n] += coef * A[m][n].
+struct DevTerm {
+  int64_t a_off, b_off;
+  int32_t a_buf, b_buf;
+  int32_t lda, ldb;
+  int32_t K, ops;
+  double coef;
+};
+struct DevOut {
+  int64_t c_off;
+  int32_t ldc, M, N;
+  int32_t t_begin, t_end;   // GEMM terms
+  int32_t d_begin, d_end;   // direct terms
+  int32_t pad;
+};
+struct DevTile {
+  int32_t out, m0, n0, cost;
+};
+
+constexpr int kMaxBufs = 6;
+struct Bufs {
+  const double* p[kMaxBufs];
+};
+
+// Host description of a grouped GEMM, lowered to device arrays once and
+// reused across launches (only the buffer base pointers change).
+struct Program {
+  std::vector<DevTerm> terms;
+  std::vector<DevOut> outs;
+  std::vector<DevTile> tiles;
+  double flops = 0.0;
+  int64_t aux = 0;          // scratch elements needed by the program's outputs
+  // device copies
+  DevTerm* d_terms = nullptr;
+  DevOut* d_outs = nullptr;
+  DevTile* d_tiles = nullptr;
+  void* d_mem = nullptr;
+  ~Program();
+  // tile the outputs (64 x 64), order tiles by decreasing cost
+  void finalize();
+};
+
+struct DeviceBuffer {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DeviceBuffer();
+  hipError_t ensure(size_t n);
+};
+
+}  // namespace tdvp
+
+struct tdvp_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int precision = TDVP_FP64;
+  std::string err;
+  // staging for program uploads
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  hipEvent_t upload_done = nullptr;
+  // workspaces
+  tdvp::DeviceBuffer ws_scratch, ws_krylov, ws_small, ws_vec;
+  void* host_small = nullptr;   // pinned host mirror of ws_small
+  // program cache (structural hash -> program)
+  std::list<std::pair<uint64_t, std::shared_ptr<tdvp::Program>>> cache;
+  hipEvent_t ev[8] = {};
+};
+
+namespace tdvp {
+
+int hip_check(tdvp_ctx* ctx, hipError_t e, const char* what);
+#define TDVP_HIP(ctx, call)                                    \
+  do {                                                         \
+    hipError_t e__ = (call);                                   \
+    if (e__ != hipSuccess) return ::tdvp::hip_check(ctx, e__, #call); \
+  } while (0)
+
+// Upload a finalized program to the device (cached by key when key != 0).
+int upload(tdvp_ctx* ctx, Program& p);
+std::shared_ptr<Program> cache_get(tdvp_ctx* ctx, uint64_t key);
+void cache_put(tdvp_ctx* ctx, uint64_t key, std::shared_ptr<Program> p);
+
+// Launch the grouped GEMM of p writing into C (base pointer of the output
+// buffer) with operand buffers bufs.  precision: TDVP_FP64 or TDVP_FP32.
+int launch_gemm(tdvp_ctx* ctx, const Program& p, const Bufs& bufs, double* C, int precision);
+
+// Lanczos vector kernels (complex128 vectors of n elements).
+int vec_dots(tdvp_ctx* ctx, const double* V, int64_t stride, int nv, const double* w, int64_t n,
+             double* d_out /* 2*nv doubles, device */);
+int vec_subtract_combo(tdvp_ctx* ctx, double* w, const double* V, int64_t stride, int nv,
+                       const double* d_coef /* 2*nv */, int64_t n, double* d_norm2 /* or null */);
+int vec_scale_copy(tdvp_ctx* ctx, double* dst, const double* src, double s, int64_t n);
+int vec_combo(tdvp_ctx* ctx, double* out, const double* V, int64_t stride, int nv, const double* d_coef,
+              int64_t n);
+int vec_norm2(tdvp_ctx* ctx, const double* x, int64_t n, double* d_out);
+int vec_check_finite(tdvp_ctx* ctx, const double* x, int64_t n, int* d_flag);
+
+}  // namespace tdvp

@@ -1,0 +1,33 @@
+// Device-side building blocks shared by the C-ABI entry points.
+#pragma once
+
+#include <complex>
+#include <memory>
+#include <vector>
+
+#include "common.hpp"
+#include "ctx.hpp"
+
+namespace tdvp {
+
+std::shared_ptr<Program> heff_program(tdvp_ctx* ctx, const tdvp_model& m, int site, int nsites,
+                                      const HeffInputs& in, const Blocks& y, int& rc);
+
+// Environment update on the device (programs cached by structure).
+int env_update_dev(tdvp_ctx* ctx, const tdvp_model& m, int site, int dir, const EnvInputs& in);
+
+struct KrylovResult {
+  int iters = 0;
+  int converged = 0;
+  double err = 0.0, norm = 0.0;
+  std::vector<double> alpha, beta;
+  double heff_flops = 0.0;
+};
+// x <- exp(tau H_eff) x (x = in.x, data in place).
+int krylov_dev(tdvp_ctx* ctx, const tdvp_model& m, int site, int nsites, const HeffInputs& in,
+               std::complex<double> tau, double tol, int maxdim, KrylovResult& out);
+
+// Copy blocks: dst[j] = src[i] for blocks with equal keys (scaled by s).
+int copy_blocks(tdvp_ctx* ctx, const Blocks& src, const Blocks& dst, double s);
+
+}  // namespace tdvp

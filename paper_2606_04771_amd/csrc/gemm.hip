@@ -1,0 +1,376 @@
+// Output-stationary grouped complex GEMM on CDNA4 matrix cores.
+//
+// One launch evaluates every output block of an effective-Hamiltonian apply
+// (or an environment-update stage): each 64x64 output tile sums all of its
+// contributing block products (left-environment, right-environment and
+// local terms, each with its recoupling coefficient) in registers and is
+// written once.  No atomics, a fixed summation order, so results are
+// bit-reproducible.  The paper batches equal-size blocks into batched GEMMs
+// (supplementary section S2.3); here uneven blocks go out in one grid whose
+// tiles are ordered by decreasing work, so the hardware dispatcher hands the
+// longest tiles out first.
+//
+// FP64 path: v_mfma_f64_16x16x4_f64, complex products as four real products
+// on planar (re, im) LDS tiles.  Lane layout of the instruction: A[i][k] in
+// lane i + 16 k, B[k][j] in lane j + 16 k, D[4 r + l/16][l % 16] in register r.
+// FP32 path: the same tiling on v_mfma_f32_16x16x4_f32 with FP32 operands and
+// accumulators (D[4 (l/16) + r][l % 16]), converted from and to FP64 at the
+// tile boundary.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "ctx.hpp"
+
+namespace tdvp {
+
+namespace {
+
+constexpr int TM = 64, TN = 64, TK = 16, PAD = 2;
+constexpr int NT = 256;
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+struct Stage {
+  double2 a[4], b[4];
+};
+
+// Load this thread's four A and four B elements of the K-tile (k0) of term tm.
+__device__ __forceinline__ void load_stage(Stage& st, const DevTerm& tm, const Bufs& bufs, int m0, int n0,
+                                           int M, int N, int k0, int tid) {
+  const double2* A = reinterpret_cast<const double2*>(bufs.p[tm.a_buf]) + tm.a_off;
+  const double2* B = reinterpret_cast<const double2*>(bufs.p[tm.b_buf]) + tm.b_off;
+  const bool ta = tm.ops & 1, tb = tm.ops & 4;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    int e = tid + NT * r;
+    int m = ta ? (e >> 4) : (e & 63);
+    int k = ta ? (e & 15) : (e >> 6);
+    int gm = m0 + m, gk = k0 + k;
+    double2 v = make_double2(0.0, 0.0);
+    if (gm < M && gk < tm.K)
+      v = ta ? A[(int64_t)gk + (int64_t)gm * tm.lda] : A[(int64_t)gm + (int64_t)gk * tm.lda];
+    st.a[r] = v;
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    int e = tid + NT * r;
+    int n = tb ? (e & 63) : (e >> 4);
+    int k = tb ? (e >> 6) : (e & 15);
+    int gn = n0 + n, gk = k0 + k;
+    double2 v = make_double2(0.0, 0.0);
+    if (gn < N && gk < tm.K)
+      v = tb ? B[(int64_t)gn + (int64_t)gk * tm.ldb] : B[(int64_t)gk + (int64_t)gn * tm.ldb];
+    st.b[r] = v;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void store_stage(const Stage& st, const DevTerm& tm, T (*As)[TK][TM + PAD],
+                                            T (*Bs)[TK][TN + PAD], int tid) {
+  const bool ta = tm.ops & 1, ca = tm.ops & 2, tb = tm.ops & 4, cb = tm.ops & 8;
+  const double c = tm.coef;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    int e = tid + NT * r;
+    int m = ta ? (e >> 4) : (e & 63);
+    int k = ta ? (e & 15) : (e >> 6);
+    As[0][k][m] = (T)(c * st.a[r].x);
+    As[1][k][m] = (T)(ca ? -c * st.a[r].y : c * st.a[r].y);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    int e = tid + NT * r;
+    int n = tb ? (e & 63) : (e >> 4);
+    int k = tb ? (e >> 6) : (e & 15);
+    Bs[0][k][n] = (T)st.b[r].x;
+    Bs[1][k][n] = (T)(cb ? -st.b[r].y : st.b[r].y);
+  }
+}
+
+__device__ __forceinline__ bool next_ktile(const DevTerm* terms, int t_end, int& t, int& k0) {
+  k0 += TK;
+  if (k0 >= terms[t].K) {
+    k0 = 0;
+    ++t;
+  }
+  return t < t_end;
+}
+
+__global__ __launch_bounds__(NT) void gemm_f64(Bufs bufs, double* __restrict__ Cbase,
+                                              const DevTile* __restrict__ tiles,
+                                              const DevOut* __restrict__ outs,
+                                              const DevTerm* __restrict__ terms) {
+  __shared__ double As[2][TK][TM + PAD];
+  __shared__ double Bs[2][TK][TN + PAD];
+  const DevTile tl = tiles[blockIdx.x];
+  const DevOut ob = outs[tl.out];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int li = lane & 15, lk = lane >> 4;
+
+  f64x4 accr[2][2], acci[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      accr[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+      acci[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    }
+
+  int t = ob.t_begin, k0 = 0;
+  Stage st;
+  DevTerm cur;
+  if (t < ob.t_end) {
+    cur = terms[t];
+    load_stage(st, cur, bufs, tl.m0, tl.n0, ob.M, ob.N, k0, tid);
+  }
+  while (t < ob.t_end) {
+    store_stage<double>(st, cur, As, Bs, tid);
+    __syncthreads();
+    int tn = t, kn = k0;
+    bool more = next_ktile(terms, ob.t_end, tn, kn);
+    DevTerm nxt;
+    if (more) {
+      nxt = terms[tn];
+      load_stage(st, nxt, bufs, tl.m0, tl.n0, ob.M, ob.N, kn, tid);
+    }
+#pragma unroll
+    for (int kk = 0; kk < TK; kk += 4) {
+      double ar[2], ai[2], nai[2], br[2], bi[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        ar[i] = As[0][kk + lk][wm * 32 + i * 16 + li];
+        ai[i] = As[1][kk + lk][wm * 32 + i * 16 + li];
+        nai[i] = -ai[i];
+        br[i] = Bs[0][kk + lk][wn * 32 + i * 16 + li];
+        bi[i] = Bs[1][kk + lk][wn * 32 + i * 16 + li];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], accr[i][j], 0, 0, 0);
+          accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[i], bi[j], accr[i][j], 0, 0, 0);
+          acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], acci[i][j], 0, 0, 0);
+          acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], acci[i][j], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+    t = tn;
+    k0 = kn;
+    if (more) cur = nxt;
+  }
+
+  // direct (local) terms and the store; element (row, col) of register r
+  double2* C = reinterpret_cast<double2*>(Cbase) + ob.c_off;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int row = tl.m0 + wm * 32 + i * 16 + 4 * r + lk;
+        int col = tl.n0 + wn * 32 + j * 16 + li;
+        if (row < ob.M && col < ob.N) {
+          double vr = accr[i][j][r], vi = acci[i][j][r];
+          for (int d = ob.d_begin; d < ob.d_end; ++d) {
+            const DevTerm dt = terms[d];
+            const double2 x =
+                (reinterpret_cast<const double2*>(bufs.p[dt.a_buf]) + dt.a_off)[(int64_t)row + (int64_t)col * dt.lda];
+            vr += dt.coef * x.x;
+            vi += dt.coef * x.y;
+          }
+          C[(int64_t)row + (int64_t)col * ob.ldc] = make_double2(vr, vi);
+        }
+      }
+}
+
+__global__ __launch_bounds__(NT) void gemm_f32(Bufs bufs, double* __restrict__ Cbase,
+                                              const DevTile* __restrict__ tiles,
+                                              const DevOut* __restrict__ outs,
+                                              const DevTerm* __restrict__ terms) {
+  __shared__ float As[2][TK][TM + PAD];
+  __shared__ float Bs[2][TK][TN + PAD];
+  const DevTile tl = tiles[blockIdx.x];
+  const DevOut ob = outs[tl.out];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int li = lane & 15, lk = lane >> 4;
+
+  f32x4 accr[2][2], acci[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      accr[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+      acci[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+
+  int t = ob.t_begin, k0 = 0;
+  Stage st;
+  DevTerm cur;
+  if (t < ob.t_end) {
+    cur = terms[t];
+    load_stage(st, cur, bufs, tl.m0, tl.n0, ob.M, ob.N, k0, tid);
+  }
+  while (t < ob.t_end) {
+    store_stage<float>(st, cur, As, Bs, tid);
+    __syncthreads();
+    int tn = t, kn = k0;
+    bool more = next_ktile(terms, ob.t_end, tn, kn);
+    DevTerm nxt;
+    if (more) {
+      nxt = terms[tn];
+      load_stage(st, nxt, bufs, tl.m0, tl.n0, ob.M, ob.N, kn, tid);
+    }
+#pragma unroll
+    for (int kk = 0; kk < TK; kk += 4) {
+      float ar[2], ai[2], nai[2], br[2], bi[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        ar[i] = As[0][kk + lk][wm * 32 + i * 16 + li];
+        ai[i] = As[1][kk + lk][wm * 32 + i * 16 + li];
+        nai[i] = -ai[i];
+        br[i] = Bs[0][kk + lk][wn * 32 + i * 16 + li];
+        bi[i] = Bs[1][kk + lk][wn * 32 + i * 16 + li];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          accr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], br[j], accr[i][j], 0, 0, 0);
+          accr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai[i], bi[j], accr[i][j], 0, 0, 0);
+          acci[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], bi[j], acci[i][j], 0, 0, 0);
+          acci[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[i], br[j], acci[i][j], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+    t = tn;
+    k0 = kn;
+    if (more) cur = nxt;
+  }
+
+  double2* C = reinterpret_cast<double2*>(Cbase) + ob.c_off;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int row = tl.m0 + wm * 32 + i * 16 + 4 * lk + r;
+        int col = tl.n0 + wn * 32 + j * 16 + li;
+        if (row < ob.M && col < ob.N) {
+          double vr = accr[i][j][r], vi = acci[i][j][r];
+          for (int d = ob.d_begin; d < ob.d_end; ++d) {
+            const DevTerm dt = terms[d];
+            const double2 x =
+                (reinterpret_cast<const double2*>(bufs.p[dt.a_buf]) + dt.a_off)[(int64_t)row + (int64_t)col * dt.lda];
+            vr += dt.coef * x.x;
+            vi += dt.coef * x.y;
+          }
+          C[(int64_t)row + (int64_t)col * ob.ldc] = make_double2(vr, vi);
+        }
+      }
+}
+
+}  // namespace
+
+Program::~Program() {
+  if (d_mem) (void)hipFree(d_mem);
+}
+
+void Program::finalize() {
+  tiles.clear();
+  for (int o = 0; o < (int)outs.size(); ++o) {
+    const DevOut& ob = outs[o];
+    int64_t kc = 0;
+    for (int t = ob.t_begin; t < ob.t_end; ++t) kc += (terms[t].K + TK - 1) / TK;
+    int cost = (int)std::min<int64_t>(kc * TK + 4 * (ob.d_end - ob.d_begin), 0x7fffffff);
+    for (int m0 = 0; m0 < ob.M; m0 += TM)
+      for (int n0 = 0; n0 < ob.N; n0 += TN) tiles.push_back(DevTile{o, m0, n0, cost});
+  }
+  std::stable_sort(tiles.begin(), tiles.end(),
+                   [](const DevTile& a, const DevTile& b) { return a.cost > b.cost; });
+}
+
+DeviceBuffer::~DeviceBuffer() {
+  if (p) (void)hipFree(p);
+}
+
+hipError_t DeviceBuffer::ensure(size_t n) {
+  if (n <= bytes) return hipSuccess;
+  if (p) {
+    hipError_t e = hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    if (e != hipSuccess) return e;
+  }
+  size_t want = std::max(n, (size_t)256);
+  hipError_t e = hipMalloc(&p, want);
+  if (e == hipSuccess) bytes = want;
+  return e;
+}
+
+int upload(tdvp_ctx* ctx, Program& p) {
+  size_t bt = p.terms.size() * sizeof(DevTerm), bo = p.outs.size() * sizeof(DevOut),
+         bl = p.tiles.size() * sizeof(DevTile);
+  size_t total = bt + bo + bl + 3 * 256;
+  if (p.d_mem) {
+    TDVP_HIP(ctx, hipFree(p.d_mem));
+    p.d_mem = nullptr;
+  }
+  TDVP_HIP(ctx, hipMalloc(&p.d_mem, total));
+  char* base = (char*)p.d_mem;
+  auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  p.d_terms = (DevTerm*)base;
+  p.d_outs = (DevOut*)(base + align(bt));
+  p.d_tiles = (DevTile*)(base + align(bt) + align(bo));
+  // stage through pinned memory; wait for the previous upload before reuse
+  if (ctx->upload_done) TDVP_HIP(ctx, hipEventSynchronize(ctx->upload_done));
+  if (ctx->pinned_bytes < total) {
+    if (ctx->pinned) TDVP_HIP(ctx, hipHostFree(ctx->pinned));
+    ctx->pinned = nullptr;
+    ctx->pinned_bytes = 0;
+    TDVP_HIP(ctx, hipHostMalloc(&ctx->pinned, total));
+    ctx->pinned_bytes = total;
+  }
+  char* h = (char*)ctx->pinned;
+  if (bt) std::memcpy(h, p.terms.data(), bt);
+  if (bo) std::memcpy(h + align(bt), p.outs.data(), bo);
+  if (bl) std::memcpy(h + align(bt) + align(bo), p.tiles.data(), bl);
+  TDVP_HIP(ctx, hipMemcpyAsync(p.d_mem, h, align(bt) + align(bo) + bl, hipMemcpyHostToDevice, ctx->stream));
+  if (!ctx->upload_done) TDVP_HIP(ctx, hipEventCreateWithFlags(&ctx->upload_done, hipEventDisableTiming));
+  TDVP_HIP(ctx, hipEventRecord(ctx->upload_done, ctx->stream));
+  return TDVP_OK;
+}
+
+std::shared_ptr<Program> cache_get(tdvp_ctx* ctx, uint64_t key) {
+  for (auto it = ctx->cache.begin(); it != ctx->cache.end(); ++it)
+    if (it->first == key) {
+      auto p = it->second;
+      ctx->cache.splice(ctx->cache.begin(), ctx->cache, it);
+      return p;
+    }
+  return nullptr;
+}
+
+void cache_put(tdvp_ctx* ctx, uint64_t key, std::shared_ptr<Program> p) {
+  ctx->cache.emplace_front(key, std::move(p));
+  while (ctx->cache.size() > 24) ctx->cache.pop_back();
+}
+
+int launch_gemm(tdvp_ctx* ctx, const Program& p, const Bufs& bufs, double* C, int precision) {
+  if (p.tiles.empty()) return TDVP_OK;
+  dim3 grid((unsigned)p.tiles.size()), block(NT);
+  if (precision == TDVP_FP32)
+    hipLaunchKernelGGL(gemm_f32, grid, block, 0, ctx->stream, bufs, C, p.d_tiles, p.d_outs, p.d_terms);
+  else
+    hipLaunchKernelGGL(gemm_f64, grid, block, 0, ctx->stream, bufs, C, p.d_tiles, p.d_outs, p.d_terms);
+  TDVP_HIP(ctx, hipGetLastError());
+  return TDVP_OK;
+}
+
+}  // namespace tdvp

@@ -1,0 +1,193 @@
+// Krylov exponential exp(tau H_eff) x on the device.
+//
+// The paper evolves each merged block with a Krylov matrix exponential whose
+// dimension is chosen adaptively (supplementary section S2.2).  Here: Lanczos
+// with two passes of classical Gram-Schmidt against the whole basis (FP64),
+// the small tridiagonal exponential on the host, and the a-posteriori
+// estimate beta_m |[exp(tau T_m)]_{m,1}| |x| as the stopping rule.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstring>
+
+#include "device.hpp"
+#include "tridiag.hpp"
+
+namespace tdvp {
+
+int copy_blocks(tdvp_ctx* ctx, const Blocks& src, const Blocks& dst, double s) {
+  // a grouped-GEMM program made only of direct terms
+  Program p;
+  for (int j = 0; j < dst.n(); ++j) {
+    int i = src.find(dst.k(j));
+    DevOut ob{};
+    ob.c_off = dst.off[j];
+    ob.ldc = ob.M = (int32_t)dst.rows[j];
+    ob.N = (int32_t)dst.cols[j];
+    ob.t_begin = ob.t_end = ob.d_begin = (int32_t)p.terms.size();
+    if (i >= 0) {
+      DevTerm d{};
+      d.a_buf = 0;
+      d.a_off = src.off[i];
+      d.lda = (int32_t)src.rows[i];
+      d.coef = s;
+      p.terms.push_back(d);
+    }
+    ob.d_end = (int32_t)p.terms.size();
+    p.outs.push_back(ob);
+  }
+  p.finalize();
+  int rc = upload(ctx, p);
+  if (rc) return rc;
+  Bufs b{};
+  b.p[0] = (const double*)src.data;
+  rc = launch_gemm(ctx, p, b, (double*)dst.data, TDVP_FP64);
+  if (rc) return rc;
+  // the program's device arrays are freed when p goes out of scope: wait
+  TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return TDVP_OK;
+}
+
+namespace {
+
+bool contiguous(const Blocks& x, int64_t& n) {
+  std::vector<std::pair<int64_t, int64_t>> iv;
+  for (int i = 0; i < x.n(); ++i) iv.push_back({x.off[i], x.rows[i] * x.cols[i]});
+  std::sort(iv.begin(), iv.end());
+  int64_t pos = 0;
+  for (auto& v : iv) {
+    if (v.first != pos) return false;
+    pos += v.second;
+  }
+  n = pos;
+  return true;
+}
+
+}  // namespace
+
+int krylov_dev(tdvp_ctx* ctx, const tdvp_model& m, int site, int nsites, const HeffInputs& in_user,
+               std::complex<double> tau, double tol, int maxdim, KrylovResult& out) {
+  out = KrylovResult();
+  int64_t n = 0;
+  HeffInputs in = in_user;
+  bool compact = contiguous(in.x, n);
+  if (!compact) {
+    // Lanczos vectors use a compact copy of the block layout
+    Blocks xc;
+    xc.keylen = in.x.keylen;
+    int64_t o = 0;
+    for (int i = 0; i < in.x.n(); ++i) {
+      xc.push(in.x.k(i), o, in.x.rows[i], in.x.cols[i]);
+      o += in.x.rows[i] * in.x.cols[i];
+    }
+    xc.size = o;
+    in.x = xc;
+    n = o;
+  }
+  if (n == 0) return TDVP_OK;
+  const int64_t stride = n;
+  TDVP_HIP(ctx, ctx->ws_krylov.ensure(sizeof(double) * 2 * (size_t)stride * (maxdim + 1)));
+  TDVP_HIP(ctx, ctx->ws_small.ensure(1 << 16));
+  double* V = (double*)ctx->ws_krylov.p;
+  double* W = V + 2 * stride * maxdim;
+  double* d_small = (double*)ctx->ws_small.p;
+  double* h_small = (double*)ctx->host_small;
+  double* d_c1 = d_small;          // 2*64
+  double* d_c2 = d_small + 128;    // 2*64
+  double* d_nrm = d_small + 256;   // 2
+  double* d_y = d_small + 512;     // 2*64
+
+  // v0 = x / |x|
+  Blocks v0 = in.x;
+  v0.data = V;
+  int rc;
+  if (compact) {
+    TDVP_HIP(ctx, hipMemcpyAsync(V, in_user.x.data, sizeof(double) * 2 * n, hipMemcpyDeviceToDevice, ctx->stream));
+  } else {
+    rc = copy_blocks(ctx, in_user.x, v0, 1.0);
+    if (rc) return rc;
+  }
+  rc = vec_norm2(ctx, V, n, d_nrm);
+  if (rc) return rc;
+  TDVP_HIP(ctx, hipMemcpyAsync(h_small, d_nrm, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (h_small[1] != 0.0 || !std::isfinite(h_small[0]))
+    return set_error(ctx, TDVP_E_NONFINITE, "non-finite entries in the Krylov start vector");
+  const double nrm = std::sqrt(h_small[0]);
+  out.norm = nrm;
+  if (nrm == 0.0) {
+    out.converged = 1;
+    return TDVP_OK;
+  }
+  rc = vec_scale_copy(ctx, V, V, 1.0 / nrm, n);
+  if (rc) return rc;
+
+  Blocks yb = in.x;   // output layout of the apply = compact layout
+  auto prog = heff_program(ctx, m, site, nsites, in, yb, rc);
+  if (rc) return rc;
+  Bufs bufs{};
+  bufs.p[1] = (const double*)in.Le.data;
+  bufs.p[2] = (const double*)in.Re.data;
+
+  std::vector<double> alpha, beta;
+  std::vector<std::complex<double>> y;
+  for (int j = 0; j < maxdim; ++j) {
+    double* vj = V + 2 * stride * j;
+    bufs.p[0] = vj;
+    rc = launch_gemm(ctx, *prog, bufs, W, ctx->precision);
+    if (rc) return rc;
+    out.heff_flops += prog->flops;
+    // two passes of classical Gram-Schmidt against v_0..v_j
+    if ((rc = vec_dots(ctx, V, stride, j + 1, W, n, d_c1))) return rc;
+    if ((rc = vec_subtract_combo(ctx, W, V, stride, j + 1, d_c1, n, nullptr))) return rc;
+    if ((rc = vec_dots(ctx, V, stride, j + 1, W, n, d_c2))) return rc;
+    if ((rc = vec_subtract_combo(ctx, W, V, stride, j + 1, d_c2, n, d_nrm))) return rc;
+    TDVP_HIP(ctx, hipMemcpyAsync(h_small, d_small, 258 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    double a = h_small[2 * j] + h_small[128 + 2 * j];
+    double b2 = h_small[256];
+    if (!std::isfinite(a) || !std::isfinite(b2))
+      return set_error(ctx, TDVP_E_NONFINITE, "non-finite Lanczos coefficient");
+    double b = std::sqrt(std::max(b2, 0.0));
+    alpha.push_back(a);
+    if (!tridiag_expm_e1(alpha, beta, tau, nrm, y))
+      return set_error(ctx, TDVP_E_NOCONV, "tridiagonal eigensolver did not converge");
+    double err = b * std::abs(y[j]);
+    bool breakdown = b < 1e-14 * 1.0;   // basis vectors have unit norm
+    bool done = breakdown || err <= tol * nrm || j + 1 == maxdim;
+    out.iters = j + 1;
+    out.err = err;
+    if (done) {
+      out.converged = (breakdown || err <= tol * nrm) ? 1 : 0;
+      out.alpha = alpha;
+      out.beta = beta;
+      out.beta.push_back(b);
+      for (int k = 0; k <= j; ++k) {
+        h_small[512 + 2 * k] = y[k].real();
+        h_small[512 + 2 * k + 1] = y[k].imag();
+      }
+      TDVP_HIP(ctx, hipMemcpyAsync(d_y, h_small + 512, sizeof(double) * 2 * (j + 1), hipMemcpyHostToDevice,
+                                   ctx->stream));
+      if (compact) {
+        rc = vec_combo(ctx, (double*)in_user.x.data, V, stride, j + 1, d_y, n);
+        if (rc) return rc;
+      } else {
+        rc = vec_combo(ctx, W, V, stride, j + 1, d_y, n);
+        if (rc) return rc;
+        Blocks wb = in.x;
+        wb.data = W;
+        rc = copy_blocks(ctx, wb, in_user.x, 1.0);
+        if (rc) return rc;
+      }
+      TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+      if (!out.converged) return set_error(ctx, TDVP_E_NOCONV, "Krylov tolerance not reached within maxdim");
+      return TDVP_OK;
+    }
+    beta.push_back(b);
+    if ((rc = vec_scale_copy(ctx, V + 2 * stride * (j + 1), W, 1.0 / b, n))) return rc;
+  }
+  return TDVP_OK;
+}
+
+}  // namespace tdvp

@@ -1,0 +1,225 @@
+// FP64 Lanczos vector kernels on complex128 vectors.
+//
+// The Krylov recurrence, the Gram-Schmidt re-orthogonalisation and the norms
+// stay in FP64 whatever precision the block products use.  Reductions are
+// two-pass and deterministic: wavefront shuffles, one partial per workgroup
+// written to scratch, then one workgroup per result sums the partials in a
+// fixed order.  These kernels are HBM-bound (a few bytes per flop), so they
+// are written for coalesced 16-byte loads and enough waves to fill 256 CUs.
+#include <hip/hip_runtime.h>
+
+#include "ctx.hpp"
+
+namespace tdvp {
+
+namespace {
+
+constexpr int NT = 256;
+constexpr int kMaxV = 72;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// block-level sum of (a, b); result valid in thread 0
+__device__ __forceinline__ void block_sum2(double& a, double& b) {
+  __shared__ double sa[NT / 64], sb[NT / 64];
+  a = wave_sum(a);
+  b = wave_sum(b);
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    sa[w] = a;
+    sb[w] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a = 0.0;
+    b = 0.0;
+    for (int i = 0; i < NT / 64; ++i) {
+      a += sa[i];
+      b += sb[i];
+    }
+  }
+}
+
+int nblocks_for(int64_t n) {
+  int64_t g = (n + NT * 4 - 1) / (NT * 4);
+  if (g < 1) g = 1;
+  if (g > 1024) g = 1024;
+  return (int)g;
+}
+
+// partial[k * G + g] = sum_{i in chunk g} conj(V_k[i]) w[i]
+__global__ __launch_bounds__(NT) void k_dots_partial(const double2* __restrict__ V, int64_t stride,
+                                                     const double2* __restrict__ w, int64_t n,
+                                                     double2* __restrict__ partial) {
+  const int g = blockIdx.x, G = gridDim.x, k = blockIdx.y;
+  const double2* v = V + (int64_t)k * stride;
+  int64_t chunk = (n + G - 1) / G;
+  int64_t lo = (int64_t)g * chunk, hi = lo + chunk < n ? lo + chunk : n;
+  double re = 0.0, im = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += NT) {
+    double2 a = v[i], b = w[i];
+    re += a.x * b.x + a.y * b.y;
+    im += a.x * b.y - a.y * b.x;
+  }
+  block_sum2(re, im);
+  if (threadIdx.x == 0) partial[(int64_t)k * G + g] = make_double2(re, im);
+}
+
+__global__ __launch_bounds__(NT) void k_reduce(const double2* __restrict__ partial, int G,
+                                               double* __restrict__ out) {
+  const int k = blockIdx.x;
+  double re = 0.0, im = 0.0;
+  for (int i = threadIdx.x; i < G; i += NT) {
+    double2 p = partial[(int64_t)k * G + i];
+    re += p.x;
+    im += p.y;
+  }
+  block_sum2(re, im);
+  if (threadIdx.x == 0) {
+    out[2 * k] = re;
+    out[2 * k + 1] = im;
+  }
+}
+
+// w -= sum_k c_k V_k ; optional partial |w|^2
+__global__ __launch_bounds__(NT) void k_sub_combo(double2* __restrict__ w, const double2* __restrict__ V,
+                                                  int64_t stride, int nv, const double* __restrict__ coef,
+                                                  int64_t n, double2* __restrict__ partial) {
+  __shared__ double c[2 * kMaxV];
+  for (int i = threadIdx.x; i < 2 * nv; i += NT) c[i] = coef[i];
+  __syncthreads();
+  const int g = blockIdx.x, G = gridDim.x;
+  int64_t chunk = (n + G - 1) / G;
+  int64_t lo = (int64_t)g * chunk, hi = lo + chunk < n ? lo + chunk : n;
+  double nrm = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += NT) {
+    double2 x = w[i];
+    for (int k = 0; k < nv; ++k) {
+      double2 v = V[(int64_t)k * stride + i];
+      double cr = c[2 * k], ci = c[2 * k + 1];
+      x.x -= cr * v.x - ci * v.y;
+      x.y -= cr * v.y + ci * v.x;
+    }
+    w[i] = x;
+    nrm += x.x * x.x + x.y * x.y;
+  }
+  if (partial) {
+    double z = 0.0;
+    block_sum2(nrm, z);
+    if (threadIdx.x == 0) partial[g] = make_double2(nrm, 0.0);
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_combo(double2* __restrict__ out, const double2* __restrict__ V,
+                                              int64_t stride, int nv, const double* __restrict__ coef,
+                                              int64_t n) {
+  __shared__ double c[2 * kMaxV];
+  for (int i = threadIdx.x; i < 2 * nv; i += NT) c[i] = coef[i];
+  __syncthreads();
+  for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+    double2 x = make_double2(0.0, 0.0);
+    for (int k = 0; k < nv; ++k) {
+      double2 v = V[(int64_t)k * stride + i];
+      double cr = c[2 * k], ci = c[2 * k + 1];
+      x.x += cr * v.x - ci * v.y;
+      x.y += cr * v.y + ci * v.x;
+    }
+    out[i] = x;
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_scale_copy(double2* __restrict__ dst, const double2* __restrict__ src,
+                                                   double s, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+    double2 x = src[i];
+    dst[i] = make_double2(s * x.x, s * x.y);
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_norm_partial(const double2* __restrict__ x, int64_t n,
+                                                     double2* __restrict__ partial) {
+  const int g = blockIdx.x, G = gridDim.x;
+  int64_t chunk = (n + G - 1) / G;
+  int64_t lo = (int64_t)g * chunk, hi = lo + chunk < n ? lo + chunk : n;
+  double s = 0.0, nonfinite = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += NT) {
+    double2 v = x[i];
+    double q = v.x * v.x + v.y * v.y;
+    if (!isfinite(v.x) || !isfinite(v.y)) nonfinite += 1.0;
+    s += q;
+  }
+  block_sum2(s, nonfinite);
+  if (threadIdx.x == 0) partial[g] = make_double2(s, nonfinite);
+}
+
+int grid_1d(int64_t n) {
+  int64_t g = (n + NT - 1) / NT;
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+}  // namespace
+
+int vec_dots(tdvp_ctx* ctx, const double* V, int64_t stride, int nv, const double* w, int64_t n,
+             double* d_out) {
+  if (nv <= 0) return TDVP_OK;
+  int G = nblocks_for(n);
+  size_t need = sizeof(double2) * (size_t)G * nv;
+  TDVP_HIP(ctx, ctx->ws_vec.ensure(need));
+  double2* partial = (double2*)ctx->ws_vec.p;
+  hipLaunchKernelGGL(k_dots_partial, dim3(G, nv), dim3(NT), 0, ctx->stream, (const double2*)V, stride,
+                     (const double2*)w, n, partial);
+  hipLaunchKernelGGL(k_reduce, dim3(nv), dim3(NT), 0, ctx->stream, partial, G, d_out);
+  TDVP_HIP(ctx, hipGetLastError());
+  return TDVP_OK;
+}
+
+int vec_subtract_combo(tdvp_ctx* ctx, double* w, const double* V, int64_t stride, int nv, const double* d_coef,
+                       int64_t n, double* d_norm2) {
+  if (nv > kMaxV) return TDVP_E_INVALID;
+  int G = nblocks_for(n);
+  double2* partial = nullptr;
+  if (d_norm2) {
+    TDVP_HIP(ctx, ctx->ws_vec.ensure(sizeof(double2) * (size_t)G));
+    partial = (double2*)ctx->ws_vec.p;
+  }
+  hipLaunchKernelGGL(k_sub_combo, dim3(G), dim3(NT), 0, ctx->stream, (double2*)w, (const double2*)V, stride, nv,
+                     d_coef, n, partial);
+  if (d_norm2) hipLaunchKernelGGL(k_reduce, dim3(1), dim3(NT), 0, ctx->stream, partial, G, d_norm2);
+  TDVP_HIP(ctx, hipGetLastError());
+  return TDVP_OK;
+}
+
+int vec_scale_copy(tdvp_ctx* ctx, double* dst, const double* src, double s, int64_t n) {
+  hipLaunchKernelGGL(k_scale_copy, dim3(grid_1d(n)), dim3(NT), 0, ctx->stream, (double2*)dst,
+                     (const double2*)src, s, n);
+  TDVP_HIP(ctx, hipGetLastError());
+  return TDVP_OK;
+}
+
+int vec_combo(tdvp_ctx* ctx, double* out, const double* V, int64_t stride, int nv, const double* d_coef,
+              int64_t n) {
+  if (nv > kMaxV) return TDVP_E_INVALID;
+  hipLaunchKernelGGL(k_combo, dim3(grid_1d(n)), dim3(NT), 0, ctx->stream, (double2*)out, (const double2*)V,
+                     stride, nv, d_coef, n);
+  TDVP_HIP(ctx, hipGetLastError());
+  return TDVP_OK;
+}
+
+// d_out[0] = |x|^2, d_out[1] = number of non-finite entries
+int vec_norm2(tdvp_ctx* ctx, const double* x, int64_t n, double* d_out) {
+  int G = nblocks_for(n);
+  TDVP_HIP(ctx, ctx->ws_vec.ensure(sizeof(double2) * (size_t)G));
+  double2* partial = (double2*)ctx->ws_vec.p;
+  hipLaunchKernelGGL(k_norm_partial, dim3(G), dim3(NT), 0, ctx->stream, (const double2*)x, n, partial);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(NT), 0, ctx->stream, partial, G, d_out);
+  TDVP_HIP(ctx, hipGetLastError());
+  return TDVP_OK;
+}
+
+}  // namespace tdvp

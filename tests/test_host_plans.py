@@ -1,0 +1,170 @@
+"""Host logic of the library (no GPU): layouts and the exported term lists of
+the effective-Hamiltonian apply and the environment updates, executed with
+numpy and compared with the oracle's dense definitions on expanded tensors.
+
+This pins every recoupling coefficient the kernels use."""
+import numpy as np
+import pytest
+
+import paper_2606_04771_amd as T
+from oracle import dense as D
+from oracle import reduced as R
+from tests._harness import (exec_env_plan, exec_heff_plan, random_blocks, keyed, theta_dict, env_dict)
+import synth
+
+TOL = 1e-12
+
+
+def _setup(site, seed, chi=30):
+    lp = (site - 1) % 2
+    left = synth.sector_profile(chi, seed, parity=lp)
+    right = synth.sector_profile(chi, seed + 1, parity=lp)   # two sites later: same parity
+    return left, right
+
+
+@pytest.mark.parametrize("site", [2, 3, 4, 5])
+def test_heff_two_site_plan_matches_dense(site):
+    t, U = 1.0, 4.0
+    left, right = _setup(site, 10 + site)
+    bl, br = T.Bond(left), T.Bond(right)
+    model = T.Model(8, t, U)
+    xk, xo, xt, xd = T.center_layout(bl, br, 2)
+    lk, lo, lt, ld = T.env_layout(bl)
+    rk, ro, rt, rd = T.env_layout(br)
+    xs = keyed(xk, random_blocks(xk, xd, 1))
+    Ls = keyed(lk, random_blocks(lk, ld, 2))
+    Rs = keyed(rk, random_blocks(rk, rd, 3))
+    terms, flops = T.heff_plan(model, site, 2, bl, br, T.Blocks(lk, lo, size=lt), T.Blocks(rk, ro, size=rt),
+                               T.Blocks(xk, xo, size=xt))
+    assert flops > 0
+    ys = exec_heff_plan(terms, xs, Ls, Rs)
+    Lf = R.expand_env(env_dict(lk, Ls), left)
+    Rf = R.expand_env(env_dict(rk, Rs), right)
+    Th = R.expand_theta(theta_dict(xk, xs), left, right, site)
+    ref = D.heff2(Lf, Rf, Th, site, t, U)
+    got = R.expand_theta(theta_dict(xk, ys), left, right, site)
+    assert np.abs(got - ref).max() < TOL * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("site", [2, 3])
+def test_heff_one_site_plan_matches_dense(site):
+    t, U = 1.0, 3.0
+    lp = (site - 1) % 2
+    left = synth.sector_profile(30, 20 + site, parity=lp)
+    right = synth.sector_profile(30, 21 + site, parity=1 - lp)
+    bl, br = T.Bond(left), T.Bond(right)
+    model = T.Model(8, t, U)
+    xk, xo, xt, xd = T.center_layout(bl, br, 1)
+    lk, lo, lt, ld = T.env_layout(bl)
+    rk, ro, rt, rd = T.env_layout(br)
+    xs = keyed(xk, random_blocks(xk, xd, 4))
+    Ls = keyed(lk, random_blocks(lk, ld, 5))
+    Rs = keyed(rk, random_blocks(rk, rd, 6))
+    terms, _ = T.heff_plan(model, site, 1, bl, br, T.Blocks(lk, lo, size=lt), T.Blocks(rk, ro, size=rt),
+                           T.Blocks(xk, xo, size=xt))
+    ys = exec_heff_plan(terms, xs, Ls, Rs)
+    Lf = R.expand_env(env_dict(lk, Ls), left)
+    Rf = R.expand_env(env_dict(rk, Rs), right)
+    C1 = R.expand_site("C", theta_dict(xk, xs), left, right, site)
+    ref = D.heff1(Lf, Rf, C1, site, t, U)
+    got = R.expand_site("C", theta_dict(xk, ys), left, right, site)
+    assert np.abs(got - ref).max() < TOL * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("site", [2, 3])
+def test_env_left_plan_matches_dense(site):
+    t, U = 1.0, 4.0
+    bin_ = synth.sector_profile(24, 30 + site, parity=(site - 1) % 2)
+    bout = synth.sector_profile(24, 31 + site, parity=site % 2)
+    bi, bo = T.Bond(bin_), T.Bond(bout)
+    model = T.Model(8, t, U)
+    ak, ao, at, ad = T.center_layout(bi, bo, 1)
+    ek, eo, et, ed = T.env_layout(bi)
+    ok, oo, ot, od = T.env_layout(bo)
+    As = keyed(ak, random_blocks(ak, ad, 7))
+    Es = keyed(ek, random_blocks(ek, ed, 8))
+    terms, flops = T.env_plan(model, site, +1, bi, bo, T.Blocks(ek, eo, size=et), T.Blocks(ak, ao, size=at),
+                              T.Blocks(ok, oo, size=ot))
+    assert flops > 0
+    outs = exec_env_plan(terms, +1, As, Es, od)
+    Ef = R.expand_env(env_dict(ek, Es), bin_)
+    Af = R.expand_site("A", theta_dict(ak, As), bin_, bout, site)
+    ref = D.left_env_update(Ef, Af, site, t, U)
+    got = R.expand_env(env_dict(ok, outs), bout)
+    for w in range(3):
+        assert np.abs(got[w] - ref[w]).max() < TOL * max(1.0, np.abs(ref[0]).max())
+
+
+@pytest.mark.parametrize("site", [3, 4])
+def test_env_right_plan_matches_dense(site):
+    t, U = 1.0, 4.0
+    bout = synth.sector_profile(24, 40 + site, parity=(site - 1) % 2)   # bond site-1
+    bin_ = synth.sector_profile(24, 41 + site, parity=site % 2)        # bond site
+    bi, bo = T.Bond(bin_), T.Bond(bout)
+    model = T.Model(8, t, U)
+    bk, bof, bt, bd = T.center_layout(bo, bi, 1)
+    ek, eo, et, ed = T.env_layout(bi)
+    ok, oo, ot, od = T.env_layout(bo)
+    Bs = keyed(bk, random_blocks(bk, bd, 9))
+    Es = keyed(ek, random_blocks(ek, ed, 10))
+    terms, _ = T.env_plan(model, site, -1, bi, bo, T.Blocks(ek, eo, size=et), T.Blocks(bk, bof, size=bt),
+                          T.Blocks(ok, oo, size=ot))
+    outs = exec_env_plan(terms, -1, Bs, Es, od)
+    Ef = R.expand_env(env_dict(ek, Es), bin_)
+    Bf = R.expand_site("B", theta_dict(bk, Bs), bout, bin_, site)
+    ref = D.right_env_update(Ef, Bf, site, t, U)
+    got = R.expand_env(env_dict(ok, outs), bout)
+    for w in range(3):
+        assert np.abs(got[w] - ref[w]).max() < TOL * max(1.0, np.abs(ref[0]).max())
+
+
+def test_layout_matches_independent_enumeration():
+    left = synth.sector_profile(60, 1, parity=0)
+    right = synth.sector_profile(60, 2, parity=0)
+    keys, offs, total, dims = T.center_layout(T.Bond(left), T.Bond(right), 2)
+    ref = set()
+    for ia, (qa, tja, da) in enumerate(left):
+        for s1, (q1, t1) in enumerate(R.MULTIPLETS):
+            for tjx in range(abs(tja - t1), tja + t1 + 1, 2):
+                for s2, (q2, t2) in enumerate(R.MULTIPLETS):
+                    for ib, (qb, tjb, db) in enumerate(right):
+                        if qa + q1 + q2 == qb and abs(tjx - t2) <= tjb <= tjx + t2:
+                            ref.add((ia, s1, tjx, s2, ib))
+    assert set(map(tuple, keys.tolist())) == ref
+    assert total == sum(r * c for r, c in dims)
+    assert np.all(np.diff(offs) >= 0)
+
+
+def test_tridiagonal_exponential_matches_scipy():
+    import scipy.linalg
+    rng = np.random.default_rng(0)
+    for n in (1, 2, 5, 17, 40):
+        a = rng.normal(size=n)
+        b = np.abs(rng.normal(size=n - 1)) + 0.1
+        Tm = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+        for tau in (-0.025j, 0.3j, -1.0j + 0.1):
+            ref = 2.5 * scipy.linalg.expm(tau * Tm)[:, 0]
+            got = T.tridiag_expm(a, b, tau, 2.5)
+            assert np.abs(got - ref).max() < 1e-13 * max(1, np.abs(ref).max())
+
+
+def test_invalid_inputs_return_errors():
+    left = T.Bond(synth.sector_profile(20, 1, parity=0))
+    right = T.Bond(synth.sector_profile(20, 2, parity=0))
+    model = T.Model(8)
+    xk, xo, xt, xd = T.center_layout(left, right, 2)
+    lk, lo, lt, ld = T.env_layout(left)
+    rk, ro, rt, rd = T.env_layout(right)
+    L_ = T.Blocks(lk, lo, size=lt)
+    R_ = T.Blocks(rk, ro, size=rt)
+    bad = xk.copy()
+    bad[0, 2] += 2          # break the fusion rule
+    with pytest.raises(T.TdvpError) as e:
+        T.heff_plan(model, 3, 2, left, right, L_, R_, T.Blocks(bad, xo, size=xt))
+    assert e.value.code == -3
+    with pytest.raises(T.TdvpError) as e:
+        T.heff_plan(model, 3, 2, left, right, L_, R_, T.Blocks(xk, xo, size=xt - 1))
+    assert e.value.code == -2
+    with pytest.raises(T.TdvpError) as e:
+        T.heff_plan(model, 8, 2, left, right, L_, R_, T.Blocks(xk, xo, size=xt))
+    assert e.value.code == -1
