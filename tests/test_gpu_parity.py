@@ -1,0 +1,247 @@
+"""GPU parity of the HIP path against the CPU oracle (FP64 to 1e-12 relative,
+FP32 to 1e-5 relative), through the C ABI.
+
+Sizes: bonds with a handful of sectors and degeneracies up to ~80, so blocks
+span several 64x64 tiles with ragged tails while the oracle's dense
+expansion still finishes in seconds."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_2606_04771_amd as T
+from oracle import dense as D
+from oracle import reduced as R
+import synth
+from tests._harness import keyed, pack, random_blocks, theta_dict, env_dict, unpack
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 2e-5
+
+
+def _bond(parity, seed, big=80, n_small=3):
+    """A few sectors with one big degeneracy (several tiles, ragged tail)."""
+    rng = np.random.default_rng(seed)
+    labels = [(q, tj) for q in range(-3, 4) for tj in range(0, 4) if (q - tj - parity) % 2 == 0]
+    rng.shuffle(labels)
+    out = [(labels[0][0], labels[0][1], big + int(rng.integers(0, 9)))]
+    for q, tj in labels[1:1 + n_small + 3]:
+        out.append((q, tj, int(rng.integers(1, 30))))
+    return sorted(out)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    c = T.Context(0)
+    yield c
+    c.close()
+
+
+def dev(buf):
+    return torch.from_numpy(buf).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _heff_case(site, nsites, seed):
+    lp = (site - 1) % 2
+    left = _bond(lp, seed)
+    right = _bond(lp if nsites == 2 else 1 - lp, seed + 1)
+    bl, br = T.Bond(left), T.Bond(right)
+    xk, xo, xt, xd = T.center_layout(bl, br, nsites)
+    lk, lo, lt, ld = T.env_layout(bl)
+    rk, ro, rt, rd = T.env_layout(br)
+    xs = keyed(xk, random_blocks(xk, xd, seed + 2))
+    Ls = keyed(lk, random_blocks(lk, ld, seed + 3))
+    Rs = keyed(rk, random_blocks(rk, rd, seed + 4))
+    return left, right, bl, br, (xk, xo, xt, xd, xs), (lk, lo, lt, ld, Ls), (rk, ro, rt, rd, Rs)
+
+
+@pytest.mark.parametrize("site,prec", [(3, T.FP64), (4, T.FP64), (3, T.FP32)])
+def test_heff_two_site(ctx, site, prec):
+    t, U = 1.0, 4.0
+    print(f"heff2 site={site} prec={prec}", flush=True)
+    left, right, bl, br, X, Lx, Rx = _heff_case(site, 2, 100 + site)
+    xk, xo, xt, xd, xs = X
+    lk, lo, lt, ld, Ls = Lx
+    rk, ro, rt, rd, Rs = Rx
+    x_d = dev(pack(xs, xo, xt))
+    y_d = torch.zeros_like(x_d)
+    L_d = dev(pack(Ls, lo, lt))
+    R_d = dev(pack(Rs, ro, rt))
+    model = T.Model(8, t, U)
+    ctx.set_precision(prec)
+    try:
+        ctx.heff_apply(model, site, 2, bl, br, T.Blocks(lk, lo, L_d.data_ptr(), lt),
+                       T.Blocks(rk, ro, R_d.data_ptr(), rt), T.Blocks(xk, xo, x_d.data_ptr(), xt),
+                       T.Blocks(xk, xo, y_d.data_ptr(), xt))
+    finally:
+        ctx.set_precision(T.FP64)
+    ys = unpack(host(y_d), xo, xd)
+    ref = D.heff2(R.expand_env(env_dict(lk, Ls), left), R.expand_env(env_dict(rk, Rs), right),
+                  R.expand_theta(theta_dict(xk, xs), left, right, site), site, t, U)
+    got = R.expand_theta(theta_dict(xk, ys), left, right, site)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"  max rel err {err:.3e}", flush=True)
+    assert err < (FP64_TOL if prec == T.FP64 else FP32_TOL)
+
+
+def test_heff_one_site(ctx):
+    t, U, site = 1.0, 4.0, 5
+    left, right, bl, br, X, Lx, Rx = _heff_case(site, 1, 200)
+    xk, xo, xt, xd, xs = X
+    lk, lo, lt, ld, Ls = Lx
+    rk, ro, rt, rd, Rs = Rx
+    x_d = dev(pack(xs, xo, xt))
+    y_d = torch.zeros_like(x_d)
+    L_d = dev(pack(Ls, lo, lt))
+    R_d = dev(pack(Rs, ro, rt))
+    ctx.heff_apply(T.Model(8, t, U), site, 1, bl, br, T.Blocks(lk, lo, L_d.data_ptr(), lt),
+                   T.Blocks(rk, ro, R_d.data_ptr(), rt), T.Blocks(xk, xo, x_d.data_ptr(), xt),
+                   T.Blocks(xk, xo, y_d.data_ptr(), xt))
+    ys = unpack(host(y_d), xo, xd)
+    ref = D.heff1(R.expand_env(env_dict(lk, Ls), left), R.expand_env(env_dict(rk, Rs), right),
+                  R.expand_site("C", theta_dict(xk, xs), left, right, site), site, t, U)
+    got = R.expand_site("C", theta_dict(xk, ys), left, right, site)
+    assert np.abs(got - ref).max() / np.abs(ref).max() < FP64_TOL
+
+
+@pytest.mark.parametrize("direction", [1, -1])
+def test_env_update(ctx, direction):
+    t, U, site = 1.0, 4.0, 4
+    print(f"env update direction={direction}", flush=True)
+    b_site_left = _bond((site - 1) % 2, 300)     # bond site-1
+    b_site_right = _bond(site % 2, 301)          # bond site
+    if direction > 0:
+        bin_, bout = b_site_left, b_site_right
+        tk, to, tt, td = T.center_layout(T.Bond(bin_), T.Bond(bout), 1)
+    else:
+        bin_, bout = b_site_right, b_site_left
+        tk, to, tt, td = T.center_layout(T.Bond(bout), T.Bond(bin_), 1)
+    bi, bo = T.Bond(bin_), T.Bond(bout)
+    ek, eo, et, ed = T.env_layout(bi)
+    ok, oo, ot, od = T.env_layout(bo)
+    ts = keyed(tk, random_blocks(tk, td, 302))
+    Es = keyed(ek, random_blocks(ek, ed, 303))
+    t_d = dev(pack(ts, to, tt))
+    e_d = dev(pack(Es, eo, et))
+    o_d = torch.zeros(max(ot, 1), dtype=torch.complex128, device="cuda")
+    ctx.env_update(T.Model(8, t, U), site, direction, bi, bo, T.Blocks(ek, eo, e_d.data_ptr(), et),
+                   T.Blocks(tk, to, t_d.data_ptr(), tt), T.Blocks(ok, oo, o_d.data_ptr(), ot))
+    outs = unpack(host(o_d), oo, od)
+    Ef = R.expand_env(env_dict(ek, Es), bin_)
+    if direction > 0:
+        ref = D.left_env_update(Ef, R.expand_site("A", theta_dict(tk, ts), bin_, bout, site), site, t, U)
+    else:
+        ref = D.right_env_update(Ef, R.expand_site("B", theta_dict(tk, ts), bout, bin_, site), site, t, U)
+    got = R.expand_env(env_dict(ok, outs), bout)
+    scale = max(np.abs(ref[w]).max() for w in range(3))
+    for w in range(3):
+        assert np.abs(got[w] - ref[w]).max() < FP64_TOL * scale
+
+
+def test_heff_deterministic(ctx):
+    """FP64 reruns are bit-identical (no atomics, fixed summation order)."""
+    left, right, bl, br, X, Lx, Rx = _heff_case(3, 2, 400)
+    xk, xo, xt, xd, xs = X
+    lk, lo, lt, ld, Ls = Lx
+    rk, ro, rt, rd, Rs = Rx
+    x_d = dev(pack(xs, xo, xt))
+    L_d = dev(pack(Ls, lo, lt))
+    R_d = dev(pack(Rs, ro, rt))
+    outs = []
+    for _ in range(3):
+        y_d = torch.full_like(x_d, float("nan"))
+        ctx.heff_apply(T.Model(8), 3, 2, bl, br, T.Blocks(lk, lo, L_d.data_ptr(), lt),
+                       T.Blocks(rk, ro, R_d.data_ptr(), rt), T.Blocks(xk, xo, x_d.data_ptr(), xt),
+                       T.Blocks(xk, xo, y_d.data_ptr(), xt))
+        outs.append(host(y_d))
+    assert np.isfinite(outs[0]).all()
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+def _physical_envs(ctx, L, site, nsites, seed, t, U, chi):
+    """Reduced MPS (random, mixed-canonical at `site`), environments built on
+    the GPU with env_update; returns everything needed for a Krylov test."""
+    bonds, sites = synth.random_mps(L, chi, seed, center=site)
+    model = T.Model(L, t, U)
+    # left environments
+    b0 = T.Bond(bonds[0])
+    ek, eo, et, ed = T.env_layout(b0)
+    env = torch.zeros(max(et, 1), dtype=torch.complex128, device="cuda")
+    env_desc = (ek, eo, et, ed)
+    keep = []
+    for k in range(1, site):
+        bi, bo = T.Bond(bonds[k - 1]), T.Bond(bonds[k])
+        tk, to, tt, td = T.center_layout(bi, bo, 1)
+        t_d = dev(pack(keyed(tk, sites[k - 1]), to, tt))
+        ok, oo, ot, od = T.env_layout(bo)
+        out = torch.zeros(max(ot, 1), dtype=torch.complex128, device="cuda")
+        ctx.env_update(model, k, 1, bi, bo, T.Blocks(env_desc[0], env_desc[1], env.data_ptr(), env_desc[2]),
+                       T.Blocks(tk, to, t_d.data_ptr(), tt), T.Blocks(ok, oo, out.data_ptr(), ot))
+        keep.append((env, t_d))
+        env, env_desc = out, (ok, oo, ot, od)
+    Lenv, Ldesc = env, env_desc
+    bL = T.Bond(bonds[L])
+    ek, eo, et, ed = T.env_layout(bL)
+    env = torch.zeros(max(et, 1), dtype=torch.complex128, device="cuda")
+    env_desc = (ek, eo, et, ed)
+    last = site + nsites - 1
+    for k in range(L, last, -1):
+        bi, bo = T.Bond(bonds[k]), T.Bond(bonds[k - 1])
+        tk, to, tt, td = T.center_layout(bo, bi, 1)
+        t_d = dev(pack(keyed(tk, sites[k - 1]), to, tt))
+        ok, oo, ot, od = T.env_layout(bo)
+        out = torch.zeros(max(ot, 1), dtype=torch.complex128, device="cuda")
+        ctx.env_update(model, k, -1, bi, bo, T.Blocks(env_desc[0], env_desc[1], env.data_ptr(), env_desc[2]),
+                       T.Blocks(tk, to, t_d.data_ptr(), tt), T.Blocks(ok, oo, out.data_ptr(), ot))
+        keep.append((env, t_d))
+        env, env_desc = out, (ok, oo, ot, od)
+    torch.cuda.synchronize()
+    return bonds, sites, model, (Lenv, Ldesc), (env, env_desc)
+
+
+@pytest.mark.parametrize("nsites,tau", [(2, -0.025j), (1, 0.025j), (2, -0.3j)])
+def test_krylov_expm_against_dense_oracle(ctx, nsites, tau):
+    L, site, t, U = 6, 3, 1.0, 4.0
+    print(f"krylov nsites={nsites} tau={tau}", flush=True)
+    bonds, sites, model, (Lenv, Ld), (Renv, Rd) = _physical_envs(ctx, L, site, nsites, 7, t, U, 24)
+    left, right = bonds[site - 1], bonds[site + nsites - 1]
+    bl, br = T.Bond(left), T.Bond(right)
+    xk, xo, xt, xd = T.center_layout(bl, br, nsites)
+    xs = keyed(xk, random_blocks(xk, xd, 55))
+    nrm = np.sqrt(sum(np.sum(np.abs(a) ** 2) for a in xs))
+    xs = [a / nrm for a in xs]
+    x_d = dev(pack(xs, xo, xt))
+    rc, info = ctx.krylov_expm(model, site, nsites, bl, br, T.Blocks(Ld[0], Ld[1], Lenv.data_ptr(), Ld[2]),
+                               T.Blocks(Rd[0], Rd[1], Renv.data_ptr(), Rd[2]),
+                               T.Blocks(xk, xo, x_d.data_ptr(), xt), tau, tol=1e-13, maxdim=40)
+    assert info["converged"], info
+    ys = unpack(host(x_d), xo, xd)
+    # oracle: dense environments from the expanded MPS, dense exponential
+    full = [R.expand_site("A" if k < site else ("C" if k == site else "B"), sites[k - 1], bonds[k - 1],
+                          bonds[k], k) for k in range(1, L + 1)]
+    Lf = D.empty_env()
+    for k in range(1, site):
+        Lf = D.left_env_update(Lf, full[k - 1], k, t, U)
+    Rf = D.empty_env()
+    for k in range(L, site + nsites - 1, -1):
+        Rf = D.right_env_update(Rf, full[k - 1], k, t, U)
+    if nsites == 2:
+        v = R.expand_theta(theta_dict(xk, xs), left, right, site)
+        ref, _ = D.lanczos_expm(lambda z: D.heff2(Lf, Rf, z, site, t, U), v, tau, tol=1e-15, maxdim=60)
+        got = R.expand_theta(theta_dict(xk, ys), left, right, site)
+    else:
+        v = R.expand_site("C", theta_dict(xk, xs), left, right, site)
+        ref, _ = D.lanczos_expm(lambda z: D.heff1(Lf, Rf, z, site, t, U), v, tau, tol=1e-15, maxdim=60)
+        got = R.expand_site("C", theta_dict(xk, ys), left, right, site)
+    err = np.abs(got - ref).max()
+    print(f"  iters={info['iters']} err={err:.2e}", flush=True)
+    assert err < 1e-10
+    assert abs(np.linalg.norm(got) - 1.0) < 1e-12
