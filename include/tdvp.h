@@ -248,6 +248,7 @@ int tdvp_env_plan(const tdvp_model* model, int32_t site, int32_t direction, cons
 int tdvp_mps_create(tdvp_ctx* ctx, const tdvp_model* model, const tdvp_bond* bonds,
                     const tdvp_blocks* sites, tdvp_mps** out);
 int tdvp_mps_create_neel(tdvp_ctx* ctx, const tdvp_model* model, int32_t complete, tdvp_mps** out);
+/* Releases the MPS; safe after its context has been destroyed. */
 void tdvp_mps_destroy(tdvp_mps* mps);
 /* bond k in 0..L: sector count, and (if arrays non-NULL) the sectors. */
 int tdvp_mps_bond(const tdvp_mps* mps, int32_t k, int32_t* n, int32_t* q, int32_t* tj, int64_t* dim);

@@ -278,3 +278,63 @@ class Context:
     def env_update(self, model, site, direction, bond_in, bond_out, env_in, tensor, env_out):
         _check(lib.tdvp_env_update(self.h, model.ref, site, direction, bond_in.ref, bond_out.ref, env_in.ref,
                                    tensor.ref, env_out.ref), self.h)
+
+
+class MPS:
+    """Library-owned U(1)xSU(2) MPS (right-canonical, centre on site 1)."""
+
+    def __init__(self, ctx, handle, model):
+        self.ctx, self.h, self.model = ctx, handle, model
+
+    @classmethod
+    def neel(cls, ctx, model, complete=False):
+        h = C.c_void_p()
+        _check(lib.tdvp_mps_create_neel(ctx.h, model.ref, int(bool(complete)), C.byref(h)), ctx.h)
+        return cls(ctx, h, model)
+
+    @classmethod
+    def from_blocks(cls, ctx, model, bonds, sites):
+        """bonds: L+1 Bond objects; sites: L Blocks (device data, keys (ia, s, ib))."""
+        barr = (_Bond * len(bonds))(*[b._s for b in bonds])
+        sarr = (_Blocks * len(sites))(*[s._s for s in sites])
+        h = C.c_void_p()
+        _check(lib.tdvp_mps_create(ctx.h, model.ref, barr, sarr, C.byref(h)), ctx.h)
+        return cls(ctx, h, model)
+
+    def close(self):
+        if self.h:
+            lib.tdvp_mps_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def bond(self, k):
+        n = C.c_int32()
+        _check(lib.tdvp_mps_bond(self.h, k, C.byref(n), None, None, None))
+        q = np.zeros(n.value, np.int32)
+        tj = np.zeros(n.value, np.int32)
+        d = np.zeros(n.value, np.int64)
+        _check(lib.tdvp_mps_bond(self.h, k, C.byref(n), _ptr(q), _ptr(tj), _ptr(d)))
+        return [(int(a), int(b), int(c)) for a, b, c in zip(q, tj, d)]
+
+    def site(self, k):
+        """(keys, offsets, host complex data) of site tensor k (1-based)."""
+        n = C.c_int32()
+        tot = C.c_int64()
+        _check(lib.tdvp_mps_site_layout(self.h, k, C.byref(n), None, None, C.byref(tot)))
+        keys = np.zeros((n.value, 3), np.int32)
+        offs = np.zeros(n.value, np.int64)
+        _check(lib.tdvp_mps_site_layout(self.h, k, C.byref(n), _ptr(keys), _ptr(offs), C.byref(tot)))
+        data = np.zeros(max(tot.value, 1), np.complex128)
+        _check(lib.tdvp_mps_site_read(self.ctx.h, self.h, k, _ptr(data)), self.ctx.h)
+        return keys, offs, data[:tot.value]
+
+    def sweep(self, dt, eps_tol=1e-4, chi_cap=4096, keep_all=False, krylov_tol=1e-12, krylov_maxdim=40):
+        tr = _Trunc(float(eps_tol), int(chi_cap), int(bool(keep_all)), float(krylov_tol), int(krylov_maxdim))
+        info = _SweepInfo()
+        _check(lib.tdvp_sweep(self.ctx.h, self.h, float(dt), C.byref(tr), C.byref(info)), self.ctx.h)
+        return {f: getattr(info, f) for f, _ in _SweepInfo._fields_}

@@ -229,10 +229,11 @@ EnvPrograms env_programs(tdvp_ctx* ctx, const tdvp_model& m, int site, int dir, 
   return ep;
 }
 
-int env_update_dev(tdvp_ctx* ctx, const tdvp_model& m, int site, int dir, const EnvInputs& in) {
+int env_update_dev(tdvp_ctx* ctx, const tdvp_model& m, int site, int dir, const EnvInputs& in, double* flops) {
   int rc;
   EnvPrograms ep = env_programs(ctx, m, site, dir, in, rc);
   if (rc) return rc;
+  if (flops) *flops = ep.s2->flops;
   TDVP_HIP(ctx, ctx->ws_scratch.ensure(sizeof(double) * 2 * (size_t)std::max<int64_t>(ep.scratch, 1)));
   Bufs b{};
   b.p[1] = (const double*)in.ein.data;

@@ -18,7 +18,8 @@ namespace tdvp {
 //   C[m][n] += coef * sum_k opA(A)[m][k] * opB(B)[k][n]
 // ops bits: 0 transpose A, 1 conjugate A, 2 transpose B, 3 conjugate B.
 // Element (r, c) of an untransposed operand sits at off + r + c * ld
-// (complex128, column-major).  Direct terms (K = 0): C[m][n] += coef * A[m][n].
+// (complex128, column-major).  Direct terms (K = 0): C[m][n] += coef * op(A)[m][n]
+// with ops bit 0 = transpose, bit 1 = conjugate.
 struct DevTerm {
   int64_t a_off, b_off;
   int32_t a_buf, b_buf;
@@ -80,7 +81,8 @@ struct tdvp_ctx {
   size_t pinned_bytes = 0;
   hipEvent_t upload_done = nullptr;
   // workspaces
-  tdvp::DeviceBuffer ws_scratch, ws_krylov, ws_small, ws_vec;
+  tdvp::DeviceBuffer ws_scratch, ws_krylov, ws_small, ws_vec, ws_theta, ws_svd;
+  void* solver = nullptr;       // rocblas handle for the eigensolver (created on first use)
   void* host_small = nullptr;   // pinned host mirror of ws_small
   // program cache (structural hash -> program)
   std::list<std::pair<uint64_t, std::shared_ptr<tdvp::Program>>> cache;

@@ -14,7 +14,8 @@ std::shared_ptr<Program> heff_program(tdvp_ctx* ctx, const tdvp_model& m, int si
                                       const HeffInputs& in, const Blocks& y, int& rc);
 
 // Environment update on the device (programs cached by structure).
-int env_update_dev(tdvp_ctx* ctx, const tdvp_model& m, int site, int dir, const EnvInputs& in);
+int env_update_dev(tdvp_ctx* ctx, const tdvp_model& m, int site, int dir, const EnvInputs& in,
+                   double* flops = nullptr);
 
 struct KrylovResult {
   int iters = 0;

@@ -178,10 +178,11 @@ __global__ __launch_bounds__(NT) void gemm_f64(Bufs bufs, double* __restrict__ C
           double vr = accr[i][j][r], vi = acci[i][j][r];
           for (int d = ob.d_begin; d < ob.d_end; ++d) {
             const DevTerm dt = terms[d];
-            const double2 x =
-                (reinterpret_cast<const double2*>(bufs.p[dt.a_buf]) + dt.a_off)[(int64_t)row + (int64_t)col * dt.lda];
+            const int64_t idx = (dt.ops & 1) ? (int64_t)col + (int64_t)row * dt.lda
+                                             : (int64_t)row + (int64_t)col * dt.lda;
+            const double2 x = (reinterpret_cast<const double2*>(bufs.p[dt.a_buf]) + dt.a_off)[idx];
             vr += dt.coef * x.x;
-            vi += dt.coef * x.y;
+            vi += (dt.ops & 2) ? -dt.coef * x.y : dt.coef * x.y;
           }
           C[(int64_t)row + (int64_t)col * ob.ldc] = make_double2(vr, vi);
         }
@@ -266,10 +267,11 @@ __global__ __launch_bounds__(NT) void gemm_f32(Bufs bufs, double* __restrict__ C
           double vr = accr[i][j][r], vi = acci[i][j][r];
           for (int d = ob.d_begin; d < ob.d_end; ++d) {
             const DevTerm dt = terms[d];
-            const double2 x =
-                (reinterpret_cast<const double2*>(bufs.p[dt.a_buf]) + dt.a_off)[(int64_t)row + (int64_t)col * dt.lda];
+            const int64_t idx = (dt.ops & 1) ? (int64_t)col + (int64_t)row * dt.lda
+                                             : (int64_t)row + (int64_t)col * dt.lda;
+            const double2 x = (reinterpret_cast<const double2*>(bufs.p[dt.a_buf]) + dt.a_off)[idx];
             vr += dt.coef * x.x;
-            vi += dt.coef * x.y;
+            vi += (dt.ops & 2) ? -dt.coef * x.y : dt.coef * x.y;
           }
           C[(int64_t)row + (int64_t)col * ob.ldc] = make_double2(vr, vi);
         }

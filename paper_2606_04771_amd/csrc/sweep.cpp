@@ -1,0 +1,777 @@
+// Matrix product state object and the symmetric second-order two-site TDVP
+// sweep (supplementary section S2.2: merge two sites, evolve them with the
+// Krylov exponential, split by SVD to let the bond grow, evolve the one-site
+// centre backwards; truncation by discarded weight, section S2.4).
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <numeric>
+
+#include "device.hpp"
+
+using namespace tdvp;
+
+namespace tdvp {
+
+struct Tensor {
+  Blocks blk;
+  DeviceBuffer buf;
+};
+
+}  // namespace tdvp
+
+struct tdvp_mps {
+  tdvp_ctx* ctx = nullptr;
+  tdvp_model model{};
+  int L = 0;
+  std::vector<Bond> bonds;                       // 0..L
+  std::vector<std::unique_ptr<Tensor>> site;     // site k at index k-1
+  std::vector<std::unique_ptr<Tensor>> Lenv, Renv;   // bond 0..L
+};
+
+namespace tdvp {
+
+namespace {
+
+double now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+int set_site_layout(tdvp_ctx* ctx, Tensor& t, const Bond& l, const Bond& r) {
+  layout_site(l, r, t.blk);
+  TDVP_HIP(ctx, t.buf.ensure(sizeof(double) * 2 * (size_t)std::max<int64_t>(t.blk.size, 1)));
+  t.blk.data = t.buf.p;
+  return TDVP_OK;
+}
+
+int set_env_layout(tdvp_ctx* ctx, Tensor& t, const Bond& b) {
+  layout_env(b, t.blk);
+  TDVP_HIP(ctx, t.buf.ensure(sizeof(double) * 2 * (size_t)std::max<int64_t>(t.blk.size, 1)));
+  t.blk.data = t.buf.p;
+  return TDVP_OK;
+}
+
+// environment of the empty block (bond [(0,0,1)]): zero Hamiltonian
+int empty_env(tdvp_ctx* ctx, Tensor& t, const Bond& b) {
+  int rc = set_env_layout(ctx, t, b);
+  if (rc) return rc;
+  TDVP_HIP(ctx, hipMemsetAsync(t.blk.data, 0, sizeof(double) * 2 * std::max<int64_t>(t.blk.size, 1), ctx->stream));
+  return TDVP_OK;
+}
+
+int env_step(tdvp_ctx* ctx, tdvp_mps* m, int site, int dir, double* flops = nullptr) {
+  // dir +1: Lenv[site] from Lenv[site-1] and site tensor; -1: Renv[site-1] from Renv[site]
+  EnvInputs in;
+  if (dir > 0) {
+    in.bin = m->bonds[site - 1];
+    in.bout = m->bonds[site];
+    in.ein = m->Lenv[site - 1]->blk;
+    in.ten = m->site[site - 1]->blk;
+    int rc = set_env_layout(ctx, *m->Lenv[site], in.bout);
+    if (rc) return rc;
+    in.eout = m->Lenv[site]->blk;
+  } else {
+    in.bin = m->bonds[site];
+    in.bout = m->bonds[site - 1];
+    in.ein = m->Renv[site]->blk;
+    in.ten = m->site[site - 1]->blk;
+    int rc = set_env_layout(ctx, *m->Renv[site - 1], in.bout);
+    if (rc) return rc;
+    in.eout = m->Renv[site - 1]->blk;
+  }
+  return env_update_dev(ctx, m->model, site, dir, in, flops);
+}
+
+int env_step_sync(tdvp_ctx* ctx, tdvp_mps* m, int site, int dir, tdvp_sweep_info* inf) {
+  double f = 0.0;
+  int rc = env_step(ctx, m, site, dir, &f);
+  if (rc) return rc;
+  inf->env_flops += f;
+  TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return TDVP_OK;
+}
+
+// Theta(a, s1, x, s2, b) = X(a, s1, x) Y(x, s2, b) for the bond between i and i+1
+int merge(tdvp_ctx* ctx, tdvp_mps* m, int i, Blocks& th) {
+  const Bond &l = m->bonds[i - 1], &c = m->bonds[i], &r = m->bonds[i + 1];
+  layout_center(l, r, 2, th);
+  TDVP_HIP(ctx, ctx->ws_theta.ensure(sizeof(double) * 2 * (size_t)std::max<int64_t>(th.size, 1)));
+  th.data = ctx->ws_theta.p;
+  const Blocks &X = m->site[i - 1]->blk, &Y = m->site[i]->blk;
+  auto p = std::make_shared<Program>();
+  for (int o = 0; o < th.n(); ++o) {
+    const int* k = th.k(o);
+    DevOut ob{};
+    ob.c_off = th.off[o];
+    ob.ldc = ob.M = (int32_t)th.rows[o];
+    ob.N = (int32_t)th.cols[o];
+    ob.t_begin = (int32_t)p->terms.size();
+    int ix = c.find(l.q[k[0]] + kLocQ[k[1]], k[2]);
+    if (ix >= 0) {
+      int a = X.find3(k[0], k[1], ix), b = Y.find3(ix, k[3], k[4]);
+      if (a >= 0 && b >= 0) {
+        DevTerm d{};
+        d.coef = 1.0;
+        d.a_buf = 0; d.a_off = X.off[a]; d.lda = (int32_t)X.rows[a];
+        d.b_buf = 1; d.b_off = Y.off[b]; d.ldb = (int32_t)Y.rows[b];
+        d.K = (int32_t)c.d[ix];
+        p->terms.push_back(d);
+      }
+    }
+    ob.t_end = ob.d_begin = ob.d_end = (int32_t)p->terms.size();
+    p->outs.push_back(ob);
+  }
+  p->finalize();
+  int rc = upload(ctx, *p);
+  if (rc) return rc;
+  Bufs b{};
+  b.p[0] = (const double*)X.data;
+  b.p[1] = (const double*)Y.data;
+  rc = launch_gemm(ctx, *p, b, (double*)th.data, TDVP_FP64);
+  if (rc) return rc;
+  TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));   // program freed on return
+  return TDVP_OK;
+}
+
+struct Sector {
+  int q, tj;
+  int64_t rows = 0, cols = 0, g = 0;
+  std::map<std::pair<int, int>, int64_t> roff, coff;   // (a, s1) -> row, (s2, b) -> col
+  int64_t moff = 0, goff = 0, doff = 0;
+  bool left_gram = true;   // Gram matrix M M^dag (else M^dag M), always the smaller side
+  bool qr = false;         // the isometry lives on the other side: orthonormalise by QR
+  int64_t qoff = 0, iso_off = 0, iso_ld = 0;
+  int keep = 0;
+};
+
+int ensure_solver(tdvp_ctx* ctx) {
+  if (ctx->solver) return TDVP_OK;
+  rocblas_handle h;
+  if (rocblas_create_handle(&h) != rocblas_status_success)
+    return set_error(ctx, TDVP_E_HIP, "rocblas_create_handle failed");
+  if (rocblas_set_stream(h, ctx->stream) != rocblas_status_success)
+    return set_error(ctx, TDVP_E_HIP, "rocblas_set_stream failed");
+  ctx->solver = h;
+  return TDVP_OK;
+}
+
+int run_program(tdvp_ctx* ctx, Program& p, const Bufs& b, double* C) {
+  p.finalize();
+  int rc = upload(ctx, p);
+  if (!rc) rc = launch_gemm(ctx, p, b, C, TDVP_FP64);
+  return rc;
+}
+
+// Split Theta at bond i.  dir +1: A_i (left-canonical) and one-site centre on
+// site i+1; dir -1: centre on site i and right-canonical B_{i+1}.
+//
+// Per coupled sector x the block matrix M_x (rows (a, s1), columns (s2, b)) is
+// decomposed through the eigenvectors of its smaller Gram matrix (M M^dag or
+// M^dag M, dimension g = min(rows, cols)), whose eigenvalues are the squared
+// singular values.  That eigenbasis is square, so no part of the range of M
+// is lost however small its singular values; when the isometry needed lives on
+// the larger side it is obtained by a Householder QR of M V_k (or M^dag U_k).
+// The centre is then the exact projection of M on the kept isometry.
+int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const tdvp_trunc& tr, double& disc,
+          double& t_svd) {
+  double t0 = now();
+  const Bond &l = m->bonds[i - 1], &r = m->bonds[i + 1];
+  std::map<std::pair<int, int>, Sector> secs;
+  for (int o = 0; o < th.n(); ++o) {
+    const int* k = th.k(o);
+    int qx = l.q[k[0]] + kLocQ[k[1]];
+    Sector& s = secs[{qx, k[2]}];
+    s.q = qx;
+    s.tj = k[2];
+  }
+  for (auto& kv : secs) {   // every fusion partner of x, in a fixed order
+    Sector& s = kv.second;
+    for (int a = 0; a < l.size(); ++a)
+      for (int s1 = 0; s1 < 3; ++s1)
+        if (l.q[a] + kLocQ[s1] == s.q && triangle(l.tj[a], kLocTJ[s1], s.tj)) {
+          s.roff[{a, s1}] = s.rows;
+          s.rows += l.d[a];
+        }
+    for (int s2 = 0; s2 < 3; ++s2)
+      for (int b = 0; b < r.size(); ++b)
+        if (s.q + kLocQ[s2] == r.q[b] && triangle(s.tj, kLocTJ[s2], r.tj[b])) {
+          s.coff[{s2, b}] = s.cols;
+          s.cols += r.d[b];
+        }
+  }
+  int64_t mtot = 0, gtot = 0, dtot = 0, gmax = 0;
+  for (auto& kv : secs) {
+    Sector& s = kv.second;
+    // smaller Gram side; on a tie the side whose eigenvectors are the isometry needed
+    s.left_gram = s.rows < s.cols || (s.rows == s.cols && dir > 0);
+    s.g = std::min(s.rows, s.cols);
+    s.qr = (dir > 0) != s.left_gram;
+    s.moff = mtot;
+    mtot += s.rows * s.cols;
+    s.goff = gtot;
+    gtot += s.g * s.g;
+    s.doff = dtot;
+    dtot += s.g;
+    gmax = std::max(gmax, s.g);
+  }
+  size_t bytes = sizeof(double) * 2 * (size_t)(mtot + gtot) + sizeof(double) * (size_t)(2 * dtot + gmax) + 4096;
+  TDVP_HIP(ctx, ctx->ws_svd.ensure(bytes));
+  double* Mbase = (double*)ctx->ws_svd.p;
+  double* Gbase = Mbase + 2 * mtot;
+  double* Dbase = Gbase + 2 * gtot;
+  double* Ework = Dbase + dtot;
+  rocblas_int* dinfo = (rocblas_int*)(Ework + dtot + gmax + 8);
+  int rc;
+  Bufs b{};
+  // gather Theta blocks into the sector matrices (zeros elsewhere)
+  TDVP_HIP(ctx, hipMemsetAsync(Mbase, 0, sizeof(double) * 2 * (size_t)std::max<int64_t>(mtot, 1), ctx->stream));
+  {
+    Program p;
+    for (int o = 0; o < th.n(); ++o) {
+      const int* k = th.k(o);
+      Sector& s = secs[{l.q[k[0]] + kLocQ[k[1]], k[2]}];
+      DevOut ob{};
+      ob.c_off = s.moff + s.roff.at({k[0], k[1]}) + s.coff.at({k[3], k[4]}) * s.rows;
+      ob.ldc = (int32_t)s.rows;
+      ob.M = (int32_t)th.rows[o];
+      ob.N = (int32_t)th.cols[o];
+      ob.t_begin = ob.t_end = ob.d_begin = (int32_t)p.terms.size();
+      DevTerm d{};
+      d.a_buf = 0; d.a_off = th.off[o]; d.lda = (int32_t)th.rows[o]; d.coef = 1.0;
+      p.terms.push_back(d);
+      ob.d_end = (int32_t)p.terms.size();
+      p.outs.push_back(ob);
+    }
+    b.p[0] = (const double*)th.data;
+    if ((rc = run_program(ctx, p, b, Mbase))) return rc;
+  }
+  {
+    Program g;   // Gram matrix of the smaller side
+    for (auto& kv : secs) {
+      Sector& s = kv.second;
+      DevOut ob{};
+      ob.c_off = s.goff;
+      ob.ldc = ob.M = ob.N = (int32_t)s.g;
+      ob.t_begin = (int32_t)g.terms.size();
+      DevTerm d{};
+      d.coef = 1.0;
+      d.a_buf = 0; d.a_off = s.moff; d.lda = (int32_t)s.rows;
+      d.b_buf = 0; d.b_off = s.moff; d.ldb = (int32_t)s.rows;
+      if (s.left_gram) { d.ops = 4 | 8; d.K = (int32_t)s.cols; }
+      else { d.ops = 1 | 2; d.K = (int32_t)s.rows; }
+      if (d.K > 0 && s.g > 0) g.terms.push_back(d);
+      ob.t_end = ob.d_begin = ob.d_end = (int32_t)g.terms.size();
+      if (s.g > 0) g.outs.push_back(ob);
+    }
+    b.p[0] = Mbase;
+    if ((rc = run_program(ctx, g, b, Gbase))) return rc;
+  }
+  if ((rc = ensure_solver(ctx))) return rc;
+  for (auto& kv : secs) {
+    Sector& s = kv.second;
+    if (s.g == 0) continue;
+    rocblas_status st = rocsolver_zheevd((rocblas_handle)ctx->solver, rocblas_evect_original, rocblas_fill_upper,
+                                         (rocblas_int)s.g, (rocblas_double_complex*)(Gbase + 2 * s.goff),
+                                         (rocblas_int)s.g, Dbase + s.doff, Ework, dinfo);
+    if (st != rocblas_status_success) return set_error(ctx, TDVP_E_HIP, "rocsolver_zheevd failed");
+  }
+  std::vector<double> ev(std::max<int64_t>(dtot, 1));
+  TDVP_HIP(ctx, hipMemcpyAsync(ev.data(), Dbase, sizeof(double) * dtot, hipMemcpyDeviceToHost, ctx->stream));
+  TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  // truncation: whole multiplets by descending full-state singular value
+  struct Ent { double w, sfull; int q, tj, idx; Sector* s; };
+  std::vector<Ent> ents;
+  double W = 0.0;
+  for (auto& kv : secs) {
+    Sector& s = kv.second;
+    for (int64_t e = 0; e < s.g; ++e) {
+      double lam = std::max(ev[s.doff + s.g - 1 - e], 0.0);   // descending
+      ents.push_back({lam, lam / (s.tj + 1), s.q, s.tj, (int)e, &s});
+      W += lam;
+    }
+  }
+  if (!std::isfinite(W)) return set_error(ctx, TDVP_E_NONFINITE, "non-finite singular values");
+  std::stable_sort(ents.begin(), ents.end(), [](const Ent& a, const Ent& b) {
+    if (a.sfull != b.sfull) return a.sfull > b.sfull;
+    if (a.q != b.q) return a.q < b.q;
+    if (a.tj != b.tj) return a.tj < b.tj;
+    return a.idx < b.idx;
+  });
+  size_t keep = ents.size();
+  if (!tr.keep_all) {
+    double tail = 0.0;
+    while (keep > 1 && tail + ents[keep - 1].w <= tr.eps_tol * W) {
+      tail += ents[keep - 1].w;
+      --keep;
+    }
+    int64_t chi = 0;
+    size_t p = 0;
+    for (; p < keep; ++p) {
+      if (p > 0 && chi + ents[p].tj + 1 > tr.chi_cap) break;
+      chi += ents[p].tj + 1;
+    }
+    keep = std::max<size_t>(p, 1);
+  }
+  double kept = 0.0;
+  for (size_t e = 0; e < keep; ++e) {
+    ents[e].s->keep++;
+    kept += ents[e].w;
+  }
+  disc = W > 0 ? (W - kept) / W : 0.0;
+  double renorm = (!tr.keep_all && kept > 0 && W > 0) ? std::sqrt(W / kept) : 1.0;
+  // isometries: eigenvectors directly, or a QR of M V_k / M^dag U_k
+  int64_t qtot = 0, ktot = 0;
+  for (auto& kv : secs) {
+    Sector& s = kv.second;
+    if (s.keep == 0) continue;
+    if (s.qr) {
+      int64_t n = dir > 0 ? s.rows : s.cols;
+      s.qoff = qtot;
+      qtot += n * s.keep;
+      ktot += s.keep;
+      s.iso_off = s.qoff;
+      s.iso_ld = n;
+    } else {
+      s.iso_off = s.goff + (s.g - s.keep) * s.g;
+      s.iso_ld = s.g;
+    }
+  }
+  TDVP_HIP(ctx, ctx->ws_scratch.ensure(sizeof(double) * 2 * (size_t)(qtot + ktot + 1)));
+  double* Qbase = (double*)ctx->ws_scratch.p;
+  double* tau = Qbase + 2 * qtot;
+  if (qtot > 0) {
+    Program pq;
+    for (auto& kv : secs) {
+      Sector& s = kv.second;
+      if (s.keep == 0 || !s.qr) continue;
+      DevOut ob{};
+      ob.c_off = s.qoff;
+      ob.ldc = ob.M = (int32_t)s.iso_ld;
+      ob.N = s.keep;
+      ob.t_begin = (int32_t)pq.terms.size();
+      DevTerm d{};
+      d.coef = 1.0;
+      d.a_buf = 0; d.a_off = s.moff; d.lda = (int32_t)s.rows;
+      d.b_buf = 1; d.b_off = s.goff + (s.g - s.keep) * s.g; d.ldb = (int32_t)s.g;
+      if (dir > 0) { d.K = (int32_t)s.cols; d.ops = 0; }       // M V_k
+      else { d.K = (int32_t)s.rows; d.ops = 1 | 2; }           // M^dag U_k
+      pq.terms.push_back(d);
+      ob.t_end = ob.d_begin = ob.d_end = (int32_t)pq.terms.size();
+      pq.outs.push_back(ob);
+    }
+    b.p[0] = Mbase;
+    b.p[1] = Gbase;
+    if ((rc = run_program(ctx, pq, b, Qbase))) return rc;
+    int64_t kofs = 0;
+    for (auto& kv : secs) {
+      Sector& s = kv.second;
+      if (s.keep == 0 || !s.qr) continue;
+      auto* A = (rocblas_double_complex*)(Qbase + 2 * s.qoff);
+      auto* tq = (rocblas_double_complex*)(tau + 2 * kofs);
+      kofs += s.keep;
+      rocblas_status st = rocsolver_zgeqrf((rocblas_handle)ctx->solver, (rocblas_int)s.iso_ld, s.keep, A,
+                                           (rocblas_int)s.iso_ld, tq);
+      if (st == rocblas_status_success)
+        st = rocsolver_zungqr((rocblas_handle)ctx->solver, (rocblas_int)s.iso_ld, s.keep, s.keep, A,
+                              (rocblas_int)s.iso_ld, tq);
+      if (st != rocblas_status_success) return set_error(ctx, TDVP_E_HIP, "rocsolver QR failed");
+    }
+  }
+  // new bond i
+  Bond nb;
+  for (auto& kv : secs)
+    if (kv.second.keep > 0) nb.add(kv.second.q, kv.second.tj, kv.second.keep);
+  m->bonds[i] = nb;
+  Tensor& TA = *m->site[i - 1];
+  Tensor& TB = *m->site[i];
+  rc = set_site_layout(ctx, TA, m->bonds[i - 1], nb);
+  if (!rc) rc = set_site_layout(ctx, TB, nb, m->bonds[i + 1]);
+  if (rc) return rc;
+  // buffers: 0 = eigenvectors (Gbase), 1 = M, 2 = QR isometries
+  auto iso_buf = [](const Sector& s) { return s.qr ? 2 : 0; };
+  Program pa, pb;
+  auto sector_of = [&](int ix) -> Sector& { return secs[{nb.q[ix], nb.tj[ix]}]; };
+  if (dir > 0) {
+    for (int o = 0; o < TA.blk.n(); ++o) {   // A(a, s1, x) = U_k rows (a, s1)
+      const int* k = TA.blk.k(o);
+      Sector& s = sector_of(k[2]);
+      DevOut ob{};
+      ob.c_off = TA.blk.off[o];
+      ob.ldc = ob.M = (int32_t)TA.blk.rows[o];
+      ob.N = (int32_t)TA.blk.cols[o];
+      ob.t_begin = ob.t_end = ob.d_begin = (int32_t)pa.terms.size();
+      DevTerm d{};
+      d.a_buf = iso_buf(s); d.a_off = s.iso_off + s.roff.at({k[0], k[1]}); d.lda = (int32_t)s.iso_ld;
+      d.coef = 1.0;
+      pa.terms.push_back(d);
+      ob.d_end = (int32_t)pa.terms.size();
+      pa.outs.push_back(ob);
+    }
+    for (int o = 0; o < TB.blk.n(); ++o) {   // C(x, s2, b) = U_k^dag M[:, (s2, b)]
+      const int* k = TB.blk.k(o);
+      Sector& s = sector_of(k[0]);
+      DevOut ob{};
+      ob.c_off = TB.blk.off[o];
+      ob.ldc = ob.M = (int32_t)TB.blk.rows[o];
+      ob.N = (int32_t)TB.blk.cols[o];
+      ob.t_begin = (int32_t)pb.terms.size();
+      DevTerm d{};
+      d.coef = renorm;
+      d.a_buf = iso_buf(s); d.a_off = s.iso_off; d.lda = (int32_t)s.iso_ld; d.ops = 1 | 2;
+      d.b_buf = 1; d.b_off = s.moff + s.coff.at({k[1], k[2]}) * s.rows; d.ldb = (int32_t)s.rows;
+      d.K = (int32_t)s.rows;
+      pb.terms.push_back(d);
+      ob.t_end = ob.d_begin = ob.d_end = (int32_t)pb.terms.size();
+      pb.outs.push_back(ob);
+    }
+  } else {
+    for (int o = 0; o < TA.blk.n(); ++o) {   // C(a, s1, x) = M[(a, s1), :] V_k
+      const int* k = TA.blk.k(o);
+      Sector& s = sector_of(k[2]);
+      DevOut ob{};
+      ob.c_off = TA.blk.off[o];
+      ob.ldc = ob.M = (int32_t)TA.blk.rows[o];
+      ob.N = (int32_t)TA.blk.cols[o];
+      ob.t_begin = (int32_t)pa.terms.size();
+      DevTerm d{};
+      d.coef = renorm;
+      d.a_buf = 1; d.a_off = s.moff + s.roff.at({k[0], k[1]}); d.lda = (int32_t)s.rows;
+      d.b_buf = iso_buf(s); d.b_off = s.iso_off; d.ldb = (int32_t)s.iso_ld;
+      d.K = (int32_t)s.cols;
+      pa.terms.push_back(d);
+      ob.t_end = ob.d_begin = ob.d_end = (int32_t)pa.terms.size();
+      pa.outs.push_back(ob);
+    }
+    for (int o = 0; o < TB.blk.n(); ++o) {   // B(x, s2, b) = (V_k[(s2, b), :])^dag
+      const int* k = TB.blk.k(o);
+      Sector& s = sector_of(k[0]);
+      DevOut ob{};
+      ob.c_off = TB.blk.off[o];
+      ob.ldc = ob.M = (int32_t)TB.blk.rows[o];
+      ob.N = (int32_t)TB.blk.cols[o];
+      ob.t_begin = ob.t_end = ob.d_begin = (int32_t)pb.terms.size();
+      DevTerm d{};
+      d.a_buf = iso_buf(s); d.a_off = s.iso_off + s.coff.at({k[1], k[2]}); d.lda = (int32_t)s.iso_ld;
+      d.ops = 1 | 2;
+      d.coef = 1.0;
+      pb.terms.push_back(d);
+      ob.d_end = (int32_t)pb.terms.size();
+      pb.outs.push_back(ob);
+    }
+  }
+  b.p[0] = Gbase;
+  b.p[1] = Mbase;
+  b.p[2] = Qbase;
+  if ((rc = run_program(ctx, pa, b, (double*)TA.blk.data))) return rc;
+  if ((rc = run_program(ctx, pb, b, (double*)TB.blk.data))) return rc;
+  TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  t_svd += now() - t0;
+  return TDVP_OK;
+}
+
+int evolve(tdvp_ctx* ctx, tdvp_mps* m, int site, int nsites, Blocks& x, const Blocks& Le, const Blocks& Re,
+           double tau_im, const tdvp_trunc& tr, tdvp_sweep_info* info) {
+  HeffInputs in;
+  in.l = m->bonds[site - 1];
+  in.r = m->bonds[site + nsites - 1];
+  in.Le = Le;
+  in.Re = Re;
+  in.x = x;
+  KrylovResult kr;
+  int rc = krylov_dev(ctx, m->model, site, nsites, in, {0.0, tau_im}, tr.krylov_tol, tr.krylov_maxdim, kr);
+  info->krylov_iters += kr.iters;
+  info->krylov_max = std::max(info->krylov_max, kr.iters);
+  info->heff_flops += kr.heff_flops;
+  if (rc == TDVP_E_NOCONV) {
+    info->nonconverged++;
+    rc = TDVP_OK;
+  }
+  return rc;
+}
+
+int build_right_envs(tdvp_ctx* ctx, tdvp_mps* m) {
+  int L = m->L;
+  int rc = empty_env(ctx, *m->Renv[L], m->bonds[L]);
+  if (rc) return rc;
+  for (int k = L; k >= 2; --k)
+    if ((rc = env_step(ctx, m, k, -1))) return rc;
+  return empty_env(ctx, *m->Lenv[0], m->bonds[0]);
+}
+
+tdvp_mps* new_mps(tdvp_ctx* ctx, const tdvp_model& model) {
+  auto* m = new tdvp_mps();
+  m->ctx = ctx;
+  m->model = model;
+  m->L = model.L;
+  m->bonds.resize(m->L + 1);
+  for (int k = 0; k < m->L; ++k) m->site.emplace_back(new Tensor());
+  for (int k = 0; k <= m->L; ++k) {
+    m->Lenv.emplace_back(new Tensor());
+    m->Renv.emplace_back(new Tensor());
+  }
+  return m;
+}
+
+// multiplet counts of every (q, tj) in a block of n sites
+std::map<std::pair<int, int>, int64_t> multiplicity(int n) {
+  std::map<std::pair<int, int>, int64_t> cur{{{0, 0}, 1}};
+  for (int s = 0; s < n; ++s) {
+    std::map<std::pair<int, int>, int64_t> nxt;
+    for (auto& kv : cur)
+      for (int l = 0; l < 3; ++l)
+        for (int tj = std::abs(kv.first.second - kLocTJ[l]); tj <= kv.first.second + kLocTJ[l]; tj += 2)
+          nxt[{kv.first.first + kLocQ[l], tj}] += kv.second;
+    cur.swap(nxt);
+  }
+  return cur;
+}
+
+}  // namespace
+
+}  // namespace tdvp
+
+extern "C" {
+
+int tdvp_mps_create_neel(tdvp_ctx* ctx, const tdvp_model* model, int32_t complete, tdvp_mps** out) {
+  if (!ctx || !model || !out) return set_error(ctx, TDVP_E_INVALID, "null argument");
+  return guarded(ctx, [&]() -> int {
+    *out = nullptr;
+    const int L = model->L;
+    if (L < 2 || L % 2) return set_error(ctx, TDVP_E_INVALID, "the Neel state needs an even L >= 2");
+    TDVP_HIP(ctx, hipSetDevice(ctx->device));
+    std::unique_ptr<tdvp_mps> m(new_mps(ctx, *model));
+    auto neel_s = [](int k) { return (k & 1) ? 1 : 2; };   // up on odd sites
+    // bond sectors
+    std::vector<std::map<std::pair<int, int>, int64_t>> mult(L + 1);
+    for (int n = 0; n <= L; ++n) mult[n] = multiplicity(n);
+    for (int k = 0; k <= L; ++k) {
+      Bond b;
+      if (complete) {
+        for (auto& kv : mult[k]) {
+          auto it = mult[L - k].find({-kv.first.first, kv.first.second});
+          if (it == mult[L - k].end()) continue;
+          b.add(kv.first.first, kv.first.second, std::min(kv.second, it->second));
+        }
+      } else {
+        b.add(k & 1, 0, 1);
+      }
+      m->bonds[k] = b;
+    }
+    // right-canonical tensors by selecting rows of the identity on the fused
+    // space, always keeping the Neel path; centre on site 1 selects the Neel path
+    std::vector<int64_t> neel_idx(L + 1, 0);
+    std::vector<std::vector<double>> host(L);
+    for (int k = L; k >= 1; --k) {
+      Tensor& T = *m->site[k - 1];
+      int rc = set_site_layout(ctx, T, m->bonds[k - 1], m->bonds[k]);
+      if (rc) return rc;
+      const Bond &l = m->bonds[k - 1], &r = m->bonds[k];
+      host[k - 1].assign(2 * (size_t)T.blk.size, 0.0);
+      int ia_neel = l.find((k - 1) & 1, 0), ib_neel = r.find(k & 1, 0);
+      for (int ia = 0; ia < l.size(); ++ia) {
+        // columns of the fused space for row sector ia, in block order
+        std::vector<int> blocks;
+        int64_t F = 0;
+        std::vector<int64_t> coff;
+        for (int o = 0; o < T.blk.n(); ++o)
+          if (T.blk.k(o)[0] == ia) {
+            blocks.push_back(o);
+            coff.push_back(F);
+            F += T.blk.cols[o];
+          }
+        int64_t d = l.d[ia];
+        int64_t pos_neel = -1;
+        if (ia == ia_neel)
+          for (size_t j = 0; j < blocks.size(); ++j) {
+            const int* kk = T.blk.k(blocks[j]);
+            if (kk[1] == neel_s(k) && kk[2] == ib_neel) pos_neel = coff[j] + neel_idx[k];
+          }
+        if (k == 1) {   // centre: only the Neel entry
+          for (size_t j = 0; j < blocks.size(); ++j) {
+            const int* kk = T.blk.k(blocks[j]);
+            if (ia == ia_neel && kk[1] == neel_s(k) && kk[2] == ib_neel)
+              host[0][2 * (T.blk.off[blocks[j]] + 0 + neel_idx[1] * T.blk.rows[blocks[j]])] = 1.0;
+          }
+          continue;
+        }
+        std::vector<int64_t> sel;
+        if (pos_neel >= 0) sel.push_back(pos_neel);
+        for (int64_t c = 0; (int64_t)sel.size() < d && c < F; ++c)
+          if (c != pos_neel) sel.push_back(c);
+        std::sort(sel.begin(), sel.end());
+        if ((int64_t)sel.size() != d) return set_error(ctx, TDVP_E_SHAPE, "inconsistent complete bond dimensions");
+        if (pos_neel >= 0)
+          neel_idx[k - 1] = std::lower_bound(sel.begin(), sel.end(), pos_neel) - sel.begin();
+        for (int64_t rr = 0; rr < d; ++rr) {
+          int64_t c = sel[rr];
+          size_t j = std::upper_bound(coff.begin(), coff.end(), c) - coff.begin() - 1;
+          int o = blocks[j];
+          int64_t cc = c - coff[j];
+          host[k - 1][2 * (T.blk.off[o] + rr + cc * T.blk.rows[o])] = 1.0;
+        }
+      }
+    }
+    for (int k = 1; k <= L; ++k)
+      TDVP_HIP(ctx, hipMemcpy(m->site[k - 1]->blk.data, host[k - 1].data(), sizeof(double) * host[k - 1].size(),
+                              hipMemcpyHostToDevice));
+    int rc = build_right_envs(ctx, m.get());
+    if (rc) return rc;
+    TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *out = m.release();
+    return TDVP_OK;
+  });
+}
+
+int tdvp_mps_create(tdvp_ctx* ctx, const tdvp_model* model, const tdvp_bond* bonds, const tdvp_blocks* sites,
+                    tdvp_mps** out) {
+  if (!ctx || !model || !out || !bonds || !sites) return set_error(ctx, TDVP_E_INVALID, "null argument");
+  return guarded(ctx, [&]() -> int {
+    *out = nullptr;
+    if (model->L < 2) return set_error(ctx, TDVP_E_INVALID, "L must be >= 2");
+    TDVP_HIP(ctx, hipSetDevice(ctx->device));
+    std::unique_ptr<tdvp_mps> m(new_mps(ctx, *model));
+    std::string err;
+    for (int k = 0; k <= m->L; ++k) {
+      int rc = load_bond(m->bonds[k], &bonds[k], err);
+      if (rc) return set_error(ctx, rc, err);
+    }
+    if (m->bonds[0].size() != 1 || m->bonds[0].q[0] != 0 || m->bonds[0].tj[0] != 0 || m->bonds[0].d[0] != 1 ||
+        m->bonds[m->L].size() != 1 || m->bonds[m->L].q[0] != 0 || m->bonds[m->L].tj[0] != 0 ||
+        m->bonds[m->L].d[0] != 1)
+      return set_error(ctx, TDVP_E_SECTOR, "boundary bonds must be the single sector (0,0) of dimension 1");
+    for (int k = 1; k <= m->L; ++k) {
+      Blocks src;
+      int rc = load_site(src, &sites[k - 1], m->bonds[k - 1], m->bonds[k], err);
+      if (rc) return set_error(ctx, rc, err);
+      if (src.n() && !src.data) return set_error(ctx, TDVP_E_INVALID, "null device data");
+      rc = set_site_layout(ctx, *m->site[k - 1], m->bonds[k - 1], m->bonds[k]);
+      if (rc) return rc;
+      TDVP_HIP(ctx, hipMemsetAsync(m->site[k - 1]->blk.data, 0,
+                                   sizeof(double) * 2 * std::max<int64_t>(m->site[k - 1]->blk.size, 1), ctx->stream));
+      rc = copy_blocks(ctx, src, m->site[k - 1]->blk, 1.0);
+      if (rc) return rc;
+    }
+    int rc = build_right_envs(ctx, m.get());
+    if (rc) return rc;
+    TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *out = m.release();
+    return TDVP_OK;
+  });
+}
+
+void tdvp_mps_destroy(tdvp_mps* mps) {
+  // The owning context may already be gone: do not touch it.  Device memory
+  // is released with hipFree, which waits for outstanding work.
+  if (!mps) return;
+  (void)hipDeviceSynchronize();
+  delete mps;
+}
+
+int tdvp_mps_bond(const tdvp_mps* m, int32_t k, int32_t* n, int32_t* q, int32_t* tj, int64_t* dim) {
+  if (!m || !n || k < 0 || k > m->L) return set_error(nullptr, TDVP_E_INVALID, "bad arguments");
+  const Bond& b = m->bonds[k];
+  *n = b.size();
+  for (int i = 0; i < b.size(); ++i) {
+    if (q) q[i] = b.q[i];
+    if (tj) tj[i] = b.tj[i];
+    if (dim) dim[i] = b.d[i];
+  }
+  return TDVP_OK;
+}
+
+int tdvp_mps_site_layout(const tdvp_mps* m, int32_t k, int32_t* nblocks, int32_t* keys, int64_t* offsets,
+                         int64_t* total) {
+  if (!m || !nblocks || k < 1 || k > m->L) return set_error(nullptr, TDVP_E_INVALID, "bad arguments");
+  const Blocks& b = m->site[k - 1]->blk;
+  *nblocks = b.n();
+  if (total) *total = b.size;
+  if (keys) std::memcpy(keys, b.key.data(), sizeof(int) * b.key.size());
+  if (offsets) std::memcpy(offsets, b.off.data(), sizeof(int64_t) * b.off.size());
+  return TDVP_OK;
+}
+
+int tdvp_mps_site_read(tdvp_ctx* ctx, const tdvp_mps* m, int32_t k, void* host_dst) {
+  if (!ctx || !m || !host_dst || k < 1 || k > m->L) return set_error(ctx, TDVP_E_INVALID, "bad arguments");
+  const Blocks& b = m->site[k - 1]->blk;
+  TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  TDVP_HIP(ctx, hipMemcpy(host_dst, b.data, sizeof(double) * 2 * b.size, hipMemcpyDeviceToHost));
+  return TDVP_OK;
+}
+
+int tdvp_sweep(tdvp_ctx* ctx, tdvp_mps* m, double dt, const tdvp_trunc* tr, tdvp_sweep_info* info) {
+  if (!ctx || !m || !tr) return set_error(ctx, TDVP_E_INVALID, "null argument");
+  return guarded(ctx, [&]() -> int {
+    if (m->ctx != ctx) return set_error(ctx, TDVP_E_INVALID, "MPS belongs to another context");
+    if (tr->krylov_maxdim < 1 || tr->krylov_maxdim > 64) return set_error(ctx, TDVP_E_INVALID, "bad krylov_maxdim");
+    TDVP_HIP(ctx, hipSetDevice(ctx->device));
+    tdvp_sweep_info inf{};
+    double t0 = now();
+    const int L = m->L;
+    const double tau = 0.5 * dt;
+    int rc;
+    Blocks th;
+    auto timed = [&](double& acc, auto&& f) -> int {
+      double s = now();
+      int r = f();
+      acc += now() - s;
+      return r;
+    };
+    for (int i = 1; i <= L - 1; ++i) {
+      if ((rc = merge(ctx, m, i, th))) return rc;
+      if ((rc = timed(inf.t_lanczos, [&] {
+             return evolve(ctx, m, i, 2, th, m->Lenv[i - 1]->blk, m->Renv[i + 1]->blk, -tau, *tr, &inf);
+           })))
+        return rc;
+      double d = 0;
+      if ((rc = split(ctx, m, i, th, +1, *tr, d, inf.t_svd))) return rc;
+      inf.max_discarded = std::max(inf.max_discarded, d);
+      inf.sum_discarded += d;
+      if ((rc = timed(inf.t_env, [&] { return env_step_sync(ctx, m, i, +1, &inf); })))
+        return rc;
+      if (i < L - 1) {
+        Blocks& c = m->site[i]->blk;
+        if ((rc = timed(inf.t_lanczos, [&] {
+               return evolve(ctx, m, i + 1, 1, c, m->Lenv[i]->blk, m->Renv[i + 1]->blk, +tau, *tr, &inf);
+             })))
+          return rc;
+      }
+    }
+    for (int i = L - 1; i >= 1; --i) {
+      if ((rc = merge(ctx, m, i, th))) return rc;
+      if ((rc = timed(inf.t_lanczos, [&] {
+             return evolve(ctx, m, i, 2, th, m->Lenv[i - 1]->blk, m->Renv[i + 1]->blk, -tau, *tr, &inf);
+           })))
+        return rc;
+      double d = 0;
+      if ((rc = split(ctx, m, i, th, -1, *tr, d, inf.t_svd))) return rc;
+      inf.max_discarded = std::max(inf.max_discarded, d);
+      inf.sum_discarded += d;
+      if ((rc = timed(inf.t_env, [&] { return env_step_sync(ctx, m, i + 1, -1, &inf); })))
+        return rc;
+      if (i > 1) {
+        Blocks& c = m->site[i - 1]->blk;
+        if ((rc = timed(inf.t_lanczos, [&] {
+               return evolve(ctx, m, i, 1, c, m->Lenv[i - 1]->blk, m->Renv[i]->blk, +tau, *tr, &inf);
+             })))
+          return rc;
+      }
+    }
+    TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (int k = 0; k <= L; ++k) {
+      inf.max_chi = std::max(inf.max_chi, m->bonds[k].chi_full());
+      inf.max_chi_su2 = std::max(inf.max_chi_su2, m->bonds[k].chi_su2());
+    }
+    inf.seconds = now() - t0;
+    if (info) *info = inf;
+    return TDVP_OK;
+  });
+}
+
+}  // extern "C"

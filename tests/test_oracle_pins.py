@@ -344,3 +344,48 @@ def test_synthetic_profile_shape():
     assert synth.chi_full(p) == 4096
     ratio = synth.chi_full(p) / synth.chi_su2(p)
     assert 2.3 < ratio < 2.6                                 # the paper's chi ~ 2.4 chi_SU(2)
+
+
+def test_sector_restricted_block_equals_full_dense():
+    """The restricted evaluation of one output block equals that block of the
+    full dense effective Hamiltonian (checked by expanding the block back)."""
+    from oracle import sampled as S
+    site, t, U = 3, 1.0, 4.0
+    left = synth.sector_profile(40, 71, parity=0)
+    right = synth.sector_profile(40, 72, parity=0)
+    keys = []
+    for ia, (qa, tja, da) in enumerate(left):
+        for s1, (q1, t1) in enumerate(R.MULTIPLETS):
+            for tjx in range(abs(tja - t1), tja + t1 + 1, 2):
+                for s2, (q2, t2) in enumerate(R.MULTIPLETS):
+                    for ib, (qb, tjb, db) in enumerate(right):
+                        if qa + q1 + q2 == qb and abs(tjx - t2) <= tjb <= tjx + t2:
+                            keys.append((ia, s1, tjx, s2, ib))
+
+    def env_keys(bond):
+        out = []
+        for w, (qw, tjw) in enumerate(R.CHANNELS):
+            for ii, (qi, tji, _) in enumerate(bond):
+                for io, (qo, tjo, _) in enumerate(bond):
+                    if qo == qi + qw and abs(tji - tjw) <= tjo <= tji + tjw:
+                        out.append((io, w, ii))
+        return out
+    lk, rk = env_keys(left), env_keys(right)
+    theta = synth.block_data(keys, [(left[k[0]][2], right[k[4]][2]) for k in keys], 5)
+    Lenv = synth.block_data(lk, [(left[k[0]][2], left[k[2]][2]) for k in lk], 6)
+    Renv = synth.block_data(rk, [(right[k[0]][2], right[k[2]][2]) for k in rk], 7)
+    full = D.heff2(R.expand_env(Lenv, left), R.expand_env(Renv, right), R.expand_theta(theta, left, right, site),
+                   site, t, U)
+    rng = np.random.default_rng(0)
+    for j in rng.choice(len(keys), size=6, replace=False):
+        key = keys[j]
+        blk, _ = S.heff2_block(left, right, Lenv, Renv, theta, key, site, t, U)
+        ia, ib = key[0], key[4]
+        ref_blk = np.zeros_like(blk)
+        for x in range(left[ia][2]):
+            for y in range(right[ib][2]):
+                e = np.zeros((left[ia][2], right[ib][2]))
+                e[x, y] = 1.0
+                tree = R.expand_theta({key: e}, left, right, site)
+                ref_blk[x, y] = np.vdot(tree, full)
+        assert np.abs(blk - ref_blk).max() < 1e-12 * max(1.0, np.abs(ref_blk).max())
