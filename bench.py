@@ -126,6 +126,8 @@ def main():
     heff_tflops = flops / t_apply / 1e12
     y_host = y_d.cpu().numpy()
 
+    print(f"bench: H_eff apply {1e3 * t_apply:.3f} ms, {heff_tflops:.2f} TFLOP/s", file=sys.stderr, flush=True)
+
     # ---- full sweeps ------------------------------------------------------------
     sweep = {}
     if args.steps > 0 or args.warmup > 0:
@@ -139,14 +141,17 @@ def main():
             descs.append(T.Blocks(tk, to, d.data_ptr(), tt))
         mps = T.MPS.from_blocks(ctx, model, Tr, descs)
         del bufs, descs
-        for _ in range(args.warmup):
-            mps.sweep(0.05, eps_tol=1e-4, chi_cap=chi, krylov_tol=1e-10, krylov_maxdim=40)
+        for w in range(args.warmup):
+            info = mps.sweep(0.05, eps_tol=1e-4, chi_cap=chi, krylov_tol=1e-10, krylov_maxdim=40)
+            print(f"bench: warmup sweep {w + 1}/{args.warmup}: {info['seconds']:.2f} s", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         ctx.synchronize()
         infos = []
         t0 = time.time()
-        for _ in range(args.steps):
+        for st in range(args.steps):
             infos.append(mps.sweep(0.05, eps_tol=1e-4, chi_cap=chi, krylov_tol=1e-10, krylov_maxdim=40))
+            print(f"bench: timed sweep {st + 1}/{args.steps}: {infos[-1]['seconds']:.2f} s", file=sys.stderr,
+                  flush=True)
         ctx.synchronize()
         torch.cuda.synchronize()
         t_sw = time.time() - t0

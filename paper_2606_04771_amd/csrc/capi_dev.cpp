@@ -1,6 +1,9 @@
 // Device entry points of the C ABI: context, effective-Hamiltonian apply,
 // Krylov exponential and environment update.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <cstdlib>
 
 #include <algorithm>
 #include <chrono>
@@ -279,6 +282,8 @@ int tdvp_ctx_create(tdvp_ctx** out, int32_t device, void* hip_stream, int32_t pr
       return set_error(nullptr, TDVP_E_NOMEM, "pinned host buffer");
     }
     for (auto& ev : c->ev) (void)hipEventCreate(&ev);
+    const char* v = std::getenv("TDVP_VERBOSE");
+    c->verbose = v ? std::atoi(v) : 0;
     *out = c;
     return TDVP_OK;
   });
@@ -289,6 +294,7 @@ void tdvp_ctx_destroy(tdvp_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   ctx->cache.clear();
+  if (ctx->solver) (void)rocblas_destroy_handle((rocblas_handle)ctx->solver);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->host_small) (void)hipHostFree(ctx->host_small);
   if (ctx->upload_done) (void)hipEventDestroy(ctx->upload_done);

@@ -43,9 +43,19 @@ struct Bufs {
   const double* p[kMaxBufs];
 };
 
+// Device memory for program arrays, recycled by size class.  Every use of a
+// chunk is ordered on the context stream, so a recycled chunk is only
+// rewritten (by a stream-ordered copy) after earlier kernels have read it.
+struct ProgPool {
+  std::unordered_map<size_t, std::vector<void*>> free;
+  ~ProgPool();
+};
+
 // Host description of a grouped GEMM, lowered to device arrays once and
 // reused across launches (only the buffer base pointers change).
 struct Program {
+  std::shared_ptr<ProgPool> pool;
+  size_t cls = 0;
   std::vector<DevTerm> terms;
   std::vector<DevOut> outs;
   std::vector<DevTile> tiles;
@@ -84,6 +94,8 @@ struct tdvp_ctx {
   tdvp::DeviceBuffer ws_scratch, ws_krylov, ws_small, ws_vec, ws_theta, ws_svd;
   void* solver = nullptr;       // rocblas handle for the eigensolver (created on first use)
   void* host_small = nullptr;   // pinned host mirror of ws_small
+  std::shared_ptr<tdvp::ProgPool> pool = std::make_shared<tdvp::ProgPool>();
+  int verbose = 0;
   // program cache (structural hash -> program)
   std::list<std::pair<uint64_t, std::shared_ptr<tdvp::Program>>> cache;
   hipEvent_t ev[8] = {};

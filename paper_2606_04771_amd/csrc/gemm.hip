@@ -281,7 +281,14 @@ __global__ __launch_bounds__(NT) void gemm_f32(Bufs bufs, double* __restrict__ C
 }  // namespace
 
 Program::~Program() {
-  if (d_mem) (void)hipFree(d_mem);
+  if (!d_mem) return;
+  if (pool) pool->free[cls].push_back(d_mem);
+  else (void)hipFree(d_mem);
+}
+
+ProgPool::~ProgPool() {
+  for (auto& kv : free)
+    for (void* p : kv.second) (void)hipFree(p);
 }
 
 void Program::finalize() {
@@ -321,10 +328,21 @@ int upload(tdvp_ctx* ctx, Program& p) {
          bl = p.tiles.size() * sizeof(DevTile);
   size_t total = bt + bo + bl + 3 * 256;
   if (p.d_mem) {
-    TDVP_HIP(ctx, hipFree(p.d_mem));
+    if (p.pool) p.pool->free[p.cls].push_back(p.d_mem);
+    else TDVP_HIP(ctx, hipFree(p.d_mem));
     p.d_mem = nullptr;
   }
-  TDVP_HIP(ctx, hipMalloc(&p.d_mem, total));
+  size_t cls = 4096;
+  while (cls < total) cls <<= 1;
+  p.pool = ctx->pool;
+  p.cls = cls;
+  auto& fl = ctx->pool->free[cls];
+  if (!fl.empty()) {
+    p.d_mem = fl.back();
+    fl.pop_back();
+  } else {
+    TDVP_HIP(ctx, hipMalloc(&p.d_mem, cls));
+  }
   char* base = (char*)p.d_mem;
   auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
   p.d_terms = (DevTerm*)base;

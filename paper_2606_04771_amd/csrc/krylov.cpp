@@ -42,11 +42,8 @@ int copy_blocks(tdvp_ctx* ctx, const Blocks& src, const Blocks& dst, double s) {
   if (rc) return rc;
   Bufs b{};
   b.p[0] = (const double*)src.data;
-  rc = launch_gemm(ctx, p, b, (double*)dst.data, TDVP_FP64);
-  if (rc) return rc;
-  // the program's device arrays are freed when p goes out of scope: wait
-  TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  return TDVP_OK;
+  // the program's arrays return to the stream-ordered pool when p goes out of scope
+  return launch_gemm(ctx, p, b, (double*)dst.data, TDVP_FP64);
 }
 
 namespace {

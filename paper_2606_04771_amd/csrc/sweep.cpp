@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -134,10 +135,7 @@ int merge(tdvp_ctx* ctx, tdvp_mps* m, int i, Blocks& th) {
   Bufs b{};
   b.p[0] = (const double*)X.data;
   b.p[1] = (const double*)Y.data;
-  rc = launch_gemm(ctx, *p, b, (double*)th.data, TDVP_FP64);
-  if (rc) return rc;
-  TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));   // program freed on return
-  return TDVP_OK;
+  return launch_gemm(ctx, *p, b, (double*)th.data, TDVP_FP64);
 }
 
 struct Sector {
@@ -723,7 +721,18 @@ int tdvp_sweep(tdvp_ctx* ctx, tdvp_mps* m, double dt, const tdvp_trunc* tr, tdvp
       acc += now() - s;
       return r;
     };
+    auto vlog = [&](const char* dirs, int i, double tb, const tdvp_sweep_info& a, const tdvp_sweep_info& b,
+                    int64_t n) {
+      if (!ctx->verbose) return;
+      std::fprintf(stderr,
+                   "[tdvp] %s bond %2d chi=%6lld theta=%9lld krylov=%3d t=%.3fs (lanczos %.3f svd %.3f env %.3f)\n",
+                   dirs, i, (long long)m->bonds[i].chi_full(), (long long)n, b.krylov_iters - a.krylov_iters,
+                   now() - tb, b.t_lanczos - a.t_lanczos, b.t_svd - a.t_svd, b.t_env - a.t_env);
+      std::fflush(stderr);
+    };
     for (int i = 1; i <= L - 1; ++i) {
+      double tb = now();
+      tdvp_sweep_info before = inf;
       if ((rc = merge(ctx, m, i, th))) return rc;
       if ((rc = timed(inf.t_lanczos, [&] {
              return evolve(ctx, m, i, 2, th, m->Lenv[i - 1]->blk, m->Renv[i + 1]->blk, -tau, *tr, &inf);
@@ -742,8 +751,11 @@ int tdvp_sweep(tdvp_ctx* ctx, tdvp_mps* m, double dt, const tdvp_trunc* tr, tdvp
              })))
           return rc;
       }
+      vlog("L->R", i, tb, before, inf, th.size);
     }
     for (int i = L - 1; i >= 1; --i) {
+      double tb = now();
+      tdvp_sweep_info before = inf;
       if ((rc = merge(ctx, m, i, th))) return rc;
       if ((rc = timed(inf.t_lanczos, [&] {
              return evolve(ctx, m, i, 2, th, m->Lenv[i - 1]->blk, m->Renv[i + 1]->blk, -tau, *tr, &inf);
@@ -762,6 +774,7 @@ int tdvp_sweep(tdvp_ctx* ctx, tdvp_mps* m, double dt, const tdvp_trunc* tr, tdvp
              })))
           return rc;
       }
+      vlog("R->L", i, tb, before, inf, th.size);
     }
     TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
     for (int k = 0; k <= L; ++k) {
