@@ -38,6 +38,11 @@ from .fermions import A_UP, A_DN, PARITY, N_UP, N_DN, EYE4, hubbard
 TJ_W = [0, 1, 1]
 
 
+def _es(spec, *ops):
+    """einsum with numpy's pairwise contraction order (same result, BLAS speed)."""
+    return np.einsum(spec, *ops, optimize=True)
+
+
 def left_channel_ops(k):
     """Edge operators of a left block whose last site is k (1-based):
     {w: [op_kappa=+1/2, op_kappa=-1/2]} (w = 1 'D+', 2 'D-').
@@ -154,22 +159,22 @@ def left_env_update(env, A, k, t, U):
     where hop(k-1,k) couples the old edge operators to the partners on site k."""
     Ac = A.conj()
     # H part: old block Hamiltonian carried through
-    X = np.einsum("xy,ysb->xsb", env[0][:, 0, :], A)
-    Hn = np.einsum("xsc,xsb->cb", Ac, X)
+    X = _es("xy,ysb->xsb", env[0][:, 0, :], A)
+    Hn = _es("xsc,xsb->cb", Ac, X)
     # on-site term of site k
-    Hn = Hn + np.einsum("xsc,st,xtb->cb", Ac, onsite(U), A)
+    Hn = Hn + _es("xsc,st,xtb->cb", Ac, onsite(U), A)
     # hopping across (k-1, k)
     if k > 1:
         sg = (-1.0) ** (k - 1)
         qops = right_channel_ops(k)
         for w, sign in ((1, 1.0), (2, -1.0)):
             for kap in range(2):
-                Y = np.einsum("xy,st,ytb->xsb", env[w][:, kap, :], qops[w][kap], A)
-                Hn = Hn + (-t) * sg * sign * np.einsum("xsc,xsb->cb", Ac, Y)
+                Y = _es("xy,st,ytb->xsb", env[w][:, kap, :], qops[w][kap], A)
+                Hn = Hn + (-t) * sg * sign * _es("xsc,xsb->cb", Ac, Y)
     out = {0: Hn[:, None, :]}
     ops = left_channel_ops(k)
     for w in (1, 2):
-        out[w] = np.stack([np.einsum("xsc,st,xtb->cb", Ac, op, A) for op in ops[w]], axis=1)
+        out[w] = np.stack([_es("xsc,st,xtb->cb", Ac, op, A) for op in ops[w]], axis=1)
     return out
 
 
@@ -180,19 +185,19 @@ def right_env_update(env, B, k, t, U):
       D'_w = B (Q^w_kappa(k) x 1) B^dag
     written with <Psi'| . |Psi> ordering: E'[x', x] = sum conj(B[x',..]) (.) B[x,..]."""
     Bc = B.conj()
-    X = np.einsum("xsb,yb->xsy", B, env[0][:, 0, :])        # [x, s, b']
-    Hn = np.einsum("zsy,xsy->zx", Bc, X)
-    Hn = Hn + np.einsum("zsb,st,xtb->zx", Bc, onsite(U), B)
+    X = _es("xsb,yb->xsy", B, env[0][:, 0, :])        # [x, s, b']
+    Hn = _es("zsy,xsy->zx", Bc, X)
+    Hn = Hn + _es("zsb,st,xtb->zx", Bc, onsite(U), B)
     sg = (-1.0) ** k
     oops = left_channel_ops(k)
     for w, sign in ((1, 1.0), (2, -1.0)):
         for kap in range(2):
-            Y = np.einsum("st,xtb,yb->xsy", oops[w][kap], B, env[w][:, kap, :])
-            Hn = Hn + (-t) * sg * sign * np.einsum("zsy,xsy->zx", Bc, Y)
+            Y = _es("st,xtb,yb->xsy", oops[w][kap], B, env[w][:, kap, :])
+            Hn = Hn + (-t) * sg * sign * _es("zsy,xsy->zx", Bc, Y)
     out = {0: Hn[:, None, :]}
     qops = right_channel_ops(k)
     for w in (1, 2):
-        out[w] = np.stack([np.einsum("zsb,st,xtb->zx", Bc, op, B) for op in qops[w]], axis=1)
+        out[w] = np.stack([_es("zsb,st,xtb->zx", Bc, op, B) for op in qops[w]], axis=1)
     return out
 
 
@@ -202,26 +207,26 @@ def right_env_update(env, B, k, t, U):
 def heff2(Lenv, Renv, Th, i, t, U):
     """Effective Hamiltonian of sites (i, i+1) applied to Th[a, s1, s2, b].
     Lenv: left environment at bond i-1; Renv: right environment at bond i+1."""
-    out = np.einsum("xy,ystb->xstb", Lenv[0][:, 0, :], Th)
-    out += np.einsum("zb,xstb->xstz", Renv[0][:, 0, :], Th)
+    out = _es("xy,ystb->xstb", Lenv[0][:, 0, :], Th)
+    out += _es("zb,xstb->xstz", Renv[0][:, 0, :], Th)
     hU = onsite(U)
-    out += np.einsum("su,xutb->xstb", hU, Th)
-    out += np.einsum("tu,xsub->xstb", hU, Th)
+    out += _es("su,xutb->xstb", hU, Th)
+    out += _es("tu,xsub->xstb", hU, Th)
     h2 = two_site_hop(t).reshape(4, 4, 4, 4)
-    out += np.einsum("stuv,xuvb->xstb", h2, Th)
+    out += _es("stuv,xuvb->xstb", h2, Th)
     # hopping across (i-1, i): left edge operators x partners on site i
     sgl = (-1.0) ** (i - 1)
     q = right_channel_ops(i)
     for w, sign in ((1, 1.0), (2, -1.0)):
         for kap in range(2):
-            out += (-t) * sgl * sign * np.einsum("xy,su,yutb->xstb", Lenv[w][:, kap, :],
+            out += (-t) * sgl * sign * _es("xy,su,yutb->xstb", Lenv[w][:, kap, :],
                                                  q[w][kap], Th)
     # hopping across (i+1, i+2): operators on site i+1 x right edge partners
     sgr = (-1.0) ** (i + 1)
     o = left_channel_ops(i + 1)
     for w, sign in ((1, 1.0), (2, -1.0)):
         for kap in range(2):
-            out += (-t) * sgr * sign * np.einsum("tu,zb,xsub->xstz", o[w][kap],
+            out += (-t) * sgr * sign * _es("tu,zb,xsub->xstz", o[w][kap],
                                                  Renv[w][:, kap, :], Th)
     return out
 
@@ -229,19 +234,19 @@ def heff2(Lenv, Renv, Th, i, t, U):
 def heff1(Lenv, Renv, C, k, t, U):
     """Effective Hamiltonian of site k applied to C[a, s, b].
     Lenv: left environment at bond k-1; Renv: right environment at bond k."""
-    out = np.einsum("xy,ysb->xsb", Lenv[0][:, 0, :], C)
-    out += np.einsum("zb,xsb->xsz", Renv[0][:, 0, :], C)
-    out += np.einsum("su,xub->xsb", onsite(U), C)
+    out = _es("xy,ysb->xsb", Lenv[0][:, 0, :], C)
+    out += _es("zb,xsb->xsz", Renv[0][:, 0, :], C)
+    out += _es("su,xub->xsb", onsite(U), C)
     sgl = (-1.0) ** (k - 1)
     q = right_channel_ops(k)
     for w, sign in ((1, 1.0), (2, -1.0)):
         for kap in range(2):
-            out += (-t) * sgl * sign * np.einsum("xy,su,yub->xsb", Lenv[w][:, kap, :], q[w][kap], C)
+            out += (-t) * sgl * sign * _es("xy,su,yub->xsb", Lenv[w][:, kap, :], q[w][kap], C)
     sgr = (-1.0) ** k
     o = left_channel_ops(k)
     for w, sign in ((1, 1.0), (2, -1.0)):
         for kap in range(2):
-            out += (-t) * sgr * sign * np.einsum("su,zb,xub->xsz", o[w][kap], Renv[w][:, kap, :], C)
+            out += (-t) * sgr * sign * _es("su,zb,xub->xsz", o[w][kap], Renv[w][:, kap, :], C)
     return out
 
 

@@ -61,13 +61,14 @@ struct Program {
   std::vector<DevTile> tiles;
   double flops = 0.0;
   int64_t aux = 0;          // scratch elements needed by the program's outputs
+  int tile_waves = 1;       // output tile (32 w) x (32 w): w = 1 one wave per tile, 2 four waves
   // device copies
   DevTerm* d_terms = nullptr;
   DevOut* d_outs = nullptr;
   DevTile* d_tiles = nullptr;
   void* d_mem = nullptr;
   ~Program();
-  // tile the outputs (64 x 64), order tiles by decreasing cost
+  // tile the outputs, order tiles by decreasing cost
   void finalize();
 };
 
@@ -129,5 +130,6 @@ int vec_combo(tdvp_ctx* ctx, double* out, const double* V, int64_t stride, int n
               int64_t n);
 int vec_norm2(tdvp_ctx* ctx, const double* x, int64_t n, double* d_out);
 int vec_check_finite(tdvp_ctx* ctx, const double* x, int64_t n, int* d_flag);
+int vec_pad_matrix(tdvp_ctx* ctx, double* A, int64_t n, int64_t g, double v);
 
 }  // namespace tdvp

@@ -1,7 +1,7 @@
 // Output-stationary grouped complex GEMM on CDNA4 matrix cores.
 //
 // One launch evaluates every output block of an effective-Hamiltonian apply
-// (or an environment-update stage): each 64x64 output tile sums all of its
+// (or an environment-update stage): each output tile sums all of its
 // contributing block products (left-environment, right-environment and
 // local terms, each with its recoupling coefficient) in registers and is
 // written once.  No atomics, a fixed summation order, so results are
@@ -10,6 +10,10 @@
 // tiles are ordered by decreasing work, so the hardware dispatcher hands the
 // longest tiles out first.
 //
+// Tiles are 32x32 per wave (one wave per tile by default, or 64x64 with four
+// waves).  Small output blocks dominate the block count (median 21 rows at
+// chi = 4096), so 32x32 tiles keep 76 % of the issued matrix work useful
+// against 57 % for 64x64, and give enough tiles to balance the grid.
 // FP64 path: v_mfma_f64_16x16x4_f64, complex products as four real products
 // on planar (re, im) LDS tiles.  Lane layout of the instruction: A[i][k] in
 // lane i + 16 k, B[k][j] in lane j + 16 k, D[4 r + l/16][l % 16] in register r.
@@ -19,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 
 #include "ctx.hpp"
@@ -27,27 +32,54 @@ namespace tdvp {
 
 namespace {
 
-constexpr int TM = 64, TN = 64, TK = 16, PAD = 2;
-constexpr int NT = 256;
+constexpr int TK = 16, PAD = 2;
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-struct Stage {
-  double2 a[4], b[4];
+// MFMA flavours: FP64 16x16x4 writes D[4 r + l/16][l%16], FP32 16x16x4 writes D[4 (l/16) + r][l%16].
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef f64x4 acc_t;
+  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int r, int lk) { return 4 * r + lk; }
+};
+template <> struct Mfma<float> {
+  typedef f32x4 acc_t;
+  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int r, int lk) { return 4 * lk + r; }
 };
 
-// Load this thread's four A and four B elements of the K-tile (k0) of term tm.
-__device__ __forceinline__ void load_stage(Stage& st, const DevTerm& tm, const Bufs& bufs, int m0, int n0,
+// Tile TM x TN = (32 WM) x (32 WN); WM x WN waves, each owning a 32x32 sub-tile.
+template <int WM, int WN>
+struct Shape {
+  static constexpr int TM = 32 * WM, TN = 32 * WN, NT = 64 * WM * WN;
+  static constexpr int NA = TM * TK / NT, NB = TK * TN / NT;   // elements per thread
+};
+
+template <int WM, int WN>
+struct Stage {
+  double2 a[Shape<WM, WN>::NA], b[Shape<WM, WN>::NB];
+};
+
+// Load this thread's A and B elements of the K-tile k0 of term tm (coalesced:
+// consecutive threads follow the contiguous dimension of each operand).
+template <int WM, int WN>
+__device__ __forceinline__ void load_stage(Stage<WM, WN>& st, const DevTerm& tm, const Bufs& bufs, int m0, int n0,
                                            int M, int N, int k0, int tid) {
+  typedef Shape<WM, WN> S;
   const double2* A = reinterpret_cast<const double2*>(bufs.p[tm.a_buf]) + tm.a_off;
   const double2* B = reinterpret_cast<const double2*>(bufs.p[tm.b_buf]) + tm.b_off;
   const bool ta = tm.ops & 1, tb = tm.ops & 4;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    int e = tid + NT * r;
-    int m = ta ? (e >> 4) : (e & 63);
-    int k = ta ? (e & 15) : (e >> 6);
+  for (int r = 0; r < S::NA; ++r) {
+    int e = tid + S::NT * r;
+    int m = ta ? (e / TK) : (e % S::TM);
+    int k = ta ? (e % TK) : (e / S::TM);
     int gm = m0 + m, gk = k0 + k;
     double2 v = make_double2(0.0, 0.0);
     if (gm < M && gk < tm.K)
@@ -55,10 +87,10 @@ __device__ __forceinline__ void load_stage(Stage& st, const DevTerm& tm, const B
     st.a[r] = v;
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    int e = tid + NT * r;
-    int n = tb ? (e & 63) : (e >> 4);
-    int k = tb ? (e >> 6) : (e & 15);
+  for (int r = 0; r < S::NB; ++r) {
+    int e = tid + S::NT * r;
+    int n = tb ? (e % S::TN) : (e / TK);
+    int k = tb ? (e / S::TN) : (e % TK);
     int gn = n0 + n, gk = k0 + k;
     double2 v = make_double2(0.0, 0.0);
     if (gn < N && gk < tm.K)
@@ -67,24 +99,26 @@ __device__ __forceinline__ void load_stage(Stage& st, const DevTerm& tm, const B
   }
 }
 
-template <typename T>
-__device__ __forceinline__ void store_stage(const Stage& st, const DevTerm& tm, T (*As)[TK][TM + PAD],
-                                            T (*Bs)[TK][TN + PAD], int tid) {
+template <typename T, int WM, int WN>
+__device__ __forceinline__ void store_stage(const Stage<WM, WN>& st, const DevTerm& tm,
+                                            T (*As)[TK][Shape<WM, WN>::TM + PAD],
+                                            T (*Bs)[TK][Shape<WM, WN>::TN + PAD], int tid) {
+  typedef Shape<WM, WN> S;
   const bool ta = tm.ops & 1, ca = tm.ops & 2, tb = tm.ops & 4, cb = tm.ops & 8;
   const double c = tm.coef;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    int e = tid + NT * r;
-    int m = ta ? (e >> 4) : (e & 63);
-    int k = ta ? (e & 15) : (e >> 6);
+  for (int r = 0; r < S::NA; ++r) {
+    int e = tid + S::NT * r;
+    int m = ta ? (e / TK) : (e % S::TM);
+    int k = ta ? (e % TK) : (e / S::TM);
     As[0][k][m] = (T)(c * st.a[r].x);
     As[1][k][m] = (T)(ca ? -c * st.a[r].y : c * st.a[r].y);
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    int e = tid + NT * r;
-    int n = tb ? (e & 63) : (e >> 4);
-    int k = tb ? (e >> 6) : (e & 15);
+  for (int r = 0; r < S::NB; ++r) {
+    int e = tid + S::NT * r;
+    int n = tb ? (e % S::TN) : (e / TK);
+    int k = tb ? (e / S::TN) : (e % TK);
     Bs[0][k][n] = (T)st.b[r].x;
     Bs[1][k][n] = (T)(cb ? -st.b[r].y : st.b[r].y);
   }
@@ -99,47 +133,50 @@ __device__ __forceinline__ bool next_ktile(const DevTerm* terms, int t_end, int&
   return t < t_end;
 }
 
-__global__ __launch_bounds__(NT) void gemm_f64(Bufs bufs, double* __restrict__ Cbase,
-                                              const DevTile* __restrict__ tiles,
-                                              const DevOut* __restrict__ outs,
-                                              const DevTerm* __restrict__ terms) {
-  __shared__ double As[2][TK][TM + PAD];
-  __shared__ double Bs[2][TK][TN + PAD];
+template <typename T, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(Bufs bufs, double* __restrict__ Cbase,
+                                                           const DevTile* __restrict__ tiles,
+                                                           const DevOut* __restrict__ outs,
+                                                           const DevTerm* __restrict__ terms) {
+  typedef Shape<WM, WN> S;
+  typedef Mfma<T> F;
+  __shared__ T As[2][TK][S::TM + PAD];
+  __shared__ T Bs[2][TK][S::TN + PAD];
   const DevTile tl = tiles[blockIdx.x];
   const DevOut ob = outs[tl.out];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WN, wn = wave % WN;
   const int li = lane & 15, lk = lane >> 4;
 
-  f64x4 accr[2][2], acci[2][2];
+  typename F::acc_t accr[2][2], acci[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      accr[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
-      acci[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+      accr[i][j] = typename F::acc_t{0, 0, 0, 0};
+      acci[i][j] = typename F::acc_t{0, 0, 0, 0};
     }
 
   int t = ob.t_begin, k0 = 0;
-  Stage st;
+  Stage<WM, WN> st;
   DevTerm cur;
   if (t < ob.t_end) {
     cur = terms[t];
-    load_stage(st, cur, bufs, tl.m0, tl.n0, ob.M, ob.N, k0, tid);
+    load_stage<WM, WN>(st, cur, bufs, tl.m0, tl.n0, ob.M, ob.N, k0, tid);
   }
   while (t < ob.t_end) {
-    store_stage<double>(st, cur, As, Bs, tid);
+    store_stage<T, WM, WN>(st, cur, As, Bs, tid);
     __syncthreads();
     int tn = t, kn = k0;
     bool more = next_ktile(terms, ob.t_end, tn, kn);
     DevTerm nxt;
     if (more) {
       nxt = terms[tn];
-      load_stage(st, nxt, bufs, tl.m0, tl.n0, ob.M, ob.N, kn, tid);
+      load_stage<WM, WN>(st, nxt, bufs, tl.m0, tl.n0, ob.M, ob.N, kn, tid);
     }
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 4) {
-      double ar[2], ai[2], nai[2], br[2], bi[2];
+      T ar[2], ai[2], nai[2], br[2], bi[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         ar[i] = As[0][kk + lk][wm * 32 + i * 16 + li];
@@ -152,10 +189,10 @@ __global__ __launch_bounds__(NT) void gemm_f64(Bufs bufs, double* __restrict__ C
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-          accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], accr[i][j], 0, 0, 0);
-          accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[i], bi[j], accr[i][j], 0, 0, 0);
-          acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], acci[i][j], 0, 0, 0);
-          acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], acci[i][j], 0, 0, 0);
+          accr[i][j] = F::op(ar[i], br[j], accr[i][j]);
+          accr[i][j] = F::op(nai[i], bi[j], accr[i][j]);
+          acci[i][j] = F::op(ar[i], bi[j], acci[i][j]);
+          acci[i][j] = F::op(ai[i], br[j], acci[i][j]);
         }
     }
     __syncthreads();
@@ -164,7 +201,7 @@ __global__ __launch_bounds__(NT) void gemm_f64(Bufs bufs, double* __restrict__ C
     if (more) cur = nxt;
   }
 
-  // direct (local) terms and the store; element (row, col) of register r
+  // direct (local) terms and the store
   double2* C = reinterpret_cast<double2*>(Cbase) + ob.c_off;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -172,96 +209,7 @@ __global__ __launch_bounds__(NT) void gemm_f64(Bufs bufs, double* __restrict__ C
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int row = tl.m0 + wm * 32 + i * 16 + 4 * r + lk;
-        int col = tl.n0 + wn * 32 + j * 16 + li;
-        if (row < ob.M && col < ob.N) {
-          double vr = accr[i][j][r], vi = acci[i][j][r];
-          for (int d = ob.d_begin; d < ob.d_end; ++d) {
-            const DevTerm dt = terms[d];
-            const int64_t idx = (dt.ops & 1) ? (int64_t)col + (int64_t)row * dt.lda
-                                             : (int64_t)row + (int64_t)col * dt.lda;
-            const double2 x = (reinterpret_cast<const double2*>(bufs.p[dt.a_buf]) + dt.a_off)[idx];
-            vr += dt.coef * x.x;
-            vi += (dt.ops & 2) ? -dt.coef * x.y : dt.coef * x.y;
-          }
-          C[(int64_t)row + (int64_t)col * ob.ldc] = make_double2(vr, vi);
-        }
-      }
-}
-
-__global__ __launch_bounds__(NT) void gemm_f32(Bufs bufs, double* __restrict__ Cbase,
-                                              const DevTile* __restrict__ tiles,
-                                              const DevOut* __restrict__ outs,
-                                              const DevTerm* __restrict__ terms) {
-  __shared__ float As[2][TK][TM + PAD];
-  __shared__ float Bs[2][TK][TN + PAD];
-  const DevTile tl = tiles[blockIdx.x];
-  const DevOut ob = outs[tl.out];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int li = lane & 15, lk = lane >> 4;
-
-  f32x4 accr[2][2], acci[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      accr[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-      acci[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    }
-
-  int t = ob.t_begin, k0 = 0;
-  Stage st;
-  DevTerm cur;
-  if (t < ob.t_end) {
-    cur = terms[t];
-    load_stage(st, cur, bufs, tl.m0, tl.n0, ob.M, ob.N, k0, tid);
-  }
-  while (t < ob.t_end) {
-    store_stage<float>(st, cur, As, Bs, tid);
-    __syncthreads();
-    int tn = t, kn = k0;
-    bool more = next_ktile(terms, ob.t_end, tn, kn);
-    DevTerm nxt;
-    if (more) {
-      nxt = terms[tn];
-      load_stage(st, nxt, bufs, tl.m0, tl.n0, ob.M, ob.N, kn, tid);
-    }
-#pragma unroll
-    for (int kk = 0; kk < TK; kk += 4) {
-      float ar[2], ai[2], nai[2], br[2], bi[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        ar[i] = As[0][kk + lk][wm * 32 + i * 16 + li];
-        ai[i] = As[1][kk + lk][wm * 32 + i * 16 + li];
-        nai[i] = -ai[i];
-        br[i] = Bs[0][kk + lk][wn * 32 + i * 16 + li];
-        bi[i] = Bs[1][kk + lk][wn * 32 + i * 16 + li];
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          accr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], br[j], accr[i][j], 0, 0, 0);
-          accr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai[i], bi[j], accr[i][j], 0, 0, 0);
-          acci[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], bi[j], acci[i][j], 0, 0, 0);
-          acci[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[i], br[j], acci[i][j], 0, 0, 0);
-        }
-    }
-    __syncthreads();
-    t = tn;
-    k0 = kn;
-    if (more) cur = nxt;
-  }
-
-  double2* C = reinterpret_cast<double2*>(Cbase) + ob.c_off;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int row = tl.m0 + wm * 32 + i * 16 + 4 * lk + r;
+        int row = tl.m0 + wm * 32 + i * 16 + F::row(r, lk);
         int col = tl.n0 + wn * 32 + j * 16 + li;
         if (row < ob.M && col < ob.N) {
           double vr = accr[i][j][r], vi = acci[i][j][r];
@@ -291,15 +239,26 @@ ProgPool::~ProgPool() {
     for (void* p : kv.second) (void)hipFree(p);
 }
 
+int default_tile_waves() {
+  static int w = [] {
+    const char* e = std::getenv("TDVP_TILE_WAVES");
+    int v = e ? std::atoi(e) : 1;
+    return (v == 2) ? 2 : 1;
+  }();
+  return w;
+}
+
 void Program::finalize() {
   tiles.clear();
+  tile_waves = default_tile_waves();
+  const int tm = 32 * tile_waves, tn = 32 * tile_waves;
   for (int o = 0; o < (int)outs.size(); ++o) {
     const DevOut& ob = outs[o];
     int64_t kc = 0;
     for (int t = ob.t_begin; t < ob.t_end; ++t) kc += (terms[t].K + TK - 1) / TK;
     int cost = (int)std::min<int64_t>(kc * TK + 4 * (ob.d_end - ob.d_begin), 0x7fffffff);
-    for (int m0 = 0; m0 < ob.M; m0 += TM)
-      for (int n0 = 0; n0 < ob.N; n0 += TN) tiles.push_back(DevTile{o, m0, n0, cost});
+    for (int m0 = 0; m0 < ob.M; m0 += tm)
+      for (int n0 = 0; n0 < ob.N; n0 += tn) tiles.push_back(DevTile{o, m0, n0, cost});
   }
   std::stable_sort(tiles.begin(), tiles.end(),
                    [](const DevTile& a, const DevTile& b) { return a.cost > b.cost; });
@@ -384,11 +343,22 @@ void cache_put(tdvp_ctx* ctx, uint64_t key, std::shared_ptr<Program> p) {
 
 int launch_gemm(tdvp_ctx* ctx, const Program& p, const Bufs& bufs, double* C, int precision) {
   if (p.tiles.empty()) return TDVP_OK;
-  dim3 grid((unsigned)p.tiles.size()), block(NT);
-  if (precision == TDVP_FP32)
-    hipLaunchKernelGGL(gemm_f32, grid, block, 0, ctx->stream, bufs, C, p.d_tiles, p.d_outs, p.d_terms);
-  else
-    hipLaunchKernelGGL(gemm_f64, grid, block, 0, ctx->stream, bufs, C, p.d_tiles, p.d_outs, p.d_terms);
+  dim3 grid((unsigned)p.tiles.size());
+  if (p.tile_waves == 2) {
+    if (precision == TDVP_FP32)
+      hipLaunchKernelGGL((gemm_kernel<float, 2, 2>), grid, dim3(256), 0, ctx->stream, bufs, C, p.d_tiles, p.d_outs,
+                         p.d_terms);
+    else
+      hipLaunchKernelGGL((gemm_kernel<double, 2, 2>), grid, dim3(256), 0, ctx->stream, bufs, C, p.d_tiles, p.d_outs,
+                         p.d_terms);
+  } else {
+    if (precision == TDVP_FP32)
+      hipLaunchKernelGGL((gemm_kernel<float, 1, 1>), grid, dim3(64), 0, ctx->stream, bufs, C, p.d_tiles, p.d_outs,
+                         p.d_terms);
+    else
+      hipLaunchKernelGGL((gemm_kernel<double, 1, 1>), grid, dim3(64), 0, ctx->stream, bufs, C, p.d_tiles, p.d_outs,
+                         p.d_terms);
+  }
   TDVP_HIP(ctx, hipGetLastError());
   return TDVP_OK;
 }

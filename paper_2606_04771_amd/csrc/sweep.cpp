@@ -10,6 +10,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <string>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -145,6 +146,8 @@ struct Sector {
   int64_t moff = 0, goff = 0, doff = 0;
   bool left_gram = true;   // Gram matrix M M^dag (else M^dag M), always the smaller side
   bool qr = false;         // the isometry lives on the other side: orthonormalise by QR
+  int64_t gn = 0;           // padded size of the Gram slot (rows < g hold the eigenvectors)
+  int64_t col0 = 0;         // column of the first real eigenvector (n - g padded, 0 unpadded)
   int64_t qoff = 0, iso_off = 0, iso_ld = 0;
   int keep = 0;
 };
@@ -158,6 +161,18 @@ int ensure_solver(tdvp_ctx* ctx) {
     return set_error(ctx, TDVP_E_HIP, "rocblas_set_stream failed");
   ctx->solver = h;
   return TDVP_OK;
+}
+
+int check_finite(tdvp_ctx* ctx, const Blocks& b, const char* what, int bond);
+
+// padded sizes for batched eigensolves: at most ~25 % larger than the sector
+int64_t bucket_size(int64_t g) {
+  static const int64_t sz[] = {1,   2,   4,   8,   16,  24,  32,   48,   64,   80,   96,   128,  160,  192, 224,
+                               256, 320, 384, 448, 512, 640, 768,  896,  1024, 1280, 1536, 1792, 2048, 2560,
+                               3072, 3584, 4096};
+  for (int64_t v : sz)
+    if (v >= g) return v;
+  return (g + 1023) / 1024 * 1024;
 }
 
 int run_program(tdvp_ctx* ctx, Program& p, const Bufs& b, double* C) {
@@ -204,28 +219,51 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
           s.cols += r.d[b];
         }
   }
-  int64_t mtot = 0, gtot = 0, dtot = 0, gmax = 0;
+  // Gram side: exact (keep-all) mode diagonalises the smaller side, whose
+  // eigenbasis is square, and completes the other side by QR; truncation mode
+  // diagonalises the side of the isometry directly (the directions it keeps
+  // carry squared singular values far above the Gram matrix's rounding).
+  const bool exact = tr.keep_all || tr.eps_tol < 1e-10;
+  std::map<int64_t, std::vector<Sector*>> buckets;   // padded size -> sectors
   for (auto& kv : secs) {
     Sector& s = kv.second;
-    // smaller Gram side; on a tie the side whose eigenvectors are the isometry needed
-    s.left_gram = s.rows < s.cols || (s.rows == s.cols && dir > 0);
-    s.g = std::min(s.rows, s.cols);
-    s.qr = (dir > 0) != s.left_gram;
+    if (exact) {
+      s.left_gram = s.rows < s.cols || (s.rows == s.cols && dir > 0);
+      s.g = std::min(s.rows, s.cols);
+      s.qr = (dir > 0) != s.left_gram;
+    } else {
+      s.left_gram = dir > 0;
+      s.g = dir > 0 ? s.rows : s.cols;
+      s.qr = false;
+    }
+    if (s.g > 0) buckets[bucket_size(s.g)].push_back(&s);
+  }
+  int64_t mtot = 0, gtot = 0, dtot = 0, nmax = 0, nmat = 0;
+  for (auto& kv : secs) {
+    Sector& s = kv.second;
     s.moff = mtot;
     mtot += s.rows * s.cols;
-    s.goff = gtot;
-    gtot += s.g * s.g;
-    s.doff = dtot;
-    dtot += s.g;
-    gmax = std::max(gmax, s.g);
   }
-  size_t bytes = sizeof(double) * 2 * (size_t)(mtot + gtot) + sizeof(double) * (size_t)(2 * dtot + gmax) + 4096;
+  for (auto& bk : buckets) {
+    int64_t n = bk.first;
+    nmax = std::max(nmax, n);
+    for (Sector* s : bk.second) {
+      s->gn = n;
+      s->goff = gtot;
+      gtot += n * n;
+      s->doff = dtot;
+      dtot += n;
+      ++nmat;
+    }
+  }
+  size_t bytes = sizeof(double) * 2 * (size_t)(mtot + gtot) + sizeof(double) * (size_t)(2 * dtot) +
+                 sizeof(rocblas_int) * (size_t)(nmat + 8) + 4096;
   TDVP_HIP(ctx, ctx->ws_svd.ensure(bytes));
   double* Mbase = (double*)ctx->ws_svd.p;
   double* Gbase = Mbase + 2 * mtot;
   double* Dbase = Gbase + 2 * gtot;
   double* Ework = Dbase + dtot;
-  rocblas_int* dinfo = (rocblas_int*)(Ework + dtot + gmax + 8);
+  rocblas_int* dinfo = (rocblas_int*)(Ework + dtot + 8);
   int rc;
   Bufs b{};
   // gather Theta blocks into the sector matrices (zeros elsewhere)
@@ -251,12 +289,14 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
     if ((rc = run_program(ctx, p, b, Mbase))) return rc;
   }
   {
-    Program g;   // Gram matrix of the smaller side
+    Program g;   // Gram matrices into the leading g x g part of their padded slots
     for (auto& kv : secs) {
       Sector& s = kv.second;
+      if (s.g == 0) continue;
       DevOut ob{};
       ob.c_off = s.goff;
-      ob.ldc = ob.M = ob.N = (int32_t)s.g;
+      ob.ldc = (int32_t)s.gn;
+      ob.M = ob.N = (int32_t)s.g;
       ob.t_begin = (int32_t)g.terms.size();
       DevTerm d{};
       d.coef = 1.0;
@@ -264,33 +304,110 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
       d.b_buf = 0; d.b_off = s.moff; d.ldb = (int32_t)s.rows;
       if (s.left_gram) { d.ops = 4 | 8; d.K = (int32_t)s.cols; }
       else { d.ops = 1 | 2; d.K = (int32_t)s.rows; }
-      if (d.K > 0 && s.g > 0) g.terms.push_back(d);
+      if (d.K > 0) g.terms.push_back(d);
       ob.t_end = ob.d_begin = ob.d_end = (int32_t)g.terms.size();
-      if (s.g > 0) g.outs.push_back(ob);
+      g.outs.push_back(ob);
     }
     b.p[0] = Mbase;
     if ((rc = run_program(ctx, g, b, Gbase))) return rc;
   }
-  if ((rc = ensure_solver(ctx))) return rc;
+  // padding: -1 on the diagonal below every (non-negative) Gram eigenvalue
   for (auto& kv : secs) {
     Sector& s = kv.second;
-    if (s.g == 0) continue;
-    rocblas_status st = rocsolver_zheevd((rocblas_handle)ctx->solver, rocblas_evect_original, rocblas_fill_upper,
-                                         (rocblas_int)s.g, (rocblas_double_complex*)(Gbase + 2 * s.goff),
-                                         (rocblas_int)s.g, Dbase + s.doff, Ework, dinfo);
-    if (st != rocblas_status_success) return set_error(ctx, TDVP_E_HIP, "rocsolver_zheevd failed");
+    if (s.g > 0 && s.g < s.gn && (rc = vec_pad_matrix(ctx, Gbase + 2 * s.goff, s.gn, s.g, -1.0))) return rc;
+  }
+  if ((rc = ensure_solver(ctx))) return rc;
+  auto gram_program = [&](const std::vector<Sector*>& which, Program& g) {
+    for (Sector* sp : which) {
+      Sector& s = *sp;
+      DevOut ob{};
+      ob.c_off = s.goff;
+      ob.ldc = (int32_t)s.gn;
+      ob.M = ob.N = (int32_t)s.g;
+      ob.t_begin = (int32_t)g.terms.size();
+      DevTerm d{};
+      d.coef = 1.0;
+      d.a_buf = 0; d.a_off = s.moff; d.lda = (int32_t)s.rows;
+      d.b_buf = 0; d.b_off = s.moff; d.ldb = (int32_t)s.rows;
+      if (s.left_gram) { d.ops = 4 | 8; d.K = (int32_t)s.cols; }
+      else { d.ops = 1 | 2; d.K = (int32_t)s.rows; }
+      if (d.K > 0) g.terms.push_back(d);
+      ob.t_end = ob.d_begin = ob.d_end = (int32_t)g.terms.size();
+      g.outs.push_back(ob);
+    }
+  };
+  {
+    // one strided-batched eigensolve per size bucket
+    int64_t mi = 0;
+    std::vector<std::pair<int64_t, std::vector<Sector*>*>> order;
+    for (auto& bk : buckets) {
+      int64_t n = bk.first;
+      Sector* s0 = bk.second.front();
+      for (Sector* sp : bk.second) sp->col0 = n - sp->g;
+      rocblas_status st = rocsolver_zheevd_strided_batched(
+          (rocblas_handle)ctx->solver, rocblas_evect_original, rocblas_fill_upper, (rocblas_int)n,
+          (rocblas_double_complex*)(Gbase + 2 * s0->goff), (rocblas_int)n, (rocblas_stride)(n * n),
+          Dbase + s0->doff, (rocblas_stride)n, Ework + s0->doff, (rocblas_stride)n, dinfo + mi,
+          (rocblas_int)bk.second.size());
+      if (st != rocblas_status_success) return set_error(ctx, TDVP_E_HIP, "rocsolver_zheevd_strided_batched failed");
+      mi += (int64_t)bk.second.size();
+    }
+    // verify every bucket's eigenvectors; redo failing buckets unpadded, one matrix at a time
+    double* dchk = (double*)ctx->ws_small.p + 2048;
+    TDVP_HIP(ctx, ctx->ws_small.ensure(1 << 16));
+    dchk = (double*)ctx->ws_small.p + 2048;
+    int nb = 0;
+    for (auto& bk : buckets) {
+      Sector* s0 = bk.second.front();
+      if ((rc = vec_norm2(ctx, Gbase + 2 * s0->goff, bk.first * bk.first * (int64_t)bk.second.size(),
+                          dchk + 2 * nb)))
+        return rc;
+      ++nb;
+    }
+    std::vector<double> chk(2 * std::max(nb, 1));
+    TDVP_HIP(ctx, hipMemcpyAsync(chk.data(), dchk, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, ctx->stream));
+    TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    std::vector<Sector*> redo;
+    nb = 0;
+    for (auto& bk : buckets) {
+      if (chk[2 * nb + 1] != 0.0 || !std::isfinite(chk[2 * nb])) redo.insert(redo.end(), bk.second.begin(), bk.second.end());
+      ++nb;
+    }
+    if (!redo.empty()) {
+      if (ctx->verbose) std::fprintf(stderr, "[tdvp]   bond %d: %zu Gram matrices re-solved unpadded\n", i, redo.size());
+      Program g;
+      gram_program(redo, g);
+      b.p[0] = Mbase;
+      if ((rc = run_program(ctx, g, b, Gbase))) return rc;
+      for (Sector* sp : redo) {
+        sp->col0 = 0;
+        rocblas_status st = rocsolver_zheevd((rocblas_handle)ctx->solver, rocblas_evect_original, rocblas_fill_upper,
+                                             (rocblas_int)sp->g, (rocblas_double_complex*)(Gbase + 2 * sp->goff),
+                                             (rocblas_int)sp->gn, Dbase + sp->doff, Ework + sp->doff, dinfo);
+        if (st != rocblas_status_success) return set_error(ctx, TDVP_E_HIP, "rocsolver_zheevd failed");
+      }
+    }
   }
   std::vector<double> ev(std::max<int64_t>(dtot, 1));
+  std::vector<rocblas_int> hinfo(std::max<int64_t>(nmat, 1));
   TDVP_HIP(ctx, hipMemcpyAsync(ev.data(), Dbase, sizeof(double) * dtot, hipMemcpyDeviceToHost, ctx->stream));
+  TDVP_HIP(ctx, hipMemcpyAsync(hinfo.data(), dinfo, sizeof(rocblas_int) * nmat, hipMemcpyDeviceToHost, ctx->stream));
   TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  for (int64_t q = 0; q < nmat; ++q)
+    if (hinfo[q] != 0)
+      return set_error(ctx, TDVP_E_NOCONV, "eigensolver info " + std::to_string(hinfo[q]) + " at bond " +
+                                               std::to_string(i));
+  for (int64_t q = 0; q < dtot; ++q)
+    if (!std::isfinite(ev[q]))
+      return set_error(ctx, TDVP_E_NONFINITE, "non-finite Gram eigenvalue at bond " + std::to_string(i));
   // truncation: whole multiplets by descending full-state singular value
   struct Ent { double w, sfull; int q, tj, idx; Sector* s; };
   std::vector<Ent> ents;
   double W = 0.0;
   for (auto& kv : secs) {
     Sector& s = kv.second;
-    for (int64_t e = 0; e < s.g; ++e) {
-      double lam = std::max(ev[s.doff + s.g - 1 - e], 0.0);   // descending
+    for (int64_t e = 0; e < std::min(s.rows, s.cols); ++e) {   // rank bound
+      double lam = std::max(ev[s.doff + s.col0 + s.g - 1 - e], 0.0);   // descending
       ents.push_back({lam, lam / (s.tj + 1), s.q, s.tj, (int)e, &s});
       W += lam;
     }
@@ -337,8 +454,8 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
       s.iso_off = s.qoff;
       s.iso_ld = n;
     } else {
-      s.iso_off = s.goff + (s.g - s.keep) * s.g;
-      s.iso_ld = s.g;
+      s.iso_off = s.goff + (s.col0 + s.g - s.keep) * s.gn;
+      s.iso_ld = s.gn;
     }
   }
   TDVP_HIP(ctx, ctx->ws_scratch.ensure(sizeof(double) * 2 * (size_t)(qtot + ktot + 1)));
@@ -357,7 +474,7 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
       DevTerm d{};
       d.coef = 1.0;
       d.a_buf = 0; d.a_off = s.moff; d.lda = (int32_t)s.rows;
-      d.b_buf = 1; d.b_off = s.goff + (s.g - s.keep) * s.g; d.ldb = (int32_t)s.g;
+      d.b_buf = 1; d.b_off = s.goff + (s.col0 + s.g - s.keep) * s.gn; d.ldb = (int32_t)s.gn;
       if (dir > 0) { d.K = (int32_t)s.cols; d.ops = 0; }       // M V_k
       else { d.K = (int32_t)s.rows; d.ops = 1 | 2; }           // M^dag U_k
       pq.terms.push_back(d);
@@ -492,6 +609,22 @@ int evolve(tdvp_ctx* ctx, tdvp_mps* m, int site, int nsites, Blocks& x, const Bl
     rc = TDVP_OK;
   }
   return rc;
+}
+
+// debug aid (verbose >= 2): fail with a named phase when a tensor is not finite
+int check_finite(tdvp_ctx* ctx, const Blocks& b, const char* what, int bond) {
+  if (ctx->verbose < 2 || b.size == 0) return TDVP_OK;
+  TDVP_HIP(ctx, ctx->ws_small.ensure(1 << 16));
+  double* d = (double*)ctx->ws_small.p + 1024;
+  int rc = vec_norm2(ctx, (const double*)b.data, b.size, d);
+  if (rc) return rc;
+  double h[2];
+  TDVP_HIP(ctx, hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+  TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  std::fprintf(stderr, "[tdvp]   check %-10s bond %2d |x|^2=%.6e nonfinite=%.0f\n", what, bond, h[0], h[1]);
+  if (h[1] != 0.0 || !std::isfinite(h[0]))
+    return set_error(ctx, TDVP_E_NONFINITE, std::string("non-finite ") + what + " at bond " + std::to_string(bond));
+  return TDVP_OK;
 }
 
 int build_right_envs(tdvp_ctx* ctx, tdvp_mps* m) {
@@ -734,16 +867,21 @@ int tdvp_sweep(tdvp_ctx* ctx, tdvp_mps* m, double dt, const tdvp_trunc* tr, tdvp
       double tb = now();
       tdvp_sweep_info before = inf;
       if ((rc = merge(ctx, m, i, th))) return rc;
+      if ((rc = check_finite(ctx, th, "merge", i))) return rc;
       if ((rc = timed(inf.t_lanczos, [&] {
              return evolve(ctx, m, i, 2, th, m->Lenv[i - 1]->blk, m->Renv[i + 1]->blk, -tau, *tr, &inf);
            })))
         return rc;
+      if ((rc = check_finite(ctx, th, "evolved", i))) return rc;
       double d = 0;
       if ((rc = split(ctx, m, i, th, +1, *tr, d, inf.t_svd))) return rc;
+      if ((rc = check_finite(ctx, m->site[i - 1]->blk, "split-A", i))) return rc;
+      if ((rc = check_finite(ctx, m->site[i]->blk, "split-C", i))) return rc;
       inf.max_discarded = std::max(inf.max_discarded, d);
       inf.sum_discarded += d;
       if ((rc = timed(inf.t_env, [&] { return env_step_sync(ctx, m, i, +1, &inf); })))
         return rc;
+      if ((rc = check_finite(ctx, m->Lenv[i]->blk, "Lenv", i))) return rc;
       if (i < L - 1) {
         Blocks& c = m->site[i]->blk;
         if ((rc = timed(inf.t_lanczos, [&] {

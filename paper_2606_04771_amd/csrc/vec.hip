@@ -156,6 +156,16 @@ __global__ __launch_bounds__(NT) void k_norm_partial(const double2* __restrict__
   if (threadIdx.x == 0) partial[g] = make_double2(s, nonfinite);
 }
 
+// Padding of an n x n matrix beyond its leading g x g block: distinct values
+// v - (i - g) / n on the diagonal (no degenerate cluster), zero elsewhere.
+__global__ __launch_bounds__(NT) void k_pad(double2* __restrict__ A, int64_t n, int64_t g, double v) {
+  int64_t tot = n * n;
+  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < tot; e += (int64_t)gridDim.x * NT) {
+    int64_t i = e % n, j = e / n;
+    if (i >= g || j >= g) A[e] = make_double2(i == j ? v - (double)(i - g) / (double)n : 0.0, 0.0);
+  }
+}
+
 int grid_1d(int64_t n) {
   int64_t g = (n + NT - 1) / NT;
   if (g > 8192) g = 8192;
@@ -218,6 +228,13 @@ int vec_norm2(tdvp_ctx* ctx, const double* x, int64_t n, double* d_out) {
   double2* partial = (double2*)ctx->ws_vec.p;
   hipLaunchKernelGGL(k_norm_partial, dim3(G), dim3(NT), 0, ctx->stream, (const double2*)x, n, partial);
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(NT), 0, ctx->stream, partial, G, d_out);
+  TDVP_HIP(ctx, hipGetLastError());
+  return TDVP_OK;
+}
+
+int vec_pad_matrix(tdvp_ctx* ctx, double* A, int64_t n, int64_t g, double v) {
+  if (g >= n) return TDVP_OK;
+  hipLaunchKernelGGL(k_pad, dim3(grid_1d(n * n)), dim3(NT), 0, ctx->stream, (double2*)A, n, g, v);
   TDVP_HIP(ctx, hipGetLastError());
   return TDVP_OK;
 }
