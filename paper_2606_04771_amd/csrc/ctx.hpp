@@ -61,7 +61,8 @@ struct Program {
   std::vector<DevTile> tiles;
   double flops = 0.0;
   int64_t aux = 0;          // scratch elements needed by the program's outputs
-  int tile_waves = 1;       // output tile (32 w) x (32 w): w = 1 one wave per tile, 2 four waves
+  int tile_mode = 0;        // 0: per output block the better of 64x64 / 32x32; 1: all 32x32; 2: all 64x64
+  int n64 = 0;              // tiles[0, n64) are 64x64 (four waves), the rest 32x32 (one wave)
   // device copies
   DevTerm* d_terms = nullptr;
   DevOut* d_outs = nullptr;
@@ -130,6 +131,7 @@ int vec_combo(tdvp_ctx* ctx, double* out, const double* V, int64_t stride, int n
               int64_t n);
 int vec_norm2(tdvp_ctx* ctx, const double* x, int64_t n, double* d_out);
 int vec_check_finite(tdvp_ctx* ctx, const double* x, int64_t n, int* d_flag);
-int vec_pad_matrix(tdvp_ctx* ctx, double* A, int64_t n, int64_t g, double v);
+int vec_pad_matrix(tdvp_ctx* ctx, double* A, int64_t n, int64_t g, double v, double* d_scale);
+int vec_scale_cols_rsqrt(tdvp_ctx* ctx, double* A, int64_t ld, int64_t rows, int64_t cols, const double* lam);
 
 }  // namespace tdvp

@@ -10,10 +10,10 @@
 // tiles are ordered by decreasing work, so the hardware dispatcher hands the
 // longest tiles out first.
 //
-// Tiles are 32x32 per wave (one wave per tile by default, or 64x64 with four
-// waves).  Small output blocks dominate the block count (median 21 rows at
-// chi = 4096), so 32x32 tiles keep 76 % of the issued matrix work useful
-// against 57 % for 64x64, and give enough tiles to balance the grid.
+// Tiles are 64x64 (four waves, each owning 32x32) by default; 32x32 tiles with
+// one wave are selectable.  Measured at chi = 4096 the 64x64 tiling is the
+// faster one despite more padding (57 % of issued matrix work useful against
+// 76 %): it halves the operand traffic per flop.
 // FP64 path: v_mfma_f64_16x16x4_f64, complex products as four real products
 // on planar (re, im) LDS tiles.  Lane layout of the instruction: A[i][k] in
 // lane i + 16 k, B[k][j] in lane j + 16 k, D[4 r + l/16][l % 16] in register r.
@@ -239,29 +239,52 @@ ProgPool::~ProgPool() {
     for (void* p : kv.second) (void)hipFree(p);
 }
 
-int default_tile_waves() {
+int default_tile_mode() {
   static int w = [] {
-    const char* e = std::getenv("TDVP_TILE_WAVES");
-    int v = e ? std::atoi(e) : 1;
-    return (v == 2) ? 2 : 1;
+    const char* e = std::getenv("TDVP_TILE_MODE");
+    int v = e ? std::atoi(e) : 2;
+    return (v == 0 || v == 1) ? v : 2;
   }();
   return w;
 }
 
+// useful fraction of an M x N block tiled by t x t
+static double tile_use(int M, int N, int t) {
+  double pm = (double)((M + t - 1) / t * t), pn = (double)((N + t - 1) / t * t);
+  return (double)M * (double)N / (pm * pn);
+}
+
+double tile_threshold() {
+  static double v = [] {
+    const char* e = std::getenv("TDVP_TILE_THR");
+    return e ? std::atof(e) : 0.85;
+  }();
+  return v;
+}
+
 void Program::finalize() {
   tiles.clear();
-  tile_waves = default_tile_waves();
-  const int tm = 32 * tile_waves, tn = 32 * tile_waves;
+  tile_mode = default_tile_mode();
+  const double thr = tile_threshold();
+  std::vector<DevTile> t64, t32;
   for (int o = 0; o < (int)outs.size(); ++o) {
     const DevOut& ob = outs[o];
     int64_t kc = 0;
     for (int t = ob.t_begin; t < ob.t_end; ++t) kc += (terms[t].K + TK - 1) / TK;
     int cost = (int)std::min<int64_t>(kc * TK + 4 * (ob.d_end - ob.d_begin), 0x7fffffff);
-    for (int m0 = 0; m0 < ob.M; m0 += tm)
-      for (int n0 = 0; n0 < ob.N; n0 += tn) tiles.push_back(DevTile{o, m0, n0, cost});
+    // 64x64 tiles carry twice the arithmetic intensity of 32x32 ones: prefer
+    // them unless their padding costs more than the threshold factor
+    bool big = tile_mode == 2 || (tile_mode == 0 && tile_use(ob.M, ob.N, 64) >= thr * tile_use(ob.M, ob.N, 32));
+    int tt = big ? 64 : 32;
+    for (int m0 = 0; m0 < ob.M; m0 += tt)
+      for (int n0 = 0; n0 < ob.N; n0 += tt) (big ? t64 : t32).push_back(DevTile{o, m0, n0, cost});
   }
-  std::stable_sort(tiles.begin(), tiles.end(),
-                   [](const DevTile& a, const DevTile& b) { return a.cost > b.cost; });
+  auto bycost = [](const DevTile& a, const DevTile& b) { return a.cost > b.cost; };
+  std::stable_sort(t64.begin(), t64.end(), bycost);
+  std::stable_sort(t32.begin(), t32.end(), bycost);
+  n64 = (int)t64.size();
+  tiles = t64;
+  tiles.insert(tiles.end(), t32.begin(), t32.end());
 }
 
 DeviceBuffer::~DeviceBuffer() {
@@ -343,20 +366,22 @@ void cache_put(tdvp_ctx* ctx, uint64_t key, std::shared_ptr<Program> p) {
 
 int launch_gemm(tdvp_ctx* ctx, const Program& p, const Bufs& bufs, double* C, int precision) {
   if (p.tiles.empty()) return TDVP_OK;
-  dim3 grid((unsigned)p.tiles.size());
-  if (p.tile_waves == 2) {
+  const int n32 = (int)p.tiles.size() - p.n64;
+  const DevTile* t32 = p.d_tiles + p.n64;
+  if (p.n64 > 0) {
     if (precision == TDVP_FP32)
-      hipLaunchKernelGGL((gemm_kernel<float, 2, 2>), grid, dim3(256), 0, ctx->stream, bufs, C, p.d_tiles, p.d_outs,
+      hipLaunchKernelGGL((gemm_kernel<float, 2, 2>), dim3(p.n64), dim3(256), 0, ctx->stream, bufs, C, p.d_tiles,
+                         p.d_outs, p.d_terms);
+    else
+      hipLaunchKernelGGL((gemm_kernel<double, 2, 2>), dim3(p.n64), dim3(256), 0, ctx->stream, bufs, C, p.d_tiles,
+                         p.d_outs, p.d_terms);
+  }
+  if (n32 > 0) {
+    if (precision == TDVP_FP32)
+      hipLaunchKernelGGL((gemm_kernel<float, 1, 1>), dim3(n32), dim3(64), 0, ctx->stream, bufs, C, t32, p.d_outs,
                          p.d_terms);
     else
-      hipLaunchKernelGGL((gemm_kernel<double, 2, 2>), grid, dim3(256), 0, ctx->stream, bufs, C, p.d_tiles, p.d_outs,
-                         p.d_terms);
-  } else {
-    if (precision == TDVP_FP32)
-      hipLaunchKernelGGL((gemm_kernel<float, 1, 1>), grid, dim3(64), 0, ctx->stream, bufs, C, p.d_tiles, p.d_outs,
-                         p.d_terms);
-    else
-      hipLaunchKernelGGL((gemm_kernel<double, 1, 1>), grid, dim3(64), 0, ctx->stream, bufs, C, p.d_tiles, p.d_outs,
+      hipLaunchKernelGGL((gemm_kernel<double, 1, 1>), dim3(n32), dim3(64), 0, ctx->stream, bufs, C, t32, p.d_outs,
                          p.d_terms);
   }
   TDVP_HIP(ctx, hipGetLastError());

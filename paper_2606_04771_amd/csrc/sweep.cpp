@@ -149,6 +149,7 @@ struct Sector {
   int64_t gn = 0;           // padded size of the Gram slot (rows < g hold the eigenvectors)
   int64_t col0 = 0;         // column of the first real eigenvector (n - g padded, 0 unpadded)
   int64_t qoff = 0, iso_off = 0, iso_ld = 0;
+  bool scaled = false;      // isometry = M V_k S^-1 without QR
   int keep = 0;
 };
 
@@ -219,23 +220,17 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
           s.cols += r.d[b];
         }
   }
-  // Gram side: exact (keep-all) mode diagonalises the smaller side, whose
-  // eigenbasis is square, and completes the other side by QR; truncation mode
-  // diagonalises the side of the isometry directly (the directions it keeps
-  // carry squared singular values far above the Gram matrix's rounding).
+  // Gram side: always the smaller one (its eigenbasis is square, so no part of
+  // range(M) is lost, and it is generically of full rank).  When the isometry
+  // lives on the larger side it is M V_k S^-1 (truncation mode, kept singular
+  // values far above rounding) or a Householder QR of M V_k (exact mode).
   const bool exact = tr.keep_all || tr.eps_tol < 1e-10;
   std::map<int64_t, std::vector<Sector*>> buckets;   // padded size -> sectors
   for (auto& kv : secs) {
     Sector& s = kv.second;
-    if (exact) {
-      s.left_gram = s.rows < s.cols || (s.rows == s.cols && dir > 0);
-      s.g = std::min(s.rows, s.cols);
-      s.qr = (dir > 0) != s.left_gram;
-    } else {
-      s.left_gram = dir > 0;
-      s.g = dir > 0 ? s.rows : s.cols;
-      s.qr = false;
-    }
+    s.left_gram = s.rows < s.cols || (s.rows == s.cols && dir > 0);
+    s.g = std::min(s.rows, s.cols);
+    s.qr = (dir > 0) != s.left_gram;
     if (s.g > 0) buckets[bucket_size(s.g)].push_back(&s);
   }
   int64_t mtot = 0, gtot = 0, dtot = 0, nmax = 0, nmat = 0;
@@ -311,10 +306,18 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
     b.p[0] = Mbase;
     if ((rc = run_program(ctx, g, b, Gbase))) return rc;
   }
-  // padding: -1 on the diagonal below every (non-negative) Gram eigenvalue
-  for (auto& kv : secs) {
-    Sector& s = kv.second;
-    if (s.g > 0 && s.g < s.gn && (rc = vec_pad_matrix(ctx, Gbase + 2 * s.goff, s.gn, s.g, -1.0))) return rc;
+  // padding: negative diagonal entries below every (non-negative) Gram
+  // eigenvalue, on the scale of the block's own diagonal
+  TDVP_HIP(ctx, ctx->ws_small.ensure(1 << 16));
+  {
+    double* dscale = (double*)ctx->ws_small.p + 4096;
+    int npad = 0;
+    for (auto& kv : secs) {
+      Sector& s = kv.second;
+      if (s.g > 0 && s.g < s.gn) {
+        if ((rc = vec_pad_matrix(ctx, Gbase + 2 * s.goff, s.gn, s.g, -1.0, dscale + (npad++ % 1024)))) return rc;
+      }
+    }
   }
   if ((rc = ensure_solver(ctx))) return rc;
   auto gram_program = [&](const std::vector<Sector*>& which, Program& g) {
@@ -370,7 +373,14 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
     std::vector<Sector*> redo;
     nb = 0;
     for (auto& bk : buckets) {
-      if (chk[2 * nb + 1] != 0.0 || !std::isfinite(chk[2 * nb])) redo.insert(redo.end(), bk.second.begin(), bk.second.end());
+      if (chk[2 * nb + 1] != 0.0 || !std::isfinite(chk[2 * nb])) {
+        redo.insert(redo.end(), bk.second.begin(), bk.second.end());
+        if (ctx->verbose) {
+          std::string gs;
+          for (Sector* sp : bk.second) gs += " " + std::to_string(sp->g);
+          std::fprintf(stderr, "[tdvp]   bond %d bucket n=%lld failed, g:%s\n", i, (long long)bk.first, gs.c_str());
+        }
+      }
       ++nb;
     }
     if (!redo.empty()) {
@@ -441,7 +451,16 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
   }
   disc = W > 0 ? (W - kept) / W : 0.0;
   double renorm = (!tr.keep_all && kept > 0 && W > 0) ? std::sqrt(W / kept) : 1.0;
-  // isometries: eigenvectors directly, or a QR of M V_k / M^dag U_k
+  // isometries: eigenvectors directly, or from M V_k / M^dag U_k (scaled, or QR)
+  double lam_max = 0.0;
+  for (const Ent& e : ents) lam_max = std::max(lam_max, e.w);
+  for (auto& kv : secs) {
+    Sector& s = kv.second;
+    s.scaled = false;
+    if (!s.qr || s.keep == 0 || exact) continue;
+    double lam_min_kept = ev[s.doff + s.col0 + s.g - s.keep];
+    if (lam_min_kept > 1e-14 * lam_max) s.scaled = true;
+  }
   int64_t qtot = 0, ktot = 0;
   for (auto& kv : secs) {
     Sector& s = kv.second;
@@ -481,13 +500,20 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
       ob.t_end = ob.d_begin = ob.d_end = (int32_t)pq.terms.size();
       pq.outs.push_back(ob);
     }
+    for (auto& kv : secs) {   // V_k S^-1 (or U_k S^-1) for the scaled projections
+      Sector& s = kv.second;
+      if (s.keep == 0 || !s.qr || !s.scaled) continue;
+      int64_t c0 = s.col0 + s.g - s.keep;
+      if ((rc = vec_scale_cols_rsqrt(ctx, Gbase + 2 * (s.goff + c0 * s.gn), s.gn, s.g, s.keep, Dbase + s.doff + c0)))
+        return rc;
+    }
     b.p[0] = Mbase;
     b.p[1] = Gbase;
     if ((rc = run_program(ctx, pq, b, Qbase))) return rc;
     int64_t kofs = 0;
     for (auto& kv : secs) {
       Sector& s = kv.second;
-      if (s.keep == 0 || !s.qr) continue;
+      if (s.keep == 0 || !s.qr || s.scaled) continue;
       auto* A = (rocblas_double_complex*)(Qbase + 2 * s.qoff);
       auto* tq = (rocblas_double_complex*)(tau + 2 * kofs);
       kofs += s.keep;

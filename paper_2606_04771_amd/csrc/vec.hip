@@ -156,13 +156,43 @@ __global__ __launch_bounds__(NT) void k_norm_partial(const double2* __restrict__
   if (threadIdx.x == 0) partial[g] = make_double2(s, nonfinite);
 }
 
+// scale[0] = largest |A_ii| of the leading g x g block (one workgroup)
+__global__ __launch_bounds__(NT) void k_diag_max(const double2* __restrict__ A, int64_t n, int64_t g,
+                                                 double* __restrict__ scale) {
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < g; i += NT) m = fmax(m, fabs(A[i + i * n].x));
+  __shared__ double sm[NT];
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = NT / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) scale[0] = sm[0] > 0.0 ? sm[0] : 1.0;
+}
+
 // Padding of an n x n matrix beyond its leading g x g block: distinct values
-// v - (i - g) / n on the diagonal (no degenerate cluster), zero elsewhere.
-__global__ __launch_bounds__(NT) void k_pad(double2* __restrict__ A, int64_t n, int64_t g, double v) {
+// v * scale * (1 + (i - g) / n) on the diagonal (no degenerate cluster, and on
+// the scale of the block's own eigenvalues), zero elsewhere.
+__global__ __launch_bounds__(NT) void k_pad(double2* __restrict__ A, int64_t n, int64_t g, double v,
+                                            const double* __restrict__ scale) {
   int64_t tot = n * n;
+  const double s = v * scale[0];
   for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < tot; e += (int64_t)gridDim.x * NT) {
     int64_t i = e % n, j = e / n;
-    if (i >= g || j >= g) A[e] = make_double2(i == j ? v - (double)(i - g) / (double)n : 0.0, 0.0);
+    if (i >= g || j >= g) A[e] = make_double2(i == j ? s * (1.0 + (double)(i - g) / (double)n) : 0.0, 0.0);
+  }
+}
+
+// A[:, c] *= 1 / sqrt(lam[c]) for c < cols (columns of leading dimension ld)
+__global__ __launch_bounds__(NT) void k_scale_cols(double2* __restrict__ A, int64_t ld, int64_t rows, int64_t cols,
+                                                   const double* __restrict__ lam) {
+  int64_t tot = rows * cols;
+  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < tot; e += (int64_t)gridDim.x * NT) {
+    int64_t r = e % rows, c = e / rows;
+    double s = 1.0 / sqrt(lam[c]);
+    double2 v = A[r + c * ld];
+    A[r + c * ld] = make_double2(s * v.x, s * v.y);
   }
 }
 
@@ -232,9 +262,19 @@ int vec_norm2(tdvp_ctx* ctx, const double* x, int64_t n, double* d_out) {
   return TDVP_OK;
 }
 
-int vec_pad_matrix(tdvp_ctx* ctx, double* A, int64_t n, int64_t g, double v) {
+int vec_scale_cols_rsqrt(tdvp_ctx* ctx, double* A, int64_t ld, int64_t rows, int64_t cols, const double* lam) {
+  if (rows <= 0 || cols <= 0) return TDVP_OK;
+  hipLaunchKernelGGL(k_scale_cols, dim3(grid_1d(rows * cols)), dim3(NT), 0, ctx->stream, (double2*)A, ld, rows, cols,
+                     lam);
+  TDVP_HIP(ctx, hipGetLastError());
+  return TDVP_OK;
+}
+
+int vec_pad_matrix(tdvp_ctx* ctx, double* A, int64_t n, int64_t g, double v, double* d_scale) {
   if (g >= n) return TDVP_OK;
-  hipLaunchKernelGGL(k_pad, dim3(grid_1d(n * n)), dim3(NT), 0, ctx->stream, (double2*)A, n, g, v);
+  hipLaunchKernelGGL(k_diag_max, dim3(1), dim3(NT), 0, ctx->stream, (const double2*)A, n, g, d_scale);
+  hipLaunchKernelGGL(k_pad, dim3(grid_1d(n * n)), dim3(NT), 0, ctx->stream, (double2*)A, n, g, v,
+                     (const double*)d_scale);
   TDVP_HIP(ctx, hipGetLastError());
   return TDVP_OK;
 }
