@@ -236,7 +236,7 @@ def main():
                  "env_chain_s": t_env_chain},
         "roofline": {"bound": "mfma", "achieved": heff_tflops, "peak": PEAK[args.prec], "unit": "TFLOP/s",
                      "frac": heff_tflops / PEAK[args.prec], "traffic": None,
-                     "kernel": "gemm_f64" if prec == T.FP64 else "gemm_f32"},
+                     "kernel": "heff_gemm<double, 2, 2>" if prec == T.FP64 else "heff_gemm<float, 2, 2>"},
         "cpu_baseline": cpu,
     }
     line.update(sweep)

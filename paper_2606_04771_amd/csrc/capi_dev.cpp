@@ -78,6 +78,7 @@ std::shared_ptr<Program> heff_program(tdvp_ctx* ctx, const tdvp_model& m, int si
   std::stable_sort(terms.begin(), terms.end(), [](const HTerm& a, const HTerm& b) { return a.out < b.out; });
   auto p = std::make_shared<Program>();
   p->flops = flops;
+  p->role = 1;
   size_t t = 0;
   const Blocks& x = in.x;
   std::vector<DevTerm> direct;

@@ -34,8 +34,18 @@ struct DevOut {
   int32_t d_begin, d_end;   // direct terms
   int32_t pad;
 };
+// One work item of a grouped-GEMM launch: an output tile and a contiguous
+// piece [(t0, k0), (t1, k1)) of its K chain (terms in order, each cut into
+// TK-wide steps).  slot < 0: the item owns the whole chain and writes the
+// output; otherwise it writes its partial sum to partial slot `slot`.
 struct DevTile {
-  int32_t out, m0, n0, cost;
+  int32_t out, m0, n0, slot;
+  int32_t t0, k0, t1, k1;
+};
+// Sum of the partial slots [slot0, slot0 + nparts) of one split tile, in
+// order, plus the output's direct terms, written to the output.
+struct DevRed {
+  int32_t out, m0, n0, slot0, nparts, pad[3];
 };
 
 constexpr int kMaxBufs = 6;
@@ -59,17 +69,21 @@ struct Program {
   std::vector<DevTerm> terms;
   std::vector<DevOut> outs;
   std::vector<DevTile> tiles;
+  std::vector<DevRed> reds;
+  int nslots = 0;           // partial slots of split tiles
   double flops = 0.0;
   int64_t aux = 0;          // scratch elements needed by the program's outputs
   int tile_mode = 0;        // 0: per output block the better of 64x64 / 32x32; 1: all 32x32; 2: all 64x64
   int n64 = 0;              // tiles[0, n64) are 64x64 (four waves), the rest 32x32 (one wave)
+  int role = 0;             // 1: effective-Hamiltonian apply (launched under its own kernel name)
   // device copies
   DevTerm* d_terms = nullptr;
   DevOut* d_outs = nullptr;
   DevTile* d_tiles = nullptr;
+  DevRed* d_reds = nullptr;
   void* d_mem = nullptr;
   ~Program();
-  // tile the outputs, order tiles by decreasing cost
+  // tile the outputs, split long K chains, order work items by decreasing cost
   void finalize();
 };
 
@@ -94,6 +108,7 @@ struct tdvp_ctx {
   hipEvent_t upload_done = nullptr;
   // workspaces
   tdvp::DeviceBuffer ws_scratch, ws_krylov, ws_small, ws_vec, ws_theta, ws_svd;
+  tdvp::DeviceBuffer ws_part;   // partial tiles of split K chains
   void* solver = nullptr;       // rocblas handle for the eigensolver (created on first use)
   void* host_small = nullptr;   // pinned host mirror of ws_small
   std::shared_ptr<tdvp::ProgPool> pool = std::make_shared<tdvp::ProgPool>();

@@ -124,20 +124,23 @@ __device__ __forceinline__ void store_stage(const Stage<WM, WN>& st, const DevTe
   }
 }
 
-__device__ __forceinline__ bool next_ktile(const DevTerm* terms, int t_end, int& t, int& k0) {
+__device__ __forceinline__ void next_ktile(const DevTerm* terms, int& t, int& k0) {
   k0 += TK;
   if (k0 >= terms[t].K) {
     k0 = 0;
     ++t;
   }
-  return t < t_end;
 }
 
+__device__ __forceinline__ bool before(int t, int k0, int t1, int k1) { return t < t1 || (t == t1 && k0 < k1); }
+
+// Partial tiles are stored TM_MAX x TN_MAX, column-major, whatever the tile shape.
+constexpr int kSlotDim = 64;
+
 template <typename T, int WM, int WN>
-__global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(Bufs bufs, double* __restrict__ Cbase,
-                                                           const DevTile* __restrict__ tiles,
-                                                           const DevOut* __restrict__ outs,
-                                                           const DevTerm* __restrict__ terms) {
+__device__ __forceinline__ void gemm_body(const Bufs& bufs, double* __restrict__ Cbase,
+                                          double2* __restrict__ part, const DevTile* __restrict__ tiles,
+                                          const DevOut* __restrict__ outs, const DevTerm* __restrict__ terms) {
   typedef Shape<WM, WN> S;
   typedef Mfma<T> F;
   __shared__ T As[2][TK][S::TM + PAD];
@@ -147,6 +150,14 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(Bufs bufs, double* _
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
   const int li = lane & 15, lk = lane >> 4;
+  // 16 x 16 sub-blocks of this wave that lie inside the output (wave-uniform):
+  // the matrix instructions of the others are skipped
+  bool rv[2], cv[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    rv[i] = tl.m0 + wm * 32 + i * 16 < ob.M;
+    cv[i] = tl.n0 + wn * 32 + i * 16 < ob.N;
+  }
 
   typename F::acc_t accr[2][2], acci[2][2];
 #pragma unroll
@@ -157,18 +168,20 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(Bufs bufs, double* _
       acci[i][j] = typename F::acc_t{0, 0, 0, 0};
     }
 
-  int t = ob.t_begin, k0 = 0;
+  int t = tl.t0, k0 = tl.k0;
   Stage<WM, WN> st;
   DevTerm cur;
-  if (t < ob.t_end) {
+  if (before(t, k0, tl.t1, tl.k1)) {
     cur = terms[t];
     load_stage<WM, WN>(st, cur, bufs, tl.m0, tl.n0, ob.M, ob.N, k0, tid);
   }
-  while (t < ob.t_end) {
+  while (before(t, k0, tl.t1, tl.k1)) {
     store_stage<T, WM, WN>(st, cur, As, Bs, tid);
     __syncthreads();
+    const int krem = cur.K - k0;   // valid depth of this K step
     int tn = t, kn = k0;
-    bool more = next_ktile(terms, ob.t_end, tn, kn);
+    next_ktile(terms, tn, kn);
+    const bool more = before(tn, kn, tl.t1, tl.k1);
     DevTerm nxt;
     if (more) {
       nxt = terms[tn];
@@ -176,24 +189,27 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(Bufs bufs, double* _
     }
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 4) {
-      T ar[2], ai[2], nai[2], br[2], bi[2];
+      if (kk < krem) {
+        T ar[2], ai[2], nai[2], br[2], bi[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        ar[i] = As[0][kk + lk][wm * 32 + i * 16 + li];
-        ai[i] = As[1][kk + lk][wm * 32 + i * 16 + li];
-        nai[i] = -ai[i];
-        br[i] = Bs[0][kk + lk][wn * 32 + i * 16 + li];
-        bi[i] = Bs[1][kk + lk][wn * 32 + i * 16 + li];
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          accr[i][j] = F::op(ar[i], br[j], accr[i][j]);
-          accr[i][j] = F::op(nai[i], bi[j], accr[i][j]);
-          acci[i][j] = F::op(ar[i], bi[j], acci[i][j]);
-          acci[i][j] = F::op(ai[i], br[j], acci[i][j]);
+        for (int i = 0; i < 2; ++i) {
+          ar[i] = As[0][kk + lk][wm * 32 + i * 16 + li];
+          ai[i] = As[1][kk + lk][wm * 32 + i * 16 + li];
+          nai[i] = -ai[i];
+          br[i] = Bs[0][kk + lk][wn * 32 + i * 16 + li];
+          bi[i] = Bs[1][kk + lk][wn * 32 + i * 16 + li];
         }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            if (rv[i] && cv[j]) {
+              accr[i][j] = F::op(ar[i], br[j], accr[i][j]);
+              accr[i][j] = F::op(nai[i], bi[j], accr[i][j]);
+              acci[i][j] = F::op(ar[i], bi[j], acci[i][j]);
+              acci[i][j] = F::op(ai[i], br[j], acci[i][j]);
+            }
+      }
     }
     __syncthreads();
     t = tn;
@@ -201,6 +217,21 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(Bufs bufs, double* _
     if (more) cur = nxt;
   }
 
+  if (tl.slot >= 0) {   // partial sum of a split chain
+    double2* P = part + (int64_t)tl.slot * kSlotDim * kSlotDim;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int lr = wm * 32 + i * 16 + F::row(r, lk);
+          int lc = wn * 32 + j * 16 + li;
+          if (tl.m0 + lr < ob.M && tl.n0 + lc < ob.N)
+            P[lr + lc * kSlotDim] = make_double2((double)accr[i][j][r], (double)acci[i][j][r]);
+        }
+    return;
+  }
   // direct (local) terms and the store
   double2* C = reinterpret_cast<double2*>(Cbase) + ob.c_off;
 #pragma unroll
@@ -224,6 +255,68 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(Bufs bufs, double* _
           C[(int64_t)row + (int64_t)col * ob.ldc] = make_double2(vr, vi);
         }
       }
+}
+
+// Second phase of split chains: partial slots summed in slot order (fixed,
+// so results stay bit-reproducible), direct terms added, output written.
+__global__ __launch_bounds__(256) void reduce_parts(Bufs bufs, double* __restrict__ Cbase,
+                                                    const double2* __restrict__ part,
+                                                    const DevRed* __restrict__ reds,
+                                                    const DevOut* __restrict__ outs,
+                                                    const DevTerm* __restrict__ terms) {
+  const DevRed rd = reds[blockIdx.x];
+  const DevOut ob = outs[rd.out];
+  double2* C = reinterpret_cast<double2*>(Cbase) + ob.c_off;
+  for (int e = threadIdx.x; e < kSlotDim * kSlotDim; e += 256) {
+    const int lr = e % kSlotDim, lc = e / kSlotDim;
+    const int row = rd.m0 + lr, col = rd.n0 + lc;
+    if (row >= ob.M || col >= ob.N) continue;
+    double vr = 0.0, vi = 0.0;
+    for (int q = 0; q < rd.nparts; ++q) {
+      const double2 v = part[(int64_t)(rd.slot0 + q) * kSlotDim * kSlotDim + e];
+      vr += v.x;
+      vi += v.y;
+    }
+    for (int d = ob.d_begin; d < ob.d_end; ++d) {
+      const DevTerm dt = terms[d];
+      const int64_t idx = (dt.ops & 1) ? (int64_t)col + (int64_t)row * dt.lda : (int64_t)row + (int64_t)col * dt.lda;
+      const double2 x = (reinterpret_cast<const double2*>(bufs.p[dt.a_buf]) + dt.a_off)[idx];
+      vr += dt.coef * x.x;
+      vi += (dt.ops & 2) ? -dt.coef * x.y : dt.coef * x.y;
+    }
+    C[(int64_t)row + (int64_t)col * ob.ldc] = make_double2(vr, vi);
+  }
+}
+
+// Two entry kernels with the same body, so that profiles separate the
+// effective-Hamiltonian applies from every other grouped GEMM (environment
+// updates, gathers, Gram matrices, copies).
+template <typename T, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void heff_gemm(Bufs bufs, double* __restrict__ C,
+                                                         double2* __restrict__ part,
+                                                         const DevTile* __restrict__ tiles,
+                                                         const DevOut* __restrict__ outs,
+                                                         const DevTerm* __restrict__ terms) {
+  gemm_body<T, WM, WN>(bufs, C, part, tiles, outs, terms);
+}
+template <typename T, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void block_gemm(Bufs bufs, double* __restrict__ C,
+                                                          double2* __restrict__ part,
+                                                          const DevTile* __restrict__ tiles,
+                                                          const DevOut* __restrict__ outs,
+                                                          const DevTerm* __restrict__ terms) {
+  gemm_body<T, WM, WN>(bufs, C, part, tiles, outs, terms);
+}
+
+template <typename T, int WM, int WN>
+void launch_one(tdvp_ctx* ctx, bool heff, int ntiles, const Bufs& bufs, double* C, double2* part,
+                const DevTile* tiles, const Program& p) {
+  if (heff)
+    hipLaunchKernelGGL((heff_gemm<T, WM, WN>), dim3(ntiles), dim3(64 * WM * WN), 0, ctx->stream, bufs, C, part,
+                       tiles, p.d_outs, p.d_terms);
+  else
+    hipLaunchKernelGGL((block_gemm<T, WM, WN>), dim3(ntiles), dim3(64 * WM * WN), 0, ctx->stream, bufs, C, part,
+                       tiles, p.d_outs, p.d_terms);
 }
 
 }  // namespace
@@ -262,29 +355,133 @@ double tile_threshold() {
   return v;
 }
 
+static double env_double(const char* name, double dflt) {
+  const char* e = std::getenv(name);
+  return e ? std::atof(e) : dflt;
+}
+
 void Program::finalize() {
   tiles.clear();
+  reds.clear();
+  nslots = 0;
   tile_mode = default_tile_mode();
   const double thr = tile_threshold();
-  std::vector<DevTile> t64, t32;
+  // Optional splitting of long K chains, so that no work item runs much
+  // longer than alpha x the mean work per resident workgroup (4 per CU of
+  // 64x64 tiles on 256 CUs); the pieces are summed by a second, short kernel
+  // in a fixed order.  Off by default (alpha = 0): at chi = 4096 the measured
+  // gain was negative, the skipped padding products having removed most of
+  // the imbalance.
+  static const double alpha = env_double("TDVP_SPLIT_ALPHA", 0.0);
+  static const int kmin = (int)env_double("TDVP_SPLIT_KMIN", 256);
+  static const int max_slots = (int)env_double("TDVP_SPLIT_MAXSLOTS", 2048);
+  struct Item {
+    DevTile t;
+    double cost;   // issued matrix work, in units of a 64 x 64 x 1 step
+    double kc;     // chain depth issued (K, rounded to 4 per step)
+    bool big;
+  };
+  std::vector<Item> items;
+  double total = 0.0;
   for (int o = 0; o < (int)outs.size(); ++o) {
     const DevOut& ob = outs[o];
-    int64_t kc = 0;
-    for (int t = ob.t_begin; t < ob.t_end; ++t) kc += (terms[t].K + TK - 1) / TK;
-    int cost = (int)std::min<int64_t>(kc * TK + 4 * (ob.d_end - ob.d_begin), 0x7fffffff);
+    double kc = 0;
+    for (int t = ob.t_begin; t < ob.t_end; ++t) {
+      int k0 = 0;
+      do {
+        kc += (std::min(TK, terms[t].K - k0) + 3) / 4 * 4;
+        k0 += TK;
+      } while (k0 < terms[t].K);
+    }
     // 64x64 tiles carry twice the arithmetic intensity of 32x32 ones: prefer
     // them unless their padding costs more than the threshold factor
     bool big = tile_mode == 2 || (tile_mode == 0 && tile_use(ob.M, ob.N, 64) >= thr * tile_use(ob.M, ob.N, 32));
     int tt = big ? 64 : 32;
     for (int m0 = 0; m0 < ob.M; m0 += tt)
-      for (int n0 = 0; n0 < ob.N; n0 += tt) (big ? t64 : t32).push_back(DevTile{o, m0, n0, cost});
+      for (int n0 = 0; n0 < ob.N; n0 += tt) {
+        double am = (double)((std::min(tt, ob.M - m0) + 15) / 16 * 16);
+        double an = (double)((std::min(tt, ob.N - n0) + 15) / 16 * 16);
+        Item it;
+        it.t = DevTile{o, m0, n0, -1, ob.t_begin, 0, ob.t_end, 0};
+        it.kc = kc;
+        it.cost = am * an / 4096.0 * (kc + 4.0 * (ob.d_end - ob.d_begin)) + 1.0;
+        it.big = big;
+        total += it.cost;
+        items.push_back(it);
+      }
   }
-  auto bycost = [](const DevTile& a, const DevTile& b) { return a.cost > b.cost; };
-  std::stable_sort(t64.begin(), t64.end(), bycost);
-  std::stable_sort(t32.begin(), t32.end(), bycost);
-  n64 = (int)t64.size();
-  tiles = t64;
-  tiles.insert(tiles.end(), t32.begin(), t32.end());
+  // chunk cap: alpha x mean work per slot, at least kmin deep; raised until
+  // the partial slots fit
+  double cap = alpha > 0.0 ? std::max(alpha * total / 1024.0, 1.0) : 1e300;
+  std::vector<int> nparts(items.size(), 1);
+  for (int tries = 0; tries < 32; ++tries) {
+    int ns = 0;
+    for (size_t i = 0; i < items.size(); ++i) {
+      const Item& it = items[i];
+      int n = (int)std::ceil(it.cost / cap);
+      n = std::max(1, std::min(n, (int)(it.kc / kmin)));
+      nparts[i] = n;
+      if (n > 1) ns += n;
+    }
+    if (ns <= max_slots) break;
+    cap *= 1.5;
+  }
+  std::vector<Item> out64, out32;
+  for (size_t i = 0; i < items.size(); ++i) {
+    const Item& it = items[i];
+    auto& dst = it.big ? out64 : out32;
+    const int n = nparts[i];
+    if (n == 1) {
+      dst.push_back(it);
+      continue;
+    }
+    const DevOut& ob = outs[it.t.out];
+    DevRed rd{it.t.out, it.t.m0, it.t.n0, nslots, n, {0, 0, 0}};
+    reds.push_back(rd);
+    // walk the chain's steps, cutting after the step that reaches q/n of its depth
+    double acc = 0.0;
+    int q = 0;
+    Item piece = it;
+    piece.t.t0 = ob.t_begin;
+    piece.t.k0 = 0;
+    double piece_kc = 0.0;
+    for (int t = ob.t_begin; t < ob.t_end; ++t) {
+      int k0 = 0;
+      do {
+        double d = (std::min(TK, terms[t].K - k0) + 3) / 4 * 4;
+        acc += d;
+        piece_kc += d;
+        int tn = t, kn = k0 + TK;
+        if (kn >= terms[t].K) { kn = 0; ++tn; }
+        const bool last = tn == ob.t_end;
+        if (q < n - 1 && !last && acc >= it.kc * (q + 1) / n) {
+          piece.t.t1 = tn;
+          piece.t.k1 = kn;
+          piece.t.slot = nslots + q;
+          piece.cost = it.cost * piece_kc / std::max(it.kc, 1.0);
+          dst.push_back(piece);
+          ++q;
+          piece.t.t0 = tn;
+          piece.t.k0 = kn;
+          piece_kc = 0.0;
+        }
+        k0 += TK;
+      } while (k0 < terms[t].K);
+    }
+    piece.t.t1 = ob.t_end;
+    piece.t.k1 = 0;
+    piece.t.slot = nslots + q;
+    piece.cost = it.cost * piece_kc / std::max(it.kc, 1.0);
+    dst.push_back(piece);
+    reds.back().nparts = q + 1;
+    nslots += q + 1;
+  }
+  auto bycost = [](const Item& a, const Item& b) { return a.cost > b.cost; };
+  std::stable_sort(out64.begin(), out64.end(), bycost);
+  std::stable_sort(out32.begin(), out32.end(), bycost);
+  n64 = (int)out64.size();
+  for (const Item& it : out64) tiles.push_back(it.t);
+  for (const Item& it : out32) tiles.push_back(it.t);
 }
 
 DeviceBuffer::~DeviceBuffer() {
@@ -307,8 +504,8 @@ hipError_t DeviceBuffer::ensure(size_t n) {
 
 int upload(tdvp_ctx* ctx, Program& p) {
   size_t bt = p.terms.size() * sizeof(DevTerm), bo = p.outs.size() * sizeof(DevOut),
-         bl = p.tiles.size() * sizeof(DevTile);
-  size_t total = bt + bo + bl + 3 * 256;
+         bl = p.tiles.size() * sizeof(DevTile), br = p.reds.size() * sizeof(DevRed);
+  size_t total = bt + bo + bl + br + 4 * 256;
   if (p.d_mem) {
     if (p.pool) p.pool->free[p.cls].push_back(p.d_mem);
     else TDVP_HIP(ctx, hipFree(p.d_mem));
@@ -330,6 +527,7 @@ int upload(tdvp_ctx* ctx, Program& p) {
   p.d_terms = (DevTerm*)base;
   p.d_outs = (DevOut*)(base + align(bt));
   p.d_tiles = (DevTile*)(base + align(bt) + align(bo));
+  p.d_reds = (DevRed*)(base + align(bt) + align(bo) + align(bl));
   // stage through pinned memory; wait for the previous upload before reuse
   if (ctx->upload_done) TDVP_HIP(ctx, hipEventSynchronize(ctx->upload_done));
   if (ctx->pinned_bytes < total) {
@@ -343,7 +541,9 @@ int upload(tdvp_ctx* ctx, Program& p) {
   if (bt) std::memcpy(h, p.terms.data(), bt);
   if (bo) std::memcpy(h + align(bt), p.outs.data(), bo);
   if (bl) std::memcpy(h + align(bt) + align(bo), p.tiles.data(), bl);
-  TDVP_HIP(ctx, hipMemcpyAsync(p.d_mem, h, align(bt) + align(bo) + bl, hipMemcpyHostToDevice, ctx->stream));
+  if (br) std::memcpy(h + align(bt) + align(bo) + align(bl), p.reds.data(), br);
+  TDVP_HIP(ctx, hipMemcpyAsync(p.d_mem, h, align(bt) + align(bo) + align(bl) + br, hipMemcpyHostToDevice,
+                               ctx->stream));
   if (!ctx->upload_done) TDVP_HIP(ctx, hipEventCreateWithFlags(&ctx->upload_done, hipEventDisableTiming));
   TDVP_HIP(ctx, hipEventRecord(ctx->upload_done, ctx->stream));
   return TDVP_OK;
@@ -366,24 +566,25 @@ void cache_put(tdvp_ctx* ctx, uint64_t key, std::shared_ptr<Program> p) {
 
 int launch_gemm(tdvp_ctx* ctx, const Program& p, const Bufs& bufs, double* C, int precision) {
   if (p.tiles.empty()) return TDVP_OK;
+  double2* part = nullptr;
+  if (p.nslots > 0) {
+    TDVP_HIP(ctx, ctx->ws_part.ensure(sizeof(double2) * (size_t)p.nslots * kSlotDim * kSlotDim));
+    part = (double2*)ctx->ws_part.p;
+  }
   const int n32 = (int)p.tiles.size() - p.n64;
   const DevTile* t32 = p.d_tiles + p.n64;
+  const bool heff = p.role == 1;
   if (p.n64 > 0) {
-    if (precision == TDVP_FP32)
-      hipLaunchKernelGGL((gemm_kernel<float, 2, 2>), dim3(p.n64), dim3(256), 0, ctx->stream, bufs, C, p.d_tiles,
-                         p.d_outs, p.d_terms);
-    else
-      hipLaunchKernelGGL((gemm_kernel<double, 2, 2>), dim3(p.n64), dim3(256), 0, ctx->stream, bufs, C, p.d_tiles,
-                         p.d_outs, p.d_terms);
+    if (precision == TDVP_FP32) launch_one<float, 2, 2>(ctx, heff, p.n64, bufs, C, part, p.d_tiles, p);
+    else launch_one<double, 2, 2>(ctx, heff, p.n64, bufs, C, part, p.d_tiles, p);
   }
   if (n32 > 0) {
-    if (precision == TDVP_FP32)
-      hipLaunchKernelGGL((gemm_kernel<float, 1, 1>), dim3(n32), dim3(64), 0, ctx->stream, bufs, C, t32, p.d_outs,
-                         p.d_terms);
-    else
-      hipLaunchKernelGGL((gemm_kernel<double, 1, 1>), dim3(n32), dim3(64), 0, ctx->stream, bufs, C, t32, p.d_outs,
-                         p.d_terms);
+    if (precision == TDVP_FP32) launch_one<float, 1, 1>(ctx, heff, n32, bufs, C, part, t32, p);
+    else launch_one<double, 1, 1>(ctx, heff, n32, bufs, C, part, t32, p);
   }
+  if (!p.reds.empty())
+    hipLaunchKernelGGL(reduce_parts, dim3((unsigned)p.reds.size()), dim3(256), 0, ctx->stream, bufs, C,
+                       (const double2*)part, p.d_reds, p.d_outs, p.d_terms);
   TDVP_HIP(ctx, hipGetLastError());
   return TDVP_OK;
 }

@@ -196,6 +196,11 @@ int run_program(tdvp_ctx* ctx, Program& p, const Bufs& b, double* C) {
 int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const tdvp_trunc& tr, double& disc,
           double& t_svd) {
   double t0 = now();
+  // phase timestamps (verbose >= 2 only: each one synchronises the stream)
+  double ph[4] = {t0, t0, t0, t0};
+  auto mark = [&](int k) {
+    if (ctx->verbose >= 2 && hipStreamSynchronize(ctx->stream) == hipSuccess) ph[k] = now();
+  };
   const Bond &l = m->bonds[i - 1], &r = m->bonds[i + 1];
   std::map<std::pair<int, int>, Sector> secs;
   for (int o = 0; o < th.n(); ++o) {
@@ -257,8 +262,7 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
   double* Mbase = (double*)ctx->ws_svd.p;
   double* Gbase = Mbase + 2 * mtot;
   double* Dbase = Gbase + 2 * gtot;
-  double* Ework = Dbase + dtot;
-  rocblas_int* dinfo = (rocblas_int*)(Ework + dtot + 8);
+  rocblas_int* dinfo = (rocblas_int*)(Dbase + dtot + 8);
   int rc;
   Bufs b{};
   // gather Theta blocks into the sector matrices (zeros elsewhere)
@@ -320,6 +324,7 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
     }
   }
   if ((rc = ensure_solver(ctx))) return rc;
+  mark(0);
   auto gram_program = [&](const std::vector<Sector*>& which, Program& g) {
     for (Sector* sp : which) {
       Sector& s = *sp;
@@ -347,12 +352,14 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
       int64_t n = bk.first;
       Sector* s0 = bk.second.front();
       for (Sector* sp : bk.second) sp->col0 = n - sp->g;
-      rocblas_status st = rocsolver_zheevd_strided_batched(
+      // Jacobi-based divide and conquer: the plain divide-and-conquer solver
+      // returns non-finite eigenvectors when the tridiagonal form splits
+      // (block-diagonal or zero-padded matrices), which sector Gram matrices do
+      rocblas_status st = rocsolver_zheevdj_strided_batched(
           (rocblas_handle)ctx->solver, rocblas_evect_original, rocblas_fill_upper, (rocblas_int)n,
           (rocblas_double_complex*)(Gbase + 2 * s0->goff), (rocblas_int)n, (rocblas_stride)(n * n),
-          Dbase + s0->doff, (rocblas_stride)n, Ework + s0->doff, (rocblas_stride)n, dinfo + mi,
-          (rocblas_int)bk.second.size());
-      if (st != rocblas_status_success) return set_error(ctx, TDVP_E_HIP, "rocsolver_zheevd_strided_batched failed");
+          Dbase + s0->doff, (rocblas_stride)n, dinfo + mi, (rocblas_int)bk.second.size());
+      if (st != rocblas_status_success) return set_error(ctx, TDVP_E_HIP, "rocsolver_zheevdj_strided_batched failed");
       mi += (int64_t)bk.second.size();
     }
     // verify every bucket's eigenvectors; redo failing buckets unpadded, one matrix at a time
@@ -391,13 +398,14 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
       if ((rc = run_program(ctx, g, b, Gbase))) return rc;
       for (Sector* sp : redo) {
         sp->col0 = 0;
-        rocblas_status st = rocsolver_zheevd((rocblas_handle)ctx->solver, rocblas_evect_original, rocblas_fill_upper,
-                                             (rocblas_int)sp->g, (rocblas_double_complex*)(Gbase + 2 * sp->goff),
-                                             (rocblas_int)sp->gn, Dbase + sp->doff, Ework + sp->doff, dinfo);
-        if (st != rocblas_status_success) return set_error(ctx, TDVP_E_HIP, "rocsolver_zheevd failed");
+        rocblas_status st = rocsolver_zheevdj((rocblas_handle)ctx->solver, rocblas_evect_original, rocblas_fill_upper,
+                                              (rocblas_int)sp->g, (rocblas_double_complex*)(Gbase + 2 * sp->goff),
+                                              (rocblas_int)sp->gn, Dbase + sp->doff, dinfo);
+        if (st != rocblas_status_success) return set_error(ctx, TDVP_E_HIP, "rocsolver_zheevdj failed");
       }
     }
   }
+  mark(1);
   std::vector<double> ev(std::max<int64_t>(dtot, 1));
   std::vector<rocblas_int> hinfo(std::max<int64_t>(nmat, 1));
   TDVP_HIP(ctx, hipMemcpyAsync(ev.data(), Dbase, sizeof(double) * dtot, hipMemcpyDeviceToHost, ctx->stream));
@@ -525,6 +533,7 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
       if (st != rocblas_status_success) return set_error(ctx, TDVP_E_HIP, "rocsolver QR failed");
     }
   }
+  mark(2);
   // new bond i
   Bond nb;
   for (auto& kv : secs)
@@ -614,6 +623,9 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
   if ((rc = run_program(ctx, pb, b, (double*)TB.blk.data))) return rc;
   TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
   t_svd += now() - t0;
+  if (ctx->verbose >= 2)
+    std::fprintf(stderr, "[tdvp]   split bond %d: gram %.4f eig %.4f iso %.4f out %.4f s (%zu sectors, %lld matrices)\n",
+                 i, ph[0] - t0, ph[1] - ph[0], ph[2] - ph[1], now() - ph[2], secs.size(), (long long)nmat);
   return TDVP_OK;
 }
 
