@@ -266,6 +266,17 @@ int tdvp_mps_site_read(tdvp_ctx* ctx, const tdvp_mps* mps, int32_t k, void* host
 int tdvp_sweep(tdvp_ctx* ctx, tdvp_mps* mps, double dt, const tdvp_trunc* trunc,
                tdvp_sweep_info* info);
 
+/* Site-resolved observables of the quench (the local densities the paper
+ * follows in time, main text results section): for every site k in 1..L,
+ * sz[k-1] = <S^z_k> = (<n_k,up> - <n_k,down>)/2 and docc[k-1] =
+ * <n_k,up n_k,down>, normalised by the state norm; *norm2 (optional) receives
+ * <psi|psi>.  <n_k> = 1 exactly in the pseudospin-singlet sector, so
+ * <n_k,up> = 1/2 + sz.  The MPS must have its centre on site 1 and sites
+ * 2..L right-canonical: the state after tdvp_sweep or tdvp_mps_create.
+ * sz and docc are host arrays of L doubles.  Synchronises the stream.
+ * Errors: INVALID (null or foreign MPS), NONFINITE (norm not positive). */
+int tdvp_mps_measure(tdvp_ctx* ctx, const tdvp_mps* mps, double* sz, double* docc, double* norm2);
+
 #ifdef __cplusplus
 }
 #endif

@@ -95,6 +95,7 @@ def _load():
         "tdvp_mps_site_layout": [P, I32, P, P, P, P],
         "tdvp_mps_site_read": [P, P, I32, P],
         "tdvp_sweep": [P, P, D, P, P],
+        "tdvp_mps_measure": [P, P, P, P, P],
     }
     for name, args in sig.items():
         if not hasattr(lib, name):
@@ -338,3 +339,11 @@ class MPS:
         info = _SweepInfo()
         _check(lib.tdvp_sweep(self.ctx.h, self.h, float(dt), C.byref(tr), C.byref(info)), self.ctx.h)
         return {f: getattr(info, f) for f, _ in _SweepInfo._fields_}
+
+    def measure(self):
+        """Site-resolved <S^z_k> and <n_k,up n_k,down> (arrays of L) and the norm^2."""
+        sz = np.zeros(self.model.L)
+        docc = np.zeros(self.model.L)
+        n2 = C.c_double()
+        _check(lib.tdvp_mps_measure(self.ctx.h, self.h, _ptr(sz), _ptr(docc), C.byref(n2)), self.ctx.h)
+        return sz, docc, n2.value

@@ -296,6 +296,13 @@ void tdvp_ctx_destroy(tdvp_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   ctx->cache.clear();
   if (ctx->solver) (void)rocblas_destroy_handle((rocblas_handle)ctx->solver);
+  for (int k = 0; k < tdvp_ctx::kSide; ++k) {
+    if (ctx->side[k]) (void)hipStreamSynchronize(ctx->side[k]);
+    if (ctx->side_solver[k]) (void)rocblas_destroy_handle((rocblas_handle)ctx->side_solver[k]);
+    if (ctx->side[k]) (void)hipStreamDestroy(ctx->side[k]);
+  }
+  for (auto& ev : ctx->side_ev)
+    if (ev) (void)hipEventDestroy(ev);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->host_small) (void)hipHostFree(ctx->host_small);
   if (ctx->upload_done) (void)hipEventDestroy(ctx->upload_done);

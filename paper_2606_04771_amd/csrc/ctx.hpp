@@ -110,6 +110,12 @@ struct tdvp_ctx {
   tdvp::DeviceBuffer ws_scratch, ws_krylov, ws_small, ws_vec, ws_theta, ws_svd;
   tdvp::DeviceBuffer ws_part;   // partial tiles of split K chains
   void* solver = nullptr;       // rocblas handle for the eigensolver (created on first use)
+  // side streams (default priority) with their own solver handles, for
+  // independent eigensolves; joined back to `stream` by events
+  static constexpr int kSide = 4;
+  hipStream_t side[kSide] = {};
+  void* side_solver[kSide] = {};
+  hipEvent_t side_ev[kSide + 1] = {};
   void* host_small = nullptr;   // pinned host mirror of ws_small
   std::shared_ptr<tdvp::ProgPool> pool = std::make_shared<tdvp::ProgPool>();
   int verbose = 0;
@@ -147,6 +153,10 @@ int vec_combo(tdvp_ctx* ctx, double* out, const double* V, int64_t stride, int n
 int vec_norm2(tdvp_ctx* ctx, const double* x, int64_t n, double* d_out);
 int vec_check_finite(tdvp_ctx* ctx, const double* x, int64_t n, int* d_flag);
 int vec_pad_matrix(tdvp_ctx* ctx, double* A, int64_t n, int64_t g, double v, double* d_scale);
+// d_out[2b], d_out[2b+1] = re, im of sum conj(x) y over block b, whose element
+// range is [d_meta[2b], d_meta[2b] + d_meta[2b+1]) (device metadata)
+int vec_block_dots(tdvp_ctx* ctx, const double* x, const double* y, const int64_t* d_meta, int nblocks,
+                   double* d_out);
 int vec_scale_cols_rsqrt(tdvp_ctx* ctx, double* A, int64_t ld, int64_t rows, int64_t cols, const double* lam);
 
 }  // namespace tdvp

@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <cstdlib>
 #include <cstring>
 
@@ -355,6 +356,56 @@ double tile_threshold() {
   return v;
 }
 
+// Workgroups go to the eight XCDs (each with its own L2) in round-robin order
+// of their index.  Items are grouped by output block (its tiles share operand
+// rows and columns), groups are spread over the XCDs by decreasing cost, and
+// the per-XCD queues (each still by decreasing cost) are interleaved so that
+// index i runs on XCD i mod 8.  TDVP_XCD=0 keeps the plain cost order.
+constexpr int kXcds = 8;
+
+template <typename Item>
+static std::vector<Item> xcd_order(const std::vector<Item>& items) {
+  static const bool on = [] {
+    const char* e = std::getenv("TDVP_XCD");
+    return !(e && std::atoi(e) == 0);
+  }();
+  if (!on || items.size() < 2 * kXcds) return items;
+  std::map<int, double> gcost;
+  for (const Item& it : items) gcost[it.t.out] += it.cost;
+  std::vector<std::pair<double, int>> groups;
+  for (auto& kv : gcost) groups.push_back({kv.second, kv.first});
+  std::stable_sort(groups.begin(), groups.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+    return a.first > b.first;
+  });
+  double load[kXcds] = {};
+  std::map<int, int> home;
+  for (auto& g : groups) {
+    int x = (int)(std::min_element(load, load + kXcds) - load);
+    home[g.second] = x;
+    load[x] += g.first;
+  }
+  std::vector<Item> q[kXcds];
+  for (const Item& it : items) q[home[it.t.out]].push_back(it);   // stays cost-ordered
+  std::vector<Item> out;
+  out.reserve(items.size());
+  size_t pos[kXcds] = {};
+  while (out.size() < items.size()) {
+    for (int x = 0; x < kXcds && out.size() < items.size(); ++x) {
+      int src = x;
+      if (pos[src] >= q[src].size()) {   // empty queue: borrow from the fullest one
+        size_t best = 0;
+        for (int y = 0; y < kXcds; ++y)
+          if (q[y].size() - pos[y] > best) {
+            best = q[y].size() - pos[y];
+            src = y;
+          }
+      }
+      out.push_back(q[src][pos[src]++]);
+    }
+  }
+  return out;
+}
+
 static double env_double(const char* name, double dflt) {
   const char* e = std::getenv(name);
   return e ? std::atof(e) : dflt;
@@ -480,8 +531,8 @@ void Program::finalize() {
   std::stable_sort(out64.begin(), out64.end(), bycost);
   std::stable_sort(out32.begin(), out32.end(), bycost);
   n64 = (int)out64.size();
-  for (const Item& it : out64) tiles.push_back(it.t);
-  for (const Item& it : out32) tiles.push_back(it.t);
+  for (const Item& it : xcd_order(out64)) tiles.push_back(it.t);
+  for (const Item& it : xcd_order(out32)) tiles.push_back(it.t);
 }
 
 DeviceBuffer::~DeviceBuffer() {

@@ -161,6 +161,16 @@ int ensure_solver(tdvp_ctx* ctx) {
   if (rocblas_set_stream(h, ctx->stream) != rocblas_status_success)
     return set_error(ctx, TDVP_E_HIP, "rocblas_set_stream failed");
   ctx->solver = h;
+  for (int k = 0; k < tdvp_ctx::kSide; ++k) {
+    TDVP_HIP(ctx, hipStreamCreateWithFlags(&ctx->side[k], hipStreamNonBlocking));
+    rocblas_handle hs;
+    if (rocblas_create_handle(&hs) != rocblas_status_success)
+      return set_error(ctx, TDVP_E_HIP, "rocblas_create_handle failed");
+    ctx->side_solver[k] = hs;
+    if (rocblas_set_stream(hs, ctx->side[k]) != rocblas_status_success)
+      return set_error(ctx, TDVP_E_HIP, "rocblas_set_stream failed");
+  }
+  for (auto& ev : ctx->side_ev) TDVP_HIP(ctx, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
   return TDVP_OK;
 }
 
@@ -345,22 +355,39 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
     }
   };
   {
-    // one strided-batched eigensolve per size bucket
+    // one strided-batched eigensolve per size bucket, the buckets spread over
+    // the side streams (largest first) and joined back before verification
     int64_t mi = 0;
+    TDVP_HIP(ctx, hipEventRecord(ctx->side_ev[tdvp_ctx::kSide], ctx->stream));
+    for (int k = 0; k < tdvp_ctx::kSide; ++k)
+      TDVP_HIP(ctx, hipStreamWaitEvent(ctx->side[k], ctx->side_ev[tdvp_ctx::kSide], 0));
     std::vector<std::pair<int64_t, std::vector<Sector*>*>> order;
+    for (auto& bk : buckets) order.push_back({bk.first, &bk.second});
+    std::vector<int64_t> minfo;
     for (auto& bk : buckets) {
-      int64_t n = bk.first;
-      Sector* s0 = bk.second.front();
-      for (Sector* sp : bk.second) sp->col0 = n - sp->g;
+      minfo.push_back(mi);
+      mi += (int64_t)bk.second.size();
+    }
+    std::vector<double> sload(tdvp_ctx::kSide, 0.0);
+    for (int ob = (int)order.size() - 1; ob >= 0; --ob) {
+      int64_t n = order[ob].first;
+      auto& secv = *order[ob].second;
+      Sector* s0 = secv.front();
+      for (Sector* sp : secv) sp->col0 = n - sp->g;
+      int k = (int)(std::min_element(sload.begin(), sload.end()) - sload.begin());
+      sload[k] += (double)secv.size() * (double)n * n * n;
       // Jacobi-based divide and conquer: the plain divide-and-conquer solver
       // returns non-finite eigenvectors when the tridiagonal form splits
       // (block-diagonal or zero-padded matrices), which sector Gram matrices do
       rocblas_status st = rocsolver_zheevdj_strided_batched(
-          (rocblas_handle)ctx->solver, rocblas_evect_original, rocblas_fill_upper, (rocblas_int)n,
+          (rocblas_handle)ctx->side_solver[k], rocblas_evect_original, rocblas_fill_upper, (rocblas_int)n,
           (rocblas_double_complex*)(Gbase + 2 * s0->goff), (rocblas_int)n, (rocblas_stride)(n * n),
-          Dbase + s0->doff, (rocblas_stride)n, dinfo + mi, (rocblas_int)bk.second.size());
+          Dbase + s0->doff, (rocblas_stride)n, dinfo + minfo[ob], (rocblas_int)secv.size());
       if (st != rocblas_status_success) return set_error(ctx, TDVP_E_HIP, "rocsolver_zheevdj_strided_batched failed");
-      mi += (int64_t)bk.second.size();
+    }
+    for (int k = 0; k < tdvp_ctx::kSide; ++k) {
+      TDVP_HIP(ctx, hipEventRecord(ctx->side_ev[k], ctx->side[k]));
+      TDVP_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->side_ev[k], 0));
     }
     // verify every bucket's eigenvectors; redo failing buckets unpadded, one matrix at a time
     double* dchk = (double*)ctx->ws_small.p + 2048;
@@ -964,3 +991,138 @@ int tdvp_sweep(tdvp_ctx* ctx, tdvp_mps* m, double dt, const tdvp_trunc* tr, tdvp
 }
 
 }  // extern "C"
+
+// Local observables of the state C_1 B_2 ... B_L (centre on site 1, the rest
+// right-canonical).  The overlap environment N_k[b] of bond k (one matrix per
+// sector, the full-state one being N_k[b] (x) 1) obeys
+//   N_k[b] = sum_{a,s} (2j_a+1)/(2j_b+1) T[a,s,b]^dag N_{k-1}[a] T[a,s,b]
+// for both the centre and the B tensors (the centre's left bond is the
+// vacuum), and the weight of local multiplet s on site k is
+//   W_s(k) = sum_{a,b} (2j_a+1) tr(T[a,s,b]^dag N_{k-1}[a] T[a,s,b]).
+// S^z is +1/2 on |up>, -1/2 on |down>, 0 on the doublet; in a pseudospin
+// singlet the doublet weight splits evenly between |up,down> and |0>.
+int tdvp_mps_measure(tdvp_ctx* ctx, const tdvp_mps* m, double* sz, double* docc, double* norm2) {
+  if (!ctx || !m || !sz || !docc) return set_error(ctx, TDVP_E_INVALID, "null argument");
+  return guarded(ctx, [&]() -> int {
+    if (m->ctx != ctx) return set_error(ctx, TDVP_E_INVALID, "MPS belongs to another context");
+    TDVP_HIP(ctx, hipSetDevice(ctx->device));
+    const int L = m->L;
+    int rc;
+    // sector-diagonal layout of N on bond k
+    auto nlayout = [](const Bond& b, Blocks& nb) {
+      nb = Blocks();
+      nb.keylen = 1;
+      int64_t o = 0;
+      for (int i = 0; i < b.size(); ++i) {
+        int key = i;
+        nb.push(&key, o, b.d[i], b.d[i]);
+        o += b.d[i] * b.d[i];
+      }
+      nb.size = o;
+    };
+    int64_t nmax = 1, tmax = 1, bmax = 1;
+    for (int k = 0; k <= L; ++k) {
+      int64_t s = 0;
+      for (int i = 0; i < m->bonds[k].size(); ++i) s += m->bonds[k].d[i] * m->bonds[k].d[i];
+      nmax = std::max(nmax, s);
+    }
+    for (int k = 1; k <= L; ++k) {
+      tmax = std::max(tmax, m->site[k - 1]->blk.size);
+      bmax = std::max<int64_t>(bmax, m->site[k - 1]->blk.n());
+    }
+    DeviceBuffer nbuf[2], t1, meta, part;
+    TDVP_HIP(ctx, nbuf[0].ensure(sizeof(double) * 2 * nmax));
+    TDVP_HIP(ctx, nbuf[1].ensure(sizeof(double) * 2 * nmax));
+    TDVP_HIP(ctx, t1.ensure(sizeof(double) * 2 * tmax));
+    TDVP_HIP(ctx, meta.ensure(sizeof(int64_t) * 2 * bmax));
+    TDVP_HIP(ctx, part.ensure(sizeof(double) * 2 * bmax));
+    // N_0: identity on every sector of bond 0
+    Blocks Nin, Nout;
+    nlayout(m->bonds[0], Nin);
+    {
+      std::vector<double> h(2 * (size_t)Nin.size, 0.0);
+      for (int i = 0; i < Nin.n(); ++i)
+        for (int64_t r = 0; r < Nin.rows[i]; ++r) h[2 * (Nin.off[i] + r + r * Nin.rows[i])] = 1.0;
+      TDVP_HIP(ctx, hipMemcpyAsync(nbuf[0].p, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice,
+                                   ctx->stream));
+      TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    int cur = 0;
+    double last_norm = 0.0;
+    std::vector<double> hp(2 * bmax);
+    std::vector<int64_t> hm(2 * bmax);
+    for (int k = 1; k <= L; ++k) {
+      const Blocks& T = m->site[k - 1]->blk;
+      const Bond &l = m->bonds[k - 1], &r = m->bonds[k];
+      nlayout(r, Nout);
+      Program p1, p2;
+      for (int o = 0; o < T.n(); ++o) {   // T1 = N[a] . T[a, s, b]
+        const int* key = T.k(o);
+        DevOut ob{};
+        ob.c_off = T.off[o];
+        ob.ldc = ob.M = (int32_t)T.rows[o];
+        ob.N = (int32_t)T.cols[o];
+        ob.t_begin = (int32_t)p1.terms.size();
+        DevTerm d{};
+        d.coef = 1.0;
+        d.a_buf = 0; d.a_off = Nin.off[key[0]]; d.lda = (int32_t)Nin.rows[key[0]];
+        d.b_buf = 1; d.b_off = T.off[o]; d.ldb = (int32_t)T.rows[o];
+        d.K = (int32_t)T.rows[o];
+        p1.terms.push_back(d);
+        ob.t_end = ob.d_begin = ob.d_end = (int32_t)p1.terms.size();
+        p1.outs.push_back(ob);
+      }
+      for (int b = 0; b < r.size(); ++b) {   // N'[b] = sum c T^dag T1
+        DevOut ob{};
+        ob.c_off = Nout.off[b];
+        ob.ldc = ob.M = ob.N = (int32_t)r.d[b];
+        ob.t_begin = (int32_t)p2.terms.size();
+        for (int o = 0; o < T.n(); ++o) {
+          const int* key = T.k(o);
+          if (key[2] != b) continue;
+          DevTerm d{};
+          d.coef = (double)(l.tj[key[0]] + 1) / (double)(r.tj[b] + 1);
+          d.a_buf = 1; d.a_off = T.off[o]; d.lda = (int32_t)T.rows[o]; d.ops = 1 | 2;
+          d.b_buf = 2; d.b_off = T.off[o]; d.ldb = (int32_t)T.rows[o];
+          d.K = (int32_t)T.rows[o];
+          p2.terms.push_back(d);
+        }
+        ob.t_end = ob.d_begin = ob.d_end = (int32_t)p2.terms.size();
+        p2.outs.push_back(ob);
+      }
+      Bufs bf{};
+      bf.p[0] = (const double*)nbuf[cur].p;
+      bf.p[1] = (const double*)T.data;
+      bf.p[2] = (const double*)t1.p;
+      if ((rc = run_program(ctx, p1, bf, (double*)t1.p))) return rc;
+      if ((rc = run_program(ctx, p2, bf, (double*)nbuf[1 - cur].p))) return rc;
+      for (int o = 0; o < T.n(); ++o) {
+        hm[2 * o] = T.off[o];
+        hm[2 * o + 1] = T.rows[o] * T.cols[o];
+      }
+      TDVP_HIP(ctx, hipMemcpyAsync(meta.p, hm.data(), sizeof(int64_t) * 2 * T.n(), hipMemcpyHostToDevice,
+                                   ctx->stream));
+      if ((rc = vec_block_dots(ctx, (const double*)T.data, (const double*)t1.p, (const int64_t*)meta.p, T.n(),
+                               (double*)part.p)))
+        return rc;
+      TDVP_HIP(ctx, hipMemcpyAsync(hp.data(), part.p, sizeof(double) * 2 * T.n(), hipMemcpyDeviceToHost,
+                                   ctx->stream));
+      TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+      double W[3] = {0.0, 0.0, 0.0};
+      for (int o = 0; o < T.n(); ++o) {
+        const int* key = T.k(o);
+        W[key[1]] += (double)(l.tj[key[0]] + 1) * hp[2 * o];
+      }
+      const double nrm = W[0] + W[1] + W[2];
+      if (!std::isfinite(nrm) || nrm <= 0.0)
+        return set_error(ctx, TDVP_E_NONFINITE, "state norm not positive and finite at site " + std::to_string(k));
+      sz[k - 1] = 0.5 * (W[1] - W[2]) / nrm;
+      docc[k - 1] = 0.5 * W[0] / nrm;
+      last_norm = nrm;
+      Nin = Nout;
+      cur = 1 - cur;
+    }
+    if (norm2) *norm2 = last_norm;
+    return TDVP_OK;
+  });
+}

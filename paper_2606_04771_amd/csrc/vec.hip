@@ -156,6 +156,20 @@ __global__ __launch_bounds__(NT) void k_norm_partial(const double2* __restrict__
   if (threadIdx.x == 0) partial[g] = make_double2(s, nonfinite);
 }
 
+// out[b] = sum_i conj(x_i) y_i over block b: elements [meta[2b], meta[2b] + meta[2b+1])
+__global__ __launch_bounds__(NT) void k_block_dots(const double2* __restrict__ x, const double2* __restrict__ y,
+                                                   const int64_t* __restrict__ meta, double2* __restrict__ out) {
+  const int64_t off = meta[2 * blockIdx.x], len = meta[2 * blockIdx.x + 1];
+  double re = 0.0, im = 0.0;
+  for (int64_t i = threadIdx.x; i < len; i += NT) {
+    const double2 a = x[off + i], b = y[off + i];
+    re += a.x * b.x + a.y * b.y;
+    im += a.x * b.y - a.y * b.x;
+  }
+  block_sum2(re, im);
+  if (threadIdx.x == 0) out[blockIdx.x] = make_double2(re, im);
+}
+
 // scale[0] = largest |A_ii| of the leading g x g block (one workgroup)
 __global__ __launch_bounds__(NT) void k_diag_max(const double2* __restrict__ A, int64_t n, int64_t g,
                                                  double* __restrict__ scale) {
@@ -258,6 +272,15 @@ int vec_norm2(tdvp_ctx* ctx, const double* x, int64_t n, double* d_out) {
   double2* partial = (double2*)ctx->ws_vec.p;
   hipLaunchKernelGGL(k_norm_partial, dim3(G), dim3(NT), 0, ctx->stream, (const double2*)x, n, partial);
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(NT), 0, ctx->stream, partial, G, d_out);
+  TDVP_HIP(ctx, hipGetLastError());
+  return TDVP_OK;
+}
+
+int vec_block_dots(tdvp_ctx* ctx, const double* x, const double* y, const int64_t* d_meta, int nblocks,
+                   double* d_out) {
+  if (nblocks <= 0) return TDVP_OK;
+  hipLaunchKernelGGL(k_block_dots, dim3(nblocks), dim3(NT), 0, ctx->stream, (const double2*)x, (const double2*)y,
+                     d_meta, (double2*)d_out);
   TDVP_HIP(ctx, hipGetLastError());
   return TDVP_OK;
 }

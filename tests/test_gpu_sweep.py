@@ -47,6 +47,10 @@ def test_neel_mps_is_the_neel_state(ctx):
         ref = F.neel_state(L)
         assert abs(abs(np.vdot(ref, psi)) - 1) < 1e-14
         assert abs(np.linalg.norm(psi) - 1) < 1e-14
+        sz, docc, n2 = mps.measure()
+        assert np.abs(sz - 0.5 * (-1.0) ** np.arange(L)).max() < 1e-14   # site 1 up
+        assert np.abs(docc).max() < 1e-14
+        assert abs(n2 - 1) < 1e-14
         mps.close()
 
 
@@ -73,6 +77,9 @@ def test_complete_basis_sweeps_follow_exact_evolution_L8(ctx):
             nu0, nd0, dd0 = F.local_expectations(exact[n], L)
             worst_ov = max(worst_ov, abs(1 - ov))
             worst_n = max(worst_n, np.abs(nu - nu0).max(), np.abs(dd - dd0).max())
+            # the library's own observables against the exact ones
+            sz, docc, n2 = mps.measure()
+            worst_n = max(worst_n, np.abs(sz - 0.5 * (nu0 - nd0)).max(), np.abs(docc - dd0).max(), abs(n2 - 1))
             print(f"t={n * dt:.2f} 1-|ov|={1 - ov:.2e} max|dn|={np.abs(nu - nu0).max():.2e} "
                   f"chi={info['max_chi']} krylov={info['krylov_iters']}", flush=True)
     mps.close()
@@ -90,7 +97,11 @@ def test_truncated_sweep_invariants(ctx):
         assert info["max_chi"] <= 24
         psi = mps_state(mps, L)
         assert abs(np.linalg.norm(psi) - 1) < 1e-12
-        nu, nd, _ = F.local_expectations(psi, L)
+        nu, nd, dd = F.local_expectations(psi, L)
         assert np.abs(nu + nd - 1).max() < 1e-10
         assert abs(np.sum(nu - nd)) < 1e-10
+        sz, docc, n2 = mps.measure()
+        assert np.abs(sz - 0.5 * (nu - nd)).max() < 1e-12
+        assert np.abs(docc - dd).max() < 1e-12
+        assert abs(n2 - 1) < 1e-12
     mps.close()
