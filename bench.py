@@ -12,8 +12,16 @@ Table S2.  Two measurements, both with all data resident in HBM:
   on the library's stream; throughput = algorithmic flops (8 per complex
   multiply-add of every nonzero block product) / duration.
 * One step = one full two-site TDVP sweep (dt = 0.05, discarded-weight
-  tolerance 1e-4, chi cap 4096): every bond merged, Krylov-evolved, split by
-  SVD, environments updated, centre evolved back.  Reported as s/sweep.
+  tolerance 1e-4, chi cap 4096) of a seeded random chi = 4096 MPS: every
+  bond merged, Krylov-evolved, split by SVD, environments updated, centre
+  evolved back.  Reported as s/sweep.
+* Mixed precision: the same applies with FP32 block products (error against
+  the FP64 apply), and a second run of the same sweeps from the same initial
+  state with FP32 block products in H_eff and the environment updates (FP64
+  Lanczos, SVD and gauge shifts): its s/sweep, the state error
+  |psi_64 - psi_mixed| after the first and after the last sweep (from MPS
+  overlaps), and the largest deviation of the site-resolved <S^z> and
+  double occupancy.
 
 Prints one JSON line.  ``--gpus N`` with N > 1 is refused: the build is a
 single-GPU one.
@@ -48,6 +56,7 @@ def main():
     ap.add_argument("--heff-reps", type=int, default=20)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison run")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -111,50 +120,90 @@ def main():
     xb = T.Blocks(xk, xo, x_d.data_ptr(), xt)
     yb = T.Blocks(xk, xo, y_d.data_ptr(), xt)
     terms, flops = T.heff_plan(model, site, 2, left, right, Lb, Rb, xb)
-    for _ in range(3):
-        ctx.heff_apply(model, site, 2, left, right, Lb, Rb, xb, yb)
-    ctx.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.heff_reps)]
-    for a, b in evs:
-        a.record(stream)
-        ctx.heff_apply(model, site, 2, left, right, Lb, Rb, xb, yb)
-        b.record(stream)
-    ctx.synchronize()
-    durs = np.array([a.elapsed_time(b) * 1e-3 for a, b in evs])
-    t_apply = float(np.mean(durs))
-    heff_tflops = flops / t_apply / 1e12
-    y_host = y_d.cpu().numpy()
 
-    print(f"bench: H_eff apply {1e3 * t_apply:.3f} ms, {heff_tflops:.2f} TFLOP/s", file=sys.stderr, flush=True)
+    def time_applies(p):
+        ctx.set_precision(p)
+        for _ in range(3):
+            ctx.heff_apply(model, site, 2, left, right, Lb, Rb, xb, yb)
+        ctx.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.heff_reps)]
+        for a, b in evs:
+            a.record(stream)
+            ctx.heff_apply(model, site, 2, left, right, Lb, Rb, xb, yb)
+            b.record(stream)
+        ctx.synchronize()
+        d = np.array([a.elapsed_time(b) * 1e-3 for a, b in evs])
+        return d, y_d.cpu().numpy()
 
-    # ---- full sweeps ------------------------------------------------------------
+    heff_by_prec = {}
+    ys = {}
+    for name, p in (("fp64", T.FP64), ("fp32", T.FP32)):
+        d, ys[name] = time_applies(p)
+        heff_by_prec[name] = {"ms_per_apply": 1e3 * float(np.mean(d)), "ms_min": 1e3 * float(d.min()),
+                              "tflops": flops / float(np.mean(d)) / 1e12}
+        print(f"bench: H_eff apply {name} {heff_by_prec[name]['ms_per_apply']:.3f} ms, "
+              f"{heff_by_prec[name]['tflops']:.2f} TFLOP/s", file=sys.stderr, flush=True)
+    ctx.set_precision(prec)
+    t_apply = heff_by_prec[args.prec]["ms_per_apply"] * 1e-3
+    heff_tflops = heff_by_prec[args.prec]["tflops"]
+    ref64 = ys["fp64"]
+    for name in heff_by_prec:
+        heff_by_prec[name]["rel_err_vs_fp64"] = float(np.linalg.norm(ys[name] - ref64) / np.linalg.norm(ref64))
+
+    # ---- full sweeps: the step at the working precision, and the mixed path
+    # (FP32 block products, FP64 Lanczos / SVD) from the same initial state ----
     sweep = {}
+    mixed = None
     if args.steps > 0 or args.warmup > 0:
         bonds_r, sites_r = synth.random_mps(L, chi, args.seed + 100, center=1)
         Tr = [T.Bond(b) for b in bonds_r]
-        bufs, descs = [], []
-        for k in range(1, L + 1):
-            tk, to, tt, _ = T.center_layout(Tr[k - 1], Tr[k], 1)
-            d = dev(pack(sites_r[k - 1], tk, to, tt))
-            bufs.append(d)
-            descs.append(T.Blocks(tk, to, d.data_ptr(), tt))
-        mps = T.MPS.from_blocks(ctx, model, Tr, descs)
-        del bufs, descs
-        for w in range(args.warmup):
-            info = mps.sweep(0.05, eps_tol=1e-4, chi_cap=chi, krylov_tol=1e-10, krylov_maxdim=40)
-            print(f"bench: warmup sweep {w + 1}/{args.warmup}: {info['seconds']:.2f} s", file=sys.stderr, flush=True)
-        torch.cuda.synchronize()
-        ctx.synchronize()
-        infos = []
-        t0 = time.time()
-        for st in range(args.steps):
-            infos.append(mps.sweep(0.05, eps_tol=1e-4, chi_cap=chi, krylov_tol=1e-10, krylov_maxdim=40))
-            print(f"bench: timed sweep {st + 1}/{args.steps}: {infos[-1]['seconds']:.2f} s", file=sys.stderr,
-                  flush=True)
-        ctx.synchronize()
-        torch.cuda.synchronize()
-        t_sw = time.time() - t0
+
+        def new_mps(c):
+            bufs, descs = [], []
+            for k in range(1, L + 1):
+                tk, to, tt, _ = T.center_layout(Tr[k - 1], Tr[k], 1)
+                d = dev(pack(sites_r[k - 1], tk, to, tt))
+                bufs.append(d)
+                descs.append(T.Blocks(tk, to, d.data_ptr(), tt))
+            m = T.MPS.from_blocks(c, model, Tr, descs)
+            torch.cuda.synchronize()
+            return m
+
+        run = dict(dt=0.05, eps_tol=1e-4, chi_cap=chi, krylov_tol=1e-10, krylov_maxdim=40)
+        mps = new_mps(ctx)
+        other = None
+        if not args.no_mixed:
+            octx = T.Context(0, stream=stream.cuda_stream, precision=T.FP32 if prec == T.FP64 else T.FP64)
+            other = new_mps(octx)
+        infos, oinfos, cmp = [], [], []
+        t_sw = 0.0
+        for st in range(args.warmup + args.steps):
+            timed = st >= args.warmup
+            ctx.synchronize()
+            torch.cuda.synchronize()
+            t0 = time.time()
+            info = mps.sweep(run["dt"], eps_tol=run["eps_tol"], chi_cap=run["chi_cap"],
+                             krylov_tol=run["krylov_tol"], krylov_maxdim=run["krylov_maxdim"])
+            ctx.synchronize()
+            torch.cuda.synchronize()
+            if timed:
+                t_sw += time.time() - t0
+                infos.append(info)
+            print(f"bench: {'timed' if timed else 'warmup'} sweep {st + 1}: {info['seconds']:.2f} s",
+                  file=sys.stderr, flush=True)
+            if other is not None:
+                oinfo = other.sweep(run["dt"], eps_tol=run["eps_tol"], chi_cap=run["chi_cap"],
+                                    krylov_tol=run["krylov_tol"], krylov_maxdim=run["krylov_maxdim"])
+                oinfos.append(oinfo)
+                ov = mps.overlap(other)
+                n1, n2 = mps.overlap(mps).real, other.overlap(other).real
+                sz1, dc1, _ = mps.measure()
+                sz2, dc2, _ = other.measure()
+                cmp.append({"state_err": float(np.sqrt(max(n1 + n2 - 2 * ov.real, 0.0))),
+                            "d_sz": float(np.abs(sz1 - sz2).max()), "d_docc": float(np.abs(dc1 - dc2).max())})
+                print(f"bench: other-precision sweep {st + 1}: {oinfo['seconds']:.2f} s, |psi-phi| "
+                      f"{cmp[-1]['state_err']:.2e}, max|dSz| {cmp[-1]['d_sz']:.2e}", file=sys.stderr, flush=True)
         if args.steps > 0:
             sweep = {
                 "s_per_sweep": t_sw / args.steps,
@@ -166,6 +215,22 @@ def main():
                 "max_chi": int(max(i["max_chi"] for i in infos)),
                 "max_discarded": float(max(i["max_discarded"] for i in infos)),
             }
+        if other is not None:
+            tail = oinfos[args.warmup:] or oinfos
+            mixed = {
+                "precision": "fp32" if prec == T.FP64 else "fp64",
+                "s_per_sweep": float(np.mean([i["seconds"] for i in tail])),
+                "sweep_phase_s": {k: float(np.mean([i[k] for i in tail])) for k in
+                                  ("t_lanczos", "t_svd", "t_env")},
+                "state_err_first_step": cmp[0]["state_err"],
+                "state_err_after_all": cmp[-1]["state_err"],
+                "max_obs_err": max(max(c["d_sz"], c["d_docc"]) for c in cmp),
+                "sweeps_compared": len(cmp),
+                "note": "both runs start from the same seeded random MPS; errors are |psi_64 - psi_mixed| and "
+                        "max over sites of |d<S^z>|, |d<n_up n_dn>| after each sweep",
+            }
+            other.close()
+            octx.close()
         mps.close()
 
     # ---- CPU baseline: the oracle on sampled output blocks ------------------------
@@ -231,13 +296,14 @@ def main():
                                "Table-S2-shaped sectors; H_eff.Theta at sites 30-31 + full two-site TDVP sweep "
                                "(dt=0.05, eps_tol=1e-4, chi cap)",
                    "L": L, "chi": chi, "precision": args.prec},
-        "heff": {"flops_per_apply": flops, "ms_per_apply": 1e3 * t_apply, "ms_min": 1e3 * float(durs.min()),
+        "heff": {"flops_per_apply": flops, "ms_per_apply": 1e3 * t_apply,
                  "blocks": len(xk), "terms": len(terms), "theta_elems": int(xt),
-                 "env_chain_s": t_env_chain},
+                 "env_chain_s": t_env_chain, "by_precision": heff_by_prec},
         "roofline": {"bound": "mfma", "achieved": heff_tflops, "peak": PEAK[args.prec], "unit": "TFLOP/s",
                      "frac": heff_tflops / PEAK[args.prec], "traffic": None,
                      "kernel": "heff_gemm<double, 2, 2>" if prec == T.FP64 else "heff_gemm<float, 2, 2>"},
         "cpu_baseline": cpu,
+        "mixed": mixed,
     }
     line.update(sweep)
     print(json.dumps(line), flush=True)

@@ -277,6 +277,18 @@ int tdvp_sweep(tdvp_ctx* ctx, tdvp_mps* mps, double dt, const tdvp_trunc* trunc,
  * Errors: INVALID (null or foreign MPS), NONFINITE (norm not positive). */
 int tdvp_mps_measure(tdvp_ctx* ctx, const tdvp_mps* mps, double* sz, double* docc, double* norm2);
 
+/* Overlap <bra|ket> of two MPS of the same chain, in any gauge and with any
+ * bond dimensions (sectors present in only one of them contribute nothing):
+ * out[0], out[1] = real and imaginary part.  Used to state the error of a
+ * time step against another run (e.g. reduced against full precision):
+ * |psi - phi|^2 = <psi|psi> + <phi|phi> - 2 Re <phi|psi>.  The two MPS may
+ * belong to different contexts on the device of ctx (e.g. one per
+ * precision); work runs on ctx's stream, so the caller finishes pending work
+ * on the other context's stream first (tdvp_sweep returns synchronised).
+ * Synchronises the stream.  Errors: INVALID (null argument or MPS on another
+ * device), SHAPE (different L). */
+int tdvp_mps_overlap(tdvp_ctx* ctx, const tdvp_mps* bra, const tdvp_mps* ket, double* out);
+
 #ifdef __cplusplus
 }
 #endif

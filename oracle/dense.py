@@ -333,23 +333,54 @@ def complete_right_canonical(psi, L):
     return mps
 
 
-def _svd_split(M, keep_all, eps_tol, chi_cap):
+def _svd_split(M, keep_all, eps_tol, chi_cap, multiplets=False):
+    """SVD of the merged two-site matrix with the truncation of supplementary
+    section S2: singular values are dropped from the smallest while the
+    discarded squared weight stays within eps_tol of the total and while more
+    than chi_cap values remain (at least one is kept); the kept values are
+    renormalised to the original norm.  With ``multiplets`` the values are
+    handled in groups of (numerically) equal ones -- for a state with the
+    pseudospin symmetry these are the 2j+1 copies of one multiplet -- and a
+    group is kept or dropped whole, the cap stopping at the first group that
+    does not fit."""
     U_, S, Vh = np.linalg.svd(M, full_matrices=False)
     if keep_all:
         return U_, S, Vh, 0.0
     w = S ** 2
     tot = w.sum()
-    keep = S.size
-    disc = 0.0
-    while keep > 1 and (disc + w[keep - 1] <= eps_tol * tot or keep > chi_cap):
-        disc += w[keep - 1]
-        keep -= 1
+    if multiplets:
+        tolg = 1e-9 * (S[0] if S.size else 0.0)
+        groups, start = [], 0
+        for i in range(1, S.size + 1):
+            if i == S.size or S[i - 1] - S[i] > tolg:
+                groups.append((start, i))
+                start = i
+        keep_g = len(groups)
+        tail = 0.0
+        while keep_g > 1:
+            a, b = groups[keep_g - 1]
+            if tail + w[a:b].sum() > eps_tol * tot:
+                break
+            tail += w[a:b].sum()
+            keep_g -= 1
+        for g in range(keep_g):
+            if g > 0 and groups[g][1] > chi_cap:
+                keep_g = g
+                break
+        keep = groups[max(keep_g, 1) - 1][1]
+        disc = w[keep:].sum()
+    else:
+        keep = S.size
+        disc = 0.0
+        while keep > 1 and (disc + w[keep - 1] <= eps_tol * tot or keep > chi_cap):
+            disc += w[keep - 1]
+            keep -= 1
     S = S[:keep] / np.sqrt(1.0 - disc / tot) if tot > 0 else S[:keep]
     return U_[:, :keep], S, Vh[:keep], disc / tot if tot > 0 else 0.0
 
 
 def tdvp2_sweep(mps, dt, t, U, tol=1e-12, maxdim=40, keep_all=True, eps_tol=0.0,
-                chi_cap=10 ** 9, use_dense_expm=False):
+                chi_cap=10 ** 9, use_dense_expm=False, multiplets=False):
     """One time step dt of symmetric second-order two-site TDVP.
 
     Input: right-canonical MPS [C_1, B_2, ..., B_L] (centre on site 1).
@@ -376,7 +407,7 @@ def tdvp2_sweep(mps, dt, t, U, tol=1e-12, maxdim=40, keep_all=True, eps_tol=0.0,
         Th = np.tensordot(C, mps[i], axes=([2], [0]))
         Th = expm(lambda x: heff2(Lf[i - 1], R[i + 1], x, i, t, U), Th, -1j * tau)
         a, s1, s2, b = Th.shape
-        Um, S, Vh, d = _svd_split(Th.reshape(a * 4, 4 * b), keep_all, eps_tol, chi_cap)
+        Um, S, Vh, d = _svd_split(Th.reshape(a * 4, 4 * b), keep_all, eps_tol, chi_cap, multiplets)
         disc.append(d)
         mps[i - 1] = Um.reshape(a, 4, -1)
         C = (S[:, None] * Vh).reshape(-1, 4, b)
@@ -387,7 +418,7 @@ def tdvp2_sweep(mps, dt, t, U, tol=1e-12, maxdim=40, keep_all=True, eps_tol=0.0,
         Th = np.tensordot(mps[i - 1], C, axes=([2], [0]))
         Th = expm(lambda x: heff2(Lf[i - 1], R[i + 1], x, i, t, U), Th, -1j * tau)
         a, s1, s2, b = Th.shape
-        Um, S, Vh, d = _svd_split(Th.reshape(a * 4, 4 * b), keep_all, eps_tol, chi_cap)
+        Um, S, Vh, d = _svd_split(Th.reshape(a * 4, 4 * b), keep_all, eps_tol, chi_cap, multiplets)
         disc.append(d)
         mps[i] = Vh.reshape(-1, 4, b)
         C = (Um * S).reshape(a, 4, -1)

@@ -96,6 +96,7 @@ def _load():
         "tdvp_mps_site_read": [P, P, I32, P],
         "tdvp_sweep": [P, P, D, P, P],
         "tdvp_mps_measure": [P, P, P, P, P],
+        "tdvp_mps_overlap": [P, P, P, P],
     }
     for name, args in sig.items():
         if not hasattr(lib, name):
@@ -339,6 +340,12 @@ class MPS:
         info = _SweepInfo()
         _check(lib.tdvp_sweep(self.ctx.h, self.h, float(dt), C.byref(tr), C.byref(info)), self.ctx.h)
         return {f: getattr(info, f) for f, _ in _SweepInfo._fields_}
+
+    def overlap(self, ket):
+        """<self|ket> as a complex number."""
+        out = np.zeros(2)
+        _check(lib.tdvp_mps_overlap(self.ctx.h, self.h, ket.h, _ptr(out)), self.ctx.h)
+        return complex(out[0], out[1])
 
     def measure(self):
         """Site-resolved <S^z_k> and <n_k,up n_k,down> (arrays of L) and the norm^2."""

@@ -1126,3 +1126,145 @@ int tdvp_mps_measure(tdvp_ctx* ctx, const tdvp_mps* m, double* sz, double* docc,
     return TDVP_OK;
   });
 }
+
+// <bra|ket> of two MPS on the same chain (any gauge, bond dimensions may
+// differ): the mixed overlap environment on bond k, one d_bra x d_ket matrix
+// per sector present in both, obeys
+//   N_k[b] = sum_{a,s} (2j_a+1)/(2j_b+1) bra[a,s,b]^dag N_{k-1}[a] ket[a,s,b]
+// (the same recoupling as the norm), and <bra|ket> = N_L on the vacuum.
+int tdvp_mps_overlap(tdvp_ctx* ctx, const tdvp_mps* bra, const tdvp_mps* ket, double* out) {
+  if (!ctx || !bra || !ket || !out) return set_error(ctx, TDVP_E_INVALID, "null argument");
+  return guarded(ctx, [&]() -> int {
+    if (bra->ctx->device != ctx->device || ket->ctx->device != ctx->device)
+      return set_error(ctx, TDVP_E_INVALID, "MPS on another device");
+    if (bra->L != ket->L) return set_error(ctx, TDVP_E_SHAPE, "chains of different length");
+    TDVP_HIP(ctx, hipSetDevice(ctx->device));
+    const int L = ket->L;
+    int rc;
+    // environment layout on bond k: blocks keyed by the ket's sector index
+    struct Env {
+      Blocks blk;
+      std::vector<int> bra_ix;   // bra sector of each block
+    };
+    auto layout = [&](int k, Env& e) {
+      e.blk = Blocks();
+      e.blk.keylen = 1;
+      e.bra_ix.clear();
+      const Bond &bb = bra->bonds[k], &kb = ket->bonds[k];
+      int64_t o = 0;
+      for (int i = 0; i < kb.size(); ++i) {
+        int j = bb.find(kb.q[i], kb.tj[i]);
+        if (j < 0) continue;
+        e.blk.push(&i, o, bb.d[j], kb.d[i]);
+        e.bra_ix.push_back(j);
+        o += bb.d[j] * kb.d[i];
+      }
+      e.blk.size = o;
+    };
+    int64_t nmax = 1, tmax = 1;
+    for (int k = 0; k <= L; ++k) {
+      Env e;
+      layout(k, e);
+      nmax = std::max(nmax, e.blk.size);
+    }
+    for (int k = 1; k <= L; ++k) {
+      const Blocks& T = ket->site[k - 1]->blk;
+      const Bond& lb = bra->bonds[k - 1];
+      int64_t s = 0;
+      for (int o = 0; o < T.n(); ++o) {
+        int j = lb.find(ket->bonds[k - 1].q[T.k(o)[0]], ket->bonds[k - 1].tj[T.k(o)[0]]);
+        if (j >= 0) s += lb.d[j] * T.cols[o];
+      }
+      tmax = std::max(tmax, s);
+    }
+    DeviceBuffer nbuf[2], t1;
+    TDVP_HIP(ctx, nbuf[0].ensure(sizeof(double) * 2 * nmax));
+    TDVP_HIP(ctx, nbuf[1].ensure(sizeof(double) * 2 * nmax));
+    TDVP_HIP(ctx, t1.ensure(sizeof(double) * 2 * tmax));
+    Env Nin, Nout;
+    layout(0, Nin);
+    {
+      std::vector<double> h(2 * (size_t)std::max<int64_t>(Nin.blk.size, 1), 0.0);
+      for (int i = 0; i < Nin.blk.n(); ++i)
+        for (int64_t r = 0; r < std::min(Nin.blk.rows[i], Nin.blk.cols[i]); ++r)
+          h[2 * (Nin.blk.off[i] + r + r * Nin.blk.rows[i])] = 1.0;
+      TDVP_HIP(ctx, hipMemcpyAsync(nbuf[0].p, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice,
+                                   ctx->stream));
+      TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    int cur = 0;
+    for (int k = 1; k <= L; ++k) {
+      const Blocks &K = ket->site[k - 1]->blk, &B = bra->site[k - 1]->blk;
+      const Bond &kl = ket->bonds[k - 1], &kr = ket->bonds[k];
+      const Bond &bl = bra->bonds[k - 1], &br = bra->bonds[k];
+      layout(k, Nout);
+      // stage 1: T1[o] = N[a] . ket[o] for ket blocks whose left sector is common
+      Program p1, p2;
+      std::vector<int64_t> t1off(K.n(), -1);
+      int64_t to = 0;
+      std::map<int, int> nin_of;   // ket sector -> Nin block
+      for (int i = 0; i < Nin.blk.n(); ++i) nin_of[Nin.blk.k(i)[0]] = i;
+      for (int o = 0; o < K.n(); ++o) {
+        const int* key = K.k(o);
+        auto it = nin_of.find(key[0]);
+        if (it == nin_of.end()) continue;
+        const int ni = it->second;
+        t1off[o] = to;
+        DevOut ob{};
+        ob.c_off = to;
+        ob.ldc = ob.M = (int32_t)Nin.blk.rows[ni];
+        ob.N = (int32_t)K.cols[o];
+        ob.t_begin = (int32_t)p1.terms.size();
+        DevTerm d{};
+        d.coef = 1.0;
+        d.a_buf = 0; d.a_off = Nin.blk.off[ni]; d.lda = (int32_t)Nin.blk.rows[ni];
+        d.b_buf = 1; d.b_off = K.off[o]; d.ldb = (int32_t)K.rows[o];
+        d.K = (int32_t)K.rows[o];
+        p1.terms.push_back(d);
+        ob.t_end = ob.d_begin = ob.d_end = (int32_t)p1.terms.size();
+        p1.outs.push_back(ob);
+        to += Nin.blk.rows[ni] * K.cols[o];
+      }
+      // stage 2: Nout[b] = sum c bra[a', s, b']^dag T1[o]
+      for (int i = 0; i < Nout.blk.n(); ++i) {
+        const int kb = Nout.blk.k(i)[0], bb = Nout.bra_ix[i];
+        DevOut ob{};
+        ob.c_off = Nout.blk.off[i];
+        ob.ldc = ob.M = (int32_t)br.d[bb];
+        ob.N = (int32_t)kr.d[kb];
+        ob.t_begin = (int32_t)p2.terms.size();
+        for (int o = 0; o < K.n(); ++o) {
+          const int* key = K.k(o);
+          if (key[2] != kb || t1off[o] < 0) continue;
+          int ba = bl.find(kl.q[key[0]], kl.tj[key[0]]);
+          int bo = B.find3(ba, key[1], bb);
+          if (bo < 0) continue;
+          DevTerm d{};
+          d.coef = (double)(kl.tj[key[0]] + 1) / (double)(kr.tj[kb] + 1);
+          d.a_buf = 2; d.a_off = B.off[bo]; d.lda = (int32_t)B.rows[bo]; d.ops = 1 | 2;
+          d.b_buf = 3; d.b_off = t1off[o]; d.ldb = (int32_t)B.rows[bo];
+          d.K = (int32_t)B.rows[bo];
+          p2.terms.push_back(d);
+        }
+        ob.t_end = ob.d_begin = ob.d_end = (int32_t)p2.terms.size();
+        p2.outs.push_back(ob);
+      }
+      Bufs bf{};
+      bf.p[0] = (const double*)nbuf[cur].p;
+      bf.p[1] = (const double*)K.data;
+      bf.p[2] = (const double*)B.data;
+      bf.p[3] = (const double*)t1.p;
+      if ((rc = run_program(ctx, p1, bf, (double*)t1.p))) return rc;
+      if ((rc = run_program(ctx, p2, bf, (double*)nbuf[1 - cur].p))) return rc;
+      Nin = Nout;
+      cur = 1 - cur;
+    }
+    double h[2] = {0.0, 0.0};
+    if (Nin.blk.n() == 1 && Nin.blk.rows[0] == 1 && Nin.blk.cols[0] == 1)
+      TDVP_HIP(ctx, hipMemcpyAsync(h, nbuf[cur].p, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    out[0] = h[0];
+    out[1] = h[1];
+    return TDVP_OK;
+  });
+}

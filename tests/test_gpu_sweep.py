@@ -105,3 +105,64 @@ def test_truncated_sweep_invariants(ctx):
         assert np.abs(docc - dd).max() < 1e-12
         assert abs(n2 - 1) < 1e-12
     mps.close()
+
+
+def _library_mps(ctx, model, bonds, sites):
+    from tests._harness import pack
+    Tb = [T.Bond(b) for b in bonds]
+    bufs, descs = [], []
+    for k in range(1, len(sites) + 1):
+        tk, to, tt, _ = T.center_layout(Tb[k - 1], Tb[k], 1)
+        d = torch.from_numpy(pack([sites[k - 1][tuple(int(v) for v in kk)] for kk in tk], to, tt)).to("cuda")
+        bufs.append(d)
+        descs.append(T.Blocks(tk, to, d.data_ptr(), tt))
+    mps = T.MPS.from_blocks(ctx, model, Tb, descs)
+    torch.cuda.synchronize()
+    return mps
+
+
+@pytest.mark.parametrize("chi_cap,eps", [(24, 1e-8), (40, 1e-3)])
+def test_truncated_sweeps_match_oracle(ctx, chi_cap, eps):
+    """Truncated two-site TDVP from a seeded random reduced MPS (L = 8): the
+    library and the dense oracle, which truncates whole degenerate groups of
+    singular values by the same rule, give the same state after each sweep."""
+    import synth
+    L, t, U, dt = 8, 1.0, 4.0, 0.05
+    bonds, sites = synth.random_mps(L, 48, 17, center=1)
+    model = T.Model(L, t, U)
+    mps = _library_mps(ctx, model, bonds, sites)
+    ref = [R.expand_site("C" if k == 1 else "B", sites[k - 1], bonds[k - 1], bonds[k], k) for k in range(1, L + 1)]
+    assert abs(np.linalg.norm(D.mps_state(ref)) - 1) < 1e-12
+    for n in range(3):
+        info = mps.sweep(dt, eps_tol=eps, chi_cap=chi_cap, keep_all=False, krylov_tol=1e-14, krylov_maxdim=50)
+        ref, disc = D.tdvp2_sweep(ref, dt, t, U, tol=1e-14, maxdim=50, keep_all=False, eps_tol=eps,
+                                  chi_cap=chi_cap, multiplets=True)
+        psi, phi = mps_state(mps, L), D.mps_state(ref)
+        ov = abs(np.vdot(phi, psi))
+        nu, nd, dd = F.local_expectations(psi, L)
+        mu, md, de = F.local_expectations(phi, L)
+        print(f"sweep {n + 1}: 1-|ov| {1 - ov:.2e} chi {info['max_chi']} max disc {info['max_discarded']:.2e} "
+              f"(oracle {max(disc):.2e})", flush=True)
+        assert info["max_chi"] <= chi_cap
+        assert abs(info["max_discarded"] - max(disc)) < 1e-10
+        assert 1 - ov < 1e-10
+        assert max(np.abs(nu - mu).max(), np.abs(dd - de).max()) < 1e-10
+    mps.close()
+
+
+def test_overlap_matches_dense_states(ctx):
+    """<phi|psi> of two seeded random MPS with different bond dimensions
+    against the vdot of the oracle's expanded state vectors."""
+    import synth
+    L = 8
+    model = T.Model(L, 1.0, 4.0)
+    b1, s1 = synth.random_mps(L, 40, 3, center=1)
+    b2, s2 = synth.random_mps(L, 24, 9, center=1)
+    m1, m2 = _library_mps(ctx, model, b1, s1), _library_mps(ctx, model, b2, s2)
+    psi1 = D.mps_state([R.expand_site("C" if k == 1 else "B", s1[k - 1], b1[k - 1], b1[k], k) for k in range(1, L + 1)])
+    psi2 = D.mps_state([R.expand_site("C" if k == 1 else "B", s2[k - 1], b2[k - 1], b2[k], k) for k in range(1, L + 1)])
+    assert abs(m1.overlap(m2) - np.vdot(psi1, psi2)) < 1e-13
+    assert abs(m2.overlap(m1) - np.vdot(psi2, psi1)) < 1e-13
+    assert abs(m1.overlap(m1) - 1) < 1e-13
+    m1.close()
+    m2.close()

@@ -389,3 +389,71 @@ def test_sector_restricted_block_equals_full_dense():
                 tree = R.expand_theta({key: e}, left, right, site)
                 ref_blk[x, y] = np.vdot(tree, full)
         assert np.abs(blk - ref_blk).max() < 1e-12 * max(1.0, np.abs(ref_blk).max())
+
+
+def _theta_keys(left, right):
+    """Reduced two-site blocks (ia, s1, 2j_x, s2, ib) allowed by the fusion rules."""
+    fuse = lambda a, b: range(abs(a - b), a + b + 1, 2)
+    keys = []
+    for ia, (qa, ja, _) in enumerate(left):
+        for s1, (q1, j1) in enumerate(R.MULTIPLETS):
+            for jx in fuse(ja, j1):
+                for s2, (q2, j2) in enumerate(R.MULTIPLETS):
+                    for ib, (qb, jb, _) in enumerate(right):
+                        if qa + q1 + q2 == qb and jb in fuse(jx, j2):
+                            keys.append((ia, s1, jx, s2, ib))
+    return keys
+
+
+def test_multiplet_truncation_matches_reduced_singular_values():
+    """The dense singular values of an expanded symmetric two-site tensor are
+    the reduced ones of each coupled sector x divided by sqrt(2j_x+1), each
+    (2j_x+1)-fold; the grouped truncation keeps exactly the multiplets that
+    the rule of supplementary section S2 keeps on the reduced values."""
+    import synth
+    left = synth.sector_profile(20, 5, parity=1)
+    right = synth.sector_profile(20, 6, parity=1)
+    keys = _theta_keys(left, right)
+    rng = np.random.default_rng(4)
+    blocks = {k: rng.standard_normal((left[k[0]][2], right[k[4]][2]))
+              + 1j * rng.standard_normal((left[k[0]][2], right[k[4]][2])) for k in keys}
+    Th = R.expand_theta(blocks, left, right, 2)
+    a, b = Th.shape[0], Th.shape[-1]
+    M = Th.reshape(a * 4, 4 * b)
+    # reduced singular values per coupled sector (q_x, 2j_x)
+    red = []
+    sectors = {}
+    for k in keys:
+        sectors.setdefault((left[k[0]][0] + R.MULTIPLETS[k[1]][0], k[2]), []).append(k)
+    for (qx, jx), ks in sectors.items():
+        rows = sorted({(k[0], k[1]) for k in ks})
+        cols = sorted({(k[3], k[4]) for k in ks})
+        ro = np.cumsum([0] + [left[r[0]][2] for r in rows])
+        co = np.cumsum([0] + [right[c[1]][2] for c in cols])
+        Mx = np.zeros((ro[-1], co[-1]), complex)
+        for k in ks:
+            i, j = rows.index((k[0], k[1])), cols.index((k[3], k[4]))
+            Mx[ro[i]:ro[i + 1], co[j]:co[j + 1]] = blocks[k]
+        for sv in np.linalg.svd(Mx, compute_uv=False):
+            red.append((sv / np.sqrt(jx + 1), jx + 1, qx, jx))
+    full = np.sort(np.concatenate([[s] * m for s, m, _, _ in red]))[::-1]
+    dense = np.linalg.svd(M, compute_uv=False)
+    assert np.allclose(dense[:full.size], full, rtol=0, atol=1e-12 * full[0])
+    assert np.all(dense[full.size:] < 1e-12 * full[0])
+    # the rule on whole multiplets, applied to the reduced list
+    red.sort(key=lambda e: (-e[0], e[2], e[3]))
+    W = sum(m * s * s for s, m, _, _ in red)
+    for eps, cap in ((1e-2, 10 ** 9), (0.0, 40), (1e-3, 60), (0.2, 25)):
+        keep, tail = len(red), 0.0
+        while keep > 1 and tail + red[keep - 1][1] * red[keep - 1][0] ** 2 <= eps * W:
+            tail += red[keep - 1][1] * red[keep - 1][0] ** 2
+            keep -= 1
+        n = p = 0
+        while p < keep and (p == 0 or n + red[p][1] <= cap):
+            n += red[p][1]
+            p += 1
+        Um, S, Vh, disc = D._svd_split(M, False, eps, cap, multiplets=True)
+        assert S.size == n
+        kept_w = sum(m * s * s for s, m, _, _ in red[:p])
+        assert abs(disc - (W - kept_w) / W) < 1e-12
+        assert abs(np.sum(S ** 2) - np.sum(dense ** 2)) < 1e-10 * np.sum(dense ** 2)
