@@ -94,17 +94,29 @@ std::shared_ptr<Program> heff_program(tdvp_ctx* ctx, const tdvp_model& m, int si
       const HTerm& h = terms[t];
       DevTerm d{};
       d.coef = h.coef;
+      // block-Hamiltonian terms (channel H, diagonal in the sector) carry the
+      // diagonal shift of their environment, compensated by a direct term
+      auto shifted = [&](const Blocks& E, int bit) {
+        if (E.k(h.env)[1] != 0 || h.in != h.out) return;
+        d.ops |= bit;
+        DevTerm c{};
+        c.a_buf = 0; c.a_off = x.off[h.in]; c.lda = (int32_t)x.rows[h.in];
+        c.K = 0; c.coef = h.coef; c.ops = bit;
+        direct.push_back(c);
+      };
       if (h.kind == 0) {   // E(a', a) . x(a, .)
         d.a_buf = 1; d.a_off = in.Le.off[h.env]; d.lda = (int32_t)in.Le.rows[h.env];
         d.b_buf = 0; d.b_off = x.off[h.in]; d.ldb = (int32_t)x.rows[h.in];
         d.K = (int32_t)x.rows[h.in];
         d.ops = 0;
+        shifted(in.Le, 16);
         p->terms.push_back(d);
       } else if (h.kind == 1) {   // x(., b) . E(b', b)^T
         d.a_buf = 0; d.a_off = x.off[h.in]; d.lda = (int32_t)x.rows[h.in];
         d.b_buf = 2; d.b_off = in.Re.off[h.env]; d.ldb = (int32_t)in.Re.rows[h.env];
         d.K = (int32_t)x.cols[h.in];
         d.ops = 4;
+        shifted(in.Re, 32);
         p->terms.push_back(d);
       } else {
         d.a_buf = 0; d.a_off = x.off[h.in]; d.lda = (int32_t)x.rows[h.in];
@@ -118,6 +130,18 @@ std::shared_ptr<Program> heff_program(tdvp_ctx* ctx, const tdvp_model& m, int si
     ob.d_end = (int32_t)p->terms.size();
     p->outs.push_back(ob);
   }
+  // diagonal blocks of the block-Hamiltonian channels (shifts of reduced-precision launches)
+  const Blocks* E[2] = {&in.Le, &in.Re};
+  const Bond* B[2] = {&in.l, &in.r};
+  for (int s = 0; s < 2; ++s)
+    for (int i = 0; i < E[s]->n(); ++i) {
+      const int* k = E[s]->k(i);
+      if (k[1] != 0 || k[0] != k[2] || E[s]->rows[i] != E[s]->cols[i]) continue;
+      p->shift_meta.push_back(E[s]->off[i]);
+      p->shift_meta.push_back(E[s]->rows[i]);
+      p->shift_meta.push_back(B[s]->tj[k[0]] + 1);
+      p->nshift[s]++;
+    }
   p->finalize();
   rc = upload(ctx, *p);
   if (rc) return nullptr;

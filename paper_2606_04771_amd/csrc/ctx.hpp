@@ -16,7 +16,8 @@ namespace tdvp {
 
 // One term of an output-stationary grouped GEMM:
 //   C[m][n] += coef * sum_k opA(A)[m][k] * opB(B)[k][n]
-// ops bits: 0 transpose A, 1 conjugate A, 2 transpose B, 3 conjugate B.
+// ops bits: 0 transpose A, 1 conjugate A, 2 transpose B, 3 conjugate B,
+// 4/5 diagonal shift of A/B (see Bufs).
 // Element (r, c) of an untransposed operand sits at off + r + c * ld
 // (complex128, column-major).  Direct terms (K = 0): C[m][n] += coef * op(A)[m][n]
 // with ops bit 0 = transpose, bit 1 = conjugate.
@@ -49,8 +50,15 @@ struct DevRed {
 };
 
 constexpr int kMaxBufs = 6;
+// Operand base pointers of a launch, and optionally two diagonal shifts in
+// device memory: a GEMM term with ops bit 4 (bit 5) has shift[0] (shift[1])
+// subtracted from the diagonal of its A (B) operand; a direct term with ops
+// bit 4 (bit 5) has its coefficient multiplied by shift[0] (shift[1]) (by
+// zero when there are no shifts).  Used to take an energy offset out of the
+// environment blocks before reduced-precision products and add it back exactly.
 struct Bufs {
   const double* p[kMaxBufs];
+  const double* shift;
 };
 
 // Device memory for program arrays, recycled by size class.  Every use of a
@@ -71,6 +79,10 @@ struct Program {
   std::vector<DevTile> tiles;
   std::vector<DevRed> reds;
   int nslots = 0;           // partial slots of split tiles
+  // diagonal blocks whose (2j+1)-weighted mean diagonal gives the shifts of
+  // reduced-precision launches: (offset, dimension, weight) for buffer 1, then buffer 2
+  std::vector<int64_t> shift_meta;
+  int nshift[2] = {0, 0};
   double flops = 0.0;
   int64_t aux = 0;          // scratch elements needed by the program's outputs
   int tile_mode = 0;        // 0: per output block the better of 64x64 / 32x32; 1: all 32x32; 2: all 64x64
@@ -81,6 +93,7 @@ struct Program {
   DevOut* d_outs = nullptr;
   DevTile* d_tiles = nullptr;
   DevRed* d_reds = nullptr;
+  int64_t* d_shift_meta = nullptr;
   void* d_mem = nullptr;
   ~Program();
   // tile the outputs, split long K chains, order work items by decreasing cost
@@ -109,6 +122,7 @@ struct tdvp_ctx {
   // workspaces
   tdvp::DeviceBuffer ws_scratch, ws_krylov, ws_small, ws_vec, ws_theta, ws_svd;
   tdvp::DeviceBuffer ws_part;   // partial tiles of split K chains
+  tdvp::DeviceBuffer ws_shift;  // diagonal shifts of reduced-precision launches
   void* solver = nullptr;       // rocblas handle for the eigensolver (created on first use)
   // side streams (default priority) with their own solver handles, for
   // independent eigensolves; joined back to `stream` by events
@@ -157,6 +171,7 @@ int vec_pad_matrix(tdvp_ctx* ctx, double* A, int64_t n, int64_t g, double v, dou
 // range is [d_meta[2b], d_meta[2b] + d_meta[2b+1]) (device metadata)
 int vec_block_dots(tdvp_ctx* ctx, const double* x, const double* y, const int64_t* d_meta, int nblocks,
                    double* d_out);
+
 int vec_scale_cols_rsqrt(tdvp_ctx* ctx, double* A, int64_t ld, int64_t rows, int64_t cols, const double* lam);
 
 }  // namespace tdvp

@@ -69,13 +69,16 @@ struct Stage {
 
 // Load this thread's A and B elements of the K-tile k0 of term tm (coalesced:
 // consecutive threads follow the contiguous dimension of each operand).
-template <int WM, int WN>
+template <int WM, int WN, bool SH>
 __device__ __forceinline__ void load_stage(Stage<WM, WN>& st, const DevTerm& tm, const Bufs& bufs, int m0, int n0,
                                            int M, int N, int k0, int tid) {
   typedef Shape<WM, WN> S;
   const double2* A = reinterpret_cast<const double2*>(bufs.p[tm.a_buf]) + tm.a_off;
   const double2* B = reinterpret_cast<const double2*>(bufs.p[tm.b_buf]) + tm.b_off;
   const bool ta = tm.ops & 1, tb = tm.ops & 4;
+  // diagonal shifts only where this K step meets the diagonal (uniform test)
+  const bool shA = SH && (tm.ops & 16) && m0 < k0 + TK && k0 < m0 + S::TM;
+  const bool shB = SH && (tm.ops & 32) && n0 < k0 + TK && k0 < n0 + S::TN;
 #pragma unroll
   for (int r = 0; r < S::NA; ++r) {
     int e = tid + S::NT * r;
@@ -83,8 +86,10 @@ __device__ __forceinline__ void load_stage(Stage<WM, WN>& st, const DevTerm& tm,
     int k = ta ? (e % TK) : (e / S::TM);
     int gm = m0 + m, gk = k0 + k;
     double2 v = make_double2(0.0, 0.0);
-    if (gm < M && gk < tm.K)
+    if (gm < M && gk < tm.K) {
       v = ta ? A[(int64_t)gk + (int64_t)gm * tm.lda] : A[(int64_t)gm + (int64_t)gk * tm.lda];
+      if (shA && gm == gk) v.x -= bufs.shift[0];
+    }
     st.a[r] = v;
   }
 #pragma unroll
@@ -94,8 +99,10 @@ __device__ __forceinline__ void load_stage(Stage<WM, WN>& st, const DevTerm& tm,
     int k = tb ? (e / S::TN) : (e % TK);
     int gn = n0 + n, gk = k0 + k;
     double2 v = make_double2(0.0, 0.0);
-    if (gn < N && gk < tm.K)
+    if (gn < N && gk < tm.K) {
       v = tb ? B[(int64_t)gn + (int64_t)gk * tm.ldb] : B[(int64_t)gk + (int64_t)gn * tm.ldb];
+      if (shB && gn == gk) v.x -= bufs.shift[1];
+    }
     st.b[r] = v;
   }
 }
@@ -138,7 +145,7 @@ __device__ __forceinline__ bool before(int t, int k0, int t1, int k1) { return t
 // Partial tiles are stored TM_MAX x TN_MAX, column-major, whatever the tile shape.
 constexpr int kSlotDim = 64;
 
-template <typename T, int WM, int WN>
+template <typename T, int WM, int WN, bool SH>
 __device__ __forceinline__ void gemm_body(const Bufs& bufs, double* __restrict__ Cbase,
                                           double2* __restrict__ part, const DevTile* __restrict__ tiles,
                                           const DevOut* __restrict__ outs, const DevTerm* __restrict__ terms) {
@@ -174,7 +181,7 @@ __device__ __forceinline__ void gemm_body(const Bufs& bufs, double* __restrict__
   DevTerm cur;
   if (before(t, k0, tl.t1, tl.k1)) {
     cur = terms[t];
-    load_stage<WM, WN>(st, cur, bufs, tl.m0, tl.n0, ob.M, ob.N, k0, tid);
+    load_stage<WM, WN, SH>(st, cur, bufs, tl.m0, tl.n0, ob.M, ob.N, k0, tid);
   }
   while (before(t, k0, tl.t1, tl.k1)) {
     store_stage<T, WM, WN>(st, cur, As, Bs, tid);
@@ -185,8 +192,8 @@ __device__ __forceinline__ void gemm_body(const Bufs& bufs, double* __restrict__
     const bool more = before(tn, kn, tl.t1, tl.k1);
     DevTerm nxt;
     if (more) {
-      nxt = terms[tn];
-      load_stage<WM, WN>(st, nxt, bufs, tl.m0, tl.n0, ob.M, ob.N, kn, tid);
+      nxt = (tn == t) ? cur : terms[tn];   // the term is reloaded only when it changes
+      load_stage<WM, WN, SH>(st, nxt, bufs, tl.m0, tl.n0, ob.M, ob.N, kn, tid);
     }
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 4) {
@@ -247,15 +254,53 @@ __device__ __forceinline__ void gemm_body(const Bufs& bufs, double* __restrict__
           double vr = accr[i][j][r], vi = acci[i][j][r];
           for (int d = ob.d_begin; d < ob.d_end; ++d) {
             const DevTerm dt = terms[d];
+            if (!SH && (dt.ops & 48)) continue;   // compensation of shifts not applied
             const int64_t idx = (dt.ops & 1) ? (int64_t)col + (int64_t)row * dt.lda
                                              : (int64_t)row + (int64_t)col * dt.lda;
             const double2 x = (reinterpret_cast<const double2*>(bufs.p[dt.a_buf]) + dt.a_off)[idx];
-            vr += dt.coef * x.x;
-            vi += (dt.ops & 2) ? -dt.coef * x.y : dt.coef * x.y;
+            double c = dt.coef;
+            if (SH && (dt.ops & 16)) c *= bufs.shift[0];
+            if (SH && (dt.ops & 32)) c *= bufs.shift[1];
+            vr += c * x.x;
+            vi += (dt.ops & 2) ? -c * x.y : c * x.y;
           }
           C[(int64_t)row + (int64_t)col * ob.ldc] = make_double2(vr, vi);
         }
       }
+}
+
+// Diagonal shifts of a reduced-precision launch: out[s] = sum_b w_b tr(E_b) /
+// sum_b w_b d_b over the listed diagonal blocks of operand buffer 1 + s.
+// First pass: one workgroup per listed block writes w_b tr(E_b) and w_b d_b.
+__global__ __launch_bounds__(256) void env_shift_parts(Bufs bufs, const int64_t* __restrict__ meta, int n0,
+                                                       double2* __restrict__ part) {
+  const int b = blockIdx.x;
+  const double2* E = reinterpret_cast<const double2*>(bufs.p[b < n0 ? 1 : 2]);
+  const int64_t off = meta[3 * b], d = meta[3 * b + 1];
+  const double w = (double)meta[3 * b + 2];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < d; i += 256) s += E[off + i * (d + 1)].x;
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[b] = make_double2(w * red[0], w * (double)d);
+}
+
+// Second pass (one workgroup): the two weighted means.
+__global__ __launch_bounds__(64) void env_shift_final(const double2* __restrict__ part, int n0, int n1,
+                                                      double* __restrict__ out) {
+  if (threadIdx.x >= 2) return;
+  const int s = threadIdx.x, b0 = s ? n0 : 0, b1 = s ? n0 + n1 : n0;
+  double num = 0.0, den = 0.0;
+  for (int b = b0; b < b1; ++b) {
+    num += part[b].x;
+    den += part[b].y;
+  }
+  out[s] = (den > 0.0 && isfinite(num)) ? num / den : 0.0;
 }
 
 // Second phase of split chains: partial slots summed in slot order (fixed,
@@ -280,10 +325,14 @@ __global__ __launch_bounds__(256) void reduce_parts(Bufs bufs, double* __restric
     }
     for (int d = ob.d_begin; d < ob.d_end; ++d) {
       const DevTerm dt = terms[d];
+      if ((dt.ops & 48) && !bufs.shift) continue;
       const int64_t idx = (dt.ops & 1) ? (int64_t)col + (int64_t)row * dt.lda : (int64_t)row + (int64_t)col * dt.lda;
       const double2 x = (reinterpret_cast<const double2*>(bufs.p[dt.a_buf]) + dt.a_off)[idx];
-      vr += dt.coef * x.x;
-      vi += (dt.ops & 2) ? -dt.coef * x.y : dt.coef * x.y;
+      double c = dt.coef;
+      if (dt.ops & 16) c *= bufs.shift[0];
+      if (dt.ops & 32) c *= bufs.shift[1];
+      vr += c * x.x;
+      vi += (dt.ops & 2) ? -c * x.y : c * x.y;
     }
     C[(int64_t)row + (int64_t)col * ob.ldc] = make_double2(vr, vi);
   }
@@ -292,32 +341,38 @@ __global__ __launch_bounds__(256) void reduce_parts(Bufs bufs, double* __restric
 // Two entry kernels with the same body, so that profiles separate the
 // effective-Hamiltonian applies from every other grouped GEMM (environment
 // updates, gathers, Gram matrices, copies).
-template <typename T, int WM, int WN>
+template <typename T, int WM, int WN, bool SH>
 __global__ __launch_bounds__(64 * WM * WN) void heff_gemm(Bufs bufs, double* __restrict__ C,
                                                          double2* __restrict__ part,
                                                          const DevTile* __restrict__ tiles,
                                                          const DevOut* __restrict__ outs,
                                                          const DevTerm* __restrict__ terms) {
-  gemm_body<T, WM, WN>(bufs, C, part, tiles, outs, terms);
+  gemm_body<T, WM, WN, SH>(bufs, C, part, tiles, outs, terms);
 }
-template <typename T, int WM, int WN>
+template <typename T, int WM, int WN, bool SH>
 __global__ __launch_bounds__(64 * WM * WN) void block_gemm(Bufs bufs, double* __restrict__ C,
                                                           double2* __restrict__ part,
                                                           const DevTile* __restrict__ tiles,
                                                           const DevOut* __restrict__ outs,
                                                           const DevTerm* __restrict__ terms) {
-  gemm_body<T, WM, WN>(bufs, C, part, tiles, outs, terms);
+  gemm_body<T, WM, WN, SH>(bufs, C, part, tiles, outs, terms);
 }
 
 template <typename T, int WM, int WN>
 void launch_one(tdvp_ctx* ctx, bool heff, int ntiles, const Bufs& bufs, double* C, double2* part,
                 const DevTile* tiles, const Program& p) {
-  if (heff)
-    hipLaunchKernelGGL((heff_gemm<T, WM, WN>), dim3(ntiles), dim3(64 * WM * WN), 0, ctx->stream, bufs, C, part,
-                       tiles, p.d_outs, p.d_terms);
-  else
-    hipLaunchKernelGGL((block_gemm<T, WM, WN>), dim3(ntiles), dim3(64 * WM * WN), 0, ctx->stream, bufs, C, part,
-                       tiles, p.d_outs, p.d_terms);
+  const dim3 g(ntiles), b(64 * WM * WN);
+  if (bufs.shift) {
+    if (heff)
+      hipLaunchKernelGGL((heff_gemm<T, WM, WN, true>), g, b, 0, ctx->stream, bufs, C, part, tiles, p.d_outs, p.d_terms);
+    else
+      hipLaunchKernelGGL((block_gemm<T, WM, WN, true>), g, b, 0, ctx->stream, bufs, C, part, tiles, p.d_outs, p.d_terms);
+  } else {
+    if (heff)
+      hipLaunchKernelGGL((heff_gemm<T, WM, WN, false>), g, b, 0, ctx->stream, bufs, C, part, tiles, p.d_outs, p.d_terms);
+    else
+      hipLaunchKernelGGL((block_gemm<T, WM, WN, false>), g, b, 0, ctx->stream, bufs, C, part, tiles, p.d_outs, p.d_terms);
+  }
 }
 
 }  // namespace
@@ -555,8 +610,9 @@ hipError_t DeviceBuffer::ensure(size_t n) {
 
 int upload(tdvp_ctx* ctx, Program& p) {
   size_t bt = p.terms.size() * sizeof(DevTerm), bo = p.outs.size() * sizeof(DevOut),
-         bl = p.tiles.size() * sizeof(DevTile), br = p.reds.size() * sizeof(DevRed);
-  size_t total = bt + bo + bl + br + 4 * 256;
+         bl = p.tiles.size() * sizeof(DevTile), br = p.reds.size() * sizeof(DevRed),
+         bs = p.shift_meta.size() * sizeof(int64_t);
+  size_t total = bt + bo + bl + br + bs + 5 * 256;
   if (p.d_mem) {
     if (p.pool) p.pool->free[p.cls].push_back(p.d_mem);
     else TDVP_HIP(ctx, hipFree(p.d_mem));
@@ -579,6 +635,7 @@ int upload(tdvp_ctx* ctx, Program& p) {
   p.d_outs = (DevOut*)(base + align(bt));
   p.d_tiles = (DevTile*)(base + align(bt) + align(bo));
   p.d_reds = (DevRed*)(base + align(bt) + align(bo) + align(bl));
+  p.d_shift_meta = (int64_t*)(base + align(bt) + align(bo) + align(bl) + align(br));
   // stage through pinned memory; wait for the previous upload before reuse
   if (ctx->upload_done) TDVP_HIP(ctx, hipEventSynchronize(ctx->upload_done));
   if (ctx->pinned_bytes < total) {
@@ -593,8 +650,9 @@ int upload(tdvp_ctx* ctx, Program& p) {
   if (bo) std::memcpy(h + align(bt), p.outs.data(), bo);
   if (bl) std::memcpy(h + align(bt) + align(bo), p.tiles.data(), bl);
   if (br) std::memcpy(h + align(bt) + align(bo) + align(bl), p.reds.data(), br);
-  TDVP_HIP(ctx, hipMemcpyAsync(p.d_mem, h, align(bt) + align(bo) + align(bl) + br, hipMemcpyHostToDevice,
-                               ctx->stream));
+  if (bs) std::memcpy(h + align(bt) + align(bo) + align(bl) + align(br), p.shift_meta.data(), bs);
+  TDVP_HIP(ctx, hipMemcpyAsync(p.d_mem, h, align(bt) + align(bo) + align(bl) + align(br) + bs,
+                               hipMemcpyHostToDevice, ctx->stream));
   if (!ctx->upload_done) TDVP_HIP(ctx, hipEventCreateWithFlags(&ctx->upload_done, hipEventDisableTiming));
   TDVP_HIP(ctx, hipEventRecord(ctx->upload_done, ctx->stream));
   return TDVP_OK;
@@ -625,16 +683,29 @@ int launch_gemm(tdvp_ctx* ctx, const Program& p, const Bufs& bufs, double* C, in
   const int n32 = (int)p.tiles.size() - p.n64;
   const DevTile* t32 = p.d_tiles + p.n64;
   const bool heff = p.role == 1;
+  Bufs bf = bufs;
+  bf.shift = nullptr;
+  if (precision != TDVP_FP64 && p.nshift[0] + p.nshift[1] > 0) {
+    const int nb = p.nshift[0] + p.nshift[1];
+    TDVP_HIP(ctx, ctx->ws_shift.ensure(sizeof(double) * 2 * (size_t)(nb + 1)));
+    double* out = (double*)ctx->ws_shift.p;
+    double2* partial = (double2*)ctx->ws_shift.p + 1;
+    hipLaunchKernelGGL(env_shift_parts, dim3(nb), dim3(256), 0, ctx->stream, bufs, (const int64_t*)p.d_shift_meta,
+                       p.nshift[0], partial);
+    hipLaunchKernelGGL(env_shift_final, dim3(1), dim3(64), 0, ctx->stream, (const double2*)partial, p.nshift[0],
+                       p.nshift[1], out);
+    bf.shift = out;
+  }
   if (p.n64 > 0) {
-    if (precision == TDVP_FP32) launch_one<float, 2, 2>(ctx, heff, p.n64, bufs, C, part, p.d_tiles, p);
-    else launch_one<double, 2, 2>(ctx, heff, p.n64, bufs, C, part, p.d_tiles, p);
+    if (precision == TDVP_FP32) launch_one<float, 2, 2>(ctx, heff, p.n64, bf, C, part, p.d_tiles, p);
+    else launch_one<double, 2, 2>(ctx, heff, p.n64, bf, C, part, p.d_tiles, p);
   }
   if (n32 > 0) {
-    if (precision == TDVP_FP32) launch_one<float, 1, 1>(ctx, heff, n32, bufs, C, part, t32, p);
-    else launch_one<double, 1, 1>(ctx, heff, n32, bufs, C, part, t32, p);
+    if (precision == TDVP_FP32) launch_one<float, 1, 1>(ctx, heff, n32, bf, C, part, t32, p);
+    else launch_one<double, 1, 1>(ctx, heff, n32, bf, C, part, t32, p);
   }
   if (!p.reds.empty())
-    hipLaunchKernelGGL(reduce_parts, dim3((unsigned)p.reds.size()), dim3(256), 0, ctx->stream, bufs, C,
+    hipLaunchKernelGGL(reduce_parts, dim3((unsigned)p.reds.size()), dim3(256), 0, ctx->stream, bf, C,
                        (const double2*)part, p.d_reds, p.d_outs, p.d_terms);
   TDVP_HIP(ctx, hipGetLastError());
   return TDVP_OK;
