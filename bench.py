@@ -45,6 +45,24 @@ def pack(blocks, keys, offs, total):
     return buf
 
 
+def measured_traffic(prec):
+    """HBM bytes per FP64 H_eff launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads
+    for a plain copy of known size), or None when the kernel sources changed
+    since the counters were taken."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "heff_gemm_fp64_chi4096_traffic.json")
+    if prec != "fp64" or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in ("gemm.hip", "ctx.hpp", "capi_dev.cpp", "plan.cpp"):
+        with open(os.path.join(here, "paper_2606_04771_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return rec["bytes_per_launch"] if h.hexdigest() == rec["sources_sha256"] else None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -58,7 +76,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison run")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 1 GiB three times (reference for the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = 2 ** 26                       # 64 Mi complex128 = 1 GiB
+        x = torch.ones(n, dtype=torch.complex128, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 3 * n * 16, "copy_bytes_written": 3 * n * 16}))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported",
               file=sys.stderr)
@@ -300,7 +331,7 @@ def main():
                  "blocks": len(xk), "terms": len(terms), "theta_elems": int(xt),
                  "env_chain_s": t_env_chain, "by_precision": heff_by_prec},
         "roofline": {"bound": "mfma", "achieved": heff_tflops, "peak": PEAK[args.prec], "unit": "TFLOP/s",
-                     "frac": heff_tflops / PEAK[args.prec], "traffic": None,
+                     "frac": heff_tflops / PEAK[args.prec], "traffic": measured_traffic(args.prec),
                      "kernel": "heff_gemm<double, 2, 2>" if prec == T.FP64 else "heff_gemm<float, 2, 2>"},
         "cpu_baseline": cpu,
         "mixed": mixed,
