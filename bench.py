@@ -75,6 +75,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison run")
+    ap.add_argument("--one-site-steps", type=int, default=2, help="one-site sweeps timed after the two-site ones")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB three times (reference for the HBM byte counters)")
@@ -235,6 +236,13 @@ def main():
                             "d_sz": float(np.abs(sz1 - sz2).max()), "d_docc": float(np.abs(dc1 - dc2).max())})
                 print(f"bench: other-precision sweep {st + 1}: {oinfo['seconds']:.2f} s, |psi-phi| "
                       f"{cmp[-1]['state_err']:.2e}, max|dSz| {cmp[-1]['d_sz']:.2e}", file=sys.stderr, flush=True)
+        # one-site sweeps on the saturated state (bond dimensions fixed)
+        one = []
+        for st in range(args.one_site_steps):
+            ctx.synchronize()
+            info1 = mps.sweep1(run["dt"], krylov_tol=run["krylov_tol"], krylov_maxdim=run["krylov_maxdim"])
+            one.append(info1)
+            print(f"bench: one-site sweep {st + 1}: {info1['seconds']:.2f} s", file=sys.stderr, flush=True)
         if args.steps > 0:
             sweep = {
                 "s_per_sweep": t_sw / args.steps,
@@ -246,6 +254,14 @@ def main():
                 "max_chi": int(max(i["max_chi"] for i in infos)),
                 "max_discarded": float(max(i["max_discarded"] for i in infos)),
             }
+            if one:
+                sweep["one_site"] = {
+                    "s_per_sweep": float(np.mean([i["seconds"] for i in one])),
+                    "sweep_phase_s": {k: float(np.mean([i[k] for i in one])) for k in
+                                      ("t_lanczos", "t_svd", "t_env")},
+                    "krylov_iters_per_sweep": float(np.mean([i["krylov_iters"] for i in one])),
+                    "note": "one-site TDVP sweeps continuing from the saturated two-site state "
+                            "(QR gauge moves instead of SVD splits; bond dimensions fixed)"}
         if other is not None:
             tail = oinfos[args.warmup:] or oinfos
             mixed = {

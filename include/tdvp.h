@@ -266,6 +266,18 @@ int tdvp_mps_site_read(tdvp_ctx* ctx, const tdvp_mps* mps, int32_t k, void* host
 int tdvp_sweep(tdvp_ctx* ctx, tdvp_mps* mps, double dt, const tdvp_trunc* trunc,
                tdvp_sweep_info* info);
 
+/* One time step dt of symmetric second-order one-site TDVP (supplementary
+ * section S2.2: once the bond dimensions have saturated the single-site
+ * projector splitting needs no SVD): left to right with tau = dt/2 every
+ * centre is evolved by exp(-i tau H1), moved on by a QR of the one-site
+ * tensor (sector by sector; bond dimensions unchanged), the environment
+ * updated and the bond matrix evolved back by exp(+i tau H0); then right to
+ * left, mirrored.  trunc supplies only krylov_tol and krylov_maxdim.  The MPS
+ * must have its centre on site 1 (as after tdvp_sweep); it returns there.
+ * Errors as tdvp_sweep; SHAPE if a bond is larger than the space its site can
+ * support. */
+int tdvp_sweep1(tdvp_ctx* ctx, tdvp_mps* mps, double dt, const tdvp_trunc* trunc, tdvp_sweep_info* info);
+
 /* Site-resolved observables of the quench (the local densities the paper
  * follows in time, main text results section): for every site k in 1..L,
  * sz[k-1] = <S^z_k> = (<n_k,up> - <n_k,down>)/2 and docc[k-1] =

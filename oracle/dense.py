@@ -427,3 +427,61 @@ def tdvp2_sweep(mps, dt, t, U, tol=1e-12, maxdim=40, keep_all=True, eps_tol=0.0,
             C = expm(lambda x: heff1(Lf[i - 1], R[i], x, i, t, U), C, +1j * tau)
     mps[0] = C
     return mps, disc
+
+
+def tdvp1_sweep(mps, dt, t, U, tol=1e-12, maxdim=40):
+    """One time step dt of symmetric second-order one-site TDVP (supplementary
+    section S2.2, projector splitting once the bond dimension is fixed).
+
+    Input: right-canonical MPS [C_1, B_2, ..., B_L].  Left-to-right with
+    tau = dt/2: for i = 1..L, C_i <- exp(-i tau H1_eff) C_i; for i < L,
+    C_i = A_i R (QR), update the left environment, R <- exp(+i tau H0_eff) R
+    with H0_eff = A_i^dag H1_eff A_i (the bond Hamiltonian between the new left
+    environment and the right one), C_{i+1} = R B_{i+1}.  Then right-to-left,
+    mirrored (C_i = R B_i by a QR of C_i^dag), ending with the centre on site 1."""
+    L = len(mps)
+    tau = dt / 2.0
+
+    def expm(f, v, z):
+        return lanczos_expm(f, v, z, tol=tol, maxdim=maxdim)[0]
+
+    R = [None] * (L + 1)
+    R[L] = empty_env()
+    for k in range(L, 1, -1):
+        R[k - 1] = right_env_update(R[k], mps[k - 1], k, t, U)
+    Lf = [None] * (L + 1)
+    Lf[0] = empty_env()
+    mps = list(mps)
+    for i in range(1, L + 1):
+        C = expm(lambda v: heff1(Lf[i - 1], R[i], v, i, t, U), mps[i - 1], -1j * tau)
+        if i == L:
+            mps[i - 1] = C
+            break
+        a, _, b = C.shape
+        Q, Rm = np.linalg.qr(C.reshape(a * 4, b))
+        A = Q.reshape(a, 4, -1)
+        mps[i - 1] = A
+        Lf[i] = left_env_update(Lf[i - 1], A, i, t, U)
+
+        def h0(x, A=A, i=i):
+            y = heff1(Lf[i - 1], R[i], np.tensordot(A, x, axes=([2], [0])), i, t, U)
+            return np.tensordot(A.conj(), y, axes=([0, 1], [0, 1]))
+        x = expm(h0, Rm, +1j * tau)
+        mps[i] = np.tensordot(x, mps[i], axes=([1], [0]))
+    for i in range(L, 0, -1):
+        C = expm(lambda v: heff1(Lf[i - 1], R[i], v, i, t, U), mps[i - 1], -1j * tau)
+        if i == 1:
+            mps[0] = C
+            break
+        a, _, b = C.shape
+        Q, Rm = np.linalg.qr(C.reshape(a, 4 * b).conj().T)
+        B = Q.conj().T.reshape(-1, 4, b)
+        mps[i - 1] = B
+        R[i - 1] = right_env_update(R[i], B, i, t, U)
+
+        def h0(x, B=B, i=i):
+            y = heff1(Lf[i - 1], R[i], np.tensordot(x, B, axes=([1], [0])), i, t, U)
+            return np.tensordot(y, B.conj(), axes=([1, 2], [1, 2]))
+        x = expm(h0, Rm.conj().T, +1j * tau)
+        mps[i - 2] = np.tensordot(mps[i - 2], x, axes=([2], [0]))
+    return mps

@@ -97,6 +97,7 @@ def _load():
         "tdvp_sweep": [P, P, D, P, P],
         "tdvp_mps_measure": [P, P, P, P, P],
         "tdvp_mps_overlap": [P, P, P, P],
+        "tdvp_sweep1": [P, P, D, P, P],
     }
     for name, args in sig.items():
         if not hasattr(lib, name):
@@ -339,6 +340,13 @@ class MPS:
         tr = _Trunc(float(eps_tol), int(chi_cap), int(bool(keep_all)), float(krylov_tol), int(krylov_maxdim))
         info = _SweepInfo()
         _check(lib.tdvp_sweep(self.ctx.h, self.h, float(dt), C.byref(tr), C.byref(info)), self.ctx.h)
+        return {f: getattr(info, f) for f, _ in _SweepInfo._fields_}
+
+    def sweep1(self, dt, krylov_tol=1e-12, krylov_maxdim=40):
+        """One time step of one-site TDVP (bond dimensions fixed)."""
+        tr = _Trunc(0.0, 0, 1, float(krylov_tol), int(krylov_maxdim))
+        info = _SweepInfo()
+        _check(lib.tdvp_sweep1(self.ctx.h, self.h, float(dt), C.byref(tr), C.byref(info)), self.ctx.h)
         return {f: getattr(info, f) for f, _ in _SweepInfo._fields_}
 
     def overlap(self, ket):

@@ -123,6 +123,7 @@ struct tdvp_ctx {
   tdvp::DeviceBuffer ws_scratch, ws_krylov, ws_small, ws_vec, ws_theta, ws_svd;
   tdvp::DeviceBuffer ws_part;   // partial tiles of split K chains
   tdvp::DeviceBuffer ws_shift;  // diagonal shifts of reduced-precision launches
+  tdvp::DeviceBuffer ws_compact;  // compact copy of a non-contiguous Krylov start vector
   void* solver = nullptr;       // rocblas handle for the eigensolver (created on first use)
   // side streams (default priority) with their own solver handles, for
   // independent eigensolves; joined back to `stream` by events
@@ -172,6 +173,10 @@ int vec_pad_matrix(tdvp_ctx* ctx, double* A, int64_t n, int64_t g, double v, dou
 int vec_block_dots(tdvp_ctx* ctx, const double* x, const double* y, const int64_t* d_meta, int nblocks,
                    double* d_out);
 
+// n x n matrix: everything outside the leading g x g block becomes the identity
+int vec_pad_identity(tdvp_ctx* ctx, double* A, int64_t n, int64_t g);
+// zero the strictly lower triangles of `count` consecutive n x n matrices
+int vec_zero_lower(tdvp_ctx* ctx, double* A, int64_t n, int64_t count);
 int vec_scale_cols_rsqrt(tdvp_ctx* ctx, double* A, int64_t ld, int64_t rows, int64_t cols, const double* lam);
 
 }  // namespace tdvp

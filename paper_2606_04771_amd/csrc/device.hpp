@@ -2,6 +2,7 @@
 #pragma once
 
 #include <complex>
+#include <functional>
 #include <memory>
 #include <vector>
 
@@ -27,6 +28,10 @@ struct KrylovResult {
 // x <- exp(tau H_eff) x (x = in.x, data in place).
 int krylov_dev(tdvp_ctx* ctx, const tdvp_model& m, int site, int nsites, const HeffInputs& in,
                std::complex<double> tau, double tol, int maxdim, KrylovResult& out);
+
+// x <- exp(tau op) x for a device operator on n contiguous complex elements.
+int krylov_core(tdvp_ctx* ctx, int64_t n, double* x, const std::function<int(const double*, double*)>& op,
+                double flops_per_apply, std::complex<double> tau, double tol, int maxdim, KrylovResult& out);
 
 // Copy blocks: dst[j] = src[i] for blocks with equal keys (scaled by s).
 int copy_blocks(tdvp_ctx* ctx, const Blocks& src, const Blocks& dst, double s);

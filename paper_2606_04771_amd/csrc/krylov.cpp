@@ -10,6 +10,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <functional>
 
 #include "device.hpp"
 #include "tridiag.hpp"
@@ -63,25 +64,12 @@ bool contiguous(const Blocks& x, int64_t& n) {
 
 }  // namespace
 
-int krylov_dev(tdvp_ctx* ctx, const tdvp_model& m, int site, int nsites, const HeffInputs& in_user,
-               std::complex<double> tau, double tol, int maxdim, KrylovResult& out) {
+// Lanczos exponential of a device operator on a contiguous vector of n
+// complex elements, in place.  The operator writes op(v) to w (both
+// contiguous, n elements); flops_per_apply is added to out.heff_flops.
+int krylov_core(tdvp_ctx* ctx, int64_t n, double* x, const std::function<int(const double*, double*)>& op,
+                double flops_per_apply, std::complex<double> tau, double tol, int maxdim, KrylovResult& out) {
   out = KrylovResult();
-  int64_t n = 0;
-  HeffInputs in = in_user;
-  bool compact = contiguous(in.x, n);
-  if (!compact) {
-    // Lanczos vectors use a compact copy of the block layout
-    Blocks xc;
-    xc.keylen = in.x.keylen;
-    int64_t o = 0;
-    for (int i = 0; i < in.x.n(); ++i) {
-      xc.push(in.x.k(i), o, in.x.rows[i], in.x.cols[i]);
-      o += in.x.rows[i] * in.x.cols[i];
-    }
-    xc.size = o;
-    in.x = xc;
-    n = o;
-  }
   if (n == 0) return TDVP_OK;
   const int64_t stride = n;
   TDVP_HIP(ctx, ctx->ws_krylov.ensure(sizeof(double) * 2 * (size_t)stride * (maxdim + 1)));
@@ -96,17 +84,9 @@ int krylov_dev(tdvp_ctx* ctx, const tdvp_model& m, int site, int nsites, const H
   double* d_y = d_small + 512;     // 2*64
 
   // v0 = x / |x|
-  Blocks v0 = in.x;
-  v0.data = V;
   int rc;
-  if (compact) {
-    TDVP_HIP(ctx, hipMemcpyAsync(V, in_user.x.data, sizeof(double) * 2 * n, hipMemcpyDeviceToDevice, ctx->stream));
-  } else {
-    rc = copy_blocks(ctx, in_user.x, v0, 1.0);
-    if (rc) return rc;
-  }
-  rc = vec_norm2(ctx, V, n, d_nrm);
-  if (rc) return rc;
+  TDVP_HIP(ctx, hipMemcpyAsync(V, x, sizeof(double) * 2 * n, hipMemcpyDeviceToDevice, ctx->stream));
+  if ((rc = vec_norm2(ctx, V, n, d_nrm))) return rc;
   TDVP_HIP(ctx, hipMemcpyAsync(h_small, d_nrm, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
   if (h_small[1] != 0.0 || !std::isfinite(h_small[0]))
@@ -117,24 +97,14 @@ int krylov_dev(tdvp_ctx* ctx, const tdvp_model& m, int site, int nsites, const H
     out.converged = 1;
     return TDVP_OK;
   }
-  rc = vec_scale_copy(ctx, V, V, 1.0 / nrm, n);
-  if (rc) return rc;
-
-  Blocks yb = in.x;   // output layout of the apply = compact layout
-  auto prog = heff_program(ctx, m, site, nsites, in, yb, rc);
-  if (rc) return rc;
-  Bufs bufs{};
-  bufs.p[1] = (const double*)in.Le.data;
-  bufs.p[2] = (const double*)in.Re.data;
+  if ((rc = vec_scale_copy(ctx, V, V, 1.0 / nrm, n))) return rc;
 
   std::vector<double> alpha, beta;
   std::vector<std::complex<double>> y;
   for (int j = 0; j < maxdim; ++j) {
     double* vj = V + 2 * stride * j;
-    bufs.p[0] = vj;
-    rc = launch_gemm(ctx, *prog, bufs, W, ctx->precision);
-    if (rc) return rc;
-    out.heff_flops += prog->flops;
+    if ((rc = op(vj, W))) return rc;
+    out.heff_flops += flops_per_apply;
     // two passes of classical Gram-Schmidt against v_0..v_j
     if ((rc = vec_dots(ctx, V, stride, j + 1, W, n, d_c1))) return rc;
     if ((rc = vec_subtract_combo(ctx, W, V, stride, j + 1, d_c1, n, nullptr))) return rc;
@@ -166,17 +136,7 @@ int krylov_dev(tdvp_ctx* ctx, const tdvp_model& m, int site, int nsites, const H
       }
       TDVP_HIP(ctx, hipMemcpyAsync(d_y, h_small + 512, sizeof(double) * 2 * (j + 1), hipMemcpyHostToDevice,
                                    ctx->stream));
-      if (compact) {
-        rc = vec_combo(ctx, (double*)in_user.x.data, V, stride, j + 1, d_y, n);
-        if (rc) return rc;
-      } else {
-        rc = vec_combo(ctx, W, V, stride, j + 1, d_y, n);
-        if (rc) return rc;
-        Blocks wb = in.x;
-        wb.data = W;
-        rc = copy_blocks(ctx, wb, in_user.x, 1.0);
-        if (rc) return rc;
-      }
+      if ((rc = vec_combo(ctx, x, V, stride, j + 1, d_y, n))) return rc;
       TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
       if (!out.converged) return set_error(ctx, TDVP_E_NOCONV, "Krylov tolerance not reached within maxdim");
       return TDVP_OK;
@@ -185,6 +145,58 @@ int krylov_dev(tdvp_ctx* ctx, const tdvp_model& m, int site, int nsites, const H
     if ((rc = vec_scale_copy(ctx, V + 2 * stride * (j + 1), W, 1.0 / b, n))) return rc;
   }
   return TDVP_OK;
+}
+
+int krylov_dev(tdvp_ctx* ctx, const tdvp_model& m, int site, int nsites, const HeffInputs& in_user,
+               std::complex<double> tau, double tol, int maxdim, KrylovResult& out) {
+  out = KrylovResult();
+  int64_t n = 0;
+  HeffInputs in = in_user;
+  bool compact = contiguous(in.x, n);
+  if (!compact) {
+    // Lanczos vectors use a compact copy of the block layout
+    Blocks xc;
+    xc.keylen = in.x.keylen;
+    int64_t o = 0;
+    for (int i = 0; i < in.x.n(); ++i) {
+      xc.push(in.x.k(i), o, in.x.rows[i], in.x.cols[i]);
+      o += in.x.rows[i] * in.x.cols[i];
+    }
+    xc.size = o;
+    in.x = xc;
+    n = o;
+  }
+  if (n == 0) return TDVP_OK;
+  int rc;
+  Blocks yb = in.x;   // output layout of the apply = compact layout
+  auto prog = heff_program(ctx, m, site, nsites, in, yb, rc);
+  if (rc) return rc;
+  Bufs bufs{};
+  bufs.p[1] = (const double*)in.Le.data;
+  bufs.p[2] = (const double*)in.Re.data;
+  auto op = [&](const double* v, double* w) -> int {
+    bufs.p[0] = v;
+    return launch_gemm(ctx, *prog, bufs, w, ctx->precision);
+  };
+  double* xd = (double*)in_user.x.data;
+  if (!compact) {
+    // work on a compact copy (after the Krylov basis in the scratch area)
+    TDVP_HIP(ctx, ctx->ws_compact.ensure(sizeof(double) * 2 * (size_t)n));
+    Blocks xc = in.x;
+    xc.data = ctx->ws_compact.p;
+    if ((rc = copy_blocks(ctx, in_user.x, xc, 1.0))) return rc;
+    xd = (double*)ctx->ws_compact.p;
+  }
+  rc = krylov_core(ctx, n, xd, op, prog->flops, tau, tol, maxdim, out);
+  if (rc && rc != TDVP_E_NOCONV) return rc;
+  if (!compact) {
+    Blocks xc = in.x;
+    xc.data = ctx->ws_compact.p;
+    int rc2 = copy_blocks(ctx, xc, in_user.x, 1.0);
+    if (rc2) return rc2;
+    TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  return rc;
 }
 
 }  // namespace tdvp

@@ -1268,3 +1268,487 @@ int tdvp_mps_overlap(tdvp_ctx* ctx, const tdvp_mps* bra, const tdvp_mps* ket, do
     return TDVP_OK;
   });
 }
+
+// ---------------------------------------------------------------------------
+// One-site TDVP (supplementary section S2.2: once the bond dimension has
+// saturated, the single-site projector splitting needs no SVD; the centre
+// moves by a QR of the one-site tensor and the bond matrix is evolved
+// backwards with the zero-site effective Hamiltonian).
+namespace tdvp {
+namespace {
+
+// One square block per sector of bond b (the bond matrix), contiguous.
+void bondmat_layout(const Bond& b, Blocks& x) {
+  x = Blocks();
+  x.keylen = 1;
+  int64_t o = 0;
+  for (int i = 0; i < b.size(); ++i) {
+    int key = i;
+    x.push(&key, o, b.d[i], b.d[i]);
+    o += b.d[i] * b.d[i];
+  }
+  x.size = o;
+}
+
+// The sector (of the bond being cut) that block o of a one-site tensor belongs to.
+inline int cut_sector(const Blocks& T, int o, int dir) { return dir > 0 ? T.k(o)[2] : T.k(o)[0]; }
+
+// Gauge move of the one-site tensor T at site i by QR (dir +1: T = A x on bond
+// i, A left-canonical) or LQ (dir -1: T = x B on bond i-1, B right-canonical),
+// sector by sector of the cut bond, with the bond dimensions unchanged.
+// CholeskyQR2: G = M^dag M per sector (grouped GEMM), G = R^dag R (batched
+// Cholesky), Q1 = M R^-1 (batched triangular inverse + grouped GEMM), and
+// the same once more on Q1, which restores orthogonality to rounding for
+// condition numbers up to ~1e7.  A bond whose Cholesky fails (rank-deficient
+// centre, e.g. complete bases) is done by Householder QR per sector instead.
+// On return T holds A (or B) and xbuf the bond matrix (layout bondmat_layout).
+int gauge_qr(tdvp_ctx* ctx, tdvp_mps* m, int i, int dir, Blocks& x, DeviceBuffer& xbuf, DeviceBuffer& qbuf) {
+  Tensor& TT = *m->site[i - 1];
+  Blocks& T = TT.blk;
+  const Bond& cut = dir > 0 ? m->bonds[i] : m->bonds[i - 1];
+  bondmat_layout(cut, x);
+  TDVP_HIP(ctx, xbuf.ensure(sizeof(double) * 2 * (size_t)std::max<int64_t>(x.size, 1)));
+  x.data = xbuf.p;
+  TDVP_HIP(ctx, qbuf.ensure(sizeof(double) * 2 * (size_t)std::max<int64_t>(T.size, 1)));
+  int rc;
+  if ((rc = ensure_solver(ctx))) return rc;
+  const int ns = cut.size();
+  // padded Gram slots by size bucket
+  std::vector<int64_t> gn(ns), goff(ns);
+  std::map<int64_t, std::vector<int>> buckets;
+  for (int s = 0; s < ns; ++s) buckets[bucket_size(cut.d[s])].push_back(s);
+  int64_t gtot = 0;
+  for (auto& bk : buckets)
+    for (int s : bk.second) {
+      gn[s] = bk.first;
+      goff[s] = gtot;
+      gtot += bk.first * bk.first;
+    }
+  // regions: G (work), R1, R2 (kept), info
+  size_t bytes = sizeof(double) * 2 * (size_t)(3 * gtot) + sizeof(rocblas_int) * (size_t)(ns + 8) + 4096;
+  TDVP_HIP(ctx, ctx->ws_svd.ensure(bytes));
+  double* G = (double*)ctx->ws_svd.p;
+  double* R1 = G + 2 * gtot;
+  double* R2 = R1 + 2 * gtot;
+  rocblas_int* dinfo = (rocblas_int*)(R2 + 2 * gtot);
+  Bufs b{};
+  // one CholeskyQR round on the tensor in buffer src (layout of T) into dst; R kept in Rk
+  auto round = [&](const double* src, double* dst, double* Rk) -> int {
+    TDVP_HIP(ctx, hipMemsetAsync(G, 0, sizeof(double) * 2 * (size_t)gtot, ctx->stream));
+    Program pg;
+    for (int s = 0; s < ns; ++s) {
+      DevOut ob{};
+      ob.c_off = goff[s];
+      ob.ldc = (int32_t)gn[s];
+      ob.M = ob.N = (int32_t)cut.d[s];
+      ob.t_begin = (int32_t)pg.terms.size();
+      for (int o = 0; o < T.n(); ++o) {
+        if (cut_sector(T, o, dir) != s) continue;
+        DevTerm d{};
+        d.coef = 1.0;
+        d.a_buf = 0; d.a_off = T.off[o]; d.lda = (int32_t)T.rows[o];
+        d.b_buf = 0; d.b_off = T.off[o]; d.ldb = (int32_t)T.rows[o];
+        if (dir > 0) { d.ops = 1 | 2; d.K = (int32_t)T.rows[o]; }   // M^dag M over rows (a, s)
+        else { d.ops = 4 | 8; d.K = (int32_t)T.cols[o]; }           // M M^dag over columns (s, b)
+        pg.terms.push_back(d);
+      }
+      ob.t_end = ob.d_begin = ob.d_end = (int32_t)pg.terms.size();
+      pg.outs.push_back(ob);
+    }
+    b.p[0] = src;
+    int r;
+    if ((r = run_program(ctx, pg, b, G))) return r;
+    for (int s = 0; s < ns; ++s)
+      if ((r = vec_pad_identity(ctx, G + 2 * goff[s], gn[s], cut.d[s]))) return r;
+    int64_t mi = 0;
+    for (auto& bk : buckets) {
+      const int64_t n = bk.first;
+      const int s0 = bk.second.front(), cnt = (int)bk.second.size();
+      rocblas_status st = rocsolver_zpotrf_strided_batched(
+          (rocblas_handle)ctx->solver, rocblas_fill_upper, (rocblas_int)n, (rocblas_double_complex*)(G + 2 * goff[s0]),
+          (rocblas_int)n, (rocblas_stride)(n * n), dinfo + mi, cnt);
+      if (st != rocblas_status_success) return set_error(ctx, TDVP_E_HIP, "rocsolver_zpotrf_strided_batched failed");
+      mi += cnt;
+    }
+    std::vector<rocblas_int> info(ns);
+    TDVP_HIP(ctx, hipMemcpyAsync(info.data(), dinfo, sizeof(rocblas_int) * ns, hipMemcpyDeviceToHost, ctx->stream));
+    TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (int q = 0; q < ns; ++q)
+      if (info[q] != 0) return TDVP_E_NOCONV;   // not positive definite to working precision
+    // keep R (upper), then invert it in place in G
+    TDVP_HIP(ctx, hipMemcpyAsync(Rk, G, sizeof(double) * 2 * (size_t)gtot, hipMemcpyDeviceToDevice, ctx->stream));
+    for (auto& bk : buckets) {
+      const int64_t n = bk.first;
+      const int s0 = bk.second.front(), cnt = (int)bk.second.size();
+      if ((r = vec_zero_lower(ctx, Rk + 2 * goff[s0], n, cnt))) return r;
+      if ((r = vec_zero_lower(ctx, G + 2 * goff[s0], n, cnt))) return r;
+      rocblas_status st = rocsolver_ztrtri_strided_batched(
+          (rocblas_handle)ctx->solver, rocblas_fill_upper, rocblas_diagonal_non_unit, (rocblas_int)n,
+          (rocblas_double_complex*)(G + 2 * goff[s0]), (rocblas_int)n, (rocblas_stride)(n * n), dinfo, cnt);
+      if (st != rocblas_status_success) return set_error(ctx, TDVP_E_HIP, "rocsolver_ztrtri_strided_batched failed");
+    }
+    // dst = src R^-1 (dir +1) or R^-dag src (dir -1), block by block
+    Program pq;
+    for (int o = 0; o < T.n(); ++o) {
+      const int s = cut_sector(T, o, dir);
+      DevOut ob{};
+      ob.c_off = T.off[o];
+      ob.ldc = ob.M = (int32_t)T.rows[o];
+      ob.N = (int32_t)T.cols[o];
+      ob.t_begin = (int32_t)pq.terms.size();
+      DevTerm d{};
+      d.coef = 1.0;
+      if (dir > 0) {
+        d.a_buf = 0; d.a_off = T.off[o]; d.lda = (int32_t)T.rows[o];
+        d.b_buf = 1; d.b_off = goff[s]; d.ldb = (int32_t)gn[s];
+        d.K = (int32_t)cut.d[s];
+      } else {
+        d.a_buf = 1; d.a_off = goff[s]; d.lda = (int32_t)gn[s]; d.ops = 1 | 2;
+        d.b_buf = 0; d.b_off = T.off[o]; d.ldb = (int32_t)T.rows[o];
+        d.K = (int32_t)cut.d[s];
+      }
+      pq.terms.push_back(d);
+      ob.t_end = ob.d_begin = ob.d_end = (int32_t)pq.terms.size();
+      pq.outs.push_back(ob);
+    }
+    b.p[0] = src;
+    b.p[1] = G;
+    return run_program(ctx, pq, b, dst);
+  };
+  double* Q1 = (double*)qbuf.p;
+  rc = round((const double*)T.data, Q1, R1);
+  if (!rc) rc = round(Q1, (double*)T.data, R2);
+  if (rc == TDVP_OK) {
+    // x = R2 R1 (dir +1) or (R2 R1)^dag = R1^dag R2^dag (dir -1)
+    Program px;
+    for (int s = 0; s < ns; ++s) {
+      DevOut ob{};
+      ob.c_off = x.off[s];
+      ob.ldc = ob.M = ob.N = (int32_t)cut.d[s];
+      ob.t_begin = (int32_t)px.terms.size();
+      DevTerm d{};
+      d.coef = 1.0;
+      d.K = (int32_t)cut.d[s];
+      if (dir > 0) {
+        d.a_buf = 0; d.a_off = goff[s]; d.lda = (int32_t)gn[s];
+        d.b_buf = 1; d.b_off = goff[s]; d.ldb = (int32_t)gn[s];
+      } else {
+        d.a_buf = 1; d.a_off = goff[s]; d.lda = (int32_t)gn[s]; d.ops = 1 | 2;
+        d.b_buf = 0; d.b_off = goff[s]; d.ldb = (int32_t)gn[s]; d.ops |= 4 | 8;
+      }
+      px.terms.push_back(d);
+      ob.t_end = ob.d_begin = ob.d_end = (int32_t)px.terms.size();
+      px.outs.push_back(ob);
+    }
+    b.p[0] = R2;
+    b.p[1] = R1;
+    if ((rc = run_program(ctx, px, b, (double*)x.data))) return rc;
+    TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return TDVP_OK;
+  }
+  if (rc != TDVP_E_NOCONV) return rc;
+  // Householder QR per sector (rank-deficient centre).  A failed round stops
+  // before writing its output, so T still holds the original tensor.
+  std::vector<int64_t> rows(ns, 0), moff(ns, 0), roff(T.n(), 0);
+  for (int o = 0; o < T.n(); ++o) {
+    const int sct = cut_sector(T, o, dir);
+    roff[o] = rows[sct];
+    rows[sct] += dir > 0 ? T.rows[o] : T.cols[o];
+  }
+  int64_t mtot = 0, ktot = 0;
+  for (int sct = 0; sct < ns; ++sct) {
+    if (rows[sct] < cut.d[sct])
+      return set_error(ctx, TDVP_E_SHAPE, "one-site gauge move: bond larger than its support");
+    moff[sct] = mtot;
+    mtot += rows[sct] * cut.d[sct];
+    ktot += cut.d[sct];
+  }
+  TDVP_HIP(ctx, ctx->ws_scratch.ensure(sizeof(double) * 2 * (size_t)(mtot + ktot + 1)));
+  double* Mb = (double*)ctx->ws_scratch.p;
+  double* tau = Mb + 2 * mtot;
+  // gather M_s: dir +1 the (a, s) x d_b stack of the blocks; dir -1 the stack
+  // of their conjugate transposes (the LQ of the row is a QR of its adjoint)
+  Program pgat;
+  for (int o = 0; o < T.n(); ++o) {
+    const int sct = cut_sector(T, o, dir);
+    DevOut ob{};
+    ob.c_off = moff[sct] + roff[o];
+    ob.ldc = (int32_t)rows[sct];
+    ob.M = (int32_t)(dir > 0 ? T.rows[o] : T.cols[o]);
+    ob.N = (int32_t)(dir > 0 ? T.cols[o] : T.rows[o]);
+    ob.t_begin = ob.t_end = ob.d_begin = (int32_t)pgat.terms.size();
+    DevTerm d{};
+    d.a_buf = 0; d.a_off = T.off[o]; d.lda = (int32_t)T.rows[o];
+    d.coef = 1.0;
+    d.ops = dir > 0 ? 0 : (1 | 2);
+    pgat.terms.push_back(d);
+    ob.d_end = (int32_t)pgat.terms.size();
+    pgat.outs.push_back(ob);
+  }
+  b.p[0] = (const double*)T.data;
+  if ((rc = run_program(ctx, pgat, b, Mb))) return rc;
+  // factor; keep R (upper d x d) in the R1 slots
+  TDVP_HIP(ctx, hipMemsetAsync(R1, 0, sizeof(double) * 2 * (size_t)gtot, ctx->stream));
+  int64_t kofs = 0;
+  for (int sct = 0; sct < ns; ++sct) {
+    const int64_t r = rows[sct], dd = cut.d[sct];
+    auto* A = (rocblas_double_complex*)(Mb + 2 * moff[sct]);
+    auto* tq = (rocblas_double_complex*)(tau + 2 * kofs);
+    kofs += dd;
+    rocblas_status st = rocsolver_zgeqrf((rocblas_handle)ctx->solver, (rocblas_int)r, (rocblas_int)dd, A,
+                                         (rocblas_int)r, tq);
+    if (st != rocblas_status_success) return set_error(ctx, TDVP_E_HIP, "rocsolver_zgeqrf failed");
+    TDVP_HIP(ctx, hipMemcpy2DAsync(R1 + 2 * goff[sct], sizeof(double) * 2 * gn[sct], Mb + 2 * moff[sct],
+                                   sizeof(double) * 2 * r, sizeof(double) * 2 * dd, dd, hipMemcpyDeviceToDevice,
+                                   ctx->stream));
+    st = rocsolver_zungqr((rocblas_handle)ctx->solver, (rocblas_int)r, (rocblas_int)dd, (rocblas_int)dd, A,
+                          (rocblas_int)r, tq);
+    if (st != rocblas_status_success) return set_error(ctx, TDVP_E_HIP, "rocsolver_zungqr failed");
+  }
+  for (auto& bk : buckets)
+    if ((rc = vec_zero_lower(ctx, R1 + 2 * goff[bk.second.front()], bk.first, (int64_t)bk.second.size()))) return rc;
+  // write back: the isometry into T, the triangle into x
+  Program pw, px;
+  for (int o = 0; o < T.n(); ++o) {
+    const int sct = cut_sector(T, o, dir);
+    DevOut ob{};
+    ob.c_off = T.off[o];
+    ob.ldc = ob.M = (int32_t)T.rows[o];
+    ob.N = (int32_t)T.cols[o];
+    ob.t_begin = ob.t_end = ob.d_begin = (int32_t)pw.terms.size();
+    DevTerm d{};
+    d.a_buf = 0; d.a_off = moff[sct] + roff[o]; d.lda = (int32_t)rows[sct];
+    d.coef = 1.0;
+    d.ops = dir > 0 ? 0 : (1 | 2);
+    pw.terms.push_back(d);
+    ob.d_end = (int32_t)pw.terms.size();
+    pw.outs.push_back(ob);
+  }
+  for (int sct = 0; sct < ns; ++sct) {
+    DevOut ob{};
+    ob.c_off = x.off[sct];
+    ob.ldc = ob.M = ob.N = (int32_t)cut.d[sct];
+    ob.t_begin = ob.t_end = ob.d_begin = (int32_t)px.terms.size();
+    DevTerm d{};
+    d.a_buf = 1; d.a_off = goff[sct]; d.lda = (int32_t)gn[sct];
+    d.coef = 1.0;
+    d.ops = dir > 0 ? 0 : (1 | 2);
+    px.terms.push_back(d);
+    ob.d_end = (int32_t)px.terms.size();
+    px.outs.push_back(ob);
+  }
+  b.p[0] = Mb;
+  b.p[1] = R1;
+  if ((rc = run_program(ctx, pw, b, (double*)T.data))) return rc;
+  if ((rc = run_program(ctx, px, b, (double*)x.data))) return rc;
+  TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (ctx->verbose) std::fprintf(stderr, "[tdvp]   site %d: Householder gauge move (dir %+d)\n", i, dir);
+  return TDVP_OK;
+}
+
+}  // namespace
+}  // namespace tdvp
+
+namespace tdvp {
+namespace {
+
+// Backward evolution x <- exp(+i tau H0) x of the bond matrix after a gauge
+// move at site i.  The zero-site effective Hamiltonian is the one-site one
+// projected with the new isometry (the environment just built from it is
+// exactly that projection): dir +1, x on bond i and H0 x = A^dag H1_i (A x);
+// dir -1, x on bond i-1 and H0 x = (H1_i (x B)) B^dag.
+int evolve_bond(tdvp_ctx* ctx, tdvp_mps* m, int i, int dir, Blocks& x, double tau_im, const tdvp_trunc& tr,
+                tdvp_sweep_info* info) {
+  const Blocks& T = m->site[i - 1]->blk;   // A_i (dir +1) or B_i (dir -1)
+  HeffInputs in;
+  in.l = m->bonds[i - 1];
+  in.r = m->bonds[i];
+  in.Le = m->Lenv[i - 1]->blk;
+  in.Re = m->Renv[i]->blk;
+  Blocks t1 = T;   // one-site layout of site i, compact scratch
+  int rc;
+  TDVP_HIP(ctx, ctx->ws_theta.ensure(sizeof(double) * 2 * (size_t)std::max<int64_t>(2 * T.size, 1)));
+  double* t1d = (double*)ctx->ws_theta.p;
+  double* t2d = t1d + 2 * T.size;
+  t1.data = t1d;
+  in.x = t1;
+  Blocks t2 = T;
+  t2.data = t2d;
+  auto prog = heff_program(ctx, m->model, i, 1, in, t2, rc);
+  if (rc) return rc;
+  // pin: t1 = A x (dir +1) or x B (dir -1); pout: y = A^dag t2 or t2 B^dag
+  Program pin, pout;
+  double small_flops = 0.0;
+  for (int o = 0; o < T.n(); ++o) {
+    const int sct = cut_sector(T, o, dir);
+    DevOut ob{};
+    ob.c_off = T.off[o];
+    ob.ldc = ob.M = (int32_t)T.rows[o];
+    ob.N = (int32_t)T.cols[o];
+    ob.t_begin = (int32_t)pin.terms.size();
+    DevTerm d{};
+    d.coef = 1.0;
+    if (dir > 0) {
+      d.a_buf = 0; d.a_off = T.off[o]; d.lda = (int32_t)T.rows[o];
+      d.b_buf = 1; d.b_off = x.off[sct]; d.ldb = (int32_t)x.rows[sct];
+      d.K = (int32_t)T.cols[o];
+    } else {
+      d.a_buf = 1; d.a_off = x.off[sct]; d.lda = (int32_t)x.rows[sct];
+      d.b_buf = 0; d.b_off = T.off[o]; d.ldb = (int32_t)T.rows[o];
+      d.K = (int32_t)T.rows[o];
+    }
+    small_flops += 8.0 * (double)T.rows[o] * (double)T.cols[o] * (double)d.K;
+    pin.terms.push_back(d);
+    ob.t_end = ob.d_begin = ob.d_end = (int32_t)pin.terms.size();
+    pin.outs.push_back(ob);
+  }
+  for (int sct = 0; sct < x.n(); ++sct) {
+    DevOut ob{};
+    ob.c_off = x.off[sct];
+    ob.ldc = ob.M = (int32_t)x.rows[sct];
+    ob.N = (int32_t)x.cols[sct];
+    ob.t_begin = (int32_t)pout.terms.size();
+    for (int o = 0; o < T.n(); ++o) {
+      if (cut_sector(T, o, dir) != sct) continue;
+      DevTerm d{};
+      d.coef = 1.0;
+      if (dir > 0) {   // A^dag t2 over rows (a, s)
+        d.a_buf = 0; d.a_off = T.off[o]; d.lda = (int32_t)T.rows[o]; d.ops = 1 | 2;
+        d.b_buf = 2; d.b_off = T.off[o]; d.ldb = (int32_t)T.rows[o];
+        d.K = (int32_t)T.rows[o];
+      } else {         // t2 B^dag over columns (s, b)
+        d.a_buf = 2; d.a_off = T.off[o]; d.lda = (int32_t)T.rows[o];
+        d.b_buf = 0; d.b_off = T.off[o]; d.ldb = (int32_t)T.rows[o]; d.ops = 4 | 8;
+        d.K = (int32_t)T.cols[o];
+      }
+      small_flops += 8.0 * (double)ob.M * (double)ob.N * (double)d.K;
+      pout.terms.push_back(d);
+    }
+    ob.t_end = ob.d_begin = ob.d_end = (int32_t)pout.terms.size();
+    pout.outs.push_back(ob);
+  }
+  pin.finalize();
+  pout.finalize();
+  if ((rc = upload(ctx, pin)) || (rc = upload(ctx, pout))) return rc;
+  Bufs bh{};
+  bh.p[0] = t1d;
+  bh.p[1] = (const double*)in.Le.data;
+  bh.p[2] = (const double*)in.Re.data;
+  auto op = [&](const double* v, double* w) -> int {
+    Bufs b{};
+    b.p[0] = (const double*)T.data;
+    b.p[1] = v;
+    int r = launch_gemm(ctx, pin, b, t1d, ctx->precision);
+    if (!r) r = launch_gemm(ctx, *prog, bh, t2d, ctx->precision);
+    b.p[2] = t2d;
+    if (!r) r = launch_gemm(ctx, pout, b, w, ctx->precision);
+    return r;
+  };
+  KrylovResult kr;
+  rc = krylov_core(ctx, x.size, (double*)x.data, op, prog->flops + small_flops, {0.0, tau_im}, tr.krylov_tol,
+                   tr.krylov_maxdim, kr);
+  info->krylov_iters += kr.iters;
+  info->krylov_max = std::max(info->krylov_max, kr.iters);
+  info->heff_flops += kr.heff_flops;
+  if (rc == TDVP_E_NOCONV) {
+    info->nonconverged++;
+    rc = TDVP_OK;
+  }
+  return rc;
+}
+
+// Move the bond matrix into the neighbour: dir +1, C_{i+1} = x B_{i+1};
+// dir -1, C_{i-1} = A_{i-1} x.  Layouts are unchanged (same bond dimensions).
+int absorb(tdvp_ctx* ctx, tdvp_mps* m, int i, int dir, const Blocks& x) {
+  const int j = dir > 0 ? i + 1 : i - 1;   // receiving site
+  Blocks& N = m->site[j - 1]->blk;
+  TDVP_HIP(ctx, ctx->ws_theta.ensure(sizeof(double) * 2 * (size_t)std::max<int64_t>(N.size, 1)));
+  double* tmp = (double*)ctx->ws_theta.p;
+  Program p;
+  for (int o = 0; o < N.n(); ++o) {
+    const int sct = dir > 0 ? N.k(o)[0] : N.k(o)[2];
+    DevOut ob{};
+    ob.c_off = N.off[o];
+    ob.ldc = ob.M = (int32_t)N.rows[o];
+    ob.N = (int32_t)N.cols[o];
+    ob.t_begin = (int32_t)p.terms.size();
+    DevTerm d{};
+    d.coef = 1.0;
+    if (dir > 0) {
+      d.a_buf = 1; d.a_off = x.off[sct]; d.lda = (int32_t)x.rows[sct];
+      d.b_buf = 0; d.b_off = N.off[o]; d.ldb = (int32_t)N.rows[o];
+      d.K = (int32_t)N.rows[o];
+    } else {
+      d.a_buf = 0; d.a_off = N.off[o]; d.lda = (int32_t)N.rows[o];
+      d.b_buf = 1; d.b_off = x.off[sct]; d.ldb = (int32_t)x.rows[sct];
+      d.K = (int32_t)N.cols[o];
+    }
+    p.terms.push_back(d);
+    ob.t_end = ob.d_begin = ob.d_end = (int32_t)p.terms.size();
+    p.outs.push_back(ob);
+  }
+  Bufs b{};
+  b.p[0] = (const double*)N.data;
+  b.p[1] = (const double*)x.data;
+  int rc = run_program(ctx, p, b, tmp);
+  if (rc) return rc;
+  TDVP_HIP(ctx, hipMemcpyAsync(N.data, tmp, sizeof(double) * 2 * (size_t)N.size, hipMemcpyDeviceToDevice,
+                               ctx->stream));
+  return TDVP_OK;
+}
+
+}  // namespace
+}  // namespace tdvp
+
+// One time step dt of symmetric second-order one-site TDVP (bond dimensions fixed).
+int tdvp_sweep1(tdvp_ctx* ctx, tdvp_mps* m, double dt, const tdvp_trunc* tr, tdvp_sweep_info* info) {
+  if (!ctx || !m || !tr) return set_error(ctx, TDVP_E_INVALID, "null argument");
+  return guarded(ctx, [&]() -> int {
+    if (m->ctx != ctx) return set_error(ctx, TDVP_E_INVALID, "MPS belongs to another context");
+    if (tr->krylov_maxdim < 1 || tr->krylov_maxdim > 64) return set_error(ctx, TDVP_E_INVALID, "bad krylov_maxdim");
+    TDVP_HIP(ctx, hipSetDevice(ctx->device));
+    tdvp_sweep_info inf{};
+    double t0 = now();
+    const int L = m->L;
+    const double tau = 0.5 * dt;
+    int rc;
+    Blocks x;
+    DeviceBuffer xbuf, qbuf;
+    auto timed = [&](double& acc, auto&& f) -> int {
+      double s = now();
+      int r = f();
+      acc += now() - s;
+      return r;
+    };
+    auto site_evolve = [&](int i) {
+      Blocks& c = m->site[i - 1]->blk;
+      return timed(inf.t_lanczos, [&] {
+        return evolve(ctx, m, i, 1, c, m->Lenv[i - 1]->blk, m->Renv[i]->blk, -tau, *tr, &inf);
+      });
+    };
+    for (int i = 1; i <= L; ++i) {
+      if ((rc = site_evolve(i))) return rc;
+      if (i == L) break;
+      if ((rc = timed(inf.t_svd, [&] { return gauge_qr(ctx, m, i, +1, x, xbuf, qbuf); }))) return rc;
+      if ((rc = timed(inf.t_env, [&] { return env_step_sync(ctx, m, i, +1, &inf); }))) return rc;
+      if ((rc = timed(inf.t_lanczos, [&] { return evolve_bond(ctx, m, i, +1, x, +tau, *tr, &inf); }))) return rc;
+      if ((rc = absorb(ctx, m, i, +1, x))) return rc;
+    }
+    for (int i = L; i >= 1; --i) {
+      if ((rc = site_evolve(i))) return rc;
+      if (i == 1) break;
+      if ((rc = timed(inf.t_svd, [&] { return gauge_qr(ctx, m, i, -1, x, xbuf, qbuf); }))) return rc;
+      if ((rc = timed(inf.t_env, [&] { return env_step_sync(ctx, m, i, -1, &inf); }))) return rc;
+      if ((rc = timed(inf.t_lanczos, [&] { return evolve_bond(ctx, m, i, -1, x, +tau, *tr, &inf); }))) return rc;
+      if ((rc = absorb(ctx, m, i, -1, x))) return rc;
+    }
+    TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (int k = 0; k <= L; ++k) {
+      inf.max_chi = std::max(inf.max_chi, m->bonds[k].chi_full());
+      inf.max_chi_su2 = std::max(inf.max_chi_su2, m->bonds[k].chi_su2());
+    }
+    inf.seconds = now() - t0;
+    if (info) *info = inf;
+    return TDVP_OK;
+  });
+}

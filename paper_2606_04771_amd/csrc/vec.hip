@@ -170,6 +170,24 @@ __global__ __launch_bounds__(NT) void k_block_dots(const double2* __restrict__ x
   if (threadIdx.x == 0) out[blockIdx.x] = make_double2(re, im);
 }
 
+// n x n matrix whose leading g x g block is set: the rest becomes the identity
+__global__ __launch_bounds__(NT) void k_pad_identity(double2* __restrict__ A, int64_t n, int64_t g) {
+  int64_t tot = n * n;
+  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < tot; e += (int64_t)gridDim.x * NT) {
+    int64_t i = e % n, j = e / n;
+    if (i >= g || j >= g) A[e] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+}
+
+// strictly lower triangle of `count` consecutive n x n matrices set to zero
+__global__ __launch_bounds__(NT) void k_zero_lower(double2* __restrict__ A, int64_t n, int64_t count) {
+  int64_t tot = n * n * count;
+  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < tot; e += (int64_t)gridDim.x * NT) {
+    int64_t r = e % (n * n), i = r % n, j = r / n;
+    if (i > j) A[e] = make_double2(0.0, 0.0);
+  }
+}
+
 // scale[0] = largest |A_ii| of the leading g x g block (one workgroup)
 __global__ __launch_bounds__(NT) void k_diag_max(const double2* __restrict__ A, int64_t n, int64_t g,
                                                  double* __restrict__ scale) {
@@ -281,6 +299,20 @@ int vec_block_dots(tdvp_ctx* ctx, const double* x, const double* y, const int64_
   if (nblocks <= 0) return TDVP_OK;
   hipLaunchKernelGGL(k_block_dots, dim3(nblocks), dim3(NT), 0, ctx->stream, (const double2*)x, (const double2*)y,
                      d_meta, (double2*)d_out);
+  TDVP_HIP(ctx, hipGetLastError());
+  return TDVP_OK;
+}
+
+int vec_pad_identity(tdvp_ctx* ctx, double* A, int64_t n, int64_t g) {
+  if (g >= n) return TDVP_OK;
+  hipLaunchKernelGGL(k_pad_identity, dim3(grid_1d(n * n)), dim3(NT), 0, ctx->stream, (double2*)A, n, g);
+  TDVP_HIP(ctx, hipGetLastError());
+  return TDVP_OK;
+}
+
+int vec_zero_lower(tdvp_ctx* ctx, double* A, int64_t n, int64_t count) {
+  if (n <= 1 || count <= 0) return TDVP_OK;
+  hipLaunchKernelGGL(k_zero_lower, dim3(grid_1d(n * n * count)), dim3(NT), 0, ctx->stream, (double2*)A, n, count);
   TDVP_HIP(ctx, hipGetLastError());
   return TDVP_OK;
 }

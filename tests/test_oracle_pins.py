@@ -325,6 +325,65 @@ def test_complete_basis_time_reversal():
     assert abs(abs(np.vdot(psi, D.mps_state(mps))) - 1) < 1e-12
 
 
+@pytest.mark.parametrize("L,nsteps", [(4, 3), (6, 1)])
+def test_complete_basis_one_site_tdvp_equals_exact_evolution(L, nsteps):
+    """With complete bond bases the one-site tangent-space projector is the
+    identity, so one-site TDVP is exact too."""
+    t, U, dt = 1.0, 4.0, 0.05
+    psi0 = F.neel_state(L)
+    mps = D.complete_right_canonical(psi0, L)
+    H = F.hubbard(L, t, U, symmetric=True)
+    exact = F.evolve(H, psi0, np.arange(nsteps + 1) * dt)
+    for n in range(nsteps):
+        mps = D.tdvp1_sweep(mps, dt, t, U, tol=1e-13)
+        v = D.mps_state(mps)
+        assert abs(abs(np.vdot(exact[n + 1], v)) - 1) < 1e-12
+        assert np.abs(F.local_expectations(v, L)[0] - F.local_expectations(exact[n + 1], L)[0]).max() < 1e-12
+
+
+def test_one_site_tdvp_time_reversal_and_conservation_at_fixed_bond():
+    """At a bond dimension below the maximal one (a truncated random state),
+    one-site TDVP keeps the norm and the energy exactly (projector splitting
+    of a Hermitian generator) and a step of -dt undoes a step of +dt to the
+    Krylov tolerance."""
+    L, t, U = 6, 1.0, 4.0
+    rng = np.random.default_rng(9)
+    psi = rng.normal(size=4 ** L) + 1j * rng.normal(size=4 ** L)
+    psi /= np.linalg.norm(psi)
+    mps = D.complete_right_canonical(psi, L)
+    # cut every bond to at most 6 states (SVD truncation from the right, renormalised)
+    v = D.mps_state(mps).reshape([4] * L)
+    cut = []
+    rest = v.reshape(1, -1)
+    for k in range(L - 1):
+        a = rest.shape[0]
+        U_, S, Vh = np.linalg.svd(rest.reshape(a * 4, -1), full_matrices=False)
+        keep = min(6, S.size)
+        cut.append(U_[:, :keep].reshape(a, 4, keep))
+        rest = (S[:keep, None] * Vh[:keep])
+    cut.append(rest.reshape(-1, 4, 1))
+    # right-canonical form of the truncated chain by LQ steps from the right
+    start = list(cut)
+    for k in range(L - 1, 0, -1):
+        a, _, b = start[k].shape
+        Q, Rm = np.linalg.qr(start[k].reshape(a, 4 * b).conj().T)
+        start[k] = Q.conj().T.reshape(-1, 4, b)
+        start[k - 1] = np.tensordot(start[k - 1], Rm.conj().T, axes=([2], [0]))
+    start[0] = start[0] / np.linalg.norm(start[0])
+    phi = D.mps_state(start)
+    bonds = [m.shape[2] for m in start[:-1]]
+    assert max(bonds) == 6 and abs(np.linalg.norm(phi) - 1) < 1e-12
+    H = F.hubbard(L, t, U, symmetric=True)
+    e0 = np.vdot(phi, H @ phi).real
+    fwd = D.tdvp1_sweep(start, 0.1, t, U, tol=1e-14)
+    w = D.mps_state(fwd)
+    assert [m.shape[2] for m in fwd[:-1]] == bonds
+    assert abs(np.linalg.norm(w) - 1) < 1e-12
+    assert abs(np.vdot(w, H @ w).real - e0) < 1e-10
+    back = D.tdvp1_sweep(fwd, -0.1, t, U, tol=1e-14)
+    assert abs(abs(np.vdot(phi, D.mps_state(back))) - 1) < 1e-10
+
+
 # --------------------------------------------------------------------------
 # Paper-printed values
 # --------------------------------------------------------------------------
