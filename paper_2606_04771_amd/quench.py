@@ -1,0 +1,101 @@
+"""Neel-quench driver: the L-site Fermi-Hubbard chain from the Neel state,
+evolved by symmetric second-order TDVP in full precision and with FP32 block
+products side by side, comparing the site-resolved <S^z_i> (= (<n_up> -
+<n_down>)/2) and <n_up n_down> after every time step.
+
+Two-site sweeps let the bond dimension grow (truncation: discarded weight
+eps_tol, cap chi in full-state units); once it has saturated the driver
+switches to one-site sweeps (the adaptive scheme of supplementary section
+S2.2), the two precisions switching at the same step.
+
+    python -m paper_2606_04771_amd.quench --L 60 --chi 4096 --t-end 6 --out quench.jsonl
+
+Each step prints one JSON line (time, sweep kind, seconds per precision,
+largest bond, max |d<S^z>|, max |d<n_up n_dn>|, |psi_64 - psi_32|)."""
+import argparse
+import json
+import sys
+import time
+
+
+def chi_full(bond):
+    return sum(d * (tj + 1) for _, tj, d in bond)
+
+
+def main(argv=None):
+    import numpy as np
+    import paper_2606_04771_amd as T
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--L", type=int, default=60)
+    ap.add_argument("--U", type=float, default=4.0)
+    ap.add_argument("--chi", type=int, default=4096)
+    ap.add_argument("--dt", type=float, default=0.05)
+    ap.add_argument("--t-end", type=float, default=6.0)
+    ap.add_argument("--eps", type=float, default=1e-4)
+    ap.add_argument("--krylov-tol", type=float, default=1e-10)
+    ap.add_argument("--switch", type=float, default=0.97,
+                    help="switch to one-site sweeps once the largest bond reaches this fraction of the cap")
+    ap.add_argument("--no-switch", action="store_true")
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args(argv)
+
+    model = T.Model(a.L, 1.0, a.U)
+    runs = {}
+    for name, prec in (("fp64", T.FP64), ("fp32", T.FP32)):
+        ctx = T.Context(0, precision=prec)
+        runs[name] = (ctx, T.MPS.neel(ctx, model, complete=False))
+    out = open(a.out, "w") if a.out else None
+    nsteps = int(round(a.t_end / a.dt))
+    one_site = False
+    worst = {"d_sz": 0.0, "d_docc": 0.0, "state_err": 0.0}
+    tot = {"fp64": 0.0, "fp32": 0.0}
+    for n in range(1, nsteps + 1):
+        rec = {"t": round(n * a.dt, 10), "kind": "one-site" if one_site else "two-site"}
+        obs = {}
+        for name, (ctx, mps) in runs.items():
+            t0 = time.time()
+            if one_site:
+                info = mps.sweep1(a.dt, krylov_tol=a.krylov_tol, krylov_maxdim=40)
+            else:
+                info = mps.sweep(a.dt, eps_tol=a.eps, chi_cap=a.chi, krylov_tol=a.krylov_tol, krylov_maxdim=40)
+            ctx.synchronize()
+            rec[f"s_{name}"] = time.time() - t0
+            tot[name] += rec[f"s_{name}"]
+            rec[f"chi_{name}"] = int(info["max_chi"])
+            rec[f"disc_{name}"] = float(info["max_discarded"])
+            obs[name] = mps.measure()
+        m64, m32 = runs["fp64"][1], runs["fp32"][1]
+        ov = m64.overlap(m32)
+        n1, n2 = m64.overlap(m64).real, m32.overlap(m32).real
+        rec["state_err"] = float(np.sqrt(max(n1 + n2 - 2 * ov.real, 0.0)))
+        rec["d_sz"] = float(np.abs(obs["fp64"][0] - obs["fp32"][0]).max())
+        rec["d_docc"] = float(np.abs(obs["fp64"][1] - obs["fp32"][1]).max())
+        rec["sz_mid"] = float(obs["fp64"][0][a.L // 2 - 1])
+        rec["docc_mid"] = float(obs["fp64"][1][a.L // 2 - 1])
+        for k in worst:
+            worst[k] = max(worst[k], rec[k])
+        line = json.dumps(rec)
+        print(line, flush=True)
+        if out:
+            out.write(line + "\n")
+            out.flush()
+        if not one_site and not a.no_switch:
+            big = max(chi_full(m64.bond(k)) for k in range(1, a.L))
+            if big >= a.switch * a.chi:
+                one_site = True
+    summary = {"summary": True, "L": a.L, "U": a.U, "chi_cap": a.chi, "dt": a.dt, "t_end": a.t_end,
+               "eps_tol": a.eps, "max_obs_err": max(worst["d_sz"], worst["d_docc"]), **worst,
+               "seconds_fp64": tot["fp64"], "seconds_fp32": tot["fp32"],
+               "s_per_sweep_fp64": tot["fp64"] / nsteps, "s_per_sweep_fp32": tot["fp32"] / nsteps}
+    print(json.dumps(summary), flush=True)
+    if out:
+        out.write(json.dumps(summary) + "\n")
+    for ctx, mps in runs.values():
+        mps.close()
+        ctx.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
