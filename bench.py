@@ -170,7 +170,7 @@ def main():
 
     heff_by_prec = {}
     ys = {}
-    for name, p in (("fp64", T.FP64), ("fp32", T.FP32)):
+    for name, p in (("fp64", T.FP64), ("fp32", T.FP32), ("bf16x3", T.BF16X3)):
         d, ys[name] = time_applies(p)
         heff_by_prec[name] = {"ms_per_apply": 1e3 * float(np.mean(d)), "ms_min": 1e3 * float(d.min()),
                               "tflops": flops / float(np.mean(d)) / 1e12}

@@ -77,9 +77,16 @@ enum {
   TDVP_E_NONFINITE = -7  /* NaN or Inf met in the data */
 };
 
-/* Arithmetic of the block contractions.  Lanczos scalars, reorthogonalisation,
- * the small exponential and the SVD stay in FP64 in every mode. */
-enum { TDVP_FP64 = 0, TDVP_FP32 = 1 };
+/* Arithmetic of the block contractions (effective-Hamiltonian applies and
+ * environment updates).  TDVP_FP32: FP32 operands and accumulation.
+ * TDVP_BF16X3: each operand value split into three bfloat16 slices, the six
+ * leading slice products of every real product accumulated in FP32 (about
+ * FP32 accuracy on the bfloat16 matrix cores).  In both reduced modes the
+ * block-Hamiltonian environment channels are shifted by their mean diagonal
+ * and the shift is added back exactly.  Lanczos scalars, reorthogonalisation,
+ * the small exponential, the SVD/QR splits and all local terms stay in FP64 in
+ * every mode. */
+enum { TDVP_FP64 = 0, TDVP_FP32 = 1, TDVP_BF16X3 = 2 };
 
 typedef struct tdvp_ctx tdvp_ctx;
 typedef struct tdvp_mps tdvp_mps;
@@ -168,7 +175,7 @@ typedef struct {
 
 /* ---- context -------------------------------------------------------------
  * device: HIP device ordinal; hip_stream: hipStream_t or NULL (the library
- * then creates its own default-priority stream); precision: TDVP_FP64/FP32. */
+ * then creates its own default-priority stream); precision: TDVP_FP64/FP32/BF16X3. */
 int tdvp_ctx_create(tdvp_ctx** out, int32_t device, void* hip_stream, int32_t precision);
 void tdvp_ctx_destroy(tdvp_ctx* ctx);
 int tdvp_ctx_set_precision(tdvp_ctx* ctx, int32_t precision);

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libtdvp.so")
 
 TDVP_OK = 0
 ERRORS = {-1: "INVALID", -2: "SHAPE", -3: "SECTOR", -4: "NOMEM", -5: "HIP", -6: "NOCONV", -7: "NONFINITE"}
-FP64, FP32 = 0, 1
+FP64, FP32, BF16X3 = 0, 1, 2
 
 
 class TdvpError(RuntimeError):

@@ -280,7 +280,7 @@ int tdvp_ctx_create(tdvp_ctx** out, int32_t device, void* hip_stream, int32_t pr
   return guarded(nullptr, [&]() -> int {
     if (!out) return set_error(nullptr, TDVP_E_INVALID, "out is null");
     *out = nullptr;
-    if (precision != TDVP_FP64 && precision != TDVP_FP32)
+    if (precision != TDVP_FP64 && precision != TDVP_FP32 && precision != TDVP_BF16X3)
       return set_error(nullptr, TDVP_E_INVALID, "unknown precision");
     int n = 0;
     hipError_t e = hipGetDeviceCount(&n);
@@ -338,7 +338,7 @@ void tdvp_ctx_destroy(tdvp_ctx* ctx) {
 
 int tdvp_ctx_set_precision(tdvp_ctx* ctx, int32_t precision) {
   if (!ctx) return set_error(nullptr, TDVP_E_INVALID, "null ctx");
-  if (precision != TDVP_FP64 && precision != TDVP_FP32)
+  if (precision != TDVP_FP64 && precision != TDVP_FP32 && precision != TDVP_BF16X3)
     return set_error(ctx, TDVP_E_INVALID, "unknown precision");
   ctx->precision = precision;
   return TDVP_OK;

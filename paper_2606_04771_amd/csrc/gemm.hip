@@ -269,6 +269,200 @@ __device__ __forceinline__ void gemm_body(const Bufs& bufs, double* __restrict__
       }
 }
 
+// ---------------------------------------------------------------------------
+// Split-BF16 products (Ozaki-style): every staged operand value (after its
+// coefficient, in FP64) is cut into three bfloat16 slices v = v1 + v2 + v3
+// (each the round-to-nearest of the remainder, through FP32), and each real
+// product keeps the six slice products with slice indices summing to at most
+// four, accumulated in FP32 on v_mfma_f32_16x16x32_bf16.  Lane layout of that
+// instruction: A[i][k] for i = lane % 16 and k = 8 (lane / 16) .. +7 (one
+// 16-byte vector), B[k][j] likewise with j = lane % 16, D as the FP32 16x16x4
+// one.  LDS keeps, per slice and real/imaginary plane, rows of K = 32
+// contiguous values.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int TKB = 32, PADB = 8;
+
+__device__ __forceinline__ void slice3(double v, __bf16& s1, __bf16& s2, __bf16& s3) {
+  const float f = (float)v;
+  s1 = (__bf16)f;
+  const float r1 = f - (float)s1;
+  s2 = (__bf16)r1;
+  s3 = (__bf16)(r1 - (float)s2);
+}
+
+__device__ __forceinline__ bf16x8 neg8(bf16x8 v) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q) v[q] = -v[q];
+  return v;
+}
+
+template <bool SH>
+__device__ __forceinline__ void gemm_body_b3(const Bufs& bufs, double* __restrict__ Cbase,
+                                             double2* __restrict__ part, const DevTile* __restrict__ tiles,
+                                             const DevOut* __restrict__ outs, const DevTerm* __restrict__ terms) {
+  constexpr int TM = 64, TN = 64;
+  typedef f32x4 acc_t;
+  __shared__ __attribute__((aligned(16))) __bf16 As[3][2][TM][TKB + PADB];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[3][2][TN][TKB + PADB];
+  const DevTile tl = tiles[blockIdx.x];
+  const DevOut ob = outs[tl.out];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / 2, wn = wave % 2;
+  const int li = lane & 15, lk = lane >> 4;
+  bool rv[2], cv[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    rv[i] = tl.m0 + wm * 32 + i * 16 < ob.M;
+    cv[i] = tl.n0 + wn * 32 + i * 16 < ob.N;
+  }
+  acc_t accr[2][2], acci[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      accr[i][j] = acc_t{0, 0, 0, 0};
+      acci[i][j] = acc_t{0, 0, 0, 0};
+    }
+  // staging: this thread owns row sr of the A and B tiles and 8 consecutive k
+  const int sr = tid % 64, kg = tid / 64;
+  int t = tl.t0, k0 = tl.k0;
+  while (before(t, k0, tl.t1, tl.k1)) {
+    const DevTerm tm = terms[t];
+    {
+      const double2* A = reinterpret_cast<const double2*>(bufs.p[tm.a_buf]) + tm.a_off;
+      const double2* B = reinterpret_cast<const double2*>(bufs.p[tm.b_buf]) + tm.b_off;
+      const bool ta = tm.ops & 1, ca = tm.ops & 2, tb = tm.ops & 4, cb = tm.ops & 8;
+      const double c = tm.coef;
+      bf16x8 a[3][2], b[3][2];
+      const int gm = tl.m0 + sr, gn = tl.n0 + sr;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int gk = k0 + 8 * kg + q;
+        double2 va = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
+        if (gm < ob.M && gk < tm.K) {
+          va = ta ? A[(int64_t)gk + (int64_t)gm * tm.lda] : A[(int64_t)gm + (int64_t)gk * tm.lda];
+          if (SH && (tm.ops & 16) && gm == gk) va.x -= bufs.shift[0];
+        }
+        if (gn < ob.N && gk < tm.K) {
+          vb = tb ? B[(int64_t)gn + (int64_t)gk * tm.ldb] : B[(int64_t)gk + (int64_t)gn * tm.ldb];
+          if (SH && (tm.ops & 32) && gn == gk) vb.x -= bufs.shift[1];
+        }
+        __bf16 s1, s2, s3;
+        slice3(c * va.x, s1, s2, s3);
+        a[0][0][q] = s1; a[1][0][q] = s2; a[2][0][q] = s3;
+        slice3(ca ? -c * va.y : c * va.y, s1, s2, s3);
+        a[0][1][q] = s1; a[1][1][q] = s2; a[2][1][q] = s3;
+        slice3(vb.x, s1, s2, s3);
+        b[0][0][q] = s1; b[1][0][q] = s2; b[2][0][q] = s3;
+        slice3(cb ? -vb.y : vb.y, s1, s2, s3);
+        b[0][1][q] = s1; b[1][1][q] = s2; b[2][1][q] = s3;
+      }
+#pragma unroll
+      for (int sl = 0; sl < 3; ++sl)
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          *reinterpret_cast<bf16x8*>(&As[sl][p][sr][8 * kg]) = a[sl][p];
+          *reinterpret_cast<bf16x8*>(&Bs[sl][p][sr][8 * kg]) = b[sl][p];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      if (!rv[i]) continue;
+      bf16x8 ar[3], ai[3], nai[3];
+#pragma unroll
+      for (int sl = 0; sl < 3; ++sl) {
+        ar[sl] = *reinterpret_cast<const bf16x8*>(&As[sl][0][wm * 32 + i * 16 + li][8 * lk]);
+        ai[sl] = *reinterpret_cast<const bf16x8*>(&As[sl][1][wm * 32 + i * 16 + li][8 * lk]);
+        nai[sl] = neg8(ai[sl]);
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        if (!cv[j]) continue;
+        bf16x8 br[3], bi[3];
+#pragma unroll
+        for (int sl = 0; sl < 3; ++sl) {
+          br[sl] = *reinterpret_cast<const bf16x8*>(&Bs[sl][0][wn * 32 + j * 16 + li][8 * lk]);
+          bi[sl] = *reinterpret_cast<const bf16x8*>(&Bs[sl][1][wn * 32 + j * 16 + li][8 * lk]);
+        }
+        // slice pairs (0,0) (0,1) (1,0) (0,2) (1,1) (2,0), smallest last
+#pragma unroll
+        for (int pp = 5; pp >= 0; --pp) {
+          const int x = pp == 0 ? 0 : pp == 1 ? 0 : pp == 2 ? 1 : pp == 3 ? 0 : pp == 4 ? 1 : 2;
+          const int y = pp == 0 ? 0 : pp == 1 ? 1 : pp == 2 ? 0 : pp == 3 ? 2 : pp == 4 ? 1 : 0;
+          accr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar[x], br[y], accr[i][j], 0, 0, 0);
+          acci[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar[x], bi[y], acci[i][j], 0, 0, 0);
+          accr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nai[x], bi[y], accr[i][j], 0, 0, 0);
+          acci[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[x], br[y], acci[i][j], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+    k0 += TKB;
+    if (k0 >= tm.K) {
+      k0 = 0;
+      ++t;
+    }
+  }
+
+  if (tl.slot >= 0) {
+    double2* P = part + (int64_t)tl.slot * kSlotDim * kSlotDim;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int lr = wm * 32 + i * 16 + 4 * lk + r;
+          int lc = wn * 32 + j * 16 + li;
+          if (tl.m0 + lr < ob.M && tl.n0 + lc < ob.N)
+            P[lr + lc * kSlotDim] = make_double2((double)accr[i][j][r], (double)acci[i][j][r]);
+        }
+    return;
+  }
+  double2* C = reinterpret_cast<double2*>(Cbase) + ob.c_off;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int row = tl.m0 + wm * 32 + i * 16 + 4 * lk + r;
+        int col = tl.n0 + wn * 32 + j * 16 + li;
+        if (row < ob.M && col < ob.N) {
+          double vr = accr[i][j][r], vi = acci[i][j][r];
+          for (int d = ob.d_begin; d < ob.d_end; ++d) {
+            const DevTerm dt = terms[d];
+            if (!SH && (dt.ops & 48)) continue;
+            const int64_t idx = (dt.ops & 1) ? (int64_t)col + (int64_t)row * dt.lda
+                                             : (int64_t)row + (int64_t)col * dt.lda;
+            const double2 xv = (reinterpret_cast<const double2*>(bufs.p[dt.a_buf]) + dt.a_off)[idx];
+            double cc = dt.coef;
+            if (SH && (dt.ops & 16)) cc *= bufs.shift[0];
+            if (SH && (dt.ops & 32)) cc *= bufs.shift[1];
+            vr += cc * xv.x;
+            vi += (dt.ops & 2) ? -cc * xv.y : cc * xv.y;
+          }
+          C[(int64_t)row + (int64_t)col * ob.ldc] = make_double2(vr, vi);
+        }
+      }
+}
+
+template <bool SH>
+__global__ __launch_bounds__(256) void heff_gemm_b3(Bufs bufs, double* __restrict__ C, double2* __restrict__ part,
+                                                    const DevTile* __restrict__ tiles,
+                                                    const DevOut* __restrict__ outs,
+                                                    const DevTerm* __restrict__ terms) {
+  gemm_body_b3<SH>(bufs, C, part, tiles, outs, terms);
+}
+template <bool SH>
+__global__ __launch_bounds__(256) void block_gemm_b3(Bufs bufs, double* __restrict__ C, double2* __restrict__ part,
+                                                     const DevTile* __restrict__ tiles,
+                                                     const DevOut* __restrict__ outs,
+                                                     const DevTerm* __restrict__ terms) {
+  gemm_body_b3<SH>(bufs, C, part, tiles, outs, terms);
+}
+
 // Diagonal shifts of a reduced-precision launch: out[s] = sum_b w_b tr(E_b) /
 // sum_b w_b d_b over the listed diagonal blocks of operand buffer 1 + s.
 // First pass: one workgroup per listed block writes w_b tr(E_b) and w_b d_b.
@@ -697,11 +891,23 @@ int launch_gemm(tdvp_ctx* ctx, const Program& p, const Bufs& bufs, double* C, in
     bf.shift = out;
   }
   if (p.n64 > 0) {
-    if (precision == TDVP_FP32) launch_one<float, 2, 2>(ctx, heff, p.n64, bf, C, part, p.d_tiles, p);
-    else launch_one<double, 2, 2>(ctx, heff, p.n64, bf, C, part, p.d_tiles, p);
+    if (precision == TDVP_BF16X3) {
+      const dim3 g(p.n64), bl(256);
+      if (bf.shift) {
+        if (heff) hipLaunchKernelGGL((heff_gemm_b3<true>), g, bl, 0, ctx->stream, bf, C, part, p.d_tiles, p.d_outs, p.d_terms);
+        else hipLaunchKernelGGL((block_gemm_b3<true>), g, bl, 0, ctx->stream, bf, C, part, p.d_tiles, p.d_outs, p.d_terms);
+      } else {
+        if (heff) hipLaunchKernelGGL((heff_gemm_b3<false>), g, bl, 0, ctx->stream, bf, C, part, p.d_tiles, p.d_outs, p.d_terms);
+        else hipLaunchKernelGGL((block_gemm_b3<false>), g, bl, 0, ctx->stream, bf, C, part, p.d_tiles, p.d_outs, p.d_terms);
+      }
+    } else if (precision == TDVP_FP32) {
+      launch_one<float, 2, 2>(ctx, heff, p.n64, bf, C, part, p.d_tiles, p);
+    } else {
+      launch_one<double, 2, 2>(ctx, heff, p.n64, bf, C, part, p.d_tiles, p);
+    }
   }
-  if (n32 > 0) {
-    if (precision == TDVP_FP32) launch_one<float, 1, 1>(ctx, heff, n32, bf, C, part, t32, p);
+  if (n32 > 0) {   // 32x32 tiles (optional tile modes) have no split-BF16 variant: FP32 there
+    if (precision != TDVP_FP64) launch_one<float, 1, 1>(ctx, heff, n32, bf, C, part, t32, p);
     else launch_one<double, 1, 1>(ctx, heff, n32, bf, C, part, t32, p);
   }
   if (!p.reds.empty())

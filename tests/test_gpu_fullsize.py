@@ -76,19 +76,26 @@ def test_fullsize_heff_sampled_blocks_fp64_and_fp32(problem):
     p = problem
     y64 = _apply(p, p["dev"]["x"], T.FP64)
     y32 = _apply(p, p["dev"]["x"], T.FP32)
+    yb3 = _apply(p, p["dev"]["x"], T.BF16X3)
     assert np.isfinite(y64).all()
+    print(f"norm-wise vs FP64: fp32 {np.linalg.norm(y32 - y64) / np.linalg.norm(y64):.2e} "
+          f"bf16x3 {np.linalg.norm(yb3 - y64) / np.linalg.norm(y64):.2e}", flush=True)
     ys64 = dict(zip([tuple(int(v) for v in k) for k in p["xk"]], unpack(y64, p["xo"], p["xd"])))
     ys32 = dict(zip([tuple(int(v) for v in k) for k in p["xk"]], unpack(y32, p["xo"], p["xd"])))
-    worst64 = worst32 = 0.0
+    ysb3 = dict(zip([tuple(int(v) for v in k) for k in p["xk"]], unpack(yb3, p["xo"], p["xd"])))
+    worst64 = worst32 = worstb3 = 0.0
     for key in _samples(p):
         ref, dims = S.heff2_block(p["left"], p["right"], p["Lb"], p["Rb"], p["X"], key, SITE, t_h, U)
         scale = max(np.abs(ref).max(), 1e-300)
         e64 = np.abs(ys64[key] - ref).max() / scale
         e32 = np.abs(ys32[key] - ref).max() / scale
-        print(f"block {key} dims {ref.shape} restricted {dims}: fp64 {e64:.2e} fp32 {e32:.2e}", flush=True)
-        worst64, worst32 = max(worst64, e64), max(worst32, e32)
+        eb3 = np.abs(ysb3[key] - ref).max() / scale
+        print(f"block {key} dims {ref.shape} restricted {dims}: fp64 {e64:.2e} fp32 {e32:.2e} bf16x3 {eb3:.2e}",
+              flush=True)
+        worst64, worst32, worstb3 = max(worst64, e64), max(worst32, e32), max(worstb3, eb3)
     assert worst64 < 1e-12
     assert worst32 < 2e-5
+    assert worstb3 < 2e-5
 
 
 def test_fullsize_heff_linearity_and_determinism(problem):

@@ -63,7 +63,7 @@ def _heff_case(site, nsites, seed):
     return left, right, bl, br, (xk, xo, xt, xd, xs), (lk, lo, lt, ld, Ls), (rk, ro, rt, rd, Rs)
 
 
-@pytest.mark.parametrize("site,prec", [(3, T.FP64), (4, T.FP64), (3, T.FP32)])
+@pytest.mark.parametrize("site,prec", [(3, T.FP64), (4, T.FP64), (3, T.FP32), (3, T.BF16X3), (4, T.BF16X3)])
 def test_heff_two_site(ctx, site, prec):
     t, U = 1.0, 4.0
     print(f"heff2 site={site} prec={prec}", flush=True)
