@@ -88,6 +88,21 @@ struct Program {
   int tile_mode = 0;        // 0: per output block the better of 64x64 / 32x32; 1: all 32x32; 2: all 64x64
   int n64 = 0;              // tiles[0, n64) are 64x64 (four waves), the rest 32x32 (one wave)
   int role = 0;             // 1: effective-Hamiltonian apply (launched under its own kernel name)
+  // Autotuning (effective-Hamiltonian programs): alternative tilings of the
+  // same term lists, each launched on real work while measured with events;
+  // the fastest replaces the active one.  All keep the per-element summation
+  // order, so results do not depend on the choice.
+  struct Tiling {
+    std::vector<DevTile> tiles;
+    int n64 = 0;
+    int mode = 0;
+    DevTile* d_tiles = nullptr;
+  };
+  std::vector<Tiling> alt;            // candidates (index 0 = the active tiling as built)
+  mutable int tune_next = 0;          // launches issued so far while tuning
+  mutable int tuned = -1;             // chosen candidate, -1 while measuring
+  mutable std::vector<hipEvent_t> tune_ev;
+  static constexpr int kTuneRounds = 2;
   // device copies
   DevTerm* d_terms = nullptr;
   DevOut* d_outs = nullptr;
@@ -98,6 +113,8 @@ struct Program {
   ~Program();
   // tile the outputs, split long K chains, order work items by decreasing cost
   void finalize();
+  // tiling of the outputs for a tile mode (no K-chain splitting), ordered for the XCDs
+  void tile_only(int mode, Tiling& out) const;
 };
 
 struct DeviceBuffer {
@@ -156,6 +173,8 @@ void cache_put(tdvp_ctx* ctx, uint64_t key, std::shared_ptr<Program> p);
 // Launch the grouped GEMM of p writing into C (base pointer of the output
 // buffer) with operand buffers bufs.  precision: TDVP_FP64 or TDVP_FP32.
 int launch_gemm(tdvp_ctx* ctx, const Program& p, const Bufs& bufs, double* C, int precision);
+// The same with the program's active tiling, no autotuning.
+int launch_gemm_tiles(tdvp_ctx* ctx, const Program& p, const Bufs& bufs, double* C, int precision);
 
 // Lanczos vector kernels (complex128 vectors of n elements).
 int vec_dots(tdvp_ctx* ctx, const double* V, int64_t stride, int nv, const double* w, int64_t n,

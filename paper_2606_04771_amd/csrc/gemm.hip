@@ -572,6 +572,8 @@ void launch_one(tdvp_ctx* ctx, bool heff, int ntiles, const Bufs& bufs, double* 
 }  // namespace
 
 Program::~Program() {
+  for (hipEvent_t e : tune_ev)
+    if (e) (void)hipEventDestroy(e);
   if (!d_mem) return;
   if (pool) pool->free[cls].push_back(d_mem);
   else (void)hipFree(d_mem);
@@ -782,6 +784,56 @@ void Program::finalize() {
   n64 = (int)out64.size();
   for (const Item& it : xcd_order(out64)) tiles.push_back(it.t);
   for (const Item& it : xcd_order(out32)) tiles.push_back(it.t);
+  // autotuning candidates for effective-Hamiltonian programs without split chains
+  alt.clear();
+  static const bool autotune = [] {
+    const char* e = std::getenv("TDVP_AUTOTUNE");
+    return !(e && std::atoi(e) == 0);
+  }();
+  if (autotune && role == 1 && nslots == 0) {
+    Tiling a0;
+    a0.tiles = tiles;
+    a0.n64 = n64;
+    a0.mode = tile_mode;
+    alt.push_back(a0);
+    for (int mode : {1, 0, 2})
+      if (mode != tile_mode) {
+        Tiling a;
+        tile_only(mode, a);
+        alt.push_back(a);
+      }
+  }
+}
+
+void Program::tile_only(int mode, Tiling& out) const {
+  struct It {
+    DevTile t;
+    double cost;
+  };
+  std::vector<It> t64, t32;
+  const double thr = tile_threshold();
+  for (int o = 0; o < (int)outs.size(); ++o) {
+    const DevOut& ob = outs[o];
+    double kc = 0;
+    for (int t = ob.t_begin; t < ob.t_end; ++t) kc += (terms[t].K + 3) / 4 * 4;
+    bool big = mode == 2 || (mode == 0 && tile_use(ob.M, ob.N, 64) >= thr * tile_use(ob.M, ob.N, 32));
+    int tt = big ? 64 : 32;
+    for (int m0 = 0; m0 < ob.M; m0 += tt)
+      for (int n0 = 0; n0 < ob.N; n0 += tt) {
+        double am = (double)((std::min(tt, ob.M - m0) + 15) / 16 * 16);
+        double an = (double)((std::min(tt, ob.N - n0) + 15) / 16 * 16);
+        It it{DevTile{o, m0, n0, -1, ob.t_begin, 0, ob.t_end, 0}, am * an * (kc + 4.0 * (ob.d_end - ob.d_begin)) + 1.0};
+        (big ? t64 : t32).push_back(it);
+      }
+  }
+  auto bycost = [](const It& a, const It& b) { return a.cost > b.cost; };
+  std::stable_sort(t64.begin(), t64.end(), bycost);
+  std::stable_sort(t32.begin(), t32.end(), bycost);
+  out.tiles.clear();
+  out.n64 = (int)t64.size();
+  out.mode = mode;
+  for (const It& it : xcd_order(t64)) out.tiles.push_back(it.t);
+  for (const It& it : xcd_order(t32)) out.tiles.push_back(it.t);
 }
 
 DeviceBuffer::~DeviceBuffer() {
@@ -807,6 +859,7 @@ int upload(tdvp_ctx* ctx, Program& p) {
          bl = p.tiles.size() * sizeof(DevTile), br = p.reds.size() * sizeof(DevRed),
          bs = p.shift_meta.size() * sizeof(int64_t);
   size_t total = bt + bo + bl + br + bs + 5 * 256;
+  for (auto& a : p.alt) total += a.tiles.size() * sizeof(DevTile) + 256;
   if (p.d_mem) {
     if (p.pool) p.pool->free[p.cls].push_back(p.d_mem);
     else TDVP_HIP(ctx, hipFree(p.d_mem));
@@ -845,8 +898,14 @@ int upload(tdvp_ctx* ctx, Program& p) {
   if (bl) std::memcpy(h + align(bt) + align(bo), p.tiles.data(), bl);
   if (br) std::memcpy(h + align(bt) + align(bo) + align(bl), p.reds.data(), br);
   if (bs) std::memcpy(h + align(bt) + align(bo) + align(bl) + align(br), p.shift_meta.data(), bs);
-  TDVP_HIP(ctx, hipMemcpyAsync(p.d_mem, h, align(bt) + align(bo) + align(bl) + align(br) + bs,
-                               hipMemcpyHostToDevice, ctx->stream));
+  size_t used = align(bt) + align(bo) + align(bl) + align(br) + align(bs);
+  for (auto& a : p.alt) {
+    const size_t ba = a.tiles.size() * sizeof(DevTile);
+    a.d_tiles = (DevTile*)(base + used);
+    if (ba) std::memcpy(h + used, a.tiles.data(), ba);
+    used += align(ba);
+  }
+  TDVP_HIP(ctx, hipMemcpyAsync(p.d_mem, h, used, hipMemcpyHostToDevice, ctx->stream));
   if (!ctx->upload_done) TDVP_HIP(ctx, hipEventCreateWithFlags(&ctx->upload_done, hipEventDisableTiming));
   TDVP_HIP(ctx, hipEventRecord(ctx->upload_done, ctx->stream));
   return TDVP_OK;
@@ -867,15 +926,80 @@ void cache_put(tdvp_ctx* ctx, uint64_t key, std::shared_ptr<Program> p) {
   while (ctx->cache.size() > 24) ctx->cache.pop_back();
 }
 
+static int launch_core(tdvp_ctx* ctx, const Program& p, int ntiles, int n64, const DevTile* d_tiles,
+                       const Bufs& bufs, double* C, int precision);
+
+// Autotuner step: which tiling this launch uses, with its events.  Every
+// candidate is launched kTuneRounds times, each bracketed by events; at the
+// first launch after the last measurement (the caller has synchronised in
+// between, as the Krylov loop does every iteration; otherwise this waits) the
+// fastest total wins.
+static int tune_pick(tdvp_ctx* ctx, const Program& p, hipEvent_t*& ev0, hipEvent_t*& ev1) {
+  ev0 = ev1 = nullptr;
+  const int nv = (int)p.alt.size();
+  if (nv <= 1) return -1;
+  if (p.tuned >= 0) return p.tuned;
+  const int need = nv * Program::kTuneRounds;
+  if (p.tune_next < need) {
+    if (p.tune_ev.empty()) {
+      p.tune_ev.assign(2 * need, nullptr);
+      for (auto& e : p.tune_ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+          e = nullptr;
+          p.tuned = 0;
+          return 0;
+        }
+    }
+    const int k = p.tune_next++;
+    ev0 = &p.tune_ev[2 * k];
+    ev1 = &p.tune_ev[2 * k + 1];
+    return k % nv;
+  }
+  std::vector<float> tot(nv, 0.0f);
+  for (int k = 0; k < need; ++k) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(p.tune_ev[2 * k + 1]) != hipSuccess ||
+        hipEventElapsedTime(&ms, p.tune_ev[2 * k], p.tune_ev[2 * k + 1]) != hipSuccess)
+      ms = 1e30f;
+    tot[k % nv] += ms;
+  }
+  p.tuned = (int)(std::min_element(tot.begin(), tot.end()) - tot.begin());
+  if (ctx->verbose >= 2) {
+    std::string msg;
+    for (int v = 0; v < nv; ++v) msg += " mode" + std::to_string(p.alt[v].mode) + "=" + std::to_string(tot[v]);
+    std::fprintf(stderr, "[tdvp]   autotune:%s ms -> mode %d\n", msg.c_str(), p.alt[p.tuned].mode);
+  }
+  return p.tuned;
+}
+
 int launch_gemm(tdvp_ctx* ctx, const Program& p, const Bufs& bufs, double* C, int precision) {
   if (p.tiles.empty()) return TDVP_OK;
+  hipEvent_t *ev0 = nullptr, *ev1 = nullptr;
+  const int v = tune_pick(ctx, p, ev0, ev1);
+  if (v >= 0) {   // the chosen (or measured) tiling replaces the active one
+    const Program::Tiling& a = p.alt[v];
+    if (ev0) TDVP_HIP(ctx, hipEventRecord(*ev0, ctx->stream));
+    int rc = launch_core(ctx, p, (int)a.tiles.size(), a.n64, a.d_tiles, bufs, C, precision);
+    if (ev1) TDVP_HIP(ctx, hipEventRecord(*ev1, ctx->stream));
+    return rc;
+  }
+  return launch_core(ctx, p, (int)p.tiles.size(), p.n64, p.d_tiles, bufs, C, precision);
+}
+
+int launch_gemm_tiles(tdvp_ctx* ctx, const Program& p, const Bufs& bufs, double* C, int precision) {
+  return launch_core(ctx, p, (int)p.tiles.size(), p.n64, p.d_tiles, bufs, C, precision);
+}
+
+static int launch_core(tdvp_ctx* ctx, const Program& p, int ntiles, int n64, const DevTile* d_tiles,
+                       const Bufs& bufs, double* C, int precision) {
+  if (ntiles == 0) return TDVP_OK;
   double2* part = nullptr;
   if (p.nslots > 0) {
     TDVP_HIP(ctx, ctx->ws_part.ensure(sizeof(double2) * (size_t)p.nslots * kSlotDim * kSlotDim));
     part = (double2*)ctx->ws_part.p;
   }
-  const int n32 = (int)p.tiles.size() - p.n64;
-  const DevTile* t32 = p.d_tiles + p.n64;
+  const int n32 = ntiles - n64;
+  const DevTile* t32 = d_tiles + n64;
   const bool heff = p.role == 1;
   Bufs bf = bufs;
   bf.shift = nullptr;
@@ -890,20 +1014,20 @@ int launch_gemm(tdvp_ctx* ctx, const Program& p, const Bufs& bufs, double* C, in
                        p.nshift[1], out);
     bf.shift = out;
   }
-  if (p.n64 > 0) {
+  if (n64 > 0) {
     if (precision == TDVP_BF16X3) {
-      const dim3 g(p.n64), bl(256);
+      const dim3 g(n64), bl(256);
       if (bf.shift) {
-        if (heff) hipLaunchKernelGGL((heff_gemm_b3<true>), g, bl, 0, ctx->stream, bf, C, part, p.d_tiles, p.d_outs, p.d_terms);
-        else hipLaunchKernelGGL((block_gemm_b3<true>), g, bl, 0, ctx->stream, bf, C, part, p.d_tiles, p.d_outs, p.d_terms);
+        if (heff) hipLaunchKernelGGL((heff_gemm_b3<true>), g, bl, 0, ctx->stream, bf, C, part, d_tiles, p.d_outs, p.d_terms);
+        else hipLaunchKernelGGL((block_gemm_b3<true>), g, bl, 0, ctx->stream, bf, C, part, d_tiles, p.d_outs, p.d_terms);
       } else {
-        if (heff) hipLaunchKernelGGL((heff_gemm_b3<false>), g, bl, 0, ctx->stream, bf, C, part, p.d_tiles, p.d_outs, p.d_terms);
-        else hipLaunchKernelGGL((block_gemm_b3<false>), g, bl, 0, ctx->stream, bf, C, part, p.d_tiles, p.d_outs, p.d_terms);
+        if (heff) hipLaunchKernelGGL((heff_gemm_b3<false>), g, bl, 0, ctx->stream, bf, C, part, d_tiles, p.d_outs, p.d_terms);
+        else hipLaunchKernelGGL((block_gemm_b3<false>), g, bl, 0, ctx->stream, bf, C, part, d_tiles, p.d_outs, p.d_terms);
       }
     } else if (precision == TDVP_FP32) {
-      launch_one<float, 2, 2>(ctx, heff, p.n64, bf, C, part, p.d_tiles, p);
+      launch_one<float, 2, 2>(ctx, heff, n64, bf, C, part, d_tiles, p);
     } else {
-      launch_one<double, 2, 2>(ctx, heff, p.n64, bf, C, part, p.d_tiles, p);
+      launch_one<double, 2, 2>(ctx, heff, n64, bf, C, part, d_tiles, p);
     }
   }
   if (n32 > 0) {   // 32x32 tiles (optional tile modes) have no split-BF16 variant: FP32 there
