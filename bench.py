@@ -63,6 +63,72 @@ def measured_traffic(prec):
     return rec["bytes_per_launch"] if h.hexdigest() == rec["sources_sha256"] else None
 
 
+def large_heff(args, T, torch, stream, ctx, model):
+    """H_eff.Theta at chi = 16384 (full-state units) with a few hundred uneven
+    sector blocks: degeneracies log-normal (median 200, sigma 1) over the labels
+    |q| <= 4, 2j <= 4, clipped to [8, 2048], rescaled to chi; synthetic
+    environments and Theta (complex normal).  FP64, FP32 and split-BF16
+    grouped launches, and FP64 with one launch per output block."""
+    import numpy as np
+    import synth
+    chi, site = 16384, 30
+    left = synth.lognormal_profile(chi, 7919 * (site - 1), 1, qmax=4, tjmax=4)
+    right = synth.lognormal_profile(chi, 7919 * (site + 1), 1, qmax=4, tjmax=4)
+    bl, br = T.Bond(left), T.Bond(right)
+    xk, xo, xt, xd = T.center_layout(bl, br, 2)
+    lk, lo, lt, ld = T.env_layout(bl)
+    rk, ro, rt, rd = T.env_layout(br)
+    dev = lambda a: torch.from_numpy(a).to("cuda")
+    X = synth.block_data([tuple(k) for k in xk], xd, args.seed + 31, 13)
+    Lb = synth.block_data([tuple(k) for k in lk], ld, args.seed + 32, 14)
+    Rb = synth.block_data([tuple(k) for k in rk], rd, args.seed + 33, 15)
+    x_d = dev(pack(X, xk, xo, xt))
+    L_d = dev(pack(Lb, lk, lo, lt))
+    R_d = dev(pack(Rb, rk, ro, rt))
+    del X, Lb, Rb
+    y_d = torch.zeros_like(x_d)
+    Lbk = T.Blocks(lk, lo, L_d.data_ptr(), lt)
+    Rbk = T.Blocks(rk, ro, R_d.data_ptr(), rt)
+    xb = T.Blocks(xk, xo, x_d.data_ptr(), xt)
+    yb = T.Blocks(xk, xo, y_d.data_ptr(), xt)
+    _, flops = T.heff_plan(model, site, 2, bl, br, Lbk, Rbk, xb)
+
+    def timed(p, warm, reps):
+        ctx.set_precision(p)
+        for _ in range(warm):
+            ctx.heff_apply(model, site, 2, bl, br, Lbk, Rbk, xb, yb)
+        ctx.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            ctx.heff_apply(model, site, 2, bl, br, Lbk, Rbk, xb, yb)
+        b.record(stream)
+        ctx.synchronize()
+        return a.elapsed_time(b) * 1e-3 / reps
+
+    res = {"workload": f"chi={chi} L=60 middle bond, log-normal sector dims (median 200, sigma 1, |q|<=4, "
+                       f"2j<=4, clipped 8..2048, rescaled)", "blocks": len(xk), "theta_elems": int(xt),
+           "block_dim_max": int(max(r for r, c in xd)), "flops_per_apply": flops}
+    for name, p in (("fp64", T.FP64), ("fp32", T.FP32), ("bf16x3", T.BF16X3)):
+        dt = timed(p, 10, 10)
+        res[name] = {"ms_per_apply": 1e3 * dt, "tflops": flops / dt / 1e12}
+        print(f"bench: chi=16384 H_eff {name} {1e3 * dt:.2f} ms, {flops / dt / 1e12:.2f} TFLOP/s",
+              file=sys.stderr, flush=True)
+    os.environ["TDVP_PER_BLOCK"] = "1"
+    try:
+        dt = timed(T.FP64, 2, 3)
+    finally:
+        del os.environ["TDVP_PER_BLOCK"]
+    res["fp64_one_launch_per_block"] = {"ms_per_apply": 1e3 * dt, "tflops": flops / dt / 1e12,
+                                        "launches_per_apply": len(xk)}
+    print(f"bench: chi=16384 H_eff fp64, one launch per output block: {1e3 * dt:.2f} ms, "
+          f"{flops / dt / 1e12:.2f} TFLOP/s", file=sys.stderr, flush=True)
+    ctx.set_precision(T.FP64 if args.prec == "fp64" else T.FP32)
+    del x_d, y_d, L_d, R_d
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +142,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison run")
     ap.add_argument("--one-site-steps", type=int, default=2, help="one-site sweeps timed after the two-site ones")
+    ap.add_argument("--no-large", action="store_true", help="skip the chi=16384 grouped-vs-per-block measurement")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB three times (reference for the HBM byte counters)")
@@ -104,6 +171,7 @@ def main():
     L, chi, t_h, U = args.L, args.chi, 1.0, 4.0
     prec = T.FP64 if args.prec == "fp64" else T.FP32
     stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)   # torch's work and the library's are ordered on one stream
     ctx = T.Context(0, stream=stream.cuda_stream, precision=prec)
     model = T.Model(L, t_h, U)
     dev = lambda a: torch.from_numpy(a).to("cuda")
@@ -182,6 +250,12 @@ def main():
     ref64 = ys["fp64"]
     for name in heff_by_prec:
         heff_by_prec[name]["rel_err_vs_fp64"] = float(np.linalg.norm(ys[name] - ref64) / np.linalg.norm(ref64))
+
+    # ---- larger, more uneven blocks: chi = 16384 with log-normal sector dimensions,
+    # grouped launch against one launch per output block ------------------------------
+    large = None
+    if not args.no_large:
+        large = large_heff(args, T, torch, stream, ctx, model)
 
     # ---- full sweeps: the step at the working precision, and the mixed path
     # (FP32 block products, FP64 Lanczos / SVD) from the same initial state ----
@@ -351,6 +425,7 @@ def main():
                      "kernel": "heff_gemm<double, 2, 2>" if prec == T.FP64 else "heff_gemm<float, 2, 2>"},
         "cpu_baseline": cpu,
         "mixed": mixed,
+        "large_blocks": large,
     }
     line.update(sweep)
     print(json.dumps(line), flush=True)

@@ -175,7 +175,10 @@ typedef struct {
 
 /* ---- context -------------------------------------------------------------
  * device: HIP device ordinal; hip_stream: hipStream_t or NULL (the library
- * then creates its own default-priority stream); precision: TDVP_FP64/FP32/BF16X3. */
+ * then creates its own default-priority, non-blocking stream, which is not
+ * ordered with any other stream, the null stream included: a caller whose
+ * inputs come from kernels on another stream passes that stream here or
+ * synchronises first); precision: TDVP_FP64/FP32/BF16X3. */
 int tdvp_ctx_create(tdvp_ctx** out, int32_t device, void* hip_stream, int32_t precision);
 void tdvp_ctx_destroy(tdvp_ctx* ctx);
 int tdvp_ctx_set_precision(tdvp_ctx* ctx, int32_t precision);

@@ -103,6 +103,10 @@ struct Program {
   mutable int tuned = -1;             // chosen candidate, -1 while measuring
   mutable std::vector<hipEvent_t> tune_ev;
   static constexpr int kTuneRounds = 2;
+  // one-launch-per-output-block schedule (a baseline for the grouped launch):
+  // tiles grouped by output block, uploaded on first use
+  mutable std::vector<int> blk_begin;
+  mutable void* d_by_out = nullptr;
   // device copies
   DevTerm* d_terms = nullptr;
   DevOut* d_outs = nullptr;

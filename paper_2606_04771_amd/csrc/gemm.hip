@@ -574,6 +574,7 @@ void launch_one(tdvp_ctx* ctx, bool heff, int ntiles, const Bufs& bufs, double* 
 Program::~Program() {
   for (hipEvent_t e : tune_ev)
     if (e) (void)hipEventDestroy(e);
+  if (d_by_out) (void)hipFree(d_by_out);
   if (!d_mem) return;
   if (pool) pool->free[cls].push_back(d_mem);
   else (void)hipFree(d_mem);
@@ -972,10 +973,39 @@ static int tune_pick(tdvp_ctx* ctx, const Program& p, hipEvent_t*& ev0, hipEvent
   return p.tuned;
 }
 
+// Baseline schedule: one launch per output block (64x64 tiles of that block),
+// selected with TDVP_PER_BLOCK=1 at launch time; same work, same results.
+static int launch_per_block(tdvp_ctx* ctx, const Program& p, const Bufs& bufs, double* C, int precision) {
+  if (p.blk_begin.empty()) {
+    Program::Tiling t64;
+    p.tile_only(2, t64);
+    std::vector<DevTile> v = t64.tiles;
+    std::stable_sort(v.begin(), v.end(), [](const DevTile& a, const DevTile& b) { return a.out < b.out; });
+    p.blk_begin.push_back(0);
+    for (size_t i = 1; i <= v.size(); ++i)
+      if (i == v.size() || v[i].out != v[i - 1].out) p.blk_begin.push_back((int)i);
+    TDVP_HIP(ctx, hipMalloc(&p.d_by_out, sizeof(DevTile) * std::max<size_t>(v.size(), 1)));
+    TDVP_HIP(ctx, hipMemcpy(p.d_by_out, v.data(), sizeof(DevTile) * v.size(), hipMemcpyHostToDevice));
+  }
+  const DevTile* base = (const DevTile*)p.d_by_out;
+  for (size_t b = 0; b + 1 < p.blk_begin.size(); ++b) {
+    const int n = p.blk_begin[b + 1] - p.blk_begin[b];
+    int rc = launch_core(ctx, p, n, n, base + p.blk_begin[b], bufs, C, precision);
+    if (rc) return rc;
+  }
+  return TDVP_OK;
+}
+
 int launch_gemm(tdvp_ctx* ctx, const Program& p, const Bufs& bufs, double* C, int precision) {
   if (p.tiles.empty()) return TDVP_OK;
+  if (p.nslots == 0) {
+    const char* e = std::getenv("TDVP_PER_BLOCK");
+    if (e && std::atoi(e) == 1) return launch_per_block(ctx, p, bufs, C, precision);
+  }
+  // FP64 launches only: there every tiling gives identical results, while the
+  // reduced-precision kernels differ between 64x64 and 32x32 tiles
   hipEvent_t *ev0 = nullptr, *ev1 = nullptr;
-  const int v = tune_pick(ctx, p, ev0, ev1);
+  const int v = precision == TDVP_FP64 ? tune_pick(ctx, p, ev0, ev1) : -1;
   if (v >= 0) {   // the chosen (or measured) tiling replaces the active one
     const Program::Tiling& a = p.alt[v];
     if (ev0) TDVP_HIP(ctx, hipEventRecord(*ev0, ctx->stream));

@@ -55,6 +55,34 @@ def sector_profile(chi, seed, parity=0, shape=TABLE_S2_FIT, jitter=0.10, qmax=8,
     return [(q, tj, int(di)) for (q, tj), di in zip(labels, d) if di > 0]
 
 
+def lognormal_profile(chi, seed, parity=0, median=200.0, sigma=1.0, lo=8, hi=2048, qmax=8, tjmax=8):
+    """Sectors [(q, tj, d)] over the label window (q in [-qmax, qmax],
+    2j in [0, tjmax], q - tj = parity mod 2) with degeneracies drawn from a
+    log-normal (median, sigma), clipped to [lo, hi], then rescaled and rounded
+    (largest remainder) so that sum d (tj+1) == chi."""
+    rng = _rng(seed, 3, chi, parity)
+    labels = [(q, tj) for q in range(-qmax, qmax + 1) for tj in range(0, tjmax + 1)
+              if (q - tj - parity) % 2 == 0]
+    raw = np.clip(np.exp(np.log(median) + sigma * rng.standard_normal(len(labels))), lo, hi)
+    mult = np.array([tj + 1 for _, tj in labels])
+    target = raw * chi / np.sum(raw * mult)
+    d = np.floor(target).astype(np.int64)
+    rem = chi - int(np.sum(d * mult))
+    order = np.argsort(-(target - d), kind="stable")
+    while rem > 0:
+        placed = False
+        for i in order:
+            if mult[i] <= rem:
+                d[i] += 1
+                rem -= mult[i]
+                placed = True
+                if rem == 0:
+                    break
+        if not placed:
+            raise ValueError("cannot round the profile to chi exactly")
+    return [(q, tj, int(di)) for (q, tj), di in zip(labels, d) if di > 0]
+
+
 def chi_full(bond):
     return sum(d * (tj + 1) for _, tj, d in bond)
 

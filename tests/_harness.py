@@ -6,6 +6,22 @@ import numpy as np
 import synth
 from oracle import reduced as R
 
+_STREAM = []
+
+
+def torch_stream_handle():
+    """Handle of one non-default torch stream, made current for the process,
+    so that torch's kernels and the library's (launched on the same handle)
+    run in issue order.  torch's default stream has the null handle, for
+    which the library would create a private non-blocking stream instead.
+    Work issued earlier on other streams is finished first."""
+    import torch
+    if not _STREAM:
+        _STREAM.append(torch.cuda.Stream())
+    torch.cuda.synchronize()
+    torch.cuda.set_stream(_STREAM[0])
+    return _STREAM[0].cuda_stream
+
 
 def bond_from_profile(chi, seed, parity):
     return synth.sector_profile(chi, seed, parity=parity)

@@ -1,6 +1,6 @@
-"""H_eff at the benchmark's full size: middle bond of an L = 60 chain at
-chi = 4096 (Table-S2-shaped sectors), in the launch configuration bench.py
-times.  The oracle cannot expand the whole problem, so sampled output blocks
+"""H_eff at the benchmark's full sizes: middle bond of an L = 60 chain at
+chi = 4096 (Table-S2-shaped sectors) and at chi = 16384 with a few hundred
+log-normal uneven blocks, in the launch configuration bench.py times.  The oracle cannot expand the whole problem, so sampled output blocks
 are computed one by one on sector-restricted bonds (oracle.sampled) and
 compared element by element; properties that hold at any size (linearity,
 bit-reproducibility) cover the rest.  FP32 block products are checked
@@ -13,18 +13,25 @@ torch = pytest.importorskip("torch")
 import paper_2606_04771_amd as T
 from oracle import sampled as S
 import synth
-from tests._harness import pack, unpack
+from tests._harness import torch_stream_handle, pack, unpack
 
 pytestmark = pytest.mark.gpu
 
-L, CHI, SITE, t_h, U = 60, 4096, 30, 1.0, 4.0
+L, SITE, t_h, U = 60, 30, 1.0, 4.0
 
 
-@pytest.fixture(scope="module")
-def problem():
+def _profile(kind, seed):
+    if kind == "table-s2-4096":     # the benchmark's middle bond
+        return synth.sector_profile(4096, seed, parity=(SITE - 1) % 2)
+    # a few hundred uneven blocks at chi = 16384: log-normal degeneracies
+    return synth.lognormal_profile(16384, seed, (SITE - 1) % 2, qmax=4, tjmax=4)
+
+
+@pytest.fixture(scope="module", params=["table-s2-4096", "lognormal-16384"])
+def problem(request):
     assert torch.cuda.is_available()
-    left = synth.sector_profile(CHI, 7919 * (SITE - 1), parity=(SITE - 1) % 2)
-    right = synth.sector_profile(CHI, 7919 * (SITE + 1), parity=(SITE + 1) % 2)
+    left = _profile(request.param, 7919 * (SITE - 1))
+    right = _profile(request.param, 7919 * (SITE + 1))
     bl, br = T.Bond(left), T.Bond(right)
     xk, xo, xt, xd = T.center_layout(bl, br, 2)
     lk, lo, lt, ld = T.env_layout(bl)
@@ -39,7 +46,7 @@ def problem():
         "L": torch.from_numpy(pack([Lb[tuple(k)] for k in lk], lo, lt)).to("cuda"),
         "R": torch.from_numpy(pack([Rb[tuple(k)] for k in rk], ro, rt)).to("cuda"),
     }
-    ctx = T.Context(0)
+    ctx = T.Context(0, stream=torch_stream_handle())   # ordered with torch's work
     yield dict(left=left, right=right, bl=bl, br=br, xk=xk, xo=xo, xt=xt, xd=xd, lk=lk, lo=lo, lt=lt,
                rk=rk, ro=ro, rt=rt, X=X, Lb=Lb, Rb=Rb, dev=dev, ctx=ctx)
     ctx.close()
@@ -68,7 +75,9 @@ def _samples(p, n=10):
     sizes = [np.prod(S.restricted_dims(p["left"], p["right"], Lkeys, Rkeys, k)) for k in keys]
     order = np.argsort(sizes)
     ok = [keys[i] for i in order if sizes[i] <= 800_000]
-    idx = np.linspace(0, len(ok) - 1, n).astype(int)
+    if len(ok) < 3:   # large blocks only (chi = 16384): the four smallest (~10 s of oracle each)
+        return [keys[i] for i in order[:4]]
+    idx = np.unique(np.linspace(0, len(ok) - 1, n).astype(int))
     return [ok[i] for i in idx]
 
 

@@ -13,7 +13,7 @@ import paper_2606_04771_amd as T
 from oracle import dense as D
 from oracle import reduced as R
 import synth
-from tests._harness import keyed, pack, random_blocks, theta_dict, env_dict, unpack
+from tests._harness import torch_stream_handle, keyed, pack, random_blocks, theta_dict, env_dict, unpack
 
 pytestmark = pytest.mark.gpu
 
@@ -35,7 +35,7 @@ def _bond(parity, seed, big=80, n_small=3):
 @pytest.fixture(scope="module")
 def ctx():
     assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
-    c = T.Context(0)
+    c = T.Context(0, stream=torch_stream_handle())   # ordered with torch's work
     yield c
     c.close()
 

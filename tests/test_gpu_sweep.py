@@ -13,7 +13,7 @@ import paper_2606_04771_amd as T
 from oracle import dense as D
 from oracle import fermions as F
 from oracle import reduced as R
-from tests._harness import unpack, theta_dict
+from tests._harness import torch_stream_handle, unpack, theta_dict
 
 pytestmark = pytest.mark.gpu
 
@@ -21,7 +21,7 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(scope="module")
 def ctx():
     assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
-    c = T.Context(0)
+    c = T.Context(0, stream=torch_stream_handle())   # ordered with torch's work
     yield c
     c.close()
 
