@@ -148,7 +148,11 @@ struct tdvp_ctx {
   void* solver = nullptr;       // rocblas handle for the eigensolver (created on first use)
   // side streams (default priority) with their own solver handles, for
   // independent eigensolves; joined back to `stream` by events
-  static constexpr int kSide = 4;
+  // Side streams for concurrent batched eigensolves.  HIP maps streams onto
+  // GPU_MAX_HW_QUEUES hardware queues (4 unless set before HIP starts); with
+  // 8 queues the split of a chi = 4096 sweep takes ~30 % less time than with 4.
+  static constexpr int kSide = 8;
+  int nside = 8;                      // in use (TDVP_SIDE_STREAMS, 1..kSide)
   hipStream_t side[kSide] = {};
   void* side_solver[kSide] = {};
   hipEvent_t side_ev[kSide + 1] = {};

@@ -161,7 +161,8 @@ int ensure_solver(tdvp_ctx* ctx) {
   if (rocblas_set_stream(h, ctx->stream) != rocblas_status_success)
     return set_error(ctx, TDVP_E_HIP, "rocblas_set_stream failed");
   ctx->solver = h;
-  for (int k = 0; k < tdvp_ctx::kSide; ++k) {
+  if (const char* e = std::getenv("TDVP_SIDE_STREAMS")) ctx->nside = std::max(1, std::min(tdvp_ctx::kSide, std::atoi(e)));
+  for (int k = 0; k < ctx->nside; ++k) {
     TDVP_HIP(ctx, hipStreamCreateWithFlags(&ctx->side[k], hipStreamNonBlocking));
     rocblas_handle hs;
     if (rocblas_create_handle(&hs) != rocblas_status_success)
@@ -176,14 +177,22 @@ int ensure_solver(tdvp_ctx* ctx) {
 
 int check_finite(tdvp_ctx* ctx, const Blocks& b, const char* what, int bond);
 
-// padded sizes for batched eigensolves: at most ~25 % larger than the sector
-int64_t bucket_size(int64_t g) {
-  static const int64_t sz[] = {1,   2,   4,   8,   16,  24,  32,   48,   64,   80,   96,   128,  160,  192, 224,
-                               256, 320, 384, 448, 512, 640, 768,  896,  1024, 1280, 1536, 1792, 2048, 2560,
-                               3072, 3584, 4096};
-  for (int64_t v : sz)
+// Padded sizes for the batched solves.  Every batched call is a chain of
+// many small dependent kernels whose length grows with the padded size, so
+// fewer, larger buckets beat tight ones: the eigensolves use steps of about
+// 1.5x (their calls run concurrently on the side streams), the Cholesky QR of
+// the one-site gauge move powers of two (measured at chi = 4096, L = 60).
+int64_t bucket_size(int64_t g, bool pow2) {
+  static const int64_t eig[] = {1, 2, 4, 8, 16, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096};
+  if (g > 4096) return (g + 1023) / 1024 * 1024;
+  if (pow2) {
+    int64_t v = 1;
+    while (v < g) v <<= 1;
+    return v;
+  }
+  for (int64_t v : eig)
     if (v >= g) return v;
-  return (g + 1023) / 1024 * 1024;
+  return g;
 }
 
 int run_program(tdvp_ctx* ctx, Program& p, const Bufs& b, double* C) {
@@ -246,7 +255,7 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
     s.left_gram = s.rows < s.cols || (s.rows == s.cols && dir > 0);
     s.g = std::min(s.rows, s.cols);
     s.qr = (dir > 0) != s.left_gram;
-    if (s.g > 0) buckets[bucket_size(s.g)].push_back(&s);
+    if (s.g > 0) buckets[bucket_size(s.g, false)].push_back(&s);
   }
   int64_t mtot = 0, gtot = 0, dtot = 0, nmax = 0, nmat = 0;
   for (auto& kv : secs) {
@@ -359,7 +368,7 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
     // the side streams (largest first) and joined back before verification
     int64_t mi = 0;
     TDVP_HIP(ctx, hipEventRecord(ctx->side_ev[tdvp_ctx::kSide], ctx->stream));
-    for (int k = 0; k < tdvp_ctx::kSide; ++k)
+    for (int k = 0; k < ctx->nside; ++k)
       TDVP_HIP(ctx, hipStreamWaitEvent(ctx->side[k], ctx->side_ev[tdvp_ctx::kSide], 0));
     std::vector<std::pair<int64_t, std::vector<Sector*>*>> order;
     for (auto& bk : buckets) order.push_back({bk.first, &bk.second});
@@ -368,7 +377,7 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
       minfo.push_back(mi);
       mi += (int64_t)bk.second.size();
     }
-    std::vector<double> sload(tdvp_ctx::kSide, 0.0);
+    std::vector<double> sload(ctx->nside, 0.0);
     for (int ob = (int)order.size() - 1; ob >= 0; --ob) {
       int64_t n = order[ob].first;
       auto& secv = *order[ob].second;
@@ -385,7 +394,7 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
           Dbase + s0->doff, (rocblas_stride)n, dinfo + minfo[ob], (rocblas_int)secv.size());
       if (st != rocblas_status_success) return set_error(ctx, TDVP_E_HIP, "rocsolver_zheevdj_strided_batched failed");
     }
-    for (int k = 0; k < tdvp_ctx::kSide; ++k) {
+    for (int k = 0; k < ctx->nside; ++k) {
       TDVP_HIP(ctx, hipEventRecord(ctx->side_ev[k], ctx->side[k]));
       TDVP_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->side_ev[k], 0));
     }
@@ -650,9 +659,12 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
   if ((rc = run_program(ctx, pb, b, (double*)TB.blk.data))) return rc;
   TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
   t_svd += now() - t0;
-  if (ctx->verbose >= 2)
-    std::fprintf(stderr, "[tdvp]   split bond %d: gram %.4f eig %.4f iso %.4f out %.4f s (%zu sectors, %lld matrices)\n",
-                 i, ph[0] - t0, ph[1] - ph[0], ph[2] - ph[1], now() - ph[2], secs.size(), (long long)nmat);
+  if (ctx->verbose >= 2) {
+    std::string bs;
+    for (auto& bk : buckets) bs += " " + std::to_string(bk.first) + "x" + std::to_string(bk.second.size());
+    std::fprintf(stderr, "[tdvp]   split bond %d: gram %.4f eig %.4f iso %.4f out %.4f s (%zu sectors, %lld matrices;%s)\n",
+                 i, ph[0] - t0, ph[1] - ph[0], ph[2] - ph[1], now() - ph[2], secs.size(), (long long)nmat, bs.c_str());
+  }
   return TDVP_OK;
 }
 
@@ -1316,7 +1328,7 @@ int gauge_qr(tdvp_ctx* ctx, tdvp_mps* m, int i, int dir, Blocks& x, DeviceBuffer
   // padded Gram slots by size bucket
   std::vector<int64_t> gn(ns), goff(ns);
   std::map<int64_t, std::vector<int>> buckets;
-  for (int s = 0; s < ns; ++s) buckets[bucket_size(cut.d[s])].push_back(s);
+  for (int s = 0; s < ns; ++s) buckets[bucket_size(cut.d[s], true)].push_back(s);
   int64_t gtot = 0;
   for (auto& bk : buckets)
     for (int s : bk.second) {

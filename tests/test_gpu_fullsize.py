@@ -1,6 +1,8 @@
 """H_eff at the benchmark's full sizes: middle bond of an L = 60 chain at
-chi = 4096 (Table-S2-shaped sectors) and at chi = 16384 with a few hundred
-log-normal uneven blocks, in the launch configuration bench.py times.  The oracle cannot expand the whole problem, so sampled output blocks
+chi = 4096 (Table-S2-shaped sectors), at chi = 16384 with a few hundred
+log-normal uneven blocks, and at the late-time chi ~ 62 000 (Table-S2 shape:
+a 9.4 GB two-site tensor and 6.2 GB of environments on one device), in the
+launch configuration bench.py times.  The oracle cannot expand the whole problem, so sampled output blocks
 are computed one by one on sector-restricted bonds (oracle.sampled) and
 compared element by element; properties that hold at any size (linearity,
 bit-reproducibility) cover the rest.  FP32 block products are checked
@@ -23,11 +25,13 @@ L, SITE, t_h, U = 60, 30, 1.0, 4.0
 def _profile(kind, seed):
     if kind == "table-s2-4096":     # the benchmark's middle bond
         return synth.sector_profile(4096, seed, parity=(SITE - 1) % 2)
+    if kind == "table-s2-62000":    # the late-time segment's bond dimension
+        return synth.sector_profile(62000, seed, parity=(SITE - 1) % 2)
     # a few hundred uneven blocks at chi = 16384: log-normal degeneracies
     return synth.lognormal_profile(16384, seed, (SITE - 1) % 2, qmax=4, tjmax=4)
 
 
-@pytest.fixture(scope="module", params=["table-s2-4096", "lognormal-16384"])
+@pytest.fixture(scope="module", params=["table-s2-4096", "lognormal-16384", "table-s2-62000"])
 def problem(request):
     assert torch.cuda.is_available()
     left = _profile(request.param, 7919 * (SITE - 1))
@@ -36,16 +40,17 @@ def problem(request):
     xk, xo, xt, xd = T.center_layout(bl, br, 2)
     lk, lo, lt, ld = T.env_layout(bl)
     rk, ro, rt, rd = T.env_layout(br)
+    print(f"\n{request.param}: {len(xk)} blocks, theta {xt * 16 / 1e9:.2f} GB, "
+          f"environments {(lt + rt) * 16 / 1e9:.2f} GB; drawing inputs", flush=True)
     X = synth.block_data([tuple(k) for k in xk], xd, 21)
     nrm = np.sqrt(sum(np.sum(np.abs(v) ** 2) for v in X.values()))
     X = {k: v / nrm for k, v in X.items()}
+    dev = {"x": torch.from_numpy(pack([X[tuple(k)] for k in xk], xo, xt)).to("cuda")}
     Lb = synth.block_data([tuple(k) for k in lk], ld, 22)
+    dev["L"] = torch.from_numpy(pack([Lb[tuple(k)] for k in lk], lo, lt)).to("cuda")
     Rb = synth.block_data([tuple(k) for k in rk], rd, 23)
-    dev = {
-        "x": torch.from_numpy(pack([X[tuple(k)] for k in xk], xo, xt)).to("cuda"),
-        "L": torch.from_numpy(pack([Lb[tuple(k)] for k in lk], lo, lt)).to("cuda"),
-        "R": torch.from_numpy(pack([Rb[tuple(k)] for k in rk], ro, rt)).to("cuda"),
-    }
+    dev["R"] = torch.from_numpy(pack([Rb[tuple(k)] for k in rk], ro, rt)).to("cuda")
+    print(f"{request.param}: inputs on the device", flush=True)
     ctx = T.Context(0, stream=torch_stream_handle())   # ordered with torch's work
     yield dict(left=left, right=right, bl=bl, br=br, xk=xk, xo=xo, xt=xt, xd=xd, lk=lk, lo=lo, lt=lt,
                rk=rk, ro=ro, rt=rt, X=X, Lb=Lb, Rb=Rb, dev=dev, ctx=ctx)
