@@ -147,9 +147,14 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB three times (reference for the HBM byte counters)")
     args = ap.parse_args()
-    # eight hardware queues for the eight side streams of the batched
+    # at least eight hardware queues for the eight side streams of the batched
     # eigensolves (read once, when HIP starts: before torch is imported)
-    os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+    try:
+        hwq = int(os.environ.get("GPU_MAX_HW_QUEUES", "0"))
+    except ValueError:
+        hwq = 0
+    if hwq < 8:
+        os.environ["GPU_MAX_HW_QUEUES"] = "8"
     if args.copy_calibration:
         import torch
         n = 2 ** 26                       # 64 Mi complex128 = 1 GiB

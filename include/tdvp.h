@@ -123,6 +123,7 @@ typedef struct {
   double norm_in;       /* |x| on entry */
   double alpha[64];     /* Lanczos diagonal (first min(iters,64)) */
   double beta[64];      /* Lanczos off-diagonal */
+  int32_t graph_iters;  /* iterations replayed from the captured iteration graph */
 } tdvp_krylov_info;
 
 typedef struct {
@@ -145,6 +146,7 @@ typedef struct {
   double env_flops;       /* algorithmic flops of all environment updates */
   double seconds;         /* host wall time of the call */
   double t_heff, t_lanczos, t_svd, t_env;  /* seconds per phase (device events) */
+  int32_t graph_iters;    /* Lanczos iterations replayed from captured graphs */
 } tdvp_sweep_info;
 
 /* Plan of one H_eff apply, exported for host-side inspection and tests.
@@ -182,6 +184,14 @@ typedef struct {
 int tdvp_ctx_create(tdvp_ctx** out, int32_t device, void* hip_stream, int32_t precision);
 void tdvp_ctx_destroy(tdvp_ctx* ctx);
 int tdvp_ctx_set_precision(tdvp_ctx* ctx, int32_t precision);
+/* Graph replay of Lanczos iterations (enable 1, the default unless the
+ * environment variable TDVP_GRAPH is 0, or 0).  With it on, each Krylov
+ * exponential of an effective Hamiltonian records one iteration (apply, two
+ * Gram-Schmidt passes, norm, copy of the coefficients to the host, next basis
+ * vector) as a HIP graph, once the tiling autotuner has settled, and replays
+ * it for every further iteration; the iteration index lives in device memory.
+ * Results are identical either way.  Errors: INVALID (null ctx). */
+int tdvp_ctx_set_graphs(tdvp_ctx* ctx, int32_t enable);
 int tdvp_ctx_synchronize(tdvp_ctx* ctx);
 /* Last error message of ctx, or of the calling thread when ctx is NULL. */
 const char* tdvp_last_error(const tdvp_ctx* ctx);

@@ -43,7 +43,8 @@ class _Blocks(C.Structure):
 
 class _KrylovInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("err_est", C.c_double),
-                ("norm_in", C.c_double), ("alpha", C.c_double * 64), ("beta", C.c_double * 64)]
+                ("norm_in", C.c_double), ("alpha", C.c_double * 64), ("beta", C.c_double * 64),
+                ("graph_iters", C.c_int32)]
 
 
 class _Trunc(C.Structure):
@@ -56,7 +57,7 @@ class _SweepInfo(C.Structure):
                 ("max_chi_su2", C.c_int64), ("krylov_iters", C.c_int32), ("krylov_max", C.c_int32),
                 ("nonconverged", C.c_int32), ("heff_flops", C.c_double), ("env_flops", C.c_double),
                 ("seconds", C.c_double), ("t_heff", C.c_double), ("t_lanczos", C.c_double),
-                ("t_svd", C.c_double), ("t_env", C.c_double)]
+                ("t_svd", C.c_double), ("t_env", C.c_double), ("graph_iters", C.c_int32)]
 
 
 class _Term(C.Structure):
@@ -78,6 +79,7 @@ def _load():
         "tdvp_ctx_create": [C.POINTER(C.c_void_p), I32, P, I32],
         "tdvp_ctx_destroy": [P],
         "tdvp_ctx_set_precision": [P, I32],
+        "tdvp_ctx_set_graphs": [P, I32],
         "tdvp_ctx_synchronize": [P],
         "tdvp_last_error": [P],
         "tdvp_center_layout": [P, P, I32, P, P, P, P],
@@ -259,6 +261,9 @@ class Context:
     def set_precision(self, p):
         _check(lib.tdvp_ctx_set_precision(self.h, int(p)), self.h)
 
+    def set_graphs(self, enable):
+        _check(lib.tdvp_ctx_set_graphs(self.h, int(bool(enable))), self.h)
+
     def synchronize(self):
         _check(lib.tdvp_ctx_synchronize(self.h), self.h)
 
@@ -276,7 +281,7 @@ class Context:
             _check(rc, self.h)
         return rc, {"iters": info.iters, "converged": bool(info.converged), "err": info.err_est,
                     "norm": info.norm_in, "alpha": list(info.alpha[:info.iters]),
-                    "beta": list(info.beta[:info.iters])}
+                    "beta": list(info.beta[:info.iters]), "graph_iters": info.graph_iters}
 
     def env_update(self, model, site, direction, bond_in, bond_out, env_in, tensor, env_out):
         _check(lib.tdvp_env_update(self.h, model.ref, site, direction, bond_in.ref, bond_out.ref, env_in.ref,

@@ -307,6 +307,8 @@ int tdvp_ctx_create(tdvp_ctx** out, int32_t device, void* hip_stream, int32_t pr
       return set_error(nullptr, TDVP_E_NOMEM, "pinned host buffer");
     }
     for (auto& ev : c->ev) (void)hipEventCreate(&ev);
+    const char* gr = std::getenv("TDVP_GRAPH");
+    c->graphs = !(gr && std::atoi(gr) == 0);
     const char* v = std::getenv("TDVP_VERBOSE");
     c->verbose = v ? std::atoi(v) : 0;
     *out = c;
@@ -341,6 +343,12 @@ int tdvp_ctx_set_precision(tdvp_ctx* ctx, int32_t precision) {
   if (precision != TDVP_FP64 && precision != TDVP_FP32 && precision != TDVP_BF16X3)
     return set_error(ctx, TDVP_E_INVALID, "unknown precision");
   ctx->precision = precision;
+  return TDVP_OK;
+}
+
+int tdvp_ctx_set_graphs(tdvp_ctx* ctx, int32_t enable) {
+  if (!ctx) return set_error(nullptr, TDVP_E_INVALID, "null ctx");
+  ctx->graphs = enable != 0;
   return TDVP_OK;
 }
 
@@ -425,6 +433,7 @@ int tdvp_krylov_expm(tdvp_ctx* ctx, const tdvp_model* model, int32_t site, int32
     if (info) {
       std::memset(info, 0, sizeof(*info));
       info->iters = kr.iters;
+      info->graph_iters = kr.graph_iters;
       info->converged = kr.converged;
       info->err_est = kr.err;
       info->norm_in = kr.norm;

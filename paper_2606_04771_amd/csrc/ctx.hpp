@@ -101,6 +101,7 @@ struct Program {
   std::vector<Tiling> alt;            // candidates (index 0 = the active tiling as built)
   mutable int tune_next = 0;          // launches issued so far while tuning
   mutable int tuned = -1;             // chosen candidate, -1 while measuring
+  bool tuning() const { return alt.size() > 1 && tuned < 0; }
   mutable std::vector<hipEvent_t> tune_ev;
   static constexpr int kTuneRounds = 2;
   // one-launch-per-output-block schedule (a baseline for the grouped launch):
@@ -142,6 +143,7 @@ struct tdvp_ctx {
   hipEvent_t upload_done = nullptr;
   // workspaces
   tdvp::DeviceBuffer ws_scratch, ws_krylov, ws_small, ws_vec, ws_theta, ws_svd;
+  tdvp::DeviceBuffer ws_lanczos;   // partial sums of the graph-replayed Lanczos iteration
   tdvp::DeviceBuffer ws_part;   // partial tiles of split K chains
   tdvp::DeviceBuffer ws_shift;  // diagonal shifts of reduced-precision launches
   tdvp::DeviceBuffer ws_compact;  // compact copy of a non-contiguous Krylov start vector
@@ -153,6 +155,7 @@ struct tdvp_ctx {
   // 8 queues the split of a chi = 4096 sweep takes ~30 % less time than with 4.
   static constexpr int kSide = 8;
   int nside = 8;                      // in use (TDVP_SIDE_STREAMS, 1..kSide)
+  bool graphs = true;                 // graph replay of Lanczos iterations
   hipStream_t side[kSide] = {};
   void* side_solver[kSide] = {};
   hipEvent_t side_ev[kSide + 1] = {};
@@ -193,6 +196,12 @@ int vec_scale_copy(tdvp_ctx* ctx, double* dst, const double* src, double s, int6
 int vec_combo(tdvp_ctx* ctx, double* out, const double* V, int64_t stride, int nv, const double* d_coef,
               int64_t n);
 int vec_norm2(tdvp_ctx* ctx, const double* x, int64_t n, double* d_out);
+size_t lanczos_partial_bytes(int64_t n, int maxdim);
+int vec_lanczos_orth_it(tdvp_ctx* ctx, double* W, const double* V, int64_t stride, int maxdim, int64_t n,
+                        const int* d_j, double* c1, double* c2, double* d_norm2, void* partial_buf);
+int vec_lanczos_advance_it(tdvp_ctx* ctx, double* V, int64_t stride, double* x, const double* W, int64_t n,
+                           const double* d_b2, int* d_j, int maxdim);
+int vec_set_index(tdvp_ctx* ctx, int* d_j, int v);
 int vec_check_finite(tdvp_ctx* ctx, const double* x, int64_t n, int* d_flag);
 int vec_pad_matrix(tdvp_ctx* ctx, double* A, int64_t n, int64_t g, double v, double* d_scale);
 // d_out[2b], d_out[2b+1] = re, im of sum conj(x) y over block b, whose element

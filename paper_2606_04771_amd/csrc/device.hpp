@@ -24,14 +24,19 @@ struct KrylovResult {
   double err = 0.0, norm = 0.0;
   std::vector<double> alpha, beta;
   double heff_flops = 0.0;
+  int graph_iters = 0;   // iterations replayed from the captured graph
 };
 // x <- exp(tau H_eff) x (x = in.x, data in place).
 int krylov_dev(tdvp_ctx* ctx, const tdvp_model& m, int site, int nsites, const HeffInputs& in,
                std::complex<double> tau, double tol, int maxdim, KrylovResult& out);
 
 // x <- exp(tau op) x for a device operator on n contiguous complex elements.
+// capturable(), when given, says whether op may now be recorded into a graph
+// (no allocation, synchronisation or measurement inside); from then on one
+// captured Lanczos iteration is replayed for every further iteration.
 int krylov_core(tdvp_ctx* ctx, int64_t n, double* x, const std::function<int(const double*, double*)>& op,
-                double flops_per_apply, std::complex<double> tau, double tol, int maxdim, KrylovResult& out);
+                double flops_per_apply, std::complex<double> tau, double tol, int maxdim, KrylovResult& out,
+                const std::function<bool()>& capturable = {});
 
 // Copy blocks: dst[j] = src[i] for blocks with equal keys (scaled by s).
 int copy_blocks(tdvp_ctx* ctx, const Blocks& src, const Blocks& dst, double s);

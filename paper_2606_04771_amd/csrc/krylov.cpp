@@ -9,6 +9,8 @@
 
 #include <cmath>
 #include <complex>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 
@@ -62,26 +64,46 @@ bool contiguous(const Blocks& x, int64_t& n) {
   return true;
 }
 
+// One Lanczos iteration recorded as a graph: w = op(x), two Gram-Schmidt
+// passes against v_0..v_j, |w|^2, the copy of the coefficients to the host,
+// and x = v_{j+1} = w / |w|; j is read from and advanced in device memory.
+struct IterGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~IterGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
 }  // namespace
 
 // Lanczos exponential of a device operator on a contiguous vector of n
 // complex elements, in place.  The operator writes op(v) to w (both
 // contiguous, n elements); flops_per_apply is added to out.heff_flops.
 int krylov_core(tdvp_ctx* ctx, int64_t n, double* x, const std::function<int(const double*, double*)>& op,
-                double flops_per_apply, std::complex<double> tau, double tol, int maxdim, KrylovResult& out) {
+                double flops_per_apply, std::complex<double> tau, double tol, int maxdim, KrylovResult& out,
+                const std::function<bool()>& capturable) {
   out = KrylovResult();
   if (n == 0) return TDVP_OK;
   const int64_t stride = n;
-  TDVP_HIP(ctx, ctx->ws_krylov.ensure(sizeof(double) * 2 * (size_t)stride * (maxdim + 1)));
+  // basis v_0..v_{maxdim-1}, w, and the fixed operator input of the graph
+  const bool try_graph = capturable && ctx->graphs && maxdim > 1;
+  TDVP_HIP(ctx, ctx->ws_krylov.ensure(sizeof(double) * 2 * (size_t)stride * (maxdim + (try_graph ? 2 : 1))));
   TDVP_HIP(ctx, ctx->ws_small.ensure(1 << 16));
+  if (try_graph) TDVP_HIP(ctx, ctx->ws_lanczos.ensure(lanczos_partial_bytes(n, maxdim)));
   double* V = (double*)ctx->ws_krylov.p;
   double* W = V + 2 * stride * maxdim;
+  double* Xg = try_graph ? W + 2 * stride : nullptr;
   double* d_small = (double*)ctx->ws_small.p;
   double* h_small = (double*)ctx->host_small;
   double* d_c1 = d_small;          // 2*64
   double* d_c2 = d_small + 128;    // 2*64
   double* d_nrm = d_small + 256;   // 2
   double* d_y = d_small + 512;     // 2*64
+  int* d_j = (int*)(d_small + 2048);
+  IterGraph graph;
+  bool replay = false;
 
   // v0 = x / |x|
   int rc;
@@ -103,14 +125,48 @@ int krylov_core(tdvp_ctx* ctx, int64_t n, double* x, const std::function<int(con
   std::vector<std::complex<double>> y;
   for (int j = 0; j < maxdim; ++j) {
     double* vj = V + 2 * stride * j;
-    if ((rc = op(vj, W))) return rc;
-    out.heff_flops += flops_per_apply;
-    // two passes of classical Gram-Schmidt against v_0..v_j
-    if ((rc = vec_dots(ctx, V, stride, j + 1, W, n, d_c1))) return rc;
-    if ((rc = vec_subtract_combo(ctx, W, V, stride, j + 1, d_c1, n, nullptr))) return rc;
-    if ((rc = vec_dots(ctx, V, stride, j + 1, W, n, d_c2))) return rc;
-    if ((rc = vec_subtract_combo(ctx, W, V, stride, j + 1, d_c2, n, d_nrm))) return rc;
-    TDVP_HIP(ctx, hipMemcpyAsync(h_small, d_small, 258 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    // from the second iteration on (workspaces sized), once the operator can
+    // be recorded: capture one iteration and replay it from here on
+    if (try_graph && !replay && j >= 1 && capturable()) {
+      if ((rc = vec_set_index(ctx, d_j, j))) return rc;
+      TDVP_HIP(ctx, hipMemcpyAsync(Xg, vj, sizeof(double) * 2 * n, hipMemcpyDeviceToDevice, ctx->stream));
+      bool ok = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      if (ok) {
+        int crc = op(Xg, W);
+        if (!crc) crc = vec_lanczos_orth_it(ctx, W, V, stride, maxdim, n, d_j, d_c1, d_c2, d_nrm, ctx->ws_lanczos.p);
+        if (!crc && hipMemcpyAsync(h_small, d_small, 258 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream) !=
+                        hipSuccess)
+          crc = TDVP_E_HIP;
+        if (!crc) crc = vec_lanczos_advance_it(ctx, V, stride, Xg, W, n, d_nrm, d_j, maxdim);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+        graph.graph = g;
+        ok = !crc && e == hipSuccess && g &&
+             hipGraphInstantiate(&graph.exec, g, nullptr, nullptr, 0) == hipSuccess;
+      }
+      if (!ok) {   // stay with direct launches
+        (void)hipGetLastError();
+        if (ctx->verbose) std::fprintf(stderr, "[tdvp]   Lanczos graph capture failed; direct launches\n");
+      }
+      replay = ok;
+      if (!ok) {   // the capture may have left launches unrecorded: start the iteration afresh
+        TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+      }
+    }
+    if (replay) {
+      TDVP_HIP(ctx, hipGraphLaunch(graph.exec, ctx->stream));
+      out.heff_flops += flops_per_apply;
+      ++out.graph_iters;
+    } else {
+      if ((rc = op(vj, W))) return rc;
+      out.heff_flops += flops_per_apply;
+      // two passes of classical Gram-Schmidt against v_0..v_j
+      if ((rc = vec_dots(ctx, V, stride, j + 1, W, n, d_c1))) return rc;
+      if ((rc = vec_subtract_combo(ctx, W, V, stride, j + 1, d_c1, n, nullptr))) return rc;
+      if ((rc = vec_dots(ctx, V, stride, j + 1, W, n, d_c2))) return rc;
+      if ((rc = vec_subtract_combo(ctx, W, V, stride, j + 1, d_c2, n, d_nrm))) return rc;
+      TDVP_HIP(ctx, hipMemcpyAsync(h_small, d_small, 258 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    }
     TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
     double a = h_small[2 * j] + h_small[128 + 2 * j];
     double b2 = h_small[256];
@@ -142,7 +198,11 @@ int krylov_core(tdvp_ctx* ctx, int64_t n, double* x, const std::function<int(con
       return TDVP_OK;
     }
     beta.push_back(b);
-    if ((rc = vec_scale_copy(ctx, V + 2 * stride * (j + 1), W, 1.0 / b, n))) return rc;
+    if (!replay) {   // v_{j+1} = w / |w| by the replayed iteration's own kernel (same rounding)
+      double* vn = V + 2 * stride * (j + 1);
+      if ((rc = vec_set_index(ctx, d_j, j))) return rc;
+      if ((rc = vec_lanczos_advance_it(ctx, V, stride, vn, W, n, d_nrm, d_j, maxdim))) return rc;
+    }
   }
   return TDVP_OK;
 }
@@ -178,6 +238,8 @@ int krylov_dev(tdvp_ctx* ctx, const tdvp_model& m, int site, int nsites, const H
     bufs.p[0] = v;
     return launch_gemm(ctx, *prog, bufs, w, ctx->precision);
   };
+  // recordable once the tiling autotuner (events, host reads) has decided
+  auto capturable = [&]() { return ctx->precision != TDVP_FP64 || !prog->tuning(); };
   double* xd = (double*)in_user.x.data;
   if (!compact) {
     // work on a compact copy (after the Krylov basis in the scratch area)
@@ -187,7 +249,7 @@ int krylov_dev(tdvp_ctx* ctx, const tdvp_model& m, int site, int nsites, const H
     if ((rc = copy_blocks(ctx, in_user.x, xc, 1.0))) return rc;
     xd = (double*)ctx->ws_compact.p;
   }
-  rc = krylov_core(ctx, n, xd, op, prog->flops, tau, tol, maxdim, out);
+  rc = krylov_core(ctx, n, xd, op, prog->flops, tau, tol, maxdim, out, capturable);
   if (rc && rc != TDVP_E_NOCONV) return rc;
   if (!compact) {
     Blocks xc = in.x;

@@ -679,6 +679,7 @@ int evolve(tdvp_ctx* ctx, tdvp_mps* m, int site, int nsites, Blocks& x, const Bl
   KrylovResult kr;
   int rc = krylov_dev(ctx, m->model, site, nsites, in, {0.0, tau_im}, tr.krylov_tol, tr.krylov_maxdim, kr);
   info->krylov_iters += kr.iters;
+  info->graph_iters += kr.graph_iters;
   info->krylov_max = std::max(info->krylov_max, kr.iters);
   info->heff_flops += kr.heff_flops;
   if (rc == TDVP_E_NOCONV) {
@@ -1660,6 +1661,7 @@ int evolve_bond(tdvp_ctx* ctx, tdvp_mps* m, int i, int dir, Blocks& x, double ta
   rc = krylov_core(ctx, x.size, (double*)x.data, op, prog->flops + small_flops, {0.0, tau_im}, tr.krylov_tol,
                    tr.krylov_maxdim, kr);
   info->krylov_iters += kr.iters;
+  info->graph_iters += kr.graph_iters;
   info->krylov_max = std::max(info->krylov_max, kr.iters);
   info->heff_flops += kr.heff_flops;
   if (rc == TDVP_E_NOCONV) {

@@ -51,27 +51,33 @@ int nblocks_for(int64_t n) {
   return (int)g;
 }
 
-// partial[k * G + g] = sum_{i in chunk g} conj(V_k[i]) w[i]
+// partial[k * G + g] = sum_{i in chunk g} conj(V_k[i]) w[i]: for k = blockIdx.y,
+// or, with d_j (index read on the device), for every k <= *d_j in turn
 __global__ __launch_bounds__(NT) void k_dots_partial(const double2* __restrict__ V, int64_t stride,
                                                      const double2* __restrict__ w, int64_t n,
-                                                     double2* __restrict__ partial) {
-  const int g = blockIdx.x, G = gridDim.x, k = blockIdx.y;
-  const double2* v = V + (int64_t)k * stride;
+                                                     double2* __restrict__ partial, const int* __restrict__ d_j) {
+  const int g = blockIdx.x, G = gridDim.x;
+  const int kb = d_j ? 0 : (int)blockIdx.y, ke = d_j ? *d_j + 1 : (int)blockIdx.y + 1;
   int64_t chunk = (n + G - 1) / G;
   int64_t lo = (int64_t)g * chunk, hi = lo + chunk < n ? lo + chunk : n;
-  double re = 0.0, im = 0.0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += NT) {
-    double2 a = v[i], b = w[i];
-    re += a.x * b.x + a.y * b.y;
-    im += a.x * b.y - a.y * b.x;
+  for (int k = kb; k < ke; ++k) {
+    const double2* v = V + (int64_t)k * stride;
+    double re = 0.0, im = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += NT) {
+      double2 a = v[i], b = w[i];
+      re += a.x * b.x + a.y * b.y;
+      im += a.x * b.y - a.y * b.x;
+    }
+    block_sum2(re, im);
+    if (threadIdx.x == 0) partial[(int64_t)k * G + g] = make_double2(re, im);
+    __syncthreads();   // block_sum2's shared slots are reused by the next k
   }
-  block_sum2(re, im);
-  if (threadIdx.x == 0) partial[(int64_t)k * G + g] = make_double2(re, im);
 }
 
 __global__ __launch_bounds__(NT) void k_reduce(const double2* __restrict__ partial, int G,
-                                               double* __restrict__ out) {
+                                               double* __restrict__ out, const int* __restrict__ d_j) {
   const int k = blockIdx.x;
+  if (d_j && k > *d_j) return;
   double re = 0.0, im = 0.0;
   for (int i = threadIdx.x; i < G; i += NT) {
     double2 p = partial[(int64_t)k * G + i];
@@ -85,11 +91,13 @@ __global__ __launch_bounds__(NT) void k_reduce(const double2* __restrict__ parti
   }
 }
 
-// w -= sum_k c_k V_k ; optional partial |w|^2
+// w -= sum_k c_k V_k ; optional partial |w|^2; with d_j, nv = *d_j + 1
 __global__ __launch_bounds__(NT) void k_sub_combo(double2* __restrict__ w, const double2* __restrict__ V,
                                                   int64_t stride, int nv, const double* __restrict__ coef,
-                                                  int64_t n, double2* __restrict__ partial) {
+                                                  int64_t n, double2* __restrict__ partial,
+                                                  const int* __restrict__ d_j) {
   __shared__ double c[2 * kMaxV];
+  if (d_j) nv = *d_j + 1;
   for (int i = threadIdx.x; i < 2 * nv; i += NT) c[i] = coef[i];
   __syncthreads();
   const int g = blockIdx.x, G = gridDim.x;
@@ -138,6 +146,28 @@ __global__ __launch_bounds__(NT) void k_scale_copy(double2* __restrict__ dst, co
     double2 x = src[i];
     dst[i] = make_double2(s * x.x, s * x.y);
   }
+}
+
+// Next Lanczos vector w / sqrt(b2) into basis slot *d_j + 1 (when it exists)
+// and into the fixed operator input x; b2 = |w|^2 from the device.
+__global__ __launch_bounds__(NT) void k_advance(double2* __restrict__ V, int64_t stride, double2* __restrict__ x,
+                                                const double2* __restrict__ w, int64_t n,
+                                                const double* __restrict__ b2, const int* __restrict__ d_j,
+                                                int maxdim) {
+  const double q = *b2;
+  const double s = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
+  const int j = *d_j;
+  double2* dst = j + 1 < maxdim ? V + (int64_t)(j + 1) * stride : nullptr;
+  for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+    double2 v = w[i];
+    v = make_double2(s * v.x, s * v.y);
+    x[i] = v;
+    if (dst) dst[i] = v;
+  }
+}
+
+__global__ void k_set_index(int* __restrict__ d_j, int v, int add) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *d_j = add ? *d_j + v : v;
 }
 
 __global__ __launch_bounds__(NT) void k_norm_partial(const double2* __restrict__ x, int64_t n,
@@ -245,8 +275,8 @@ int vec_dots(tdvp_ctx* ctx, const double* V, int64_t stride, int nv, const doubl
   TDVP_HIP(ctx, ctx->ws_vec.ensure(need));
   double2* partial = (double2*)ctx->ws_vec.p;
   hipLaunchKernelGGL(k_dots_partial, dim3(G, nv), dim3(NT), 0, ctx->stream, (const double2*)V, stride,
-                     (const double2*)w, n, partial);
-  hipLaunchKernelGGL(k_reduce, dim3(nv), dim3(NT), 0, ctx->stream, partial, G, d_out);
+                     (const double2*)w, n, partial, (const int*)nullptr);
+  hipLaunchKernelGGL(k_reduce, dim3(nv), dim3(NT), 0, ctx->stream, partial, G, d_out, (const int*)nullptr);
   TDVP_HIP(ctx, hipGetLastError());
   return TDVP_OK;
 }
@@ -261,8 +291,9 @@ int vec_subtract_combo(tdvp_ctx* ctx, double* w, const double* V, int64_t stride
     partial = (double2*)ctx->ws_vec.p;
   }
   hipLaunchKernelGGL(k_sub_combo, dim3(G), dim3(NT), 0, ctx->stream, (double2*)w, (const double2*)V, stride, nv,
-                     d_coef, n, partial);
-  if (d_norm2) hipLaunchKernelGGL(k_reduce, dim3(1), dim3(NT), 0, ctx->stream, partial, G, d_norm2);
+                     d_coef, n, partial, (const int*)nullptr);
+  if (d_norm2)
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(NT), 0, ctx->stream, partial, G, d_norm2, (const int*)nullptr);
   TDVP_HIP(ctx, hipGetLastError());
   return TDVP_OK;
 }
@@ -283,13 +314,56 @@ int vec_combo(tdvp_ctx* ctx, double* out, const double* V, int64_t stride, int n
   return TDVP_OK;
 }
 
+// ---- one Lanczos iteration with its index j in device memory (d_j), so that
+// a single captured graph serves every iteration of an exponential ----------
+
+size_t lanczos_partial_bytes(int64_t n, int maxdim) {
+  return sizeof(double2) * (size_t)nblocks_for(n) * (size_t)(maxdim + 1);
+}
+
+// two classical Gram-Schmidt passes of W against V_0..V_j: coefficients to
+// c1 and c2 (2 * maxdim doubles each), |W|^2 after the second pass to d_norm2
+int vec_lanczos_orth_it(tdvp_ctx* ctx, double* W, const double* V, int64_t stride, int maxdim, int64_t n,
+                        const int* d_j, double* c1, double* c2, double* d_norm2, void* partial_buf) {
+  if (maxdim > kMaxV) return TDVP_E_INVALID;
+  const int G = nblocks_for(n);
+  double2* partial = (double2*)partial_buf;
+  double* cs[2] = {c1, c2};
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL(k_dots_partial, dim3(G), dim3(NT), 0, ctx->stream, (const double2*)V, stride,
+                       (const double2*)W, n, partial, d_j);
+    hipLaunchKernelGGL(k_reduce, dim3(maxdim), dim3(NT), 0, ctx->stream, partial, G, cs[pass], d_j);
+    hipLaunchKernelGGL(k_sub_combo, dim3(G), dim3(NT), 0, ctx->stream, (double2*)W, (const double2*)V, stride, 0,
+                       (const double*)cs[pass], n, pass == 1 ? partial : nullptr, d_j);
+  }
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(NT), 0, ctx->stream, partial, G, d_norm2, (const int*)nullptr);
+  TDVP_HIP(ctx, hipGetLastError());
+  return TDVP_OK;
+}
+
+// x = V_{j+1} = W / sqrt(b2) (the basis slot only while j + 1 < maxdim), then j += 1
+int vec_lanczos_advance_it(tdvp_ctx* ctx, double* V, int64_t stride, double* x, const double* W, int64_t n,
+                           const double* d_b2, int* d_j, int maxdim) {
+  hipLaunchKernelGGL(k_advance, dim3(grid_1d(n)), dim3(NT), 0, ctx->stream, (double2*)V, stride, (double2*)x,
+                     (const double2*)W, n, d_b2, (const int*)d_j, maxdim);
+  hipLaunchKernelGGL(k_set_index, dim3(1), dim3(64), 0, ctx->stream, d_j, 1, 1);
+  TDVP_HIP(ctx, hipGetLastError());
+  return TDVP_OK;
+}
+
+int vec_set_index(tdvp_ctx* ctx, int* d_j, int v) {
+  hipLaunchKernelGGL(k_set_index, dim3(1), dim3(64), 0, ctx->stream, d_j, v, 0);
+  TDVP_HIP(ctx, hipGetLastError());
+  return TDVP_OK;
+}
+
 // d_out[0] = |x|^2, d_out[1] = number of non-finite entries
 int vec_norm2(tdvp_ctx* ctx, const double* x, int64_t n, double* d_out) {
   int G = nblocks_for(n);
   TDVP_HIP(ctx, ctx->ws_vec.ensure(sizeof(double2) * (size_t)G));
   double2* partial = (double2*)ctx->ws_vec.p;
   hipLaunchKernelGGL(k_norm_partial, dim3(G), dim3(NT), 0, ctx->stream, (const double2*)x, n, partial);
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(NT), 0, ctx->stream, partial, G, d_out);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(NT), 0, ctx->stream, partial, G, d_out, (const int*)nullptr);
   TDVP_HIP(ctx, hipGetLastError());
   return TDVP_OK;
 }

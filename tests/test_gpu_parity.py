@@ -242,6 +242,47 @@ def test_krylov_expm_against_dense_oracle(ctx, nsites, tau):
         ref, _ = D.lanczos_expm(lambda z: D.heff1(Lf, Rf, z, site, t, U), v, tau, tol=1e-15, maxdim=60)
         got = R.expand_site("C", theta_dict(xk, ys), left, right, site)
     err = np.abs(got - ref).max()
-    print(f"  iters={info['iters']} err={err:.2e}", flush=True)
+    print(f"  iters={info['iters']} (graph-replayed {info['graph_iters']}) err={err:.2e}", flush=True)
     assert err < 1e-10
     assert abs(np.linalg.norm(got) - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("prec", [T.FP64, T.FP32])
+def test_krylov_graph_replay_matches_direct_launches(ctx, prec):
+    """One captured Lanczos iteration replayed for the rest of the exponential
+    gives bit-identical results to launching every kernel directly."""
+    L, site, t, U = 6, 3, 1.0, 4.0
+    print(f"krylov graph replay prec={prec}", flush=True)
+    bonds, sites, model, (Lenv, Ld), (Renv, Rd) = _physical_envs(ctx, L, site, 2, 7, t, U, 24)
+    left, right = bonds[site - 1], bonds[site + 1]
+    bl, br = T.Bond(left), T.Bond(right)
+    xk, xo, xt, xd = T.center_layout(bl, br, 2)
+    xs = keyed(xk, random_blocks(xk, xd, 56))
+    nrm = np.sqrt(sum(np.sum(np.abs(a) ** 2) for a in xs))
+    x0 = pack([a / nrm for a in xs], xo, xt)
+    out = {}
+    ctx.set_precision(prec)
+    try:
+        for graphs in (False, True, False, True):
+            ctx.set_graphs(graphs)
+            x_d = dev(x0)
+            rc, info = ctx.krylov_expm(model, site, 2, bl, br, T.Blocks(Ld[0], Ld[1], Lenv.data_ptr(), Ld[2]),
+                                       T.Blocks(Rd[0], Rd[1], Renv.data_ptr(), Rd[2]),
+                                       T.Blocks(xk, xo, x_d.data_ptr(), xt), -0.3j, tol=1e-13, maxdim=40)
+            assert info["converged"], info
+            print(f"  graphs={graphs} iters={info['iters']} replayed={info['graph_iters']}", flush=True)
+            if graphs:   # FP64 captures once the tiling autotuner has settled, FP32 from the second iteration
+                assert info["graph_iters"] > 0
+                if prec == T.FP32:
+                    assert info["graph_iters"] == info["iters"] - 1
+            else:
+                assert info["graph_iters"] == 0
+            res = (host(x_d), info["alpha"], info["beta"])
+            if graphs in out:
+                assert np.array_equal(out[graphs][0], res[0])
+            out[graphs] = res
+    finally:
+        ctx.set_graphs(True)
+        ctx.set_precision(T.FP64)
+    assert np.array_equal(out[False][0], out[True][0])
+    assert out[False][1] == out[True][1] and out[False][2] == out[True][2]
