@@ -204,6 +204,11 @@ int vec_lanczos_advance_it(tdvp_ctx* ctx, double* V, int64_t stride, double* x, 
 int vec_set_index(tdvp_ctx* ctx, int* d_j, int v);
 int vec_check_finite(tdvp_ctx* ctx, const double* x, int64_t n, int* d_flag);
 int vec_pad_matrix(tdvp_ctx* ctx, double* A, int64_t n, int64_t g, double v, double* d_scale);
+// G -> H G H for count consecutive n x n Hermitian matrices (H = I - u u^H, a
+// fixed dense reflector of size n; P: count * n complex scratch), and back:
+// columns c >= c0 of eigenvectors W -> H W
+int vec_reflect_forward(tdvp_ctx* ctx, hipStream_t st, double* G, int64_t n, int64_t count, double* P);
+int vec_reflect_back(tdvp_ctx* ctx, hipStream_t st, double* G, int64_t n, int64_t count, int64_t c0);
 // d_out[2b], d_out[2b+1] = re, im of sum conj(x) y over block b, whose element
 // range is [d_meta[2b], d_meta[2b] + d_meta[2b+1]) (device metadata)
 int vec_block_dots(tdvp_ctx* ctx, const double* x, const double* y, const int64_t* d_meta, int nblocks,

@@ -151,7 +151,19 @@ struct Sector {
   int64_t qoff = 0, iso_off = 0, iso_ld = 0;
   bool scaled = false;      // isometry = M V_k S^-1 without QR
   int keep = 0;
+  int64_t iidx = 0;         // slot of the eigensolver's info flag
 };
+
+// Batched eigensolver of the sector Gram matrices: divide and conquer on the
+// reflected matrices (default), or the Jacobi-based divide and conquer
+// directly (TDVP_EIG=jacobi).
+bool eig_divide_conquer() {
+  static const bool dc = [] {
+    const char* e = std::getenv("TDVP_EIG");
+    return !(e && std::string(e) == "jacobi");
+  }();
+  return dc;
+}
 
 int ensure_solver(tdvp_ctx* ctx) {
   if (ctx->solver) return TDVP_OK;
@@ -275,13 +287,17 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
       ++nmat;
     }
   }
-  size_t bytes = sizeof(double) * 2 * (size_t)(mtot + gtot) + sizeof(double) * (size_t)(2 * dtot) +
+  // M | Gram slots | reflector scratch (n complex per slot) | eigenvalues |
+  // off-diagonal workspace | info flags
+  size_t bytes = sizeof(double) * (2 * (size_t)(mtot + gtot) + 2 * (size_t)dtot + 2 * ((size_t)dtot + 8)) +
                  sizeof(rocblas_int) * (size_t)(nmat + 8) + 4096;
   TDVP_HIP(ctx, ctx->ws_svd.ensure(bytes));
   double* Mbase = (double*)ctx->ws_svd.p;
   double* Gbase = Mbase + 2 * mtot;
-  double* Dbase = Gbase + 2 * gtot;
-  rocblas_int* dinfo = (rocblas_int*)(Dbase + dtot + 8);
+  double* Pbase = Gbase + 2 * gtot;
+  double* Dbase = Pbase + 2 * dtot;
+  double* Ebase = Dbase + dtot + 8;
+  rocblas_int* dinfo = (rocblas_int*)(Ebase + dtot + 8);
   int rc;
   Bufs b{};
   // gather Theta blocks into the sector matrices (zeros elsewhere)
@@ -378,21 +394,41 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
       mi += (int64_t)bk.second.size();
     }
     std::vector<double> sload(ctx->nside, 0.0);
+    const bool dc = eig_divide_conquer();
     for (int ob = (int)order.size() - 1; ob >= 0; --ob) {
       int64_t n = order[ob].first;
       auto& secv = *order[ob].second;
       Sector* s0 = secv.front();
-      for (Sector* sp : secv) sp->col0 = n - sp->g;
+      int64_t gmax = 0;
+      for (size_t q = 0; q < secv.size(); ++q) {
+        secv[q]->col0 = n - secv[q]->g;
+        secv[q]->iidx = minfo[ob] + (int64_t)q;
+        gmax = std::max(gmax, secv[q]->g);
+      }
       int k = (int)(std::min_element(sload.begin(), sload.end()) - sload.begin());
       sload[k] += (double)secv.size() * (double)n * n * n;
-      // Jacobi-based divide and conquer: the plain divide-and-conquer solver
-      // returns non-finite eigenvectors when the tridiagonal form splits
-      // (block-diagonal or zero-padded matrices), which sector Gram matrices do
-      rocblas_status st = rocsolver_zheevdj_strided_batched(
-          (rocblas_handle)ctx->side_solver[k], rocblas_evect_original, rocblas_fill_upper, (rocblas_int)n,
-          (rocblas_double_complex*)(Gbase + 2 * s0->goff), (rocblas_int)n, (rocblas_stride)(n * n),
-          Dbase + s0->doff, (rocblas_stride)n, dinfo + minfo[ob], (rocblas_int)secv.size());
-      if (st != rocblas_status_success) return set_error(ctx, TDVP_E_HIP, "rocsolver_zheevdj_strided_batched failed");
+      const int64_t cnt = (int64_t)secv.size();
+      double* G0 = Gbase + 2 * s0->goff;
+      rocblas_status st;
+      if (dc) {
+        // The divide-and-conquer solver returns non-finite eigenvectors when the
+        // tridiagonal form splits exactly, which zero-padded or block-structured
+        // Gram matrices force; a dense Householder reflection H G H (same
+        // spectrum, eigenvectors H W) removes that structure at O(n^2) cost.
+        if ((rc = vec_reflect_forward(ctx, ctx->side[k], G0, n, cnt, Pbase + 2 * s0->doff))) return rc;
+        st = rocsolver_zheevd_strided_batched(
+            (rocblas_handle)ctx->side_solver[k], rocblas_evect_original, rocblas_fill_upper, (rocblas_int)n,
+            (rocblas_double_complex*)G0, (rocblas_int)n, (rocblas_stride)(n * n), Dbase + s0->doff,
+            (rocblas_stride)n, Ebase + s0->doff, (rocblas_stride)n, dinfo + minfo[ob], (rocblas_int)cnt);
+        if (st == rocblas_status_success && (rc = vec_reflect_back(ctx, ctx->side[k], G0, n, cnt, n - gmax)))
+          return rc;
+      } else {
+        st = rocsolver_zheevdj_strided_batched(
+            (rocblas_handle)ctx->side_solver[k], rocblas_evect_original, rocblas_fill_upper, (rocblas_int)n,
+            (rocblas_double_complex*)G0, (rocblas_int)n, (rocblas_stride)(n * n), Dbase + s0->doff,
+            (rocblas_stride)n, dinfo + minfo[ob], (rocblas_int)cnt);
+      }
+      if (st != rocblas_status_success) return set_error(ctx, TDVP_E_HIP, "rocsolver batched eigensolver failed");
     }
     for (int k = 0; k < ctx->nside; ++k) {
       TDVP_HIP(ctx, hipEventRecord(ctx->side_ev[k], ctx->side[k]));
@@ -411,12 +447,16 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
       ++nb;
     }
     std::vector<double> chk(2 * std::max(nb, 1));
+    std::vector<rocblas_int> binfo(std::max<int64_t>(nmat, 1));
     TDVP_HIP(ctx, hipMemcpyAsync(chk.data(), dchk, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, ctx->stream));
+    TDVP_HIP(ctx, hipMemcpyAsync(binfo.data(), dinfo, sizeof(rocblas_int) * nmat, hipMemcpyDeviceToHost, ctx->stream));
     TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
     std::vector<Sector*> redo;
     nb = 0;
     for (auto& bk : buckets) {
-      if (chk[2 * nb + 1] != 0.0 || !std::isfinite(chk[2 * nb])) {
+      bool bad_info = false;
+      for (Sector* sp : bk.second) bad_info = bad_info || binfo[sp->iidx] != 0;
+      if (bad_info || chk[2 * nb + 1] != 0.0 || !std::isfinite(chk[2 * nb])) {
         redo.insert(redo.end(), bk.second.begin(), bk.second.end());
         if (ctx->verbose) {
           std::string gs;
@@ -436,7 +476,7 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
         sp->col0 = 0;
         rocblas_status st = rocsolver_zheevdj((rocblas_handle)ctx->solver, rocblas_evect_original, rocblas_fill_upper,
                                               (rocblas_int)sp->g, (rocblas_double_complex*)(Gbase + 2 * sp->goff),
-                                              (rocblas_int)sp->gn, Dbase + sp->doff, dinfo);
+                                              (rocblas_int)sp->gn, Dbase + sp->doff, dinfo + sp->iidx);
         if (st != rocblas_status_success) return set_error(ctx, TDVP_E_HIP, "rocsolver_zheevdj failed");
       }
     }

@@ -44,6 +44,99 @@ __device__ __forceinline__ void block_sum2(double& a, double& b) {
   }
 }
 
+// ---- Householder reflection H = I - u u^H (|u|^2 = 2) of batched Hermitian
+// n x n matrices: G -> H G H before an eigensolve, eigenvectors W -> H W after.
+// The spectrum is unchanged; a dense u removes exact block structure (zero
+// padding, decoupled sectors) that would split the tridiagonal form.
+__device__ __forceinline__ double2 reflector_u(int64_t i, int64_t n) {
+  const double f = (double)(i + 1) * 0.6180339887498949;   // golden-ratio phases
+  const double ph = 6.283185307179586 * (f - floor(f));
+  const double r = sqrt(2.0 / (double)n);
+  return make_double2(r * cos(ph), r * sin(ph));
+}
+
+// p = G u, one workgroup per 64 rows of one matrix (blockIdx.y)
+__global__ __launch_bounds__(NT) void k_reflect_p(const double2* __restrict__ G, int64_t n,
+                                                  double2* __restrict__ P) {
+  __shared__ double2 part[4][64];
+  const double2* A = G + (int64_t)blockIdx.y * n * n;
+  const int64_t r = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  const int cg = threadIdx.x >> 6;
+  double re = 0.0, im = 0.0;
+  if (r < n)
+    for (int64_t c = cg; c < n; c += 4) {
+      const double2 a = A[r + c * n], u = reflector_u(c, n);
+      re += a.x * u.x - a.y * u.y;
+      im += a.x * u.y + a.y * u.x;
+    }
+  part[cg][threadIdx.x & 63] = make_double2(re, im);
+  __syncthreads();
+  if (cg == 0 && r < n) {
+    double2 t = part[0][threadIdx.x];
+    for (int q = 1; q < 4; ++q) {
+      t.x += part[q][threadIdx.x].x;
+      t.y += part[q][threadIdx.x].y;
+    }
+    P[(int64_t)blockIdx.y * n + r] = t;
+  }
+}
+
+// w = p - (u^H p / 2) u in place, one workgroup per matrix
+__global__ __launch_bounds__(NT) void k_reflect_w(double2* __restrict__ P, int64_t n) {
+  double2* p = P + (int64_t)blockIdx.x * n;
+  double re = 0.0, im = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += NT) {
+    const double2 u = reflector_u(i, n), v = p[i];
+    re += u.x * v.x + u.y * v.y;
+    im += u.x * v.y - u.y * v.x;
+  }
+  block_sum2(re, im);
+  __shared__ double gamma;
+  if (threadIdx.x == 0) gamma = 0.5 * re;   // u^H G u is real for Hermitian G
+  __syncthreads();
+  const double g = gamma;
+  for (int64_t i = threadIdx.x; i < n; i += NT) {
+    const double2 u = reflector_u(i, n), v = p[i];
+    p[i] = make_double2(v.x - g * u.x, v.y - g * u.y);
+  }
+}
+
+// G -= u w^H + w u^H over all count matrices
+__global__ __launch_bounds__(NT) void k_reflect_update(double2* __restrict__ G, int64_t n, int64_t count,
+                                                       const double2* __restrict__ W) {
+  const int64_t nn = n * n, total = nn * count;
+  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
+    const int64_t m = e / nn, rc = e - m * nn, c = rc / n, r = rc - c * n;
+    const double2 ur = reflector_u(r, n), uc = reflector_u(c, n);
+    const double2 wr = W[m * n + r], wc = W[m * n + c];
+    double2 a = G[e];
+    // u_r conj(w_c) + w_r conj(u_c)
+    a.x -= (ur.x * wc.x + ur.y * wc.y) + (wr.x * uc.x + wr.y * uc.y);
+    a.y -= (ur.y * wc.x - ur.x * wc.y) + (wr.y * uc.x - wr.x * uc.y);
+    G[e] = a;
+  }
+}
+
+// columns c >= c0 of each matrix: W_c -= u (u^H W_c); one workgroup per column
+__global__ __launch_bounds__(NT) void k_reflect_back(double2* __restrict__ G, int64_t n, int64_t c0) {
+  double2* w = G + (int64_t)blockIdx.y * n * n + (c0 + blockIdx.x) * n;
+  double re = 0.0, im = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += NT) {
+    const double2 u = reflector_u(i, n), v = w[i];
+    re += u.x * v.x + u.y * v.y;
+    im += u.x * v.y - u.y * v.x;
+  }
+  block_sum2(re, im);
+  __shared__ double2 d;
+  if (threadIdx.x == 0) d = make_double2(re, im);
+  __syncthreads();
+  const double2 dd = d;
+  for (int64_t i = threadIdx.x; i < n; i += NT) {
+    const double2 u = reflector_u(i, n), v = w[i];
+    w[i] = make_double2(v.x - (u.x * dd.x - u.y * dd.y), v.y - (u.x * dd.y + u.y * dd.x));
+  }
+}
+
 int nblocks_for(int64_t n) {
   int64_t g = (n + NT * 4 - 1) / (NT * 4);
   if (g < 1) g = 1;
@@ -395,6 +488,24 @@ int vec_scale_cols_rsqrt(tdvp_ctx* ctx, double* A, int64_t ld, int64_t rows, int
   if (rows <= 0 || cols <= 0) return TDVP_OK;
   hipLaunchKernelGGL(k_scale_cols, dim3(grid_1d(rows * cols)), dim3(NT), 0, ctx->stream, (double2*)A, ld, rows, cols,
                      lam);
+  TDVP_HIP(ctx, hipGetLastError());
+  return TDVP_OK;
+}
+
+int vec_reflect_forward(tdvp_ctx* ctx, hipStream_t st, double* G, int64_t n, int64_t count, double* P) {
+  if (n <= 1 || count <= 0) return TDVP_OK;
+  hipLaunchKernelGGL(k_reflect_p, dim3((unsigned)((n + 63) / 64), (unsigned)count), dim3(NT), 0, st,
+                     (const double2*)G, n, (double2*)P);
+  hipLaunchKernelGGL(k_reflect_w, dim3((unsigned)count), dim3(NT), 0, st, (double2*)P, n);
+  hipLaunchKernelGGL(k_reflect_update, dim3(grid_1d(n * n * count)), dim3(NT), 0, st, (double2*)G, n, count,
+                     (const double2*)P);
+  TDVP_HIP(ctx, hipGetLastError());
+  return TDVP_OK;
+}
+
+int vec_reflect_back(tdvp_ctx* ctx, hipStream_t st, double* G, int64_t n, int64_t count, int64_t c0) {
+  if (n <= 1 || count <= 0 || c0 >= n) return TDVP_OK;
+  hipLaunchKernelGGL(k_reflect_back, dim3((unsigned)(n - c0), (unsigned)count), dim3(NT), 0, st, (double2*)G, n, c0);
   TDVP_HIP(ctx, hipGetLastError());
   return TDVP_OK;
 }
