@@ -22,6 +22,10 @@ Table S2.  Two measurements, both with all data resident in HBM:
   |psi_64 - psi_mixed| after the first and after the last sweep (from MPS
   overlaps), and the largest deviation of the site-resolved <S^z> and
   double occupancy.
+* Larger bonds (context, not the headline): H_eff.Theta at chi = 16384 with
+  a few hundred log-normal uneven blocks (grouped launch against one launch
+  per output block), and at the late-time chi ~ 62 000 (a 9.4 GB two-site
+  tensor), per precision; one-site sweeps on the saturated state.
 
 Prints one JSON line.  ``--gpus N`` with N > 1 is refused: the build is a
 single-GPU one.
@@ -63,30 +67,53 @@ def measured_traffic(prec):
     return rec["bytes_per_launch"] if h.hexdigest() == rec["sources_sha256"] else None
 
 
-def large_heff(args, T, torch, stream, ctx, model):
-    """H_eff.Theta at chi = 16384 (full-state units) with a few hundred uneven
-    sector blocks: degeneracies log-normal (median 200, sigma 1) over the labels
-    |q| <= 4, 2j <= 4, clipped to [8, 2048], rescaled to chi; synthetic
-    environments and Theta (complex normal).  FP64, FP32 and split-BF16
-    grouped launches, and FP64 with one launch per output block."""
+def large_heff(args, T, torch, stream, ctx, model, late=False):
+    """H_eff.Theta at the middle bond of L = 60 with large, uneven blocks.
+
+    Default: chi = 16384 (full-state units), a few hundred sector blocks with
+    degeneracies log-normal (median 200, sigma 1) over the labels |q| <= 4,
+    2j <= 4, clipped to [8, 2048], rescaled to chi; environments and Theta
+    complex normal (numpy, seeded); FP64, FP32 and split-BF16 grouped
+    launches, and FP64 with one launch per output block.
+    late=True: the late-time bond dimension chi ~ 62 000 with Table-S2-shaped
+    sectors (a 9.4 GB two-site tensor); operands drawn on the device (seeded
+    torch generator: only throughput is measured here, the full-size tests
+    check the values), grouped launches only."""
     import numpy as np
     import synth
-    chi, site = 16384, 30
-    left = synth.lognormal_profile(chi, 7919 * (site - 1), 1, qmax=4, tjmax=4)
-    right = synth.lognormal_profile(chi, 7919 * (site + 1), 1, qmax=4, tjmax=4)
+    site = 30
+    if late:
+        chi = 62000
+        left = synth.sector_profile(chi, 7919 * (site - 1), parity=1)
+        right = synth.sector_profile(chi, 7919 * (site + 1), parity=1)
+        label = f"chi={chi} L=60 middle bond, Table-S2-shaped sectors (late-time segment)"
+    else:
+        chi = 16384
+        left = synth.lognormal_profile(chi, 7919 * (site - 1), 1, qmax=4, tjmax=4)
+        right = synth.lognormal_profile(chi, 7919 * (site + 1), 1, qmax=4, tjmax=4)
+        label = (f"chi={chi} L=60 middle bond, log-normal sector dims (median 200, sigma 1, |q|<=4, "
+                 f"2j<=4, clipped 8..2048, rescaled)")
     bl, br = T.Bond(left), T.Bond(right)
     xk, xo, xt, xd = T.center_layout(bl, br, 2)
     lk, lo, lt, ld = T.env_layout(bl)
     rk, ro, rt, rd = T.env_layout(br)
-    dev = lambda a: torch.from_numpy(a).to("cuda")
-    X = synth.block_data([tuple(k) for k in xk], xd, args.seed + 31, 13)
-    Lb = synth.block_data([tuple(k) for k in lk], ld, args.seed + 32, 14)
-    Rb = synth.block_data([tuple(k) for k in rk], rd, args.seed + 33, 15)
-    x_d = dev(pack(X, xk, xo, xt))
-    L_d = dev(pack(Lb, lk, lo, lt))
-    R_d = dev(pack(Rb, rk, ro, rt))
-    del X, Lb, Rb
+    if late:
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(args.seed + 62)
+        draw = lambda n: torch.randn(max(n, 1), dtype=torch.complex128, device="cuda", generator=gen)
+        x_d, L_d, R_d = draw(xt), draw(lt), draw(rt)
+        x_d /= torch.linalg.vector_norm(x_d)
+    else:
+        dev = lambda a: torch.from_numpy(a).to("cuda")
+        X = synth.block_data([tuple(k) for k in xk], xd, args.seed + 31, 13)
+        Lb = synth.block_data([tuple(k) for k in lk], ld, args.seed + 32, 14)
+        Rb = synth.block_data([tuple(k) for k in rk], rd, args.seed + 33, 15)
+        x_d = dev(pack(X, xk, xo, xt))
+        L_d = dev(pack(Lb, lk, lo, lt))
+        R_d = dev(pack(Rb, rk, ro, rt))
+        del X, Lb, Rb
     y_d = torch.zeros_like(x_d)
+    torch.cuda.synchronize()
     Lbk = T.Blocks(lk, lo, L_d.data_ptr(), lt)
     Rbk = T.Blocks(rk, ro, R_d.data_ptr(), rt)
     xb = T.Blocks(xk, xo, x_d.data_ptr(), xt)
@@ -106,23 +133,27 @@ def large_heff(args, T, torch, stream, ctx, model):
         ctx.synchronize()
         return a.elapsed_time(b) * 1e-3 / reps
 
-    res = {"workload": f"chi={chi} L=60 middle bond, log-normal sector dims (median 200, sigma 1, |q|<=4, "
-                       f"2j<=4, clipped 8..2048, rescaled)", "blocks": len(xk), "theta_elems": int(xt),
+    res = {"workload": label, "blocks": len(xk), "theta_elems": int(xt),
+           "theta_gb": round(xt * 16 / 1e9, 2), "env_gb": round((lt + rt) * 16 / 1e9, 2),
            "block_dim_max": int(max(r for r, c in xd)), "flops_per_apply": flops}
-    for name, p in (("fp64", T.FP64), ("fp32", T.FP32), ("bf16x3", T.BF16X3)):
-        dt = timed(p, 10, 10)
+    # FP64 warm-up covers the tiling autotuner's measured launches
+    runs = (("fp64", T.FP64, 7, 3), ("fp32", T.FP32, 1, 3), ("bf16x3", T.BF16X3, 1, 3)) if late else \
+        (("fp64", T.FP64, 10, 10), ("fp32", T.FP32, 10, 10), ("bf16x3", T.BF16X3, 10, 10))
+    for name, p, warm, reps in runs:
+        dt = timed(p, warm, reps)
         res[name] = {"ms_per_apply": 1e3 * dt, "tflops": flops / dt / 1e12}
-        print(f"bench: chi=16384 H_eff {name} {1e3 * dt:.2f} ms, {flops / dt / 1e12:.2f} TFLOP/s",
+        print(f"bench: chi={chi} H_eff {name} {1e3 * dt:.2f} ms, {flops / dt / 1e12:.2f} TFLOP/s",
               file=sys.stderr, flush=True)
-    os.environ["TDVP_PER_BLOCK"] = "1"
-    try:
-        dt = timed(T.FP64, 2, 3)
-    finally:
-        del os.environ["TDVP_PER_BLOCK"]
-    res["fp64_one_launch_per_block"] = {"ms_per_apply": 1e3 * dt, "tflops": flops / dt / 1e12,
-                                        "launches_per_apply": len(xk)}
-    print(f"bench: chi=16384 H_eff fp64, one launch per output block: {1e3 * dt:.2f} ms, "
-          f"{flops / dt / 1e12:.2f} TFLOP/s", file=sys.stderr, flush=True)
+    if not late:
+        os.environ["TDVP_PER_BLOCK"] = "1"
+        try:
+            dt = timed(T.FP64, 2, 3)
+        finally:
+            del os.environ["TDVP_PER_BLOCK"]
+        res["fp64_one_launch_per_block"] = {"ms_per_apply": 1e3 * dt, "tflops": flops / dt / 1e12,
+                                            "launches_per_apply": len(xk)}
+        print(f"bench: chi={chi} H_eff fp64, one launch per output block: {1e3 * dt:.2f} ms, "
+              f"{flops / dt / 1e12:.2f} TFLOP/s", file=sys.stderr, flush=True)
     ctx.set_precision(T.FP64 if args.prec == "fp64" else T.FP32)
     del x_d, y_d, L_d, R_d
     torch.cuda.empty_cache()
@@ -143,6 +174,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison run")
     ap.add_argument("--one-site-steps", type=int, default=2, help="one-site sweeps timed after the two-site ones")
     ap.add_argument("--no-large", action="store_true", help="skip the chi=16384 grouped-vs-per-block measurement")
+    ap.add_argument("--no-late", action="store_true", help="skip the chi~62000 H_eff throughput measurement")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB three times (reference for the HBM byte counters)")
@@ -264,6 +296,9 @@ def main():
     large = None
     if not args.no_large:
         large = large_heff(args, T, torch, stream, ctx, model)
+    late = None
+    if not args.no_late:
+        late = large_heff(args, T, torch, stream, ctx, model, late=True)
 
     # ---- full sweeps: the step at the working precision, and the mixed path
     # (FP32 block products, FP64 Lanczos / SVD) from the same initial state ----
@@ -434,6 +469,7 @@ def main():
         "cpu_baseline": cpu,
         "mixed": mixed,
         "large_blocks": large,
+        "late_time_blocks": late,
     }
     line.update(sweep)
     print(json.dumps(line), flush=True)

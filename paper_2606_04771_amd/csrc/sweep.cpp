@@ -395,6 +395,16 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
     }
     std::vector<double> sload(ctx->nside, 0.0);
     const bool dc = eig_divide_conquer();
+    // assign the buckets to side streams (largest first, balancing the summed
+    // padded size: each batched solve is a chain of dependent launches whose
+    // length follows n), then issue them stream by stream (issuing from one
+    // host thread per stream was measured slower)
+    struct EigJob {
+      int64_t n, cnt, gmax;
+      double *G0, *P0, *D0, *E0;
+      rocblas_int* info;
+    };
+    std::vector<std::vector<EigJob>> jobs(ctx->nside);
     for (int ob = (int)order.size() - 1; ob >= 0; --ob) {
       int64_t n = order[ob].first;
       auto& secv = *order[ob].second;
@@ -406,30 +416,39 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
         gmax = std::max(gmax, secv[q]->g);
       }
       int k = (int)(std::min_element(sload.begin(), sload.end()) - sload.begin());
-      sload[k] += (double)secv.size() * (double)n * n * n;
-      const int64_t cnt = (int64_t)secv.size();
-      double* G0 = Gbase + 2 * s0->goff;
-      rocblas_status st;
-      if (dc) {
-        // The divide-and-conquer solver returns non-finite eigenvectors when the
-        // tridiagonal form splits exactly, which zero-padded or block-structured
-        // Gram matrices force; a dense Householder reflection H G H (same
-        // spectrum, eigenvectors H W) removes that structure at O(n^2) cost.
-        if ((rc = vec_reflect_forward(ctx, ctx->side[k], G0, n, cnt, Pbase + 2 * s0->doff))) return rc;
-        st = rocsolver_zheevd_strided_batched(
-            (rocblas_handle)ctx->side_solver[k], rocblas_evect_original, rocblas_fill_upper, (rocblas_int)n,
-            (rocblas_double_complex*)G0, (rocblas_int)n, (rocblas_stride)(n * n), Dbase + s0->doff,
-            (rocblas_stride)n, Ebase + s0->doff, (rocblas_stride)n, dinfo + minfo[ob], (rocblas_int)cnt);
-        if (st == rocblas_status_success && (rc = vec_reflect_back(ctx, ctx->side[k], G0, n, cnt, n - gmax)))
-          return rc;
-      } else {
-        st = rocsolver_zheevdj_strided_batched(
-            (rocblas_handle)ctx->side_solver[k], rocblas_evect_original, rocblas_fill_upper, (rocblas_int)n,
-            (rocblas_double_complex*)G0, (rocblas_int)n, (rocblas_stride)(n * n), Dbase + s0->doff,
-            (rocblas_stride)n, dinfo + minfo[ob], (rocblas_int)cnt);
-      }
-      if (st != rocblas_status_success) return set_error(ctx, TDVP_E_HIP, "rocsolver batched eigensolver failed");
+      sload[k] += (double)n;
+      jobs[k].push_back(EigJob{n, (int64_t)secv.size(), gmax, Gbase + 2 * s0->goff, Pbase + 2 * s0->doff,
+                               Dbase + s0->doff, Ebase + s0->doff, dinfo + minfo[ob]});
     }
+    auto issue = [&](int k) -> int {
+      for (const EigJob& jb : jobs[k]) {
+        const int64_t n = jb.n;
+        rocblas_status st;
+        int r;
+        if (dc) {
+          // The divide-and-conquer solver returns non-finite eigenvectors when the
+          // tridiagonal form splits exactly, which zero-padded or block-structured
+          // Gram matrices force; a dense Householder reflection H G H (same
+          // spectrum, eigenvectors H W) removes that structure at O(n^2) cost.
+          if ((r = vec_reflect_forward(ctx, ctx->side[k], jb.G0, n, jb.cnt, jb.P0))) return r;
+          st = rocsolver_zheevd_strided_batched(
+              (rocblas_handle)ctx->side_solver[k], rocblas_evect_original, rocblas_fill_upper, (rocblas_int)n,
+              (rocblas_double_complex*)jb.G0, (rocblas_int)n, (rocblas_stride)(n * n), jb.D0, (rocblas_stride)n,
+              jb.E0, (rocblas_stride)n, jb.info, (rocblas_int)jb.cnt);
+          if (st == rocblas_status_success && (r = vec_reflect_back(ctx, ctx->side[k], jb.G0, n, jb.cnt, n - jb.gmax)))
+            return r;
+        } else {
+          st = rocsolver_zheevdj_strided_batched(
+              (rocblas_handle)ctx->side_solver[k], rocblas_evect_original, rocblas_fill_upper, (rocblas_int)n,
+              (rocblas_double_complex*)jb.G0, (rocblas_int)n, (rocblas_stride)(n * n), jb.D0, (rocblas_stride)n,
+              jb.info, (rocblas_int)jb.cnt);
+        }
+        if (st != rocblas_status_success) return TDVP_E_HIP;
+      }
+      return TDVP_OK;
+    };
+    for (int k = 0; k < ctx->nside; ++k)
+      if (int r = issue(k)) return r == TDVP_E_HIP ? set_error(ctx, r, "batched eigensolver failed") : r;
     for (int k = 0; k < ctx->nside; ++k) {
       TDVP_HIP(ctx, hipEventRecord(ctx->side_ev[k], ctx->side[k]));
       TDVP_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->side_ev[k], 0));
