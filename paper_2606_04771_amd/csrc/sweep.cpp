@@ -189,6 +189,36 @@ int ensure_solver(tdvp_ctx* ctx) {
 
 int check_finite(tdvp_ctx* ctx, const Blocks& b, const char* what, int bond);
 
+// Side streams start after the work already on the context stream, and the
+// context stream waits for everything then issued on them.
+int side_fork(tdvp_ctx* ctx) {
+  TDVP_HIP(ctx, hipEventRecord(ctx->side_ev[tdvp_ctx::kSide], ctx->stream));
+  for (int k = 0; k < ctx->nside; ++k) TDVP_HIP(ctx, hipStreamWaitEvent(ctx->side[k], ctx->side_ev[tdvp_ctx::kSide], 0));
+  return TDVP_OK;
+}
+
+int side_join(tdvp_ctx* ctx) {
+  for (int k = 0; k < ctx->nside; ++k) {
+    TDVP_HIP(ctx, hipEventRecord(ctx->side_ev[k], ctx->side[k]));
+    TDVP_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->side_ev[k], 0));
+  }
+  return TDVP_OK;
+}
+
+// side stream of each size bucket, largest first, balancing the summed padded size
+template <typename Map>
+std::vector<int> side_assign(const tdvp_ctx* ctx, const Map& buckets) {
+  std::vector<int> who(buckets.size());
+  std::vector<double> load(ctx->nside, 0.0);
+  int q = (int)buckets.size();
+  for (auto it = buckets.rbegin(); it != buckets.rend(); ++it) {
+    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[k] += (double)it->first;
+    who[--q] = k;
+  }
+  return who;
+}
+
 // Padded sizes for the batched solves.  Every batched call is a chain of
 // many small dependent kernels whose length grows with the padded size, so
 // fewer, larger buckets beat tight ones: the eigensolves use steps of about
@@ -1432,16 +1462,21 @@ int gauge_qr(tdvp_ctx* ctx, tdvp_mps* m, int i, int dir, Blocks& x, DeviceBuffer
     if ((r = run_program(ctx, pg, b, G))) return r;
     for (int s = 0; s < ns; ++s)
       if ((r = vec_pad_identity(ctx, G + 2 * goff[s], gn[s], cut.d[s]))) return r;
+    // batched Cholesky per size bucket, the buckets spread over the side streams
+    const std::vector<int> who = side_assign(ctx, buckets);
+    if ((r = side_fork(ctx))) return r;
     int64_t mi = 0;
+    int q = 0;
     for (auto& bk : buckets) {
       const int64_t n = bk.first;
       const int s0 = bk.second.front(), cnt = (int)bk.second.size();
       rocblas_status st = rocsolver_zpotrf_strided_batched(
-          (rocblas_handle)ctx->solver, rocblas_fill_upper, (rocblas_int)n, (rocblas_double_complex*)(G + 2 * goff[s0]),
-          (rocblas_int)n, (rocblas_stride)(n * n), dinfo + mi, cnt);
+          (rocblas_handle)ctx->side_solver[who[q++]], rocblas_fill_upper, (rocblas_int)n,
+          (rocblas_double_complex*)(G + 2 * goff[s0]), (rocblas_int)n, (rocblas_stride)(n * n), dinfo + mi, cnt);
       if (st != rocblas_status_success) return set_error(ctx, TDVP_E_HIP, "rocsolver_zpotrf_strided_batched failed");
       mi += cnt;
     }
+    if ((r = side_join(ctx))) return r;
     std::vector<rocblas_int> info(ns);
     TDVP_HIP(ctx, hipMemcpyAsync(info.data(), dinfo, sizeof(rocblas_int) * ns, hipMemcpyDeviceToHost, ctx->stream));
     TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -1454,11 +1489,20 @@ int gauge_qr(tdvp_ctx* ctx, tdvp_mps* m, int i, int dir, Blocks& x, DeviceBuffer
       const int s0 = bk.second.front(), cnt = (int)bk.second.size();
       if ((r = vec_zero_lower(ctx, Rk + 2 * goff[s0], n, cnt))) return r;
       if ((r = vec_zero_lower(ctx, G + 2 * goff[s0], n, cnt))) return r;
-      rocblas_status st = rocsolver_ztrtri_strided_batched(
-          (rocblas_handle)ctx->solver, rocblas_fill_upper, rocblas_diagonal_non_unit, (rocblas_int)n,
-          (rocblas_double_complex*)(G + 2 * goff[s0]), (rocblas_int)n, (rocblas_stride)(n * n), dinfo, cnt);
-      if (st != rocblas_status_success) return set_error(ctx, TDVP_E_HIP, "rocsolver_ztrtri_strided_batched failed");
     }
+    if ((r = side_fork(ctx))) return r;
+    q = 0;
+    mi = 0;
+    for (auto& bk : buckets) {
+      const int64_t n = bk.first;
+      const int s0 = bk.second.front(), cnt = (int)bk.second.size();
+      rocblas_status st = rocsolver_ztrtri_strided_batched(
+          (rocblas_handle)ctx->side_solver[who[q++]], rocblas_fill_upper, rocblas_diagonal_non_unit, (rocblas_int)n,
+          (rocblas_double_complex*)(G + 2 * goff[s0]), (rocblas_int)n, (rocblas_stride)(n * n), dinfo + mi, cnt);
+      if (st != rocblas_status_success) return set_error(ctx, TDVP_E_HIP, "rocsolver_ztrtri_strided_batched failed");
+      mi += cnt;
+    }
+    if ((r = side_join(ctx))) return r;
     // dst = src R^-1 (dir +1) or R^-dag src (dir -1), block by block
     Program pq;
     for (int o = 0; o < T.n(); ++o) {
