@@ -368,6 +368,8 @@ def main():
                 "sweep_phase_s": {k: float(np.mean([i[k] for i in infos])) for k in
                                   ("t_lanczos", "t_svd", "t_env")},
                 "krylov_iters_per_sweep": float(np.mean([i["krylov_iters"] for i in infos])),
+                "graph_replayed_iters_per_sweep": float(np.mean([i["graph_iters"] for i in infos])),
+                "eig_fallbacks": int(sum(i["eig_fallbacks"] for i in infos)),
                 "max_chi": int(max(i["max_chi"] for i in infos)),
                 "max_discarded": float(max(i["max_discarded"] for i in infos)),
             }

@@ -147,6 +147,7 @@ typedef struct {
   double seconds;         /* host wall time of the call */
   double t_heff, t_lanczos, t_svd, t_env;  /* seconds per phase (device events) */
   int32_t graph_iters;    /* Lanczos iterations replayed from captured graphs */
+  int32_t eig_fallbacks;  /* sector Gram matrices re-solved by the Jacobi-based fallback */
 } tdvp_sweep_info;
 
 /* Plan of one H_eff apply, exported for host-side inspection and tests.

@@ -57,7 +57,8 @@ class _SweepInfo(C.Structure):
                 ("max_chi_su2", C.c_int64), ("krylov_iters", C.c_int32), ("krylov_max", C.c_int32),
                 ("nonconverged", C.c_int32), ("heff_flops", C.c_double), ("env_flops", C.c_double),
                 ("seconds", C.c_double), ("t_heff", C.c_double), ("t_lanczos", C.c_double),
-                ("t_svd", C.c_double), ("t_env", C.c_double), ("graph_iters", C.c_int32)]
+                ("t_svd", C.c_double), ("t_env", C.c_double), ("graph_iters", C.c_int32),
+                ("eig_fallbacks", C.c_int32)]
 
 
 class _Term(C.Structure):

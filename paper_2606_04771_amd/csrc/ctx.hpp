@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <list>
 #include <memory>
+#include <map>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -132,6 +133,10 @@ struct DeviceBuffer {
 }  // namespace tdvp
 
 struct tdvp_ctx {
+  // tiling autotuner decisions (tile mode) by program class: role and
+  // half-octave of the program's flops; later programs of a decided class
+  // start from its choice instead of measuring again
+  std::map<int, int> tuned_modes;
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;

@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <cstdlib>
 #include <cstring>
@@ -934,12 +935,24 @@ static int launch_core(tdvp_ctx* ctx, const Program& p, int ntiles, int n64, con
 // candidate is launched kTuneRounds times, each bracketed by events; at the
 // first launch after the last measurement (the caller has synchronised in
 // between, as the Krylov loop does every iteration; otherwise this waits) the
-// fastest total wins.
+// fastest total wins.  The decision is kept in the context by program class
+// (role, half-octave of flops): later programs of that class, such as the
+// next bonds of a sweep, take it without measuring.
+static int tune_class(const Program& p) {
+  return p.role * 1000 + (int)std::floor(2.0 * std::log2(std::max(p.flops, 1.0)));
+}
+
 static int tune_pick(tdvp_ctx* ctx, const Program& p, hipEvent_t*& ev0, hipEvent_t*& ev1) {
   ev0 = ev1 = nullptr;
   const int nv = (int)p.alt.size();
   if (nv <= 1) return -1;
   if (p.tuned >= 0) return p.tuned;
+  if (p.tune_next == 0) {   // a class already decided in this context: take its choice
+    auto it = ctx->tuned_modes.find(tune_class(p));
+    if (it != ctx->tuned_modes.end())
+      for (int v = 0; v < nv; ++v)
+        if (p.alt[v].mode == it->second) return p.tuned = v;
+  }
   const int need = nv * Program::kTuneRounds;
   if (p.tune_next < need) {
     if (p.tune_ev.empty()) {
@@ -965,6 +978,7 @@ static int tune_pick(tdvp_ctx* ctx, const Program& p, hipEvent_t*& ev0, hipEvent
     tot[k % nv] += ms;
   }
   p.tuned = (int)(std::min_element(tot.begin(), tot.end()) - tot.begin());
+  ctx->tuned_modes[tune_class(p)] = p.alt[p.tuned].mode;
   if (ctx->verbose >= 2) {
     std::string msg;
     for (int v = 0; v < nv; ++v) msg += " mode" + std::to_string(p.alt[v].mode) + "=" + std::to_string(tot[v]);

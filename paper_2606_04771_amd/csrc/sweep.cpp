@@ -255,7 +255,7 @@ int run_program(tdvp_ctx* ctx, Program& p, const Bufs& b, double* C) {
 // the larger side it is obtained by a Householder QR of M V_k (or M^dag U_k).
 // The centre is then the exact projection of M on the kept isometry.
 int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const tdvp_trunc& tr, double& disc,
-          double& t_svd) {
+          double& t_svd, int& fallbacks) {
   double t0 = now();
   // phase timestamps (verbose >= 2 only: each one synchronises the stream)
   double ph[4] = {t0, t0, t0, t0};
@@ -516,6 +516,7 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
       ++nb;
     }
     if (!redo.empty()) {
+      fallbacks += (int)redo.size();
       if (ctx->verbose) std::fprintf(stderr, "[tdvp]   bond %d: %zu Gram matrices re-solved unpadded\n", i, redo.size());
       Program g;
       gram_program(redo, g);
@@ -1041,7 +1042,7 @@ int tdvp_sweep(tdvp_ctx* ctx, tdvp_mps* m, double dt, const tdvp_trunc* tr, tdvp
         return rc;
       if ((rc = check_finite(ctx, th, "evolved", i))) return rc;
       double d = 0;
-      if ((rc = split(ctx, m, i, th, +1, *tr, d, inf.t_svd))) return rc;
+      if ((rc = split(ctx, m, i, th, +1, *tr, d, inf.t_svd, inf.eig_fallbacks))) return rc;
       if ((rc = check_finite(ctx, m->site[i - 1]->blk, "split-A", i))) return rc;
       if ((rc = check_finite(ctx, m->site[i]->blk, "split-C", i))) return rc;
       inf.max_discarded = std::max(inf.max_discarded, d);
@@ -1067,7 +1068,7 @@ int tdvp_sweep(tdvp_ctx* ctx, tdvp_mps* m, double dt, const tdvp_trunc* tr, tdvp
            })))
         return rc;
       double d = 0;
-      if ((rc = split(ctx, m, i, th, -1, *tr, d, inf.t_svd))) return rc;
+      if ((rc = split(ctx, m, i, th, -1, *tr, d, inf.t_svd, inf.eig_fallbacks))) return rc;
       inf.max_discarded = std::max(inf.max_discarded, d);
       inf.sum_discarded += d;
       if ((rc = timed(inf.t_env, [&] { return env_step_sync(ctx, m, i + 1, -1, &inf); })))

@@ -81,7 +81,8 @@ def test_complete_basis_sweeps_follow_exact_evolution_L8(ctx):
             sz, docc, n2 = mps.measure()
             worst_n = max(worst_n, np.abs(sz - 0.5 * (nu0 - nd0)).max(), np.abs(docc - dd0).max(), abs(n2 - 1))
             print(f"t={n * dt:.2f} 1-|ov|={1 - ov:.2e} max|dn|={np.abs(nu - nu0).max():.2e} "
-                  f"chi={info['max_chi']} krylov={info['krylov_iters']}", flush=True)
+                  f"chi={info['max_chi']} krylov={info['krylov_iters']} eig fallbacks={info['eig_fallbacks']}",
+                  flush=True)
     mps.close()
     assert worst_ov < 1e-10
     assert worst_n < 1e-10
@@ -141,7 +142,8 @@ def test_truncated_sweeps_match_oracle(ctx, chi_cap, eps):
         ov = abs(np.vdot(phi, psi))
         nu, nd, dd = F.local_expectations(psi, L)
         mu, md, de = F.local_expectations(phi, L)
-        print(f"sweep {n + 1}: 1-|ov| {1 - ov:.2e} chi {info['max_chi']} max disc {info['max_discarded']:.2e} "
+        print(f"sweep {n + 1}: eig fallbacks {info['eig_fallbacks']} 1-|ov| {1 - ov:.2e} chi {info['max_chi']} "
+              f"max disc {info['max_discarded']:.2e} "
               f"(oracle {max(disc):.2e})", flush=True)
         assert info["max_chi"] <= chi_cap
         assert abs(info["max_discarded"] - max(disc)) < 1e-10
