@@ -112,10 +112,11 @@ def test_heff_one_site(ctx):
     assert np.abs(got - ref).max() / np.abs(ref).max() < FP64_TOL
 
 
+@pytest.mark.parametrize("prec", [T.FP64, T.FP32, T.BF16X3])
 @pytest.mark.parametrize("direction", [1, -1])
-def test_env_update(ctx, direction):
+def test_env_update(ctx, direction, prec):
     t, U, site = 1.0, 4.0, 4
-    print(f"env update direction={direction}", flush=True)
+    print(f"env update direction={direction} prec={prec}", flush=True)
     b_site_left = _bond((site - 1) % 2, 300)     # bond site-1
     b_site_right = _bond(site % 2, 301)          # bond site
     if direction > 0:
@@ -132,9 +133,13 @@ def test_env_update(ctx, direction):
     t_d = dev(pack(ts, to, tt))
     e_d = dev(pack(Es, eo, et))
     o_d = torch.zeros(max(ot, 1), dtype=torch.complex128, device="cuda")
-    ctx.env_update(T.Model(8, t, U), site, direction, bi, bo, T.Blocks(ek, eo, e_d.data_ptr(), et),
-                   T.Blocks(tk, to, t_d.data_ptr(), tt), T.Blocks(ok, oo, o_d.data_ptr(), ot))
-    outs = unpack(host(o_d), oo, od)
+    ctx.set_precision(prec)
+    try:
+        ctx.env_update(T.Model(8, t, U), site, direction, bi, bo, T.Blocks(ek, eo, e_d.data_ptr(), et),
+                       T.Blocks(tk, to, t_d.data_ptr(), tt), T.Blocks(ok, oo, o_d.data_ptr(), ot))
+        outs = unpack(host(o_d), oo, od)
+    finally:
+        ctx.set_precision(T.FP64)
     Ef = R.expand_env(env_dict(ek, Es), bin_)
     if direction > 0:
         ref = D.left_env_update(Ef, R.expand_site("A", theta_dict(tk, ts), bin_, bout, site), site, t, U)
@@ -142,8 +147,10 @@ def test_env_update(ctx, direction):
         ref = D.right_env_update(Ef, R.expand_site("B", theta_dict(tk, ts), bout, bin_, site), site, t, U)
     got = R.expand_env(env_dict(ok, outs), bout)
     scale = max(np.abs(ref[w]).max() for w in range(3))
-    for w in range(3):
-        assert np.abs(got[w] - ref[w]).max() < FP64_TOL * scale
+    tol = FP64_TOL if prec == T.FP64 else 2e-5   # FP32 accumulation: ~1e-6 relative at these depths
+    err = max(np.abs(got[w] - ref[w]).max() for w in range(3)) / scale
+    print(f"  max error relative to the largest entry: {err:.2e}", flush=True)
+    assert err < tol
 
 
 def test_heff_deterministic(ctx):
