@@ -34,7 +34,15 @@ namespace tdvp {
 
 namespace {
 
-constexpr int TK = 16, PAD = 2;
+constexpr int PAD = 2;
+// K depth of one staged step: 16 for FP64 tiles, 32 for FP32 ones (measured:
+// FP64 loses occupancy at 32, FP32 gains from the longer step)
+template <typename T>
+struct KStep {
+  static constexpr int value = sizeof(T) == 8 ? 16 : 32;
+};
+// host-side stepping of K chains (cost model, split points): a multiple of every KStep
+constexpr int kHostKStep = 32;
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -57,23 +65,25 @@ template <> struct Mfma<float> {
 };
 
 // Tile TM x TN = (32 WM) x (32 WN); WM x WN waves, each owning a 32x32 sub-tile.
-template <int WM, int WN>
+template <typename T, int WM, int WN>
 struct Shape {
+  static constexpr int TK = KStep<T>::value;
   static constexpr int TM = 32 * WM, TN = 32 * WN, NT = 64 * WM * WN;
   static constexpr int NA = TM * TK / NT, NB = TK * TN / NT;   // elements per thread
 };
 
-template <int WM, int WN>
+template <typename T, int WM, int WN>
 struct Stage {
-  double2 a[Shape<WM, WN>::NA], b[Shape<WM, WN>::NB];
+  double2 a[Shape<T, WM, WN>::NA], b[Shape<T, WM, WN>::NB];
 };
 
 // Load this thread's A and B elements of the K-tile k0 of term tm (coalesced:
 // consecutive threads follow the contiguous dimension of each operand).
-template <int WM, int WN, bool SH>
-__device__ __forceinline__ void load_stage(Stage<WM, WN>& st, const DevTerm& tm, const Bufs& bufs, int m0, int n0,
+template <typename T, int WM, int WN, bool SH>
+__device__ __forceinline__ void load_stage(Stage<T, WM, WN>& st, const DevTerm& tm, const Bufs& bufs, int m0, int n0,
                                            int M, int N, int k0, int tid) {
-  typedef Shape<WM, WN> S;
+  typedef Shape<T, WM, WN> S;
+  constexpr int TK = S::TK;
   const double2* A = reinterpret_cast<const double2*>(bufs.p[tm.a_buf]) + tm.a_off;
   const double2* B = reinterpret_cast<const double2*>(bufs.p[tm.b_buf]) + tm.b_off;
   const bool ta = tm.ops & 1, tb = tm.ops & 4;
@@ -109,10 +119,11 @@ __device__ __forceinline__ void load_stage(Stage<WM, WN>& st, const DevTerm& tm,
 }
 
 template <typename T, int WM, int WN>
-__device__ __forceinline__ void store_stage(const Stage<WM, WN>& st, const DevTerm& tm,
-                                            T (*As)[TK][Shape<WM, WN>::TM + PAD],
-                                            T (*Bs)[TK][Shape<WM, WN>::TN + PAD], int tid) {
-  typedef Shape<WM, WN> S;
+__device__ __forceinline__ void store_stage(const Stage<T, WM, WN>& st, const DevTerm& tm,
+                                            T (*As)[Shape<T, WM, WN>::TK][Shape<T, WM, WN>::TM + PAD],
+                                            T (*Bs)[Shape<T, WM, WN>::TK][Shape<T, WM, WN>::TN + PAD], int tid) {
+  typedef Shape<T, WM, WN> S;
+  constexpr int TK = S::TK;
   const bool ta = tm.ops & 1, ca = tm.ops & 2, tb = tm.ops & 4, cb = tm.ops & 8;
   const double c = tm.coef;
 #pragma unroll
@@ -133,8 +144,9 @@ __device__ __forceinline__ void store_stage(const Stage<WM, WN>& st, const DevTe
   }
 }
 
+template <typename T>
 __device__ __forceinline__ void next_ktile(const DevTerm* terms, int& t, int& k0) {
-  k0 += TK;
+  k0 += KStep<T>::value;
   if (k0 >= terms[t].K) {
     k0 = 0;
     ++t;
@@ -150,8 +162,9 @@ template <typename T, int WM, int WN, bool SH>
 __device__ __forceinline__ void gemm_body(const Bufs& bufs, double* __restrict__ Cbase,
                                           double2* __restrict__ part, const DevTile* __restrict__ tiles,
                                           const DevOut* __restrict__ outs, const DevTerm* __restrict__ terms) {
-  typedef Shape<WM, WN> S;
+  typedef Shape<T, WM, WN> S;
   typedef Mfma<T> F;
+  constexpr int TK = S::TK;
   __shared__ T As[2][TK][S::TM + PAD];
   __shared__ T Bs[2][TK][S::TN + PAD];
   const DevTile tl = tiles[blockIdx.x];
@@ -178,23 +191,23 @@ __device__ __forceinline__ void gemm_body(const Bufs& bufs, double* __restrict__
     }
 
   int t = tl.t0, k0 = tl.k0;
-  Stage<WM, WN> st;
+  Stage<T, WM, WN> st;
   DevTerm cur;
   if (before(t, k0, tl.t1, tl.k1)) {
     cur = terms[t];
-    load_stage<WM, WN, SH>(st, cur, bufs, tl.m0, tl.n0, ob.M, ob.N, k0, tid);
+    load_stage<T, WM, WN, SH>(st, cur, bufs, tl.m0, tl.n0, ob.M, ob.N, k0, tid);
   }
   while (before(t, k0, tl.t1, tl.k1)) {
     store_stage<T, WM, WN>(st, cur, As, Bs, tid);
     __syncthreads();
     const int krem = cur.K - k0;   // valid depth of this K step
     int tn = t, kn = k0;
-    next_ktile(terms, tn, kn);
+    next_ktile<T>(terms, tn, kn);
     const bool more = before(tn, kn, tl.t1, tl.k1);
     DevTerm nxt;
     if (more) {
       nxt = (tn == t) ? cur : terms[tn];   // the term is reloaded only when it changes
-      load_stage<WM, WN, SH>(st, nxt, bufs, tl.m0, tl.n0, ob.M, ob.N, kn, tid);
+      load_stage<T, WM, WN, SH>(st, nxt, bufs, tl.m0, tl.n0, ob.M, ob.N, kn, tid);
     }
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 4) {
@@ -693,8 +706,8 @@ void Program::finalize() {
     for (int t = ob.t_begin; t < ob.t_end; ++t) {
       int k0 = 0;
       do {
-        kc += (std::min(TK, terms[t].K - k0) + 3) / 4 * 4;
-        k0 += TK;
+        kc += (std::min(kHostKStep, terms[t].K - k0) + 3) / 4 * 4;
+        k0 += kHostKStep;
       } while (k0 < terms[t].K);
     }
     // 64x64 tiles carry twice the arithmetic intensity of 32x32 ones: prefer
@@ -752,10 +765,10 @@ void Program::finalize() {
     for (int t = ob.t_begin; t < ob.t_end; ++t) {
       int k0 = 0;
       do {
-        double d = (std::min(TK, terms[t].K - k0) + 3) / 4 * 4;
+        double d = (std::min(kHostKStep, terms[t].K - k0) + 3) / 4 * 4;
         acc += d;
         piece_kc += d;
-        int tn = t, kn = k0 + TK;
+        int tn = t, kn = k0 + kHostKStep;
         if (kn >= terms[t].K) { kn = 0; ++tn; }
         const bool last = tn == ob.t_end;
         if (q < n - 1 && !last && acc >= it.kc * (q + 1) / n) {
@@ -769,7 +782,7 @@ void Program::finalize() {
           piece.t.k0 = kn;
           piece_kc = 0.0;
         }
-        k0 += TK;
+        k0 += kHostKStep;
       } while (k0 < terms[t].K);
     }
     piece.t.t1 = ob.t_end;
