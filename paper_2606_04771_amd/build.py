@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtdvp.so")
 SOURCES = ["symm.cpp", "plan.cpp", "common.cpp", "capi_host.cpp", "tridiag.cpp", "capi_dev.cpp",
-           "krylov.cpp", "sweep.cpp", "gemm.hip", "vec.hip", "svd.hip"]
+           "krylov.cpp", "sweep.cpp", "gemm.hip", "vec.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
