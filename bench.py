@@ -27,8 +27,8 @@ Table S2.  Two measurements, both with all data resident in HBM:
   per output block), and at the late-time chi ~ 62 000 (a 9.4 GB two-site
   tensor), per precision; one-site sweeps on the saturated state.
 
-Prints one JSON line.  ``--gpus N`` with N > 1 is refused: the build is a
-single-GPU one.
+Prints one JSON line.  ``--gpus N`` with N > 1 is refused: the library runs
+on a single GPU.
 """
 import argparse
 import json
@@ -199,7 +199,7 @@ def main():
         print(json.dumps({"copy_bytes_read": 3 * n * 16, "copy_bytes_written": 3 * n * 16}))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported",
+        print(f"bench.py: the library runs on one GPU only; --gpus {args.gpus} is not supported",
               file=sys.stderr)
         sys.exit(2)
 
