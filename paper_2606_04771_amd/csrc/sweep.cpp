@@ -501,9 +501,13 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
     TDVP_HIP(ctx, hipMemcpyAsync(binfo.data(), dinfo, sizeof(rocblas_int) * nmat, hipMemcpyDeviceToHost, ctx->stream));
     TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
     std::vector<Sector*> redo;
+    // test hook, read at every split: treat every bucket as failed, so that
+    // the unpadded fallback solve is exercised
+    const char* ff = std::getenv("TDVP_EIG_FORCE_FALLBACK");
+    const bool force_fallback = ff && std::atoi(ff) == 1;
     nb = 0;
     for (auto& bk : buckets) {
-      bool bad_info = false;
+      bool bad_info = force_fallback;
       for (Sector* sp : bk.second) bad_info = bad_info || binfo[sp->iidx] != 0;
       if (bad_info || chk[2 * nb + 1] != 0.0 || !std::isfinite(chk[2 * nb])) {
         redo.insert(redo.end(), bk.second.begin(), bk.second.end());

@@ -122,12 +122,16 @@ def _library_mps(ctx, model, bonds, sites):
     return mps
 
 
-@pytest.mark.parametrize("chi_cap,eps", [(24, 1e-8), (40, 1e-3)])
-def test_truncated_sweeps_match_oracle(ctx, chi_cap, eps):
+@pytest.mark.parametrize("chi_cap,eps,fallback", [(24, 1e-8, False), (40, 1e-3, False), (24, 1e-8, True)])
+def test_truncated_sweeps_match_oracle(ctx, chi_cap, eps, fallback, monkeypatch):
     """Truncated two-site TDVP from a seeded random reduced MPS (L = 8): the
     library and the dense oracle, which truncates whole degenerate groups of
-    singular values by the same rule, give the same state after each sweep."""
+    singular values by the same rule, give the same state after each sweep.
+    With fallback, every split re-solves its Gram matrices unpadded by the
+    Jacobi-based solver (the path taken when the main solver fails)."""
     import synth
+    if fallback:
+        monkeypatch.setenv("TDVP_EIG_FORCE_FALLBACK", "1")
     L, t, U, dt = 8, 1.0, 4.0, 0.05
     bonds, sites = synth.random_mps(L, 48, 17, center=1)
     model = T.Model(L, t, U)
@@ -146,6 +150,7 @@ def test_truncated_sweeps_match_oracle(ctx, chi_cap, eps):
               f"max disc {info['max_discarded']:.2e} "
               f"(oracle {max(disc):.2e})", flush=True)
         assert info["max_chi"] <= chi_cap
+        assert (info["eig_fallbacks"] > 0) == fallback
         assert abs(info["max_discarded"] - max(disc)) < 1e-10
         assert 1 - ov < 1e-10
         assert max(np.abs(nu - mu).max(), np.abs(dd - de).max()) < 1e-10
