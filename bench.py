@@ -280,7 +280,8 @@ def main():
     ys = {}
     for name, p in (("fp64", T.FP64), ("fp32", T.FP32), ("bf16x3", T.BF16X3)):
         d, ys[name] = time_applies(p)
-        heff_by_prec[name] = {"ms_per_apply": 1e3 * float(np.mean(d)), "ms_min": 1e3 * float(d.min()),
+        heff_by_prec[name] = {"ms_per_apply": 1e3 * float(np.mean(d)), "ms_median": 1e3 * float(np.median(d)),
+                              "ms_min": 1e3 * float(d.min()),
                               "tflops": flops / float(np.mean(d)) / 1e12}
         print(f"bench: H_eff apply {name} {heff_by_prec[name]['ms_per_apply']:.3f} ms, "
               f"{heff_by_prec[name]['tflops']:.2f} TFLOP/s", file=sys.stderr, flush=True)
