@@ -683,14 +683,17 @@ void Program::finalize() {
   nslots = 0;
   tile_mode = default_tile_mode();
   const double thr = tile_threshold();
-  // Optional splitting of long K chains, so that no work item runs much
-  // longer than alpha x the mean work per resident workgroup (4 per CU of
-  // 64x64 tiles on 256 CUs); the pieces are summed by a second, short kernel
-  // in a fixed order.  Off by default (alpha = 0): at chi = 4096 the measured
-  // gain was negative, the skipped padding products having removed most of
-  // the imbalance.
-  static const double alpha = env_double("TDVP_SPLIT_ALPHA", 0.0);
-  static const int kmin = (int)env_double("TDVP_SPLIT_KMIN", 256);
+  // Splitting of long K chains, so that no work item runs much longer than
+  // alpha x the mean work per resident workgroup (4 per CU of 64x64 tiles on
+  // 256 CUs); the pieces are summed by a second, short kernel in a fixed
+  // order.  Default: only large effective-Hamiltonian applies (>= 1e11 flops) are
+  // split, alpha = 1 and pieces >= 128 deep (measured: +7 % at chi = 16384,
+  // 4.5e11 flops; -4 % at chi = 4096, 1.8e10 flops).
+  static const double alpha_env = env_double("TDVP_SPLIT_ALPHA", -1.0);
+  static const int kmin_env = (int)env_double("TDVP_SPLIT_KMIN", -1.0);
+  const bool big_apply = role == 1 && flops >= 1e11;
+  const double alpha = alpha_env >= 0.0 ? alpha_env : (big_apply ? 1.0 : 0.0);
+  const int kmin = kmin_env > 0 ? kmin_env : 128;
   static const int max_slots = (int)env_double("TDVP_SPLIT_MAXSLOTS", 2048);
   struct Item {
     DevTile t;
