@@ -44,3 +44,12 @@ def test_context_creation_reports_missing_gpu_cleanly():
     with pytest.raises(T.TdvpError) as e:
         T.Context(0)
     assert e.value.code in (-5, -1)
+
+
+def test_context_setters_reject_a_null_context():
+    """Calls on a null context return INVALID (-1) and leave a message, on any machine."""
+    import paper_2606_04771_amd as T
+    assert T.lib.tdvp_ctx_set_graphs(None, 1) == -1
+    assert T.lib.tdvp_ctx_set_precision(None, 0) == -1
+    assert T.lib.tdvp_ctx_synchronize(None) == -1
+    assert b"null ctx" in T.lib.tdvp_last_error(None)
