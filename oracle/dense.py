@@ -262,20 +262,6 @@ def heff2_projected(H, Phi, Psi, Th):
 # ----------------------------------------------------------------------------
 # Krylov exponential
 # ----------------------------------------------------------------------------
-def expm_dense(apply, v, tau):
-    """exp(tau H) v by building the dense matrix of ``apply`` column by
-    column and calling scipy.linalg.expm (small problems only)."""
-    shape = v.shape
-    n = v.size
-    Hm = np.empty((n, n), dtype=np.complex128)
-    e = np.zeros(n, dtype=np.complex128)
-    for j in range(n):
-        e[j] = 1.0
-        Hm[:, j] = apply(e.reshape(shape)).reshape(-1)
-        e[j] = 0.0
-    return (scipy.linalg.expm(tau * Hm) @ v.reshape(-1)).reshape(shape)
-
-
 def lanczos_expm(apply, v, tau, tol=1e-12, maxdim=40):
     """exp(tau H) v for Hermitian H given as ``apply``.
 
@@ -333,54 +319,118 @@ def complete_right_canonical(psi, L):
     return mps
 
 
-def _svd_split(M, keep_all, eps_tol, chi_cap, multiplets=False):
+def _multiplet_labels(U, row_ops):
+    """(q, tj) of the left singular vectors U of one group of equal singular
+    values: U rotated to simultaneous eigenvectors of 2 S^z and T^2 of the
+    rows (row_ops = (Sz2, T2)).  Returns (R, labels), U R being the rotated
+    vectors and labels[c] = (q, tj) of column c."""
+    Sz2, T2 = row_ops
+    qv, Y = np.linalg.eigh(U.conj().T @ (Sz2 @ U))
+    R, labels = [], []
+    qr = np.rint(qv).astype(int)
+    for q in sorted(set(qr)):
+        Yq = Y[:, qr == q]
+        tv, Z = np.linalg.eigh(Yq.conj().T @ (U.conj().T @ (T2 @ (U @ Yq))))
+        tj = np.rint(np.sqrt(np.maximum(4.0 * tv + 1.0, 0.0)) - 1.0).astype(int)
+        for v in sorted(set(tj)):
+            R.append(Yq @ Z[:, tj == v])
+            labels += [(int(q), int(v))] * int(np.sum(tj == v))
+    return np.concatenate(R, axis=1), labels
+
+
+def _svd_split(M, keep_all, eps_tol, chi_cap, multiplets=False, row_ops=None):
     """SVD of the merged two-site matrix with the truncation of supplementary
     section S2: singular values are dropped from the smallest while the
     discarded squared weight stays within eps_tol of the total and while more
     than chi_cap values remain (at least one is kept); the kept values are
-    renormalised to the original norm.  With ``multiplets`` the values are
-    handled in groups of (numerically) equal ones -- for a state with the
-    pseudospin symmetry these are the 2j+1 copies of one multiplet -- and a
-    group is kept or dropped whole, the cap stopping at the first group that
-    does not fit."""
+    renormalised to the original norm.
+
+    With ``multiplets`` the values are handled as whole multiplets of the
+    pseudospin symmetry: a group of (numerically) equal values is split by
+    the quantum numbers (q, tj) of the left part (``row_ops`` = (2 S^z, T^2)
+    on the rows), each (q, tj) part into multiplets of tj + 1 values; the
+    multiplets are ordered by value (descending), ties by q, then tj
+    (ascending), and kept or dropped whole, the cap stopping at the first
+    multiplet that does not fit."""
     U_, S, Vh = np.linalg.svd(M, full_matrices=False)
     if keep_all:
         return U_, S, Vh, 0.0
     w = S ** 2
     tot = w.sum()
-    if multiplets:
-        tolg = 1e-9 * (S[0] if S.size else 0.0)
-        groups, start = [], 0
-        for i in range(1, S.size + 1):
-            if i == S.size or S[i - 1] - S[i] > tolg:
-                groups.append((start, i))
-                start = i
-        keep_g = len(groups)
-        tail = 0.0
-        while keep_g > 1:
-            a, b = groups[keep_g - 1]
-            if tail + w[a:b].sum() > eps_tol * tot:
-                break
-            tail += w[a:b].sum()
-            keep_g -= 1
-        for g in range(keep_g):
-            if g > 0 and groups[g][1] > chi_cap:
-                keep_g = g
-                break
-        keep = groups[max(keep_g, 1) - 1][1]
-        disc = w[keep:].sum()
-    else:
+    if not multiplets:
         keep = S.size
         disc = 0.0
         while keep > 1 and (disc + w[keep - 1] <= eps_tol * tot or keep > chi_cap):
             disc += w[keep - 1]
             keep -= 1
-    S = S[:keep] / np.sqrt(1.0 - disc / tot) if tot > 0 else S[:keep]
-    return U_[:, :keep], S, Vh[:keep], disc / tot if tot > 0 else 0.0
+        S = S[:keep] / np.sqrt(1.0 - disc / tot) if tot > 0 else S[:keep]
+        return U_[:, :keep], S, Vh[:keep], disc / tot if tot > 0 else 0.0
+    # groups of equal values, each split into labelled multiplets
+    tolg = 1e-9 * (S[0] if S.size else 0.0)
+    mults = []        # (value, q, tj, columns of U, rows of Vh)
+    start = 0
+    for i in range(1, S.size + 1):
+        if i < S.size and S[i - 1] - S[i] <= tolg:
+            continue
+        Ug, Vg = U_[:, start:i], Vh[start:i]
+        R, labels = _multiplet_labels(Ug, row_ops)
+        Ur, Vr = Ug @ R, R.conj().T @ Vg
+        c = 0
+        while c < len(labels):
+            q, tj = labels[c]
+            mults.append((S[start], q, tj, Ur[:, c:c + tj + 1], Vr[c:c + tj + 1], S[start:start + tj + 1]))
+            c += tj + 1
+        start = i
+    mults.sort(key=lambda m: (-m[0], m[1], m[2]))
+    mw = [np.sum(m[5] ** 2) for m in mults]
+    keep, tail = len(mults), 0.0
+    while keep > 1 and tail + mw[keep - 1] <= eps_tol * tot:
+        tail += mw[keep - 1]
+        keep -= 1
+    n, p = 0, 0
+    while p < keep and (p == 0 or n + mults[p][2] + 1 <= chi_cap):
+        n += mults[p][2] + 1
+        p += 1
+    disc = tot - sum(mw[:p])
+    Uk = np.concatenate([m[3] for m in mults[:p]], axis=1)
+    Vk = np.concatenate([m[4] for m in mults[:p]], axis=0)
+    Sk = np.concatenate([np.full(m[2] + 1, m[0]) for m in mults[:p]])
+    Sk = Sk / np.sqrt(1.0 - disc / tot) if tot > 0 else Sk
+    return Uk, Sk, Vk, disc / tot if tot > 0 else 0.0
+
+
+def left_row_ops(mps, i):
+    """(2 S^z, T^2) of sites 1..i on the row space (left bond index, state of
+    site i) of the two-site tensor at sites (i, i+1), from the left-canonical
+    tensors mps[0..i-2] (their left block basis Phi) and the fermion
+    operators: Phi^dag O_block Phi (x) 1 + 1 (x) o_site."""
+    from .fermions import pseudospin, A_UP, A_DN
+    nu, nd = A_UP.T @ A_UP, A_DN.T @ A_DN
+    tp = (-1.0) ** i * (A_UP.T @ A_DN.T)
+    tz = 0.5 * (nu + nd - np.eye(4))
+    if i == 1:
+        Jp, Jz, Q = np.zeros((1, 1)), np.zeros((1, 1)), np.zeros((1, 1))
+    else:
+        Phi = left_block_basis(mps[:i - 1])
+        Tp_b, _, Tz_b = pseudospin(i - 1)
+        sz = np.zeros(4 ** (i - 1))
+        idx = np.arange(4 ** (i - 1))
+        for k in range(i - 1):
+            s = (idx // 4 ** (i - 2 - k)) % 4
+            sz += (s == 1).astype(float) - (s == 2).astype(float)
+        Jp = Phi.conj().T @ (Tp_b @ Phi)
+        Jz = Phi.conj().T @ (Tz_b @ Phi)
+        Q = Phi.conj().T @ (sz[:, None] * Phi)
+    a = Jp.shape[0]
+    I4, Ia = np.eye(4), np.eye(a)
+    Tp = np.kron(Jp, I4) + np.kron(Ia, tp)
+    Tz = np.kron(Jz, I4) + np.kron(Ia, tz)
+    T2 = Tp @ Tp.conj().T + Tz @ Tz - Tz
+    return np.kron(Q, I4) + np.kron(Ia, nu - nd), T2
 
 
 def tdvp2_sweep(mps, dt, t, U, tol=1e-12, maxdim=40, keep_all=True, eps_tol=0.0,
-                chi_cap=10 ** 9, use_dense_expm=False, multiplets=False):
+                chi_cap=10 ** 9, multiplets=False):
     """One time step dt of symmetric second-order two-site TDVP.
 
     Input: right-canonical MPS [C_1, B_2, ..., B_L] (centre on site 1).
@@ -391,8 +441,7 @@ def tdvp2_sweep(mps, dt, t, U, tol=1e-12, maxdim=40, keep_all=True, eps_tol=0.0,
     site 1.  Returns the new MPS (same form) and the discarded weights."""
     L = len(mps)
     tau = dt / 2.0
-    expm = (lambda f, v, z: expm_dense(f, v, z)) if use_dense_expm else \
-        (lambda f, v, z: lanczos_expm(f, v, z, tol=tol, maxdim=maxdim)[0])
+    expm = (lambda f, v, z: lanczos_expm(f, v, z, tol=tol, maxdim=maxdim)[0])
     # right environments from the right-canonical tensors
     R = [None] * (L + 1)
     R[L] = empty_env()
@@ -407,7 +456,8 @@ def tdvp2_sweep(mps, dt, t, U, tol=1e-12, maxdim=40, keep_all=True, eps_tol=0.0,
         Th = np.tensordot(C, mps[i], axes=([2], [0]))
         Th = expm(lambda x: heff2(Lf[i - 1], R[i + 1], x, i, t, U), Th, -1j * tau)
         a, s1, s2, b = Th.shape
-        Um, S, Vh, d = _svd_split(Th.reshape(a * 4, 4 * b), keep_all, eps_tol, chi_cap, multiplets)
+        ops = left_row_ops(mps, i) if multiplets and not keep_all else None
+        Um, S, Vh, d = _svd_split(Th.reshape(a * 4, 4 * b), keep_all, eps_tol, chi_cap, multiplets, ops)
         disc.append(d)
         mps[i - 1] = Um.reshape(a, 4, -1)
         C = (S[:, None] * Vh).reshape(-1, 4, b)
@@ -418,7 +468,8 @@ def tdvp2_sweep(mps, dt, t, U, tol=1e-12, maxdim=40, keep_all=True, eps_tol=0.0,
         Th = np.tensordot(mps[i - 1], C, axes=([2], [0]))
         Th = expm(lambda x: heff2(Lf[i - 1], R[i + 1], x, i, t, U), Th, -1j * tau)
         a, s1, s2, b = Th.shape
-        Um, S, Vh, d = _svd_split(Th.reshape(a * 4, 4 * b), keep_all, eps_tol, chi_cap, multiplets)
+        ops = left_row_ops(mps, i) if multiplets and not keep_all else None
+        Um, S, Vh, d = _svd_split(Th.reshape(a * 4, 4 * b), keep_all, eps_tol, chi_cap, multiplets, ops)
         disc.append(d)
         mps[i] = Vh.reshape(-1, 4, b)
         C = (Um * S).reshape(a, 4, -1)

@@ -153,3 +153,130 @@ def expand_env(blocks, bond):
         full = full.reshape(do * (tjo + 1), tjw + 1, di * (tji + 1))
         out[w][offs[io]:offs[io] + do * (tjo + 1), :, offs[ii]:offs[ii] + di * (tji + 1)] += full
     return out
+
+
+# ----------------------------------------------------------------------------
+# Per-sector view of a two-site tensor and the multiplet truncation rule
+# ----------------------------------------------------------------------------
+def sector_matrices(blocks, left, right):
+    """Reduced two-site tensor as one matrix per coupled sector x = (q_x, tj_x)
+    of the bond being cut (the Wigner-Eckart grouping of supplementary section
+    S2.1 applied to that bond): rows are the fusion partners (ia, s1) of x in
+    ascending order, columns the partners (s2, ib), each a degeneracy block.
+    Returns {x: (M_x, rows, cols)} with rows/cols lists of the partner keys."""
+    fuse = lambda a, b: range(abs(a - b), a + b + 1, 2)
+    out = {}
+    for ia, (qa, tja, da) in enumerate(left):
+        for s1, (q1, t1) in enumerate(MULTIPLETS):
+            for tjx in fuse(tja, t1):
+                out.setdefault((qa + q1, tjx), ([], []))[0].append((ia, s1))
+    for (qx, tjx), (rows, cols) in out.items():
+        for s2, (q2, t2) in enumerate(MULTIPLETS):
+            for ib, (qb, tjb, db) in enumerate(right):
+                if qx + q2 == qb and tjb in fuse(tjx, t2):
+                    cols.append((s2, ib))
+    res = {}
+    for x, (rows, cols) in out.items():
+        if not rows or not cols:
+            continue
+        ro = np.cumsum([0] + [left[r[0]][2] for r in rows])
+        co = np.cumsum([0] + [right[c[1]][2] for c in cols])
+        M = np.zeros((ro[-1], co[-1]), dtype=np.complex128)
+        for i, (ia, s1) in enumerate(rows):
+            for j, (s2, ib) in enumerate(cols):
+                blk = blocks.get((ia, s1, x[1], s2, ib))
+                if blk is not None:
+                    M[ro[i]:ro[i + 1], co[j]:co[j + 1]] = blk
+        res[x] = (M, rows, cols)
+    return res
+
+
+def sector_singular_values(blocks, left, right):
+    """Reduced singular values of each coupled sector, descending:
+    {(q_x, tj_x): array}.  The full-state singular values of the expanded
+    tensor are these divided by sqrt(tj_x + 1), each tj_x + 1 times."""
+    return {x: np.linalg.svd(M, compute_uv=False) for x, (M, _, _) in sector_matrices(blocks, left, right).items()}
+
+
+def truncate_multiplets(svals, eps_tol, chi_cap):
+    """The truncation of supplementary section S2.4 on whole multiplets.
+
+    Every reduced singular value s of sector (q, tj) is one multiplet of
+    tj + 1 full-state values s / sqrt(tj + 1) and full-state weight s^2.
+    Multiplets are sorted by full-state value (descending; a value closer
+    than 1e-9 of the largest one to its predecessor is a tie, and ties are
+    ordered by q, then tj, ascending, then by position in the sector); the shortest prefix is kept
+    whose discarded weight is at most eps_tol of the total, then cut before
+    the first multiplet that would take the kept full-state dimension
+    sum (tj + 1) above chi_cap; at least one multiplet stays.
+    Returns ({(q, tj): kept count}, discarded weight / total weight)."""
+    ents = []
+    for (q, tj), s in svals.items():
+        for idx, v in enumerate(s):
+            ents.append((v / np.sqrt(tj + 1), q, tj, idx, v * v))
+    ents.sort(key=lambda e: -e[0])
+    # values closer than 1e-9 of the largest to their predecessor are ties
+    tol = 1e-9 * (ents[0][0] if ents else 0.0)
+    grouped, start = [], 0
+    for i in range(1, len(ents) + 1):
+        if i == len(ents) or ents[i - 1][0] - ents[i][0] > tol:
+            grouped += sorted(ents[start:i], key=lambda e: (e[1], e[2], e[3]))
+            start = i
+    ents = grouped
+    W = sum(e[4] for e in ents)
+    keep, tail = len(ents), 0.0
+    while keep > 1 and tail + ents[keep - 1][4] <= eps_tol * W:
+        tail += ents[keep - 1][4]
+        keep -= 1
+    chi, p = 0, 0
+    while p < keep and (p == 0 or chi + ents[p][2] + 1 <= chi_cap):
+        chi += ents[p][2] + 1
+        p += 1
+    kept = {x: 0 for x in svals}
+    for e in ents[:p]:
+        kept[(e[1], e[2])] += 1
+    kw = sum(e[4] for e in ents[:p])
+    return kept, ((W - kw) / W if W > 0 else 0.0)
+
+
+def _spin_matrices(tj):
+    """(J+, Jz) of spin tj/2 in the basis of descending m (Condon-Shortley)."""
+    n = tj + 1
+    ms = [(tj - 2 * i) / 2.0 for i in range(n)]
+    jp = np.zeros((n, n))
+    j = tj / 2.0
+    for i in range(1, n):      # J+ |m> = sqrt((j - m)(j + m + 1)) |m + 1>, m = ms[i], m + 1 = ms[i - 1]
+        m = ms[i]
+        jp[i - 1, i] = np.sqrt((j - m) * (j + m + 1))
+    return jp, np.diag(ms)
+
+
+def row_quantum_ops(left, k):
+    """(2 S^z, T^2) of the block made of everything left of the bond `left`
+    plus site k, on the row space (full left index, Jordan-Wigner state of
+    site k) of a two-site tensor reshaped to [chi_left * 4, 4 * chi_right].
+    The bond part acts on the magnetic index of every sector multiplet
+    (descending m); the site part is the eta pseudospin of site k,
+    T+ = (-1)^k c+_up c+_dn, and S^z = (n_up - n_dn) / 2."""
+    from .fermions import A_UP, A_DN
+    _, dim = bond_offsets(left)
+    Jp = np.zeros((dim, dim))
+    Jz = np.zeros((dim, dim))
+    Q = np.zeros(dim)
+    o = 0
+    for (q, tj, d) in left:
+        jp, jz = _spin_matrices(tj)
+        for _ in range(d):
+            Jp[o:o + tj + 1, o:o + tj + 1] = jp
+            Jz[o:o + tj + 1, o:o + tj + 1] = jz
+            Q[o:o + tj + 1] = q
+            o += tj + 1
+    tp = (-1.0) ** k * (A_UP.T @ A_DN.T)
+    nu, nd = A_UP.T @ A_UP, A_DN.T @ A_DN
+    tz = 0.5 * (nu + nd - np.eye(4))
+    I4, Id = np.eye(4), np.eye(dim)
+    Tp = np.kron(Jp, I4) + np.kron(Id, tp)
+    Tz = np.kron(Jz, I4) + np.kron(Id, tz)
+    T2 = Tp @ Tp.T + Tz @ Tz - Tz
+    Sz2 = np.kron(np.diag(Q), I4) + np.kron(Id, nu - nd)
+    return Sz2, T2

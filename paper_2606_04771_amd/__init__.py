@@ -5,8 +5,9 @@ It only marshals arguments: every step of the computation runs in the HIP
 library.  Device buffers are passed as raw pointers (e.g. from torch
 tensors); the binding allocates nothing on the device itself.
 
-Loading fails loudly if the library has not been built
-(``python -m paper_2606_04771_amd.build``): there is no fallback.
+The library is loaded on first use (so that ``paper_2606_04771_amd.build``
+imports in a fresh checkout); any call before it has been built
+(``python -m paper_2606_04771_amd.build``) fails loudly: there is no fallback.
 """
 import ctypes as C
 import os
@@ -111,7 +112,21 @@ def _load():
     return lib
 
 
-lib = _load()
+class _LazyLib:
+    """Loads libtdvp.so at the first attribute access and forwards to it."""
+
+    def __init__(self):
+        self._lib = None
+
+    def __getattr__(self, name):
+        if name.startswith("__"):
+            raise AttributeError(name)
+        if self._lib is None:
+            self._lib = _load()
+        return getattr(self._lib, name)
+
+
+lib = _LazyLib()
 
 
 def _check(rc, ctx=None):

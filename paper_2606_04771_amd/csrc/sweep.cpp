@@ -561,12 +561,23 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
     }
   }
   if (!std::isfinite(W)) return set_error(ctx, TDVP_E_NONFINITE, "non-finite singular values");
-  std::stable_sort(ents.begin(), ents.end(), [](const Ent& a, const Ent& b) {
-    if (a.sfull != b.sfull) return a.sfull > b.sfull;
-    if (a.q != b.q) return a.q < b.q;
-    if (a.tj != b.tj) return a.tj < b.tj;
-    return a.idx < b.idx;
-  });
+  // descending full-state value (sfull is its square); a value closer than
+  // 1e-9 of the largest one to its predecessor is a tie, and ties go by
+  // (q, 2j) ascending, then position in the sector
+  std::stable_sort(ents.begin(), ents.end(), [](const Ent& a, const Ent& b) { return a.sfull > b.sfull; });
+  {
+    const double tol = ents.empty() ? 0.0 : 1e-9 * std::sqrt(ents[0].sfull);
+    size_t g0 = 0;
+    for (size_t e = 1; e <= ents.size(); ++e) {
+      if (e < ents.size() && std::sqrt(ents[e - 1].sfull) - std::sqrt(ents[e].sfull) <= tol) continue;
+      std::stable_sort(ents.begin() + g0, ents.begin() + e, [](const Ent& a, const Ent& b) {
+        if (a.q != b.q) return a.q < b.q;
+        if (a.tj != b.tj) return a.tj < b.tj;
+        return a.idx < b.idx;
+      });
+      g0 = e;
+    }
+  }
   size_t keep = ents.size();
   if (!tr.keep_all) {
     double tail = 0.0;

@@ -53,3 +53,25 @@ def test_context_setters_reject_a_null_context():
     assert T.lib.tdvp_ctx_set_precision(None, 0) == -1
     assert T.lib.tdvp_ctx_synchronize(None) == -1
     assert b"null ctx" in T.lib.tdvp_last_error(None)
+
+
+def test_package_and_build_module_import_without_the_library(tmp_path):
+    """In a checkout where libtdvp.so has not been built yet, the package and
+    its build module import (the library is loaded at first use), and the
+    first call into the library fails loudly instead of falling back."""
+    import shutil
+    import sys
+    pkg = os.path.join(ROOT, "paper_2606_04771_amd")
+    dst = tmp_path / "paper_2606_04771_amd"
+    shutil.copytree(pkg, dst, ignore=shutil.ignore_patterns("*.so", "_build", "__pycache__"))
+    code = ("import paper_2606_04771_amd as T, paper_2606_04771_amd.build as B\n"
+            "assert callable(B.build)\n"
+            "try:\n"
+            "    T.lib.tdvp_ctx_create\n"
+            "except ImportError as e:\n"
+            "    print('missing:', e)\n"
+            "else:\n"
+            "    raise SystemExit('library loaded from nowhere')\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=str(tmp_path), capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "missing:" in r.stdout

@@ -185,9 +185,7 @@ def test_reduced_expansion_isometries_and_singlet():
     assert abs(np.sum(nu - nd)) < 1e-13                          # S^z = 0
 
 
-def test_theta_expansion_norm():
-    bonds, sites = synth.random_mps(6, 30, seed=5, center=3)
-    left, right = bonds[2], bonds[4]
+def _theta_keys_of(left, right):
     keys = []
     for ia, (qa, tja, da) in enumerate(left):
         for s1, (q1, t1) in enumerate(R.MULTIPLETS):
@@ -196,10 +194,85 @@ def test_theta_expansion_norm():
                     for ib, (qb, tjb, db) in enumerate(right):
                         if qa + q1 + q2 == qb and abs(tjx - t2) <= tjb <= tjx + t2:
                             keys.append((ia, s1, tjx, s2, ib))
+    return keys
+
+
+def test_theta_expansion_is_a_singlet_with_the_flat_norm():
+    """A state built from expanded left-canonical A's, an expanded random
+    reduced two-site tensor and expanded right-canonical B's has S^z = 0 and
+    T^2 = 0 exactly (the pseudospin singlet of section S2.1), and its norm is
+    the flat norm of the reduced blocks.  A wrong fusion tree, a reversed
+    magnetic order in one Clebsch-Gordan factor or a wrong normalisation
+    breaks one of the three."""
+    L, i = 6, 3
+    bonds, sites = synth.random_mps(L, 30, seed=5, center=i)
+    left, right = bonds[i - 1], bonds[i + 1]
+    keys = _theta_keys_of(left, right)
     blocks = synth.block_data(keys, [(left[k[0]][2], right[k[4]][2]) for k in keys], seed=1)
-    Th = R.expand_theta(blocks, left, right, 3)
-    flat = np.sqrt(sum(np.sum(np.abs(v) ** 2) for v in blocks.values()))
-    assert abs(np.linalg.norm(Th) - flat) < 1e-12
+    Th = R.expand_theta(blocks, left, right, i)
+    full = [R.expand_site("A", sites[k - 1], bonds[k - 1], bonds[k], k) for k in range(1, i)]
+    full.append(Th.reshape(Th.shape[0], 4, -1))       # sites i, i+1 as one [chi, 4, 4 chi] factor
+    psi = full[0]
+    for M in full[1:]:
+        psi = np.tensordot(psi, M, axes=([psi.ndim - 1], [0]))
+    psi = psi.reshape(-1, Th.shape[-1])
+    tail = [R.expand_site("B", sites[k - 1], bonds[k - 1], bonds[k], k) for k in range(i + 2, L + 1)]
+    rest = tail[0]
+    for M in tail[1:]:
+        rest = np.tensordot(rest, M, axes=([rest.ndim - 1], [0]))
+    psi = (psi @ rest.reshape(rest.shape[0], -1)).reshape(-1)
+    flat = np.sqrt(sum(np.sum(np.abs(b) ** 2) for b in blocks.values()))
+    assert abs(np.linalg.norm(psi) - flat) < 1e-12 * flat
+    assert abs(np.linalg.norm(Th) - flat) < 1e-12 * flat
+    Tp, Tm, Tz = F.pseudospin(L)
+    T2 = Tp @ Tm + Tz @ Tz - Tz
+    assert np.linalg.norm(T2 @ psi) < 1e-12 * flat
+    sz2 = sum(F.site_op(F.N_UP - F.N_DN, k, L) for k in range(1, L + 1))
+    assert np.linalg.norm(sz2 @ psi) < 1e-12 * flat
+
+
+def test_theta_tree_equals_merged_one_site_tensors():
+    """The two-site tree ((a s1)->x) s2->b with its 1/sqrt(2j_b+1) is what the
+    product of a one-site centre C(a, s1, x) and a right-canonical B(x, s2, b)
+    expands to: Theta(a, s1, x, s2, b) = C(a, s1, x) B(x, s2, b) blockwise."""
+    L, i = 6, 3
+    bonds, sites = synth.random_mps(L, 30, seed=8, center=i)
+    C = R.expand_site("C", sites[i - 1], bonds[i - 1], bonds[i], i)
+    B = R.expand_site("B", sites[i], bonds[i], bonds[i + 1], i + 1)
+    dense = np.tensordot(C, B, axes=([2], [0]))
+    mid = bonds[i]
+    red = {}
+    for (ia, s1, ix), c in sites[i - 1].items():
+        for (jx, s2, ib), b in sites[i].items():
+            if jx == ix:
+                key = (ia, s1, mid[ix][1], s2, ib)
+                red[key] = red.get(key, 0) + c @ b
+    Th = R.expand_theta(red, bonds[i - 1], bonds[i + 1], i)
+    assert np.abs(Th - dense).max() < 1e-13
+
+
+def test_row_operators_and_theta_labels():
+    """The left part of every reduced block (a, s1, x, s2, b) carries the
+    coupled label x: 2 S^z = q_x and T^2 = j_x (j_x + 1) on its rows.  The
+    row operators built on the reduced bond (spin matrices of each sector)
+    are the fermion operators projected on the block basis of expanded
+    left-canonical tensors."""
+    L, i = 6, 4
+    bonds, sites = synth.random_mps(L, 26, seed=6, center=i)
+    left, right = bonds[i - 1], bonds[i + 1]
+    Sz2, T2 = R.row_quantum_ops(left, i)
+    Afull = [R.expand_site("A", sites[k - 1], bonds[k - 1], bonds[k], k) for k in range(1, i)]
+    Sz2_d, T2_d = D.left_row_ops(Afull + [None], i)
+    assert np.abs(Sz2 - Sz2_d).max() < 1e-12 and np.abs(T2 - T2_d).max() < 1e-12
+    keys = _theta_keys_of(left, right)
+    for key in keys[::3]:
+        blk = synth.complex_normal((left[key[0]][2], right[key[4]][2]), 2, *key)
+        Th = R.expand_theta({key: blk}, left, right, i)
+        M = Th.reshape(Th.shape[0] * 4, -1)
+        qx = left[key[0]][0] + R.MULTIPLETS[key[1]][0]
+        jx = key[2] / 2.0
+        assert np.abs(Sz2 @ M - qx * M).max() < 1e-12 * np.abs(M).max()
+        assert np.abs(T2 @ M - jx * (jx + 1) * M).max() < 1e-12 * np.abs(M).max()
 
 
 def _project_env(E, bond):
@@ -464,12 +537,20 @@ def _theta_keys(left, right):
     return keys
 
 
+def _kept_labels(Um, row_ops):
+    """{(q, tj): number of kept multiplets} of an isometry made of whole multiplets."""
+    _, labels = D._multiplet_labels(Um, row_ops)
+    out = {}
+    for q, tj in labels:
+        out[(q, tj)] = out.get((q, tj), 0) + 1
+    return {k: v // (k[1] + 1) for k, v in out.items()}
+
+
 def test_multiplet_truncation_matches_reduced_singular_values():
     """The dense singular values of an expanded symmetric two-site tensor are
     the reduced ones of each coupled sector x divided by sqrt(2j_x+1), each
-    (2j_x+1)-fold; the grouped truncation keeps exactly the multiplets that
-    the rule of supplementary section S2 keeps on the reduced values."""
-    import synth
+    (2j_x+1)-fold; the dense truncation on labelled multiplets keeps exactly
+    the multiplets that the reduced rule of section S2.4 keeps."""
     left = synth.sector_profile(20, 5, parity=1)
     right = synth.sector_profile(20, 6, parity=1)
     keys = _theta_keys(left, right)
@@ -479,12 +560,10 @@ def test_multiplet_truncation_matches_reduced_singular_values():
     Th = R.expand_theta(blocks, left, right, 2)
     a, b = Th.shape[0], Th.shape[-1]
     M = Th.reshape(a * 4, 4 * b)
-    # reduced singular values per coupled sector (q_x, 2j_x)
-    red = []
-    sectors = {}
-    for k in keys:
-        sectors.setdefault((left[k[0]][0] + R.MULTIPLETS[k[1]][0], k[2]), []).append(k)
-    for (qx, jx), ks in sectors.items():
+    sv = R.sector_singular_values(blocks, left, right)
+    # the reduced values against an SVD of each sector matrix assembled here by hand
+    for (qx, jx), s in sv.items():
+        ks = [k for k in keys if left[k[0]][0] + R.MULTIPLETS[k[1]][0] == qx and k[2] == jx]
         rows = sorted({(k[0], k[1]) for k in ks})
         cols = sorted({(k[3], k[4]) for k in ks})
         ro = np.cumsum([0] + [left[r[0]][2] for r in rows])
@@ -493,26 +572,67 @@ def test_multiplet_truncation_matches_reduced_singular_values():
         for k in ks:
             i, j = rows.index((k[0], k[1])), cols.index((k[3], k[4]))
             Mx[ro[i]:ro[i + 1], co[j]:co[j + 1]] = blocks[k]
-        for sv in np.linalg.svd(Mx, compute_uv=False):
-            red.append((sv / np.sqrt(jx + 1), jx + 1, qx, jx))
-    full = np.sort(np.concatenate([[s] * m for s, m, _, _ in red]))[::-1]
+        ref = np.linalg.svd(Mx, compute_uv=False)
+        assert s.shape == ref.shape and np.allclose(s, ref, rtol=0, atol=1e-12 * ref[0])
+    full = np.sort(np.concatenate([np.repeat(s / np.sqrt(jx + 1), jx + 1) for (qx, jx), s in sv.items()]))[::-1]
     dense = np.linalg.svd(M, compute_uv=False)
     assert np.allclose(dense[:full.size], full, rtol=0, atol=1e-12 * full[0])
     assert np.all(dense[full.size:] < 1e-12 * full[0])
-    # the rule on whole multiplets, applied to the reduced list
-    red.sort(key=lambda e: (-e[0], e[2], e[3]))
-    W = sum(m * s * s for s, m, _, _ in red)
+    ops = R.row_quantum_ops(left, 2)
+    W = np.sum(dense ** 2)
     for eps, cap in ((1e-2, 10 ** 9), (0.0, 40), (1e-3, 60), (0.2, 25)):
-        keep, tail = len(red), 0.0
-        while keep > 1 and tail + red[keep - 1][1] * red[keep - 1][0] ** 2 <= eps * W:
-            tail += red[keep - 1][1] * red[keep - 1][0] ** 2
-            keep -= 1
-        n = p = 0
-        while p < keep and (p == 0 or n + red[p][1] <= cap):
-            n += red[p][1]
-            p += 1
-        Um, S, Vh, disc = D._svd_split(M, False, eps, cap, multiplets=True)
-        assert S.size == n
-        kept_w = sum(m * s * s for s, m, _, _ in red[:p])
-        assert abs(disc - (W - kept_w) / W) < 1e-12
-        assert abs(np.sum(S ** 2) - np.sum(dense ** 2)) < 1e-10 * np.sum(dense ** 2)
+        kept, disc_r = R.truncate_multiplets(sv, eps, cap)
+        Um, S, Vh, disc = D._svd_split(M, False, eps, cap, multiplets=True, row_ops=ops)
+        assert S.size == sum(n * (x[1] + 1) for x, n in kept.items())
+        assert abs(disc - disc_r) < 1e-12
+        assert _kept_labels(Um, ops) == {x: n for x, n in kept.items() if n}
+        assert abs(np.sum(S ** 2) - W) < 1e-10 * W
+        # the kept part is the projection of M on the kept left singular space
+        assert np.abs(Um @ (np.diag(S) @ Vh) * np.sqrt(1 - disc) - Um @ (Um.conj().T @ M)).max() < 1e-12 * dense[0]
+
+
+def test_tied_multiplets_follow_the_tie_rule():
+    """Two multiplets of different sectors with equal full-state singular
+    values: the one with the smaller (q, 2j) comes first, so a cap that fits
+    only one keeps that one, in the reduced rule and in the dense truncation
+    of the expanded tensor alike."""
+    left = synth.sector_profile(20, 5, parity=1)
+    right = synth.sector_profile(20, 6, parity=1)
+    site = 2
+    mats = R.sector_matrices({}, left, right)
+    rng = np.random.default_rng(11)
+    xs = sorted(mats)
+    big = [x for x in xs if min(mats[x][0].shape) >= 2]
+    # the tied pair: a (q, 0) singlet and a (q', 2) triplet sector, q < q'
+    x_lo = min(x for x in big if x[1] == 2)
+    x_hi = min(x for x in big if x[1] == 0 and x[0] > x_lo[0])
+    blocks = {}
+    for x in xs:
+        Mx, rows, cols = mats[x]
+        r = min(Mx.shape)
+        s = np.sort(rng.uniform(0.05, 0.5, r))[::-1] * np.sqrt(x[1] + 1)
+        if x in (x_lo, x_hi):
+            s[0] = 2.0 * np.sqrt(x[1] + 1)          # equal full-state value 2.0, above all others
+        Ux, _ = np.linalg.qr(rng.standard_normal((Mx.shape[0], r)) + 1j * rng.standard_normal((Mx.shape[0], r)))
+        Vx, _ = np.linalg.qr(rng.standard_normal((Mx.shape[1], r)) + 1j * rng.standard_normal((Mx.shape[1], r)))
+        Mx = (Ux * s) @ Vx.conj().T
+        ro = np.cumsum([0] + [left[a][2] for a, _ in rows])
+        co = np.cumsum([0] + [right[bb][2] for _, bb in cols])
+        for i, (ia, s1) in enumerate(rows):
+            for j, (s2, ib) in enumerate(cols):
+                # every (row partner, column partner) pair of a sector is an allowed block
+                blocks[(ia, s1, x[1], s2, ib)] = Mx[ro[i]:ro[i + 1], co[j]:co[j + 1]]
+    assert set(blocks) == set(map(tuple, _theta_keys(left, right)))
+    svals = R.sector_singular_values(blocks, left, right)
+    assert abs(svals[x_lo][0] / np.sqrt(x_lo[1] + 1) - svals[x_hi][0]) < 1e-12
+    Th = R.expand_theta(blocks, left, right, site)
+    M = Th.reshape(Th.shape[0] * 4, -1)
+    ops = R.row_quantum_ops(left, site)
+    first = min(x_lo, x_hi)
+    for cap in (1, 3, 4):
+        kept, _ = R.truncate_multiplets(svals, 0.0, cap)
+        Um, S, Vh, _ = D._svd_split(M, False, 0.0, cap, multiplets=True, row_ops=ops)
+        assert kept[first] == 1
+        assert _kept_labels(Um, ops) == {x: n for x, n in kept.items() if n}
+    kept1, _ = R.truncate_multiplets(svals, 0.0, 1)
+    assert {x: n for x, n in kept1.items() if n} == {first: 1}
