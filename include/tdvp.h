@@ -50,11 +50,26 @@
  * during the call only.  Block order is free, but keys must be unique and
  * offsets must not overlap; the *_layout queries give a canonical layout.
  *
+ * Device memory.  Every device buffer the library itself needs (workspaces,
+ * the Krylov basis, program arrays, the blocks of a library-owned MPS) comes
+ * from the allocator given to tdvp_ctx_create (dev_alloc / dev_free with the
+ * caller's `user` pointer), or from hipMalloc / hipFree when none is given.
+ * The library may release a buffer while work that used it is still queued
+ * on the context stream: the allocator must order reuse on that stream (a
+ * stream-ordered caching allocator bound to the context stream, such as
+ * torch's, does).  The callbacks must stay valid until the context and every
+ * MPS made with it are destroyed.  dev_alloc returning NULL makes the call
+ * that needed the memory fail with TDVP_E_NOMEM.  The batched eigensolver
+ * library behind tdvp_sweep / tdvp_split keeps its own small workspace.
+ *
  * Errors.  Every call returns TDVP_OK or a negative code and never throws;
  * tdvp_last_error() gives a message.  Work is enqueued on the context stream;
- * heff_apply and env_update do not synchronise.  krylov_expm and sweep
- * synchronise (they need the Lanczos scalars on the host) and report earlier
- * asynchronous device faults as TDVP_E_HIP.  A context is not thread-safe.
+ * heff_apply and env_update do not synchronise.  krylov_expm, split and the
+ * sweeps synchronise (they need scalars on the host) and report earlier
+ * asynchronous device faults as TDVP_E_HIP.  Every block product marks a
+ * device flag when it writes a non-finite value; the next synchronising call
+ * (tdvp_ctx_synchronize included) returns TDVP_E_NONFINITE and clears it.
+ * A context is not thread-safe; one context per stream.
  */
 #ifndef TDVP_H
 #define TDVP_H
@@ -181,10 +196,26 @@ typedef struct {
  * then creates its own default-priority, non-blocking stream, which is not
  * ordered with any other stream, the null stream included: a caller whose
  * inputs come from kernels on another stream passes that stream here or
- * synchronises first); precision: TDVP_FP64/FP32/BF16X3. */
-int tdvp_ctx_create(tdvp_ctx** out, int32_t device, void* hip_stream, int32_t precision);
+ * synchronises first); precision: TDVP_FP64/FP32/BF16X3 (the precision
+ * ladder of the block products, supplementary section S2.5 for float32);
+ * dev_alloc / dev_free / user: the device allocator (both NULL: hipMalloc).
+ * Errors: INVALID (bad ordinal, precision, or only one callback), HIP (no
+ * device), NOMEM. */
+int tdvp_ctx_create(tdvp_ctx** out, int32_t device, void* hip_stream, int32_t precision,
+                    void* (*dev_alloc)(size_t bytes, void* user), void (*dev_free)(void* ptr, void* user),
+                    void* user);
 void tdvp_ctx_destroy(tdvp_ctx* ctx);
 int tdvp_ctx_set_precision(tdvp_ctx* ctx, int32_t precision);
+/* Splitting of long K chains in effective-Hamiltonian launches: every output
+ * tile whose chain is longer than alpha x the mean work per resident
+ * workgroup is cut into pieces of at least kmin steps of depth, summed by a
+ * second kernel in a fixed order (results stay deterministic; the pieces sum
+ * in another order than the unsplit chain, so FP64 results differ in the last
+ * bits).  alpha < 0: the size rule (split only applies of >= 1e11 flops, alpha
+ * 1, kmin 128; environment updates never); alpha >= 0 (0: never) applies to
+ * applies and environment updates alike.  Applies to programs built
+ * afterwards.  Errors: INVALID. */
+int tdvp_ctx_set_split(tdvp_ctx* ctx, double alpha, int32_t kmin);
 /* Graph replay of Lanczos iterations (enable 1, the default unless the
  * environment variable TDVP_GRAPH is 0, or 0).  With it on, each Krylov
  * exponential of an effective Hamiltonian records one iteration (apply, two
@@ -193,6 +224,8 @@ int tdvp_ctx_set_precision(tdvp_ctx* ctx, int32_t precision);
  * it for every further iteration; the iteration index lives in device memory.
  * Results are identical either way.  Errors: INVALID (null ctx). */
 int tdvp_ctx_set_graphs(tdvp_ctx* ctx, int32_t enable);
+/* Waits for the context stream; HIP (earlier asynchronous fault) or
+ * NONFINITE (an earlier launch wrote non-finite values). */
 int tdvp_ctx_synchronize(tdvp_ctx* ctx);
 /* Last error message of ctx, or of the calling thread when ctx is NULL. */
 const char* tdvp_last_error(const tdvp_ctx* ctx);
@@ -209,18 +242,27 @@ int tdvp_env_layout(const tdvp_bond* bond, int32_t* nblocks, int32_t* keys, int6
                     int64_t* total);
 
 /* ---- effective Hamiltonian -----------------------------------------------
- * y = H_eff x for the block of sites site..site+nsites-1 (nsites 1 or 2):
+ * The map whose exponential TDVP takes at every step (supplementary section
+ * S2.2; the environment and Krylov contractions that dominate the cost are
+ * those of section S2.3): the Hamiltonian of Eq. (1) projected on the block
+ * of sites site..site+nsites-1 (nsites 1 or 2) between the left and right
+ * environments.  y = H_eff x for that block:
  * left = bond site-1, right = bond site+nsites-1, Lenv = left environment at
  * bond site-1, Renv = right environment at bond site+nsites-1.  x and y must
  * list the same keys (offsets may differ); y is overwritten.
  * The left-environment block products, the local two-site terms with their
  * recoupling coefficients and the right-environment block products are fused
- * in one grouped-GEMM launch. */
+ * in one grouped-GEMM launch.  x and y are caller-owned device buffers; y
+ * must not overlap x or the environments.  Does not synchronise.  Errors:
+ * INVALID (null pointer, bad site), SHAPE / SECTOR (descriptors inconsistent
+ * with the bonds), NOMEM; non-finite output surfaces at the next
+ * synchronising call as NONFINITE. */
 int tdvp_heff_apply(tdvp_ctx* ctx, const tdvp_model* model, int32_t site, int32_t nsites,
                     const tdvp_bond* left, const tdvp_bond* right, const tdvp_blocks* Lenv,
                     const tdvp_blocks* Renv, const tdvp_blocks* x, tdvp_blocks* y);
 
-/* Host-side plan of the same apply (no GPU): fills up to *nterms terms and
+/* Host-side plan of the same apply (no GPU; the sector bookkeeping and
+ * Wigner-Eckart recoupling of supplementary section S2.1): fills up to *nterms terms and
  * sets *nterms to the count (terms may be NULL) and *flops to the algorithmic
  * flop count (8 per complex multiply-add of every block product). */
 int tdvp_heff_plan(const tdvp_model* model, int32_t site, int32_t nsites, const tdvp_bond* left,
@@ -228,44 +270,62 @@ int tdvp_heff_plan(const tdvp_model* model, int32_t site, int32_t nsites, const 
                    const tdvp_blocks* x, int64_t* nterms, tdvp_term* terms, double* flops);
 
 /* ---- Krylov exponential --------------------------------------------------
+ * The local evolution of supplementary section S2.2 (a Krylov matrix
+ * exponential whose dimension is chosen adaptively):
  * x <- exp(tau H_eff) x, tau = tau_re + i tau_im (TDVP uses tau = -i dt/2
  * forward and +i dt/2 for the one-site backward step).  Lanczos with full
  * FP64 classical Gram-Schmidt re-orthogonalisation (two passes); stops when
  * beta_m |[exp(tau T_m)]_{m,1}| <= tol |x|, on breakdown, or at maxdim
- * (then TDVP_E_NOCONV with the best iterate left in x). */
+ * (then TDVP_E_NOCONV with the best iterate, the maxdim-dimensional Krylov
+ * approximation, left in x).  x is a caller-owned device buffer, updated in
+ * place; info (optional, host) receives the recurrence.  Synchronises.
+ * Errors: INVALID (maxdim outside 1..64, tol < 0), NOCONV, NONFINITE (x or
+ * the applies not finite), NOMEM, HIP. */
 int tdvp_krylov_expm(tdvp_ctx* ctx, const tdvp_model* model, int32_t site, int32_t nsites,
                      const tdvp_bond* left, const tdvp_bond* right, const tdvp_blocks* Lenv,
                      const tdvp_blocks* Renv, tdvp_blocks* x, double tau_re, double tau_im,
                      double tol, int32_t maxdim, tdvp_krylov_info* info);
 
-/* Host helper used by krylov_expm, exported for tests: y = nrm exp(tau T) e_1
- * for the real symmetric tridiagonal T with diagonal alpha[0..n) and
- * off-diagonal beta[0..n-1); y is n complex numbers, interleaved. */
+/* Host helper used by krylov_expm, exported for tests (the small exponential
+ * of the adaptive Krylov step, supplementary section S2.2): y = nrm exp(tau T)
+ * e_1 for the real symmetric tridiagonal T with diagonal alpha[0..n) and
+ * off-diagonal beta[0..n-1); y is n complex numbers, interleaved.  Host
+ * arrays.  Errors: INVALID, NOCONV (tridiagonal eigensolver). */
 int tdvp_tridiag_expm(int32_t n, const double* alpha, const double* beta, double tau_re, double tau_im,
                       double nrm, double* y);
 
 /* ---- environment update ----------------------------------------------------
+ * The environment recursion that accompanies every sweep step (supplementary
+ * sections S2.2-S2.3; L_i = A^dag (L_{i-1} x W_i) A and its mirror image).
  * direction +1: env_in = left environment at bond site-1 (bond_in), tensor =
  *   left-canonical A of `site` with keys (ia on bond_in, s, ib on bond_out);
  *   env_out = left environment at bond site (bond_out).
  * direction -1: env_in = right environment at bond site (bond_in), tensor =
  *   right-canonical B of `site` with keys (ia on bond_out, s, ib on bond_in);
  *   env_out = right environment at bond site-1 (bond_out).
- * env_out keys must be those of tdvp_env_layout(bond_out); it is overwritten. */
+ * env_out keys must be those of tdvp_env_layout(bond_out); it is overwritten.
+ * All data are caller-owned device buffers; env_out must not overlap the
+ * inputs.  Does not synchronise.  Errors as tdvp_heff_apply. */
 int tdvp_env_update(tdvp_ctx* ctx, const tdvp_model* model, int32_t site, int32_t direction,
                     const tdvp_bond* bond_in, const tdvp_bond* bond_out, const tdvp_blocks* env_in,
                     const tdvp_blocks* tensor, tdvp_blocks* env_out);
+/* Host-side plan of the same update (no GPU): terms as tdvp_env_term, flop
+ * count as tdvp_heff_plan.  Two-call pattern on *nterms. */
 int tdvp_env_plan(const tdvp_model* model, int32_t site, int32_t direction, const tdvp_bond* bond_in,
                   const tdvp_bond* bond_out, const tdvp_blocks* env_in, const tdvp_blocks* tensor,
                   const tdvp_blocks* env_out, int64_t* nterms, tdvp_env_term* terms, double* flops);
 
 /* ---- MPS and sweep ----------------------------------------------------------
- * tdvp_mps_create copies a right-canonical MPS (centre C1 on site 1, B on
- * sites 2..L; bonds[0..L], sites[0..L-1] with keys (ia, s, ib) on
- * bonds[k-1], bonds[k]; device data) into library-owned memory and builds the
+ * The state that TDVP evolves: an MPS in the reduced U(1) x SU(2) form of
+ * supplementary section S2.1.  tdvp_mps_create copies a right-canonical MPS
+ * (centre C1 on site 1, B on sites 2..L; bonds[0..L], sites[0..L-1] with keys
+ * (ia, s, ib) on bonds[k-1], bonds[k]; device data, read only during the
+ * call) into library-owned memory (the context's allocator) and builds the
  * right environments.  tdvp_mps_create_neel builds the Neel state of Eq. (2)
  * (up on odd sites); complete = 1 pads every bond to its full symmetric
- * dimension (zero-weight directions), which makes two-site TDVP exact. */
+ * dimension (zero-weight directions), which makes two-site TDVP exact.
+ * Errors: INVALID, SHAPE, SECTOR (boundary bonds must be the vacuum (0, 0)
+ * of dimension 1), NOMEM, HIP. */
 int tdvp_mps_create(tdvp_ctx* ctx, const tdvp_model* model, const tdvp_bond* bonds,
                     const tdvp_blocks* sites, tdvp_mps** out);
 int tdvp_mps_create_neel(tdvp_ctx* ctx, const tdvp_model* model, int32_t complete, tdvp_mps** out);
@@ -277,15 +337,48 @@ int tdvp_mps_bond(const tdvp_mps* mps, int32_t k, int32_t* n, int32_t* q, int32_
 int tdvp_mps_site_layout(const tdvp_mps* mps, int32_t k, int32_t* nblocks, int32_t* keys,
                          int64_t* offsets, int64_t* total);
 int tdvp_mps_site_read(tdvp_ctx* ctx, const tdvp_mps* mps, int32_t k, void* host_dst);
-/* One time step dt of symmetric second-order two-site TDVP: left-to-right
+/* One time step dt of symmetric second-order two-site TDVP (supplementary
+ * section S2.2; truncation by discarded weight, section S2.4): left-to-right
  * then right-to-left with tau = dt/2 each, every bond merged, evolved by
  * exp(-i tau H2), split by per-sector SVD (truncation: whole multiplets by
  * descending singular value while the discarded weight stays within
  * eps_tol of the total and the kept full dimension within chi_cap; kept
  * values renormalised), environments updated and the one-site centre evolved
- * back by exp(+i tau H1).  The MPS returns to right-canonical form. */
+ * back by exp(+i tau H1).  The MPS returns to right-canonical form.  The
+ * library reallocates the MPS and environment blocks as bonds change, through
+ * the context's allocator.  Synchronises.  Errors: INVALID (null, foreign or
+ * split-result MPS, bad trunc), NONFINITE, NOMEM, HIP, NOCONV (eigensolver);
+ * Krylov exponentials that reach maxdim are counted in info, not errors. */
 int tdvp_sweep(tdvp_ctx* ctx, tdvp_mps* mps, double dt, const tdvp_trunc* trunc,
                tdvp_sweep_info* info);
+
+/* ---- two-site split ---------------------------------------------------------
+ * The SVD step of a two-site update as a call of its own (supplementary
+ * section S2.2; truncated weight, section S2.4): per coupled sector x of the
+ * bond between the two sites, the matrix M_x with rows (a, s1) and columns
+ * (s2, b) of theta is decomposed, whole multiplets are kept by the rule of
+ * tdvp_sweep (eps_tol, chi_cap; keep_all keeps every value, zeros included),
+ * and theta = A . C (direction +1: A left-canonical on site 1, the centre on
+ * site 2) or C . B (direction -1: centre on site 1, B right-canonical on
+ * site 2), with the kept values renormalised to the norm of theta.
+ * tdvp_split_sectors (host only, two-call pattern): the coupled sectors in
+ * the order the singular values are reported, ascending (q, 2j), with the
+ * sizes of M_x.  tdvp_split: left/right bonds and theta (device, keys of
+ * tdvp_center_layout with nsites 2; not modified).  *out receives a
+ * two-site MPS object holding the result (bond 1 = the new bond, site 1 and
+ * site 2 the two tensors; read with tdvp_mps_bond / tdvp_mps_site_layout /
+ * tdvp_mps_site_read, release with tdvp_mps_destroy; sweeps, measurements
+ * and overlaps reject it).  svals (host, optional): sum over sectors of
+ * min(rows, cols) doubles, each sector's reduced singular values in
+ * descending order, before truncation (computed from the Gram matrix of the
+ * smaller side: absolute accuracy about 1e-16 of the largest squared
+ * value).  discarded (optional): discarded weight / total weight.
+ * Synchronises.  Errors: INVALID, SHAPE, SECTOR, NONFINITE (theta not
+ * finite), NOMEM, HIP, NOCONV (eigensolver). */
+int tdvp_split_sectors(const tdvp_bond* left, const tdvp_bond* right, int32_t* nsec, int32_t* q, int32_t* tj,
+                       int64_t* rows, int64_t* cols);
+int tdvp_split(tdvp_ctx* ctx, const tdvp_bond* left, const tdvp_bond* right, const tdvp_blocks* theta,
+               int32_t direction, const tdvp_trunc* trunc, tdvp_mps** out, double* svals, double* discarded);
 
 /* One time step dt of symmetric second-order one-site TDVP (supplementary
  * section S2.2: once the bond dimensions have saturated the single-site

@@ -30,6 +30,8 @@ the Krylov exponentials):
 The interaction is the particle-hole symmetric U (n_up - 1/2)(n_dn - 1/2),
 the form for which the pseudospin SU(2) of section S2.1 is exact.
 """
+import functools
+
 import numpy as np
 import scipy.linalg
 
@@ -67,6 +69,7 @@ def onsite(U):
     return U * (N_UP - 0.5 * EYE4) @ (N_DN - 0.5 * EYE4)
 
 
+@functools.lru_cache(maxsize=None)
 def two_site_hop(t):
     """-t sum_s (c+_1s c_2s + h.c.) on a two-site chain, as a 16x16 matrix in
     the local basis (site 1 slow).  Taken from the Jordan-Wigner Hamiltonian
@@ -399,12 +402,29 @@ def _svd_split(M, keep_all, eps_tol, chi_cap, multiplets=False, row_ops=None):
     return Uk, Sk, Vk, disc / tot if tot > 0 else 0.0
 
 
+_BLOCK_OPS = {}
+
+
+def _block_ops(n):
+    """T+, Tz and 2 S^z of a block of n sites (cached: they depend on n only)."""
+    if n not in _BLOCK_OPS:
+        from .fermions import pseudospin
+        Tp, _, Tz = pseudospin(n)
+        idx = np.arange(4 ** n)
+        sz = np.zeros(4 ** n)
+        for k in range(n):
+            s = (idx // 4 ** (n - 1 - k)) % 4
+            sz += (s == 1).astype(float) - (s == 2).astype(float)
+        _BLOCK_OPS[n] = (Tp, Tz, sz)
+    return _BLOCK_OPS[n]
+
+
 def left_row_ops(mps, i):
     """(2 S^z, T^2) of sites 1..i on the row space (left bond index, state of
     site i) of the two-site tensor at sites (i, i+1), from the left-canonical
     tensors mps[0..i-2] (their left block basis Phi) and the fermion
     operators: Phi^dag O_block Phi (x) 1 + 1 (x) o_site."""
-    from .fermions import pseudospin, A_UP, A_DN
+    from .fermions import A_UP, A_DN
     nu, nd = A_UP.T @ A_UP, A_DN.T @ A_DN
     tp = (-1.0) ** i * (A_UP.T @ A_DN.T)
     tz = 0.5 * (nu + nd - np.eye(4))
@@ -412,12 +432,7 @@ def left_row_ops(mps, i):
         Jp, Jz, Q = np.zeros((1, 1)), np.zeros((1, 1)), np.zeros((1, 1))
     else:
         Phi = left_block_basis(mps[:i - 1])
-        Tp_b, _, Tz_b = pseudospin(i - 1)
-        sz = np.zeros(4 ** (i - 1))
-        idx = np.arange(4 ** (i - 1))
-        for k in range(i - 1):
-            s = (idx // 4 ** (i - 2 - k)) % 4
-            sz += (s == 1).astype(float) - (s == 2).astype(float)
+        Tp_b, Tz_b, sz = _block_ops(i - 1)
         Jp = Phi.conj().T @ (Tp_b @ Phi)
         Jz = Phi.conj().T @ (Tz_b @ Phi)
         Q = Phi.conj().T @ (sz[:, None] * Phi)

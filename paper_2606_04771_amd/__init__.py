@@ -78,7 +78,10 @@ def _load():
     lib = C.CDLL(LIB_PATH)
     P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     sig = {
-        "tdvp_ctx_create": [C.POINTER(C.c_void_p), I32, P, I32],
+        "tdvp_ctx_create": [C.POINTER(C.c_void_p), I32, P, I32, P, P, P],
+        "tdvp_ctx_set_split": [P, D, I32],
+        "tdvp_split_sectors": [P, P, P, P, P, P, P],
+        "tdvp_split": [P, P, P, P, I32, P, P, P, P],
         "tdvp_ctx_destroy": [P],
         "tdvp_ctx_set_precision": [P, I32],
         "tdvp_ctx_set_graphs": [P, I32],
@@ -246,6 +249,18 @@ def env_plan(model, site, direction, bond_in, bond_out, env_in, tensor, env_out)
     return [(t.kind, t.out, t.bra, t.ket, t.env, t.coef) for t in arr], fl.value
 
 
+def split_sectors(left, right):
+    """Coupled sectors of the bond between two sites: [(q, tj, rows, cols)]."""
+    n = C.c_int32()
+    _check(lib.tdvp_split_sectors(left.ref, right.ref, C.byref(n), None, None, None, None))
+    q = np.zeros(n.value, np.int32)
+    tj = np.zeros(n.value, np.int32)
+    r = np.zeros(n.value, np.int64)
+    c = np.zeros(n.value, np.int64)
+    _check(lib.tdvp_split_sectors(left.ref, right.ref, C.byref(n), _ptr(q), _ptr(tj), _ptr(r), _ptr(c)))
+    return [(int(a), int(b), int(x), int(y)) for a, b, x, y in zip(q, tj, r, c)]
+
+
 def tridiag_expm(alpha, beta, tau, nrm=1.0):
     a = np.ascontiguousarray(alpha, np.float64)
     b = np.ascontiguousarray(beta if len(beta) else [0.0], np.float64)
@@ -255,12 +270,43 @@ def tridiag_expm(alpha, beta, tau, nrm=1.0):
     return y[0::2] + 1j * y[1::2]
 
 
-class Context:
-    """A library context on one HIP device and stream."""
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
-    def __init__(self, device=0, stream=None, precision=FP64):
+
+def torch_allocator(device, stream):
+    """(dev_alloc, dev_free) callbacks on torch's caching allocator, bound to
+    the raw stream handle the context runs on (stream-ordered reuse)."""
+    import torch
+
+    def alloc(n, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(n), device, int(stream))
+        except Exception:
+            return None
+
+    def free(p, user):
+        torch.cuda.caching_allocator_delete(int(p))
+
+    return _ALLOC_FN(alloc), _FREE_FN(free)
+
+
+class Context:
+    """A library context on one HIP device and stream.
+
+    allocator: "torch" (default when a stream is given: device memory from
+    torch's caching allocator on that stream), None (hipMalloc), or a pair of
+    ctypes callbacks (dev_alloc(bytes, user) -> ptr, dev_free(ptr, user))."""
+
+    def __init__(self, device=0, stream=None, precision=FP64, allocator="torch"):
+        if allocator == "torch":
+            allocator = torch_allocator(int(device), stream) if stream else None
+        self._alloc = allocator
+        a, f = allocator if allocator else (None, None)
         h = C.c_void_p()
-        _check(lib.tdvp_ctx_create(C.byref(h), int(device), C.c_void_p(stream), int(precision)))
+        _check(lib.tdvp_ctx_create(C.byref(h), int(device), C.c_void_p(stream), int(precision),
+                                   C.cast(a, C.c_void_p) if a else None,
+                                   C.cast(f, C.c_void_p) if f else None, None))
         self.h = h
 
     def close(self):
@@ -279,6 +325,28 @@ class Context:
 
     def set_graphs(self, enable):
         _check(lib.tdvp_ctx_set_graphs(self.h, int(bool(enable))), self.h)
+
+    def set_split(self, alpha=-1.0, kmin=128):
+        """K-chain splitting of effective-Hamiltonian launches (alpha < 0: size rule)."""
+        _check(lib.tdvp_ctx_set_split(self.h, float(alpha), int(kmin)), self.h)
+
+    def split(self, left, right, theta, direction, eps_tol=1e-4, chi_cap=4096, keep_all=False):
+        """Two-site split of theta (Blocks on the device).  Returns (MPS of two
+        sites holding the result, {(q, tj): reduced singular values}, discarded)."""
+        sec = split_sectors(left, right)
+        n = sum(min(r, c) for _, _, r, c in sec)
+        sv = np.zeros(max(n, 1))
+        disc = C.c_double()
+        tr = _Trunc(float(eps_tol), int(chi_cap), int(bool(keep_all)), 1e-12, 40)
+        h = C.c_void_p()
+        _check(lib.tdvp_split(self.h, left.ref, right.ref, theta.ref, int(direction), C.byref(tr), C.byref(h),
+                              _ptr(sv), C.byref(disc)), self.h)
+        out, o = {}, 0
+        for q, tj, r, c in sec:
+            k = min(r, c)
+            out[(q, tj)] = sv[o:o + k].copy()
+            o += k
+        return MPS(self, h, Model(2, 0.0, 0.0)), out, disc.value
 
     def synchronize(self):
         _check(lib.tdvp_ctx_synchronize(self.h), self.h)

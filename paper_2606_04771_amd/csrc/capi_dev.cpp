@@ -21,14 +21,19 @@ using namespace tdvp;
 namespace tdvp {
 
 int hip_check(tdvp_ctx* ctx, hipError_t e, const char* what) {
-  return set_error(ctx, TDVP_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  const int code = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? TDVP_E_NOMEM : TDVP_E_HIP;
+  return set_error(ctx, code, std::string(what) + ": " + hipGetErrorString(e));
 }
 
 namespace {
 
+// Structural hash of a program's inputs; the values hashed are also kept, so
+// that a cache hit can be confirmed by comparing them.
 struct Hasher {
   uint64_t h = 1469598103934665603ull;
+  std::vector<uint64_t> sig;
   void add(uint64_t v) {
+    sig.push_back(v);
     h ^= v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
     h *= 1099511628211ull;
   }
@@ -54,6 +59,20 @@ struct Hasher {
 
 }  // namespace
 
+int take_bad_flag(tdvp_ctx* ctx, bool& bad) {
+  bad = false;
+  if (!ctx->ws_flag.p) return TDVP_OK;
+  int h = 0;
+  TDVP_HIP(ctx, hipMemcpyAsync(&h, ctx->ws_flag.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (h) {
+    TDVP_HIP(ctx, hipMemsetAsync(ctx->ws_flag.p, 0, sizeof(int), ctx->stream));
+    TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    bad = true;
+  }
+  return TDVP_OK;
+}
+
 // Lower an H_eff plan to a grouped-GEMM program.  Buffers: 0 = x, 1 = Lenv,
 // 2 = Renv; output blocks at y's offsets.
 std::shared_ptr<Program> heff_program(tdvp_ctx* ctx, const tdvp_model& m, int site, int nsites,
@@ -70,8 +89,10 @@ std::shared_ptr<Program> heff_program(tdvp_ctx* ctx, const tdvp_model& m, int si
   hs.blocks(in.Re);
   hs.blocks(in.x);
   hs.blocks(y);
+  hs.addd(ctx->split_alpha);
+  hs.add((uint64_t)ctx->split_kmin);
   rc = TDVP_OK;
-  if (auto p = cache_get(ctx, hs.h)) return p;
+  if (auto p = cache_get(ctx, hs.h, hs.sig)) return p;
   std::vector<HTerm> terms;
   double flops = 0;
   plan_heff(m, site, nsites, in.l, in.r, in.Le, in.Re, in.x, terms, flops);
@@ -79,6 +100,9 @@ std::shared_ptr<Program> heff_program(tdvp_ctx* ctx, const tdvp_model& m, int si
   auto p = std::make_shared<Program>();
   p->flops = flops;
   p->role = 1;
+  p->sig = hs.sig;
+  p->split_alpha = ctx->split_alpha;
+  p->split_kmin = ctx->split_kmin;
   size_t t = 0;
   const Blocks& x = in.x;
   std::vector<DevTerm> direct;
@@ -170,10 +194,12 @@ EnvPrograms env_programs(tdvp_ctx* ctx, const tdvp_model& m, int site, int dir, 
   hs.blocks(in.ein);
   hs.blocks(in.ten);
   hs.blocks(in.eout);
+  hs.addd(ctx->split_alpha);
+  hs.add((uint64_t)ctx->split_kmin);
   rc = TDVP_OK;
   EnvPrograms ep;
-  auto p1 = cache_get(ctx, hs.h);
-  auto p2 = cache_get(ctx, hs.h ^ 0x5555555555555555ull);
+  auto p1 = cache_get(ctx, hs.h, hs.sig);
+  auto p2 = cache_get(ctx, hs.h ^ 0x5555555555555555ull, hs.sig);
   if (p1 && p2) {
     ep.s1 = p1;
     ep.s2 = p2;
@@ -214,10 +240,20 @@ EnvPrograms env_programs(tdvp_ctx* ctx, const tdvp_model& m, int site, int dir, 
     so += rows * cols;
   }
   s1->aux = so;
+  s1->sig = hs.sig;
+  if (ctx->split_alpha >= 0.0) {   // an explicit setting applies to the environment stages too
+    s1->split_alpha = ctx->split_alpha;
+    s1->split_kmin = ctx->split_kmin;
+  }
   s1->finalize();
   // stage 2
   auto s2 = std::make_shared<Program>();
   s2->flops = flops;
+  s2->sig = hs.sig;
+  if (ctx->split_alpha >= 0.0) {
+    s2->split_alpha = ctx->split_alpha;
+    s2->split_kmin = ctx->split_kmin;
+  }
   size_t t = 0;
   for (int o = 0; o < O.n(); ++o) {
     DevOut ob{};
@@ -276,8 +312,11 @@ int env_update_dev(tdvp_ctx* ctx, const tdvp_model& m, int site, int dir, const 
 
 extern "C" {
 
-int tdvp_ctx_create(tdvp_ctx** out, int32_t device, void* hip_stream, int32_t precision) {
+int tdvp_ctx_create(tdvp_ctx** out, int32_t device, void* hip_stream, int32_t precision,
+                    void* (*dev_alloc)(size_t, void*), void (*dev_free)(void*, void*), void* user) {
   return guarded(nullptr, [&]() -> int {
+    if ((dev_alloc == nullptr) != (dev_free == nullptr))
+      return set_error(nullptr, TDVP_E_INVALID, "dev_alloc and dev_free must be given together");
     if (!out) return set_error(nullptr, TDVP_E_INVALID, "out is null");
     *out = nullptr;
     if (precision != TDVP_FP64 && precision != TDVP_FP32 && precision != TDVP_BF16X3)
@@ -291,6 +330,19 @@ int tdvp_ctx_create(tdvp_ctx** out, int32_t device, void* hip_stream, int32_t pr
     auto* c = new tdvp_ctx();
     c->device = device;
     c->precision = precision;
+    {
+      auto al = std::make_shared<Allocator>();
+      al->alloc_fn = dev_alloc;
+      al->free_fn = dev_free;
+      al->user = user;
+      c->alloc = al;
+      c->pool->al = al;
+      for (DeviceBuffer* b : {&c->ws_scratch, &c->ws_krylov, &c->ws_small, &c->ws_vec, &c->ws_theta, &c->ws_svd,
+                              &c->ws_lanczos, &c->ws_part, &c->ws_shift, &c->ws_compact, &c->ws_flag})
+        b->al = al;
+    }
+    if (const char* e = std::getenv("TDVP_SPLIT_ALPHA")) c->split_alpha = std::atof(e);
+    if (const char* e = std::getenv("TDVP_SPLIT_KMIN")) c->split_kmin = std::max(1, std::atoi(e));
     if (hip_stream) {
       c->stream = (hipStream_t)hip_stream;
     } else {
@@ -305,6 +357,16 @@ int tdvp_ctx_create(tdvp_ctx** out, int32_t device, void* hip_stream, int32_t pr
     if (e != hipSuccess) {
       delete c;
       return set_error(nullptr, TDVP_E_NOMEM, "pinned host buffer");
+    }
+    // the non-finite flag, zeroed before any launch can be recorded into a graph
+    e = c->ws_flag.ensure(256);
+    if (e == hipSuccess) e = hipMemsetAsync(c->ws_flag.p, 0, 256, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+      if (c->own_stream) (void)hipStreamDestroy(c->stream);
+      if (c->host_small) (void)hipHostFree(c->host_small);
+      delete c;
+      return set_error(nullptr, e == hipErrorOutOfMemory ? TDVP_E_NOMEM : TDVP_E_HIP, "context flag buffer");
     }
     for (auto& ev : c->ev) (void)hipEventCreate(&ev);
     const char* gr = std::getenv("TDVP_GRAPH");
@@ -352,9 +414,21 @@ int tdvp_ctx_set_graphs(tdvp_ctx* ctx, int32_t enable) {
   return TDVP_OK;
 }
 
+int tdvp_ctx_set_split(tdvp_ctx* ctx, double alpha, int32_t kmin) {
+  if (!ctx) return set_error(nullptr, TDVP_E_INVALID, "null ctx");
+  if (std::isnan(alpha) || kmin < 1) return set_error(ctx, TDVP_E_INVALID, "bad split parameters");
+  ctx->split_alpha = alpha < 0.0 ? -1.0 : alpha;
+  ctx->split_kmin = kmin;
+  return TDVP_OK;
+}
+
 int tdvp_ctx_synchronize(tdvp_ctx* ctx) {
   if (!ctx) return set_error(nullptr, TDVP_E_INVALID, "null ctx");
+  TDVP_HIP(ctx, hipSetDevice(ctx->device));
   TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  bool bad = false;
+  if (int rc = take_bad_flag(ctx, bad)) return rc;
+  if (bad) return set_error(ctx, TDVP_E_NONFINITE, "an earlier apply or environment update produced non-finite values");
   return TDVP_OK;
 }
 
@@ -430,6 +504,11 @@ int tdvp_krylov_expm(tdvp_ctx* ctx, const tdvp_model* model, int32_t site, int32
     TDVP_HIP(ctx, hipSetDevice(ctx->device));
     KrylovResult kr;
     rc = krylov_dev(ctx, *model, site, nsites, in, {tau_re, tau_im}, tol, maxdim, kr);
+    if (rc == TDVP_OK || rc == TDVP_E_NOCONV || rc == TDVP_E_NONFINITE) {
+      bool bad = false;
+      if (int r2 = take_bad_flag(ctx, bad)) return r2;
+      if (bad && rc != TDVP_E_NONFINITE) rc = set_error(ctx, TDVP_E_NONFINITE, "non-finite values in the Krylov exponential");
+    }
     if (info) {
       std::memset(info, 0, sizeof(*info));
       info->iters = kr.iters;

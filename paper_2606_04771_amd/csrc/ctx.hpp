@@ -8,6 +8,7 @@
 #include <memory>
 #include <map>
 #include <string>
+#include <initializer_list>
 #include <unordered_map>
 #include <vector>
 
@@ -57,15 +58,31 @@ constexpr int kMaxBufs = 6;
 // bit 4 (bit 5) has its coefficient multiplied by shift[0] (shift[1]) (by
 // zero when there are no shifts).  Used to take an energy offset out of the
 // environment blocks before reduced-precision products and add it back exactly.
+// `bad` (device int, may be null): set to 1 by any launch that writes a
+// non-finite output value.
 struct Bufs {
   const double* p[kMaxBufs];
   const double* shift;
+  int* bad;
+};
+
+// Device memory of a context: the caller's allocator callbacks (torch's
+// caching allocator through the Python binding) or hipMalloc / hipFree.
+// Shared by everything the context allocates, objects that outlive the
+// context (an MPS) included.  A failed allocation is hipErrorOutOfMemory.
+struct Allocator {
+  void* (*alloc_fn)(size_t, void*) = nullptr;
+  void (*free_fn)(void*, void*) = nullptr;
+  void* user = nullptr;
+  hipError_t get(void** p, size_t n) const;
+  void put(void* p) const;
 };
 
 // Device memory for program arrays, recycled by size class.  Every use of a
 // chunk is ordered on the context stream, so a recycled chunk is only
 // rewritten (by a stream-ordered copy) after earlier kernels have read it.
 struct ProgPool {
+  std::shared_ptr<const Allocator> al;
   std::unordered_map<size_t, std::vector<void*>> free;
   ~ProgPool();
 };
@@ -75,6 +92,10 @@ struct ProgPool {
 struct Program {
   std::shared_ptr<ProgPool> pool;
   size_t cls = 0;
+  std::vector<uint64_t> sig;   // structural signature it was built from (cache check)
+  // K-chain splitting: alpha < 0 -> the default size rule; kmin: shortest piece
+  double split_alpha = -1.0;
+  int split_kmin = 128;
   std::vector<DevTerm> terms;
   std::vector<DevOut> outs;
   std::vector<DevTile> tiles;
@@ -123,11 +144,15 @@ struct Program {
   void tile_only(int mode, Tiling& out) const;
 };
 
+// Grow-only device buffer; memory comes from its allocator (set by the owner
+// before the first ensure(), hipMalloc when none is set).
 struct DeviceBuffer {
   void* p = nullptr;
   size_t bytes = 0;
+  std::shared_ptr<const Allocator> al;
   ~DeviceBuffer();
   hipError_t ensure(size_t n);
+  void release();
 };
 
 }  // namespace tdvp
@@ -167,9 +192,17 @@ struct tdvp_ctx {
   void* host_small = nullptr;   // pinned host mirror of ws_small
   std::shared_ptr<tdvp::ProgPool> pool = std::make_shared<tdvp::ProgPool>();
   int verbose = 0;
-  // program cache (structural hash -> program)
+  // program cache (structural hash -> program; a hit is confirmed by
+  // comparing the full structural signature the hash was taken of)
   std::list<std::pair<uint64_t, std::shared_ptr<tdvp::Program>>> cache;
   hipEvent_t ev[8] = {};
+  std::shared_ptr<const tdvp::Allocator> alloc = std::make_shared<tdvp::Allocator>();
+  // splitting of long K chains in effective-Hamiltonian programs
+  // (tdvp_ctx_set_split): alpha < 0 means the size rule
+  double split_alpha = -1.0;
+  int split_kmin = 128;
+  // device flag set by launches that wrote non-finite values (in ws_flag)
+  tdvp::DeviceBuffer ws_flag;
 };
 
 namespace tdvp {
@@ -183,8 +216,17 @@ int hip_check(tdvp_ctx* ctx, hipError_t e, const char* what);
 
 // Upload a finalized program to the device (cached by key when key != 0).
 int upload(tdvp_ctx* ctx, Program& p);
-std::shared_ptr<Program> cache_get(tdvp_ctx* ctx, uint64_t key);
+// Cache lookup by hash; a hit counts only if the stored signature equals sig.
+std::shared_ptr<Program> cache_get(tdvp_ctx* ctx, uint64_t key, const std::vector<uint64_t>& sig);
 void cache_put(tdvp_ctx* ctx, uint64_t key, std::shared_ptr<Program> p);
+// Device flag of non-finite outputs (allocated on first use, zeroed).
+int bad_flag(tdvp_ctx* ctx, int** flag);
+// Reads and clears the flag (synchronises the context stream).
+int take_bad_flag(tdvp_ctx* ctx, bool& bad);
+// Buffers that take their memory from the context's allocator.
+inline void use_alloc(tdvp_ctx* ctx, std::initializer_list<DeviceBuffer*> bufs) {
+  for (DeviceBuffer* b : bufs) b->al = ctx->alloc;
+}
 
 // Launch the grouped GEMM of p writing into C (base pointer of the output
 // buffer) with operand buffers bufs.  precision: TDVP_FP64 or TDVP_FP32.

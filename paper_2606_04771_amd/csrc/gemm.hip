@@ -28,6 +28,7 @@
 #include <cstdlib>
 #include <cstring>
 
+#include "common.hpp"
 #include "ctx.hpp"
 
 namespace tdvp {
@@ -278,6 +279,7 @@ __device__ __forceinline__ void gemm_body(const Bufs& bufs, double* __restrict__
             vr += c * x.x;
             vi += (dt.ops & 2) ? -c * x.y : c * x.y;
           }
+          if (bufs.bad && !(isfinite(vr) && isfinite(vi))) *bufs.bad = 1;
           C[(int64_t)row + (int64_t)col * ob.ldc] = make_double2(vr, vi);
         }
       }
@@ -457,6 +459,7 @@ __device__ __forceinline__ void gemm_body_b3(const Bufs& bufs, double* __restric
             vr += cc * xv.x;
             vi += (dt.ops & 2) ? -cc * xv.y : cc * xv.y;
           }
+          if (bufs.bad && !(isfinite(vr) && isfinite(vi))) *bufs.bad = 1;
           C[(int64_t)row + (int64_t)col * ob.ldc] = make_double2(vr, vi);
         }
       }
@@ -542,6 +545,7 @@ __global__ __launch_bounds__(256) void reduce_parts(Bufs bufs, double* __restric
       vr += c * x.x;
       vi += (dt.ops & 2) ? -c * x.y : c * x.y;
     }
+    if (bufs.bad && !(isfinite(vr) && isfinite(vi))) *bufs.bad = 1;
     C[(int64_t)row + (int64_t)col * ob.ldc] = make_double2(vr, vi);
   }
 }
@@ -585,10 +589,25 @@ void launch_one(tdvp_ctx* ctx, bool heff, int ntiles, const Bufs& bufs, double* 
 
 }  // namespace
 
+hipError_t Allocator::get(void** p, size_t n) const {
+  if (!alloc_fn) return hipMalloc(p, n);
+  *p = alloc_fn(n, user);
+  return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+
+void Allocator::put(void* p) const {
+  if (!p) return;
+  if (free_fn) free_fn(p, user);
+  else (void)hipFree(p);
+}
+
 Program::~Program() {
   for (hipEvent_t e : tune_ev)
     if (e) (void)hipEventDestroy(e);
-  if (d_by_out) (void)hipFree(d_by_out);
+  if (d_by_out) {
+    if (pool && pool->al) pool->al->put(d_by_out);
+    else (void)hipFree(d_by_out);
+  }
   if (!d_mem) return;
   if (pool) pool->free[cls].push_back(d_mem);
   else (void)hipFree(d_mem);
@@ -596,7 +615,10 @@ Program::~Program() {
 
 ProgPool::~ProgPool() {
   for (auto& kv : free)
-    for (void* p : kv.second) (void)hipFree(p);
+    for (void* p : kv.second) {
+      if (al) al->put(p);
+      else (void)hipFree(p);
+    }
 }
 
 int default_tile_mode() {
@@ -689,11 +711,9 @@ void Program::finalize() {
   // order.  Default: only large effective-Hamiltonian applies (>= 1e11 flops) are
   // split, alpha = 1 and pieces >= 128 deep (measured: +7 % at chi = 16384,
   // 4.5e11 flops; -4 % at chi = 4096, 1.8e10 flops).
-  static const double alpha_env = env_double("TDVP_SPLIT_ALPHA", -1.0);
-  static const int kmin_env = (int)env_double("TDVP_SPLIT_KMIN", -1.0);
   const bool big_apply = role == 1 && flops >= 1e11;
-  const double alpha = alpha_env >= 0.0 ? alpha_env : (big_apply ? 1.0 : 0.0);
-  const int kmin = kmin_env > 0 ? kmin_env : 128;
+  const double alpha = split_alpha >= 0.0 ? split_alpha : (big_apply ? 1.0 : 0.0);
+  const int kmin = split_kmin > 0 ? split_kmin : 128;
   static const int max_slots = (int)env_double("TDVP_SPLIT_MAXSLOTS", 2048);
   struct Item {
     DevTile t;
@@ -854,22 +874,37 @@ void Program::tile_only(int mode, Tiling& out) const {
   for (const It& it : xcd_order(t32)) out.tiles.push_back(it.t);
 }
 
-DeviceBuffer::~DeviceBuffer() {
-  if (p) (void)hipFree(p);
+DeviceBuffer::~DeviceBuffer() { release(); }
+
+void DeviceBuffer::release() {
+  if (p) {
+    if (al) al->put(p);
+    else (void)hipFree(p);
+  }
+  p = nullptr;
+  bytes = 0;
 }
 
 hipError_t DeviceBuffer::ensure(size_t n) {
   if (n <= bytes) return hipSuccess;
-  if (p) {
-    hipError_t e = hipFree(p);
-    p = nullptr;
-    bytes = 0;
-    if (e != hipSuccess) return e;
-  }
+  release();
   size_t want = std::max(n, (size_t)256);
-  hipError_t e = hipMalloc(&p, want);
+  hipError_t e = al ? al->get(&p, want) : hipMalloc(&p, want);
   if (e == hipSuccess) bytes = want;
+  else p = nullptr;
   return e;
+}
+
+int bad_flag(tdvp_ctx* ctx, int** flag) {
+  *flag = nullptr;
+  if (ctx->ws_flag.p) {
+    *flag = (int*)ctx->ws_flag.p;
+    return TDVP_OK;
+  }
+  TDVP_HIP(ctx, ctx->ws_flag.ensure(256));
+  TDVP_HIP(ctx, hipMemsetAsync(ctx->ws_flag.p, 0, 256, ctx->stream));
+  *flag = (int*)ctx->ws_flag.p;
+  return TDVP_OK;
 }
 
 int upload(tdvp_ctx* ctx, Program& p) {
@@ -892,7 +927,7 @@ int upload(tdvp_ctx* ctx, Program& p) {
     p.d_mem = fl.back();
     fl.pop_back();
   } else {
-    TDVP_HIP(ctx, hipMalloc(&p.d_mem, cls));
+    TDVP_HIP(ctx, ctx->alloc->get(&p.d_mem, cls));
   }
   char* base = (char*)p.d_mem;
   auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -929,9 +964,9 @@ int upload(tdvp_ctx* ctx, Program& p) {
   return TDVP_OK;
 }
 
-std::shared_ptr<Program> cache_get(tdvp_ctx* ctx, uint64_t key) {
+std::shared_ptr<Program> cache_get(tdvp_ctx* ctx, uint64_t key, const std::vector<uint64_t>& sig) {
   for (auto it = ctx->cache.begin(); it != ctx->cache.end(); ++it)
-    if (it->first == key) {
+    if (it->first == key && it->second->sig == sig) {
       auto p = it->second;
       ctx->cache.splice(ctx->cache.begin(), ctx->cache, it);
       return p;
@@ -1014,7 +1049,7 @@ static int launch_per_block(tdvp_ctx* ctx, const Program& p, const Bufs& bufs, d
     p.blk_begin.push_back(0);
     for (size_t i = 1; i <= v.size(); ++i)
       if (i == v.size() || v[i].out != v[i - 1].out) p.blk_begin.push_back((int)i);
-    TDVP_HIP(ctx, hipMalloc(&p.d_by_out, sizeof(DevTile) * std::max<size_t>(v.size(), 1)));
+    TDVP_HIP(ctx, ctx->alloc->get(&p.d_by_out, sizeof(DevTile) * std::max<size_t>(v.size(), 1)));
     TDVP_HIP(ctx, hipMemcpy(p.d_by_out, v.data(), sizeof(DevTile) * v.size(), hipMemcpyHostToDevice));
   }
   const DevTile* base = (const DevTile*)p.d_by_out;
@@ -1058,11 +1093,24 @@ static int launch_core(tdvp_ctx* ctx, const Program& p, int ntiles, int n64, con
     TDVP_HIP(ctx, ctx->ws_part.ensure(sizeof(double2) * (size_t)p.nslots * kSlotDim * kSlotDim));
     part = (double2*)ctx->ws_part.p;
   }
+  if (precision == TDVP_BF16X3 && ntiles > n64) {
+    // the split-BF16 kernel exists for 64x64 tiles only: take the program's
+    // all-64x64 tiling, or refuse rather than run FP32 under the BF16X3 label
+    const Program::Tiling* t64 = nullptr;
+    for (const auto& a : p.alt)
+      if (a.mode == 2) t64 = &a;
+    if (!t64 || !t64->d_tiles)
+      return set_error(ctx, TDVP_E_INVALID, "split-BF16 products need 64x64 tiles (tile mode 2)");
+    ntiles = (int)t64->tiles.size();
+    n64 = t64->n64;
+    d_tiles = t64->d_tiles;
+  }
   const int n32 = ntiles - n64;
   const DevTile* t32 = d_tiles + n64;
   const bool heff = p.role == 1;
   Bufs bf = bufs;
   bf.shift = nullptr;
+  if (int rc = bad_flag(ctx, &bf.bad)) return rc;
   if (precision != TDVP_FP64 && p.nshift[0] + p.nshift[1] > 0) {
     const int nb = p.nshift[0] + p.nshift[1];
     TDVP_HIP(ctx, ctx->ws_shift.ensure(sizeof(double) * 2 * (size_t)(nb + 1)));
@@ -1090,7 +1138,7 @@ static int launch_core(tdvp_ctx* ctx, const Program& p, int ntiles, int n64, con
       launch_one<double, 2, 2>(ctx, heff, n64, bf, C, part, d_tiles, p);
     }
   }
-  if (n32 > 0) {   // 32x32 tiles (optional tile modes) have no split-BF16 variant: FP32 there
+  if (n32 > 0) {   // 32x32 tiles (optional tile modes; never under BF16X3, see above)
     if (precision != TDVP_FP64) launch_one<float, 1, 1>(ctx, heff, n32, bf, C, part, t32, p);
     else launch_one<double, 1, 1>(ctx, heff, n32, bf, C, part, t32, p);
   }

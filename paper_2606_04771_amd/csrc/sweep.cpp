@@ -7,6 +7,7 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -33,6 +34,7 @@ struct tdvp_mps {
   tdvp_ctx* ctx = nullptr;
   tdvp_model model{};
   int L = 0;
+  bool fragment = false;   // result of tdvp_split: two sites between open bonds, not a chain
   std::vector<Bond> bonds;                       // 0..L
   std::vector<std::unique_ptr<Tensor>> site;     // site k at index k-1
   std::vector<std::unique_ptr<Tensor>> Lenv, Renv;   // bond 0..L
@@ -255,7 +257,7 @@ int run_program(tdvp_ctx* ctx, Program& p, const Bufs& b, double* C) {
 // the larger side it is obtained by a Householder QR of M V_k (or M^dag U_k).
 // The centre is then the exact projection of M on the kept isometry.
 int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const tdvp_trunc& tr, double& disc,
-          double& t_svd, int& fallbacks) {
+          double& t_svd, int& fallbacks, std::vector<double>* svals = nullptr) {
   double t0 = now();
   // phase timestamps (verbose >= 2 only: each one synchronises the stream)
   double ph[4] = {t0, t0, t0, t0};
@@ -561,6 +563,10 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
     }
   }
   if (!std::isfinite(W)) return set_error(ctx, TDVP_E_NONFINITE, "non-finite singular values");
+  if (svals) {   // reduced singular values, sector by sector (ascending (q, 2j)), descending
+    svals->clear();
+    for (const Ent& e : ents) svals->push_back(std::sqrt(e.w));
+  }
   // descending full-state value (sfull is its square); a value closer than
   // 1e-9 of the largest one to its predecessor is a tie, and ties go by
   // (q, 2j) ascending, then position in the sector
@@ -603,14 +609,23 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
   // isometries: eigenvectors directly, or from M V_k / M^dag U_k (scaled, or QR)
   double lam_max = 0.0;
   for (const Ent& e : ents) lam_max = std::max(lam_max, e.w);
+  // The scaled isometry M V_k S^-1 is orthonormal up to about
+  // eps lam_max / lam_min_kept (the Gram eigensolve's backward error); it is
+  // polished by Newton-Schulz steps Q <- Q (3 I - Q^dag Q) / 2, each of which
+  // squares that defect, until it is at rounding level.
+  double defect = 0.0;
   for (auto& kv : secs) {
     Sector& s = kv.second;
     s.scaled = false;
     if (!s.qr || s.keep == 0 || exact) continue;
     double lam_min_kept = ev[s.doff + s.col0 + s.g - s.keep];
-    if (lam_min_kept > 1e-14 * lam_max) s.scaled = true;
+    if (lam_min_kept > 1e-14 * lam_max) {
+      s.scaled = true;
+      defect = std::max(defect, 2.2e-16 * lam_max / lam_min_kept);
+    }
   }
-  int64_t qtot = 0, ktot = 0;
+  const int polish = defect > 1e-4 ? 3 : defect > 1e-8 ? 2 : defect > 1e-15 ? 1 : 0;
+  int64_t qtot = 0, ktot = 0, kk = 0;
   for (auto& kv : secs) {
     Sector& s = kv.second;
     if (s.keep == 0) continue;
@@ -619,6 +634,7 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
       s.qoff = qtot;
       qtot += n * s.keep;
       ktot += s.keep;
+      if (s.scaled) kk += (int64_t)s.keep * s.keep;
       s.iso_off = s.qoff;
       s.iso_ld = n;
     } else {
@@ -626,9 +642,12 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
       s.iso_ld = s.gn;
     }
   }
-  TDVP_HIP(ctx, ctx->ws_scratch.ensure(sizeof(double) * 2 * (size_t)(qtot + ktot + 1)));
+  const int64_t ptot = polish ? qtot : 0;   // polish scratch: Q^dag Q per sector, Q Q^dag Q
+  TDVP_HIP(ctx, ctx->ws_scratch.ensure(sizeof(double) * 2 * (size_t)(qtot + ktot + (polish ? kk : 0) + ptot + 1)));
   double* Qbase = (double*)ctx->ws_scratch.p;
   double* tau = Qbase + 2 * qtot;
+  double* Gq = tau + 2 * ktot;
+  double* Tq = Gq + 2 * (polish ? kk : 0);
   if (qtot > 0) {
     Program pq;
     for (auto& kv : secs) {
@@ -659,6 +678,58 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
     b.p[0] = Mbase;
     b.p[1] = Gbase;
     if ((rc = run_program(ctx, pq, b, Qbase))) return rc;
+    for (int step = 0; step < polish; ++step) {
+      Program pg, pt, pu;   // G = Q^dag Q; T = Q G; Q <- 1.5 Q - 0.5 T
+      int64_t go = 0;
+      for (auto& kv : secs) {
+        Sector& s = kv.second;
+        if (s.keep == 0 || !s.qr || !s.scaled) continue;
+        const int32_t n = (int32_t)s.iso_ld, k = s.keep;
+        DevOut ob{};
+        ob.c_off = go;
+        ob.ldc = ob.M = ob.N = k;
+        ob.t_begin = (int32_t)pg.terms.size();
+        DevTerm d{};
+        d.coef = 1.0;
+        d.a_buf = 0; d.a_off = s.qoff; d.lda = n; d.ops = 1 | 2;
+        d.b_buf = 0; d.b_off = s.qoff; d.ldb = n; d.K = n;
+        pg.terms.push_back(d);
+        ob.t_end = ob.d_begin = ob.d_end = (int32_t)pg.terms.size();
+        pg.outs.push_back(ob);
+        DevOut ot{};
+        ot.c_off = s.qoff;
+        ot.ldc = ot.M = n;
+        ot.N = k;
+        ot.t_begin = (int32_t)pt.terms.size();
+        DevTerm e{};
+        e.coef = 1.0;
+        e.a_buf = 0; e.a_off = s.qoff; e.lda = n;
+        e.b_buf = 1; e.b_off = go; e.ldb = k; e.K = k;
+        pt.terms.push_back(e);
+        ot.t_end = ot.d_begin = ot.d_end = (int32_t)pt.terms.size();
+        pt.outs.push_back(ot);
+        DevOut ou{};
+        ou.c_off = s.qoff;
+        ou.ldc = ou.M = n;
+        ou.N = k;
+        ou.t_begin = ou.t_end = ou.d_begin = (int32_t)pu.terms.size();
+        DevTerm u1{}, u2{};
+        u1.a_buf = 0; u1.a_off = s.qoff; u1.lda = n; u1.coef = 1.5;
+        u2.a_buf = 1; u2.a_off = s.qoff; u2.lda = n; u2.coef = -0.5;
+        pu.terms.push_back(u1);
+        pu.terms.push_back(u2);
+        ou.d_end = (int32_t)pu.terms.size();
+        pu.outs.push_back(ou);
+        go += (int64_t)k * k;
+      }
+      Bufs bq{};
+      bq.p[0] = Qbase;
+      if ((rc = run_program(ctx, pg, bq, Gq))) return rc;
+      bq.p[1] = Gq;
+      if ((rc = run_program(ctx, pt, bq, Tq))) return rc;
+      bq.p[1] = Tq;   // element-wise, in place: every output element reads only its own inputs
+      if ((rc = run_program(ctx, pu, bq, Qbase))) return rc;
+    }
     int64_t kofs = 0;
     for (auto& kv : secs) {
       Sector& s = kv.second;
@@ -830,6 +901,8 @@ tdvp_mps* new_mps(tdvp_ctx* ctx, const tdvp_model& model) {
     m->Lenv.emplace_back(new Tensor());
     m->Renv.emplace_back(new Tensor());
   }
+  for (auto* v : {&m->site, &m->Lenv, &m->Renv})
+    for (auto& t : *v) t->buf.al = ctx->alloc;
   return m;
 }
 
@@ -982,7 +1055,7 @@ int tdvp_mps_create(tdvp_ctx* ctx, const tdvp_model* model, const tdvp_bond* bon
 
 void tdvp_mps_destroy(tdvp_mps* mps) {
   // The owning context may already be gone: do not touch it.  Device memory
-  // is released with hipFree, which waits for outstanding work.
+  // goes back to the context's allocator after outstanding work has finished.
   if (!mps) return;
   (void)hipDeviceSynchronize();
   delete mps;
@@ -1023,6 +1096,7 @@ int tdvp_sweep(tdvp_ctx* ctx, tdvp_mps* m, double dt, const tdvp_trunc* tr, tdvp
   if (!ctx || !m || !tr) return set_error(ctx, TDVP_E_INVALID, "null argument");
   return guarded(ctx, [&]() -> int {
     if (m->ctx != ctx) return set_error(ctx, TDVP_E_INVALID, "MPS belongs to another context");
+    if (m->fragment) return set_error(ctx, TDVP_E_INVALID, "a split result is not a chain");
     if (tr->krylov_maxdim < 1 || tr->krylov_maxdim > 64) return set_error(ctx, TDVP_E_INVALID, "bad krylov_maxdim");
     TDVP_HIP(ctx, hipSetDevice(ctx->device));
     tdvp_sweep_info inf{};
@@ -1102,6 +1176,11 @@ int tdvp_sweep(tdvp_ctx* ctx, tdvp_mps* m, double dt, const tdvp_trunc* tr, tdvp
       inf.max_chi = std::max(inf.max_chi, m->bonds[k].chi_full());
       inf.max_chi_su2 = std::max(inf.max_chi_su2, m->bonds[k].chi_su2());
     }
+    {
+      bool bad = false;
+      if ((rc = take_bad_flag(ctx, bad))) return rc;
+      if (bad) return set_error(ctx, TDVP_E_NONFINITE, "non-finite values during the sweep");
+    }
     inf.seconds = now() - t0;
     if (info) *info = inf;
     return TDVP_OK;
@@ -1123,6 +1202,7 @@ int tdvp_mps_measure(tdvp_ctx* ctx, const tdvp_mps* m, double* sz, double* docc,
   if (!ctx || !m || !sz || !docc) return set_error(ctx, TDVP_E_INVALID, "null argument");
   return guarded(ctx, [&]() -> int {
     if (m->ctx != ctx) return set_error(ctx, TDVP_E_INVALID, "MPS belongs to another context");
+    if (m->fragment) return set_error(ctx, TDVP_E_INVALID, "a split result is not a chain");
     TDVP_HIP(ctx, hipSetDevice(ctx->device));
     const int L = m->L;
     int rc;
@@ -1149,6 +1229,7 @@ int tdvp_mps_measure(tdvp_ctx* ctx, const tdvp_mps* m, double* sz, double* docc,
       bmax = std::max<int64_t>(bmax, m->site[k - 1]->blk.n());
     }
     DeviceBuffer nbuf[2], t1, meta, part;
+    use_alloc(ctx, {&nbuf[0], &nbuf[1], &t1, &meta, &part});
     TDVP_HIP(ctx, nbuf[0].ensure(sizeof(double) * 2 * nmax));
     TDVP_HIP(ctx, nbuf[1].ensure(sizeof(double) * 2 * nmax));
     TDVP_HIP(ctx, t1.ensure(sizeof(double) * 2 * tmax));
@@ -1256,6 +1337,7 @@ int tdvp_mps_overlap(tdvp_ctx* ctx, const tdvp_mps* bra, const tdvp_mps* ket, do
     if (bra->ctx->device != ctx->device || ket->ctx->device != ctx->device)
       return set_error(ctx, TDVP_E_INVALID, "MPS on another device");
     if (bra->L != ket->L) return set_error(ctx, TDVP_E_SHAPE, "chains of different length");
+    if (bra->fragment || ket->fragment) return set_error(ctx, TDVP_E_INVALID, "a split result is not a chain");
     TDVP_HIP(ctx, hipSetDevice(ctx->device));
     const int L = ket->L;
     int rc;
@@ -1296,6 +1378,7 @@ int tdvp_mps_overlap(tdvp_ctx* ctx, const tdvp_mps* bra, const tdvp_mps* ket, do
       tmax = std::max(tmax, s);
     }
     DeviceBuffer nbuf[2], t1;
+    use_alloc(ctx, {&nbuf[0], &nbuf[1], &t1});
     TDVP_HIP(ctx, nbuf[0].ensure(sizeof(double) * 2 * nmax));
     TDVP_HIP(ctx, nbuf[1].ensure(sizeof(double) * 2 * nmax));
     TDVP_HIP(ctx, t1.ensure(sizeof(double) * 2 * tmax));
@@ -1838,6 +1921,7 @@ int tdvp_sweep1(tdvp_ctx* ctx, tdvp_mps* m, double dt, const tdvp_trunc* tr, tdv
   if (!ctx || !m || !tr) return set_error(ctx, TDVP_E_INVALID, "null argument");
   return guarded(ctx, [&]() -> int {
     if (m->ctx != ctx) return set_error(ctx, TDVP_E_INVALID, "MPS belongs to another context");
+    if (m->fragment) return set_error(ctx, TDVP_E_INVALID, "a split result is not a chain");
     if (tr->krylov_maxdim < 1 || tr->krylov_maxdim > 64) return set_error(ctx, TDVP_E_INVALID, "bad krylov_maxdim");
     TDVP_HIP(ctx, hipSetDevice(ctx->device));
     tdvp_sweep_info inf{};
@@ -1847,6 +1931,7 @@ int tdvp_sweep1(tdvp_ctx* ctx, tdvp_mps* m, double dt, const tdvp_trunc* tr, tdv
     int rc;
     Blocks x;
     DeviceBuffer xbuf, qbuf;
+    use_alloc(ctx, {&xbuf, &qbuf});
     auto timed = [&](double& acc, auto&& f) -> int {
       double s = now();
       int r = f();
@@ -1880,8 +1965,112 @@ int tdvp_sweep1(tdvp_ctx* ctx, tdvp_mps* m, double dt, const tdvp_trunc* tr, tdv
       inf.max_chi = std::max(inf.max_chi, m->bonds[k].chi_full());
       inf.max_chi_su2 = std::max(inf.max_chi_su2, m->bonds[k].chi_su2());
     }
+    {
+      bool bad = false;
+      if ((rc = take_bad_flag(ctx, bad))) return rc;
+      if (bad) return set_error(ctx, TDVP_E_NONFINITE, "non-finite values during the sweep");
+    }
     inf.seconds = now() - t0;
     if (info) *info = inf;
     return TDVP_OK;
   });
 }
+
+// ---------------------------------------------------------------------------
+// The two-site split as a call of its own (supplementary sections S2.2 and
+// S2.4: per coupled sector of the bond, an SVD of the merged tensor, whole
+// multiplets kept by discarded weight and bond-dimension cap).
+namespace tdvp {
+namespace {
+
+// Coupled sectors x of the bond between the two sites, ascending (q, 2j),
+// with the sizes of their sector matrices (rows: (a, s1), columns: (s2, b)).
+void coupled_sectors(const Bond& l, const Bond& r, std::vector<std::array<int64_t, 4>>& out) {
+  std::map<std::pair<int, int>, std::pair<int64_t, int64_t>> sec;
+  for (int a = 0; a < l.size(); ++a)
+    for (int s1 = 0; s1 < 3; ++s1)
+      for (int tj = std::abs(l.tj[a] - kLocTJ[s1]); tj <= l.tj[a] + kLocTJ[s1]; tj += 2)
+        sec[{l.q[a] + kLocQ[s1], tj}].first += l.d[a];
+  for (auto& kv : sec)
+    for (int s2 = 0; s2 < 3; ++s2)
+      for (int b = 0; b < r.size(); ++b)
+        if (kv.first.first + kLocQ[s2] == r.q[b] && triangle(kv.first.second, kLocTJ[s2], r.tj[b]))
+          kv.second.second += r.d[b];
+  out.clear();
+  for (auto& kv : sec)
+    if (kv.second.first > 0 && kv.second.second > 0)
+      out.push_back({kv.first.first, kv.first.second, kv.second.first, kv.second.second});
+}
+
+}  // namespace
+}  // namespace tdvp
+
+extern "C" {
+
+int tdvp_split_sectors(const tdvp_bond* left, const tdvp_bond* right, int32_t* nsec, int32_t* q, int32_t* tj,
+                       int64_t* rows, int64_t* cols) {
+  return guarded(nullptr, [&]() -> int {
+    if (!left || !right || !nsec) return set_error(nullptr, TDVP_E_INVALID, "null argument");
+    Bond l, r;
+    std::string err;
+    int rc = load_bond(l, left, err);
+    if (!rc) rc = load_bond(r, right, err);
+    if (rc) return set_error(nullptr, rc, err);
+    std::vector<std::array<int64_t, 4>> sec;
+    coupled_sectors(l, r, sec);
+    *nsec = (int32_t)sec.size();
+    for (size_t i = 0; i < sec.size(); ++i) {
+      if (q) q[i] = (int32_t)sec[i][0];
+      if (tj) tj[i] = (int32_t)sec[i][1];
+      if (rows) rows[i] = sec[i][2];
+      if (cols) cols[i] = sec[i][3];
+    }
+    return TDVP_OK;
+  });
+}
+
+int tdvp_split(tdvp_ctx* ctx, const tdvp_bond* left, const tdvp_bond* right, const tdvp_blocks* theta,
+               int32_t direction, const tdvp_trunc* trunc, tdvp_mps** out, double* svals, double* discarded) {
+  if (!ctx) return set_error(nullptr, TDVP_E_INVALID, "null ctx");
+  return guarded(ctx, [&]() -> int {
+    if (!left || !right || !theta || !trunc || !out) return set_error(ctx, TDVP_E_INVALID, "null argument");
+    *out = nullptr;
+    if (direction != 1 && direction != -1) return set_error(ctx, TDVP_E_INVALID, "direction must be +1 or -1");
+    if (!trunc->keep_all && !(trunc->eps_tol >= 0.0)) return set_error(ctx, TDVP_E_INVALID, "eps_tol must be >= 0");
+    if (!trunc->keep_all && trunc->chi_cap < 1) return set_error(ctx, TDVP_E_INVALID, "chi_cap must be >= 1");
+    TDVP_HIP(ctx, hipSetDevice(ctx->device));
+    tdvp_model model{0.0, 0.0, 2};
+    std::unique_ptr<tdvp_mps> m(new_mps(ctx, model));
+    m->fragment = true;
+    std::string err;
+    int rc = load_bond(m->bonds[0], left, err);
+    if (!rc) rc = load_bond(m->bonds[2], right, err);
+    Blocks th;
+    if (!rc) rc = load_center(th, theta, m->bonds[0], m->bonds[2], 2, err);
+    if (rc) return set_error(ctx, rc, err);
+    if (th.n() && !th.data) return set_error(ctx, TDVP_E_INVALID, "null device data pointer");
+    // non-finite input is reported before the split
+    if (th.size > 0) {
+      TDVP_HIP(ctx, ctx->ws_small.ensure(1 << 16));
+      double* d = (double*)ctx->ws_small.p + 1024;
+      if ((rc = vec_norm2(ctx, (const double*)th.data, th.size, d))) return rc;
+      double h[2];
+      TDVP_HIP(ctx, hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+      TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+      if (h[1] != 0.0 || !std::isfinite(h[0])) return set_error(ctx, TDVP_E_NONFINITE, "non-finite entries in theta");
+    }
+    double disc = 0.0, t_svd = 0.0;
+    int fallbacks = 0;
+    std::vector<double> sv;
+    if (th.size > 0 && (rc = split(ctx, m.get(), 1, th, direction, *trunc, disc, t_svd, fallbacks, &sv))) return rc;
+    if (svals) std::copy(sv.begin(), sv.end(), svals);
+    if (discarded) *discarded = disc;
+    bool bad = false;
+    if ((rc = take_bad_flag(ctx, bad))) return rc;
+    if (bad) return set_error(ctx, TDVP_E_NONFINITE, "non-finite values in the split");
+    *out = m.release();
+    return TDVP_OK;
+  });
+}
+
+}  // extern "C"

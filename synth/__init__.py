@@ -120,7 +120,13 @@ def block_data(keys, dims, seed, tag=0):
     return {tuple(k): complex_normal(tuple(dm), seed, tag, *k) for k, dm in zip(keys, dims)}
 
 
-def random_mps(L, chi, seed, center=1, profile_seed=None):
+def random_bonds(L, chi, seed, center=1, profile_seed=None):
+    """The bonds [(q, tj, d)] of ``random_mps`` (same arguments) without its
+    site tensors."""
+    return random_mps(L, chi, seed, center, profile_seed, bonds_only=True)
+
+
+def random_mps(L, chi, seed, center=1, profile_seed=None, bonds_only=False):
     """Random MPS of L sites in mixed-canonical form with the centre on
     ``center``: sites left of it left-canonical, right of it right-canonical.
 
@@ -173,6 +179,8 @@ def random_mps(L, chi, seed, center=1, profile_seed=None):
             if min(d, cols) > 0:
                 nb.append((q, tj, min(d, cols)))
         bonds[k] = nb
+    if bonds_only:
+        return bonds
     sites = [None] * L
     for k in range(1, L + 1):
         lb, rb = bonds[k - 1], bonds[k]

@@ -1,5 +1,6 @@
 """GPU parity of the HIP path against the CPU oracle (FP64 to 1e-12 relative,
-FP32 to 1e-5 relative), through the C ABI.
+FP32 and split-BF16 to 4e-6 relative), through the C ABI, and the error paths
+that the host can force without faulting the GPU.
 
 Sizes: bonds with a handful of sectors and degeneracies up to ~80, so blocks
 span several 64x64 tiles with ragged tails while the oracle's dense
@@ -18,7 +19,10 @@ from tests._harness import torch_stream_handle, keyed, pack, random_blocks, thet
 pytestmark = pytest.mark.gpu
 
 FP64_TOL = 1e-12
-FP32_TOL = 2e-5
+# FP32 accumulation: a few times the sqrt(K) u rounding of the longest chains
+# here (K ~ 300 summed products, u = 2^-24): 4 * 17 * 6e-8 ~ 4e-6
+FP32_TOL = 4e-6
+SPLIT = (0.01, 32)   # K-chain splitting forced down to 32-deep pieces
 
 
 def _bond(parity, seed, big=80, n_small=3):
@@ -63,10 +67,12 @@ def _heff_case(site, nsites, seed):
     return left, right, bl, br, (xk, xo, xt, xd, xs), (lk, lo, lt, ld, Ls), (rk, ro, rt, rd, Rs)
 
 
-@pytest.mark.parametrize("site,prec", [(3, T.FP64), (4, T.FP64), (3, T.FP32), (3, T.BF16X3), (4, T.BF16X3)])
-def test_heff_two_site(ctx, site, prec):
+@pytest.mark.parametrize("site,prec,split", [(3, T.FP64, False), (4, T.FP64, False), (3, T.FP32, False),
+                                             (3, T.BF16X3, False), (4, T.BF16X3, False), (3, T.FP64, True),
+                                             (4, T.FP64, True), (3, T.FP32, True), (4, T.BF16X3, True)])
+def test_heff_two_site(ctx, site, prec, split):
     t, U = 1.0, 4.0
-    print(f"heff2 site={site} prec={prec}", flush=True)
+    print(f"heff2 site={site} prec={prec} split={split}", flush=True)
     left, right, bl, br, X, Lx, Rx = _heff_case(site, 2, 100 + site)
     xk, xo, xt, xd, xs = X
     lk, lo, lt, ld, Ls = Lx
@@ -77,12 +83,16 @@ def test_heff_two_site(ctx, site, prec):
     R_d = dev(pack(Rs, ro, rt))
     model = T.Model(8, t, U)
     ctx.set_precision(prec)
+    if split:
+        ctx.set_split(*SPLIT)
     try:
         ctx.heff_apply(model, site, 2, bl, br, T.Blocks(lk, lo, L_d.data_ptr(), lt),
                        T.Blocks(rk, ro, R_d.data_ptr(), rt), T.Blocks(xk, xo, x_d.data_ptr(), xt),
                        T.Blocks(xk, xo, y_d.data_ptr(), xt))
+        ctx.synchronize()
     finally:
         ctx.set_precision(T.FP64)
+        ctx.set_split()
     ys = unpack(host(y_d), xo, xd)
     ref = D.heff2(R.expand_env(env_dict(lk, Ls), left), R.expand_env(env_dict(rk, Rs), right),
                   R.expand_theta(theta_dict(xk, xs), left, right, site), site, t, U)
@@ -112,11 +122,12 @@ def test_heff_one_site(ctx):
     assert np.abs(got - ref).max() / np.abs(ref).max() < FP64_TOL
 
 
+@pytest.mark.parametrize("split", [False, True])
 @pytest.mark.parametrize("prec", [T.FP64, T.FP32, T.BF16X3])
 @pytest.mark.parametrize("direction", [1, -1])
-def test_env_update(ctx, direction, prec):
+def test_env_update(ctx, direction, prec, split):
     t, U, site = 1.0, 4.0, 4
-    print(f"env update direction={direction} prec={prec}", flush=True)
+    print(f"env update direction={direction} prec={prec} split={split}", flush=True)
     b_site_left = _bond((site - 1) % 2, 300)     # bond site-1
     b_site_right = _bond(site % 2, 301)          # bond site
     if direction > 0:
@@ -134,12 +145,16 @@ def test_env_update(ctx, direction, prec):
     e_d = dev(pack(Es, eo, et))
     o_d = torch.zeros(max(ot, 1), dtype=torch.complex128, device="cuda")
     ctx.set_precision(prec)
+    if split:
+        ctx.set_split(*SPLIT)
     try:
         ctx.env_update(T.Model(8, t, U), site, direction, bi, bo, T.Blocks(ek, eo, e_d.data_ptr(), et),
                        T.Blocks(tk, to, t_d.data_ptr(), tt), T.Blocks(ok, oo, o_d.data_ptr(), ot))
+        ctx.synchronize()
         outs = unpack(host(o_d), oo, od)
     finally:
         ctx.set_precision(T.FP64)
+        ctx.set_split()
     Ef = R.expand_env(env_dict(ek, Es), bin_)
     if direction > 0:
         ref = D.left_env_update(Ef, R.expand_site("A", theta_dict(tk, ts), bin_, bout, site), site, t, U)
@@ -147,7 +162,7 @@ def test_env_update(ctx, direction, prec):
         ref = D.right_env_update(Ef, R.expand_site("B", theta_dict(tk, ts), bout, bin_, site), site, t, U)
     got = R.expand_env(env_dict(ok, outs), bout)
     scale = max(np.abs(ref[w]).max() for w in range(3))
-    tol = FP64_TOL if prec == T.FP64 else 2e-5   # FP32 accumulation: ~1e-6 relative at these depths
+    tol = FP64_TOL if prec == T.FP64 else FP32_TOL
     err = max(np.abs(got[w] - ref[w]).max() for w in range(3)) / scale
     print(f"  max error relative to the largest entry: {err:.2e}", flush=True)
     assert err < tol
@@ -293,3 +308,140 @@ def test_krylov_graph_replay_matches_direct_launches(ctx, prec):
         ctx.set_precision(T.FP64)
     assert np.array_equal(out[False][0], out[True][0])
     assert out[False][1] == out[True][1] and out[False][2] == out[True][2]
+
+
+# --------------------------------------------------------------------------
+# Error paths forced from the host (every kernel still runs to completion)
+# --------------------------------------------------------------------------
+def _apply_case(ctx, seed, poison=None):
+    """Two-site apply on random blocks; poison = (index, value) planted in x."""
+    left, right, bl, br, X, Lx, Rx = _heff_case(3, 2, seed)
+    xk, xo, xt, xd, xs = X
+    lk, lo, lt, ld, Ls = Lx
+    rk, ro, rt, rd, Rs = Rx
+    xb = pack(xs, xo, xt)
+    if poison is not None:
+        xb[poison[0]] = poison[1]
+    x_d, L_d, R_d = dev(xb), dev(pack(Ls, lo, lt)), dev(pack(Rs, ro, rt))
+    y_d = torch.zeros_like(x_d)
+    ctx.heff_apply(T.Model(8), 3, 2, bl, br, T.Blocks(lk, lo, L_d.data_ptr(), lt),
+                   T.Blocks(rk, ro, R_d.data_ptr(), rt), T.Blocks(xk, xo, x_d.data_ptr(), xt),
+                   T.Blocks(xk, xo, y_d.data_ptr(), xt))
+    return (x_d, L_d, R_d, y_d), (bl, br, xk, xo, xt, lk, lo, lt, rk, ro, rt)
+
+
+@pytest.mark.parametrize("value", [float("nan"), float("inf")])
+def test_nonfinite_input_surfaces_at_the_next_synchronisation(ctx, value):
+    """A NaN or Inf in the input of an apply makes the next synchronising call
+    return NONFINITE (-7), once: the flag is cleared and later clean work
+    synchronises normally."""
+    print(f"non-finite apply input {value}", flush=True)
+    keep, _ = _apply_case(ctx, 410, poison=(17, value))
+    with pytest.raises(T.TdvpError) as e:
+        ctx.synchronize()
+    assert e.value.code == -7
+    keep, _ = _apply_case(ctx, 411)
+    ctx.synchronize()
+    assert np.isfinite(host(keep[3])).all()
+
+
+def test_nonfinite_environment_in_env_update(ctx):
+    print("non-finite environment in env update", flush=True)
+    site = 4
+    bin_, bout = _bond((site - 1) % 2, 300), _bond(site % 2, 301)
+    bi, bo = T.Bond(bin_), T.Bond(bout)
+    tk, to, tt, td = T.center_layout(bi, bo, 1)
+    ek, eo, et, ed = T.env_layout(bi)
+    ok, oo, ot, od = T.env_layout(bo)
+    eb = pack(keyed(ek, random_blocks(ek, ed, 303)), eo, et)
+    eb[et // 2] = complex(float("inf"), 0.0)
+    t_d, e_d = dev(pack(keyed(tk, random_blocks(tk, td, 302)), to, tt)), dev(eb)
+    o_d = torch.zeros(max(ot, 1), dtype=torch.complex128, device="cuda")
+    ctx.env_update(T.Model(8), site, 1, bi, bo, T.Blocks(ek, eo, e_d.data_ptr(), et),
+                   T.Blocks(tk, to, t_d.data_ptr(), tt), T.Blocks(ok, oo, o_d.data_ptr(), ot))
+    with pytest.raises(T.TdvpError) as e:
+        ctx.synchronize()
+    assert e.value.code == -7
+    ctx.synchronize()
+
+
+def test_krylov_nonfinite_start_vector(ctx):
+    print("krylov with a NaN in the start vector", flush=True)
+    keep, (bl, br, xk, xo, xt, lk, lo, lt, rk, ro, rt) = _apply_case(ctx, 412)
+    ctx.synchronize()
+    x_d, L_d, R_d, _ = keep
+    x_d[5] = complex(float("nan"), 0.0)
+    rc, _ = ctx.krylov_expm(T.Model(8), 3, 2, bl, br, T.Blocks(lk, lo, L_d.data_ptr(), lt),
+                            T.Blocks(rk, ro, R_d.data_ptr(), rt), T.Blocks(xk, xo, x_d.data_ptr(), xt),
+                            -0.025j, tol=1e-12, maxdim=10, check=False)
+    assert rc == -7
+    ctx.synchronize()
+
+
+def test_krylov_noconv_leaves_the_best_iterate(ctx):
+    """maxdim = 2 with tol 1e-12 cannot converge: NOCONV (-6), and x holds the
+    two-dimensional Krylov approximation, as the oracle's Lanczos gives it."""
+    L, site, t, U = 6, 3, 1.0, 4.0
+    print("krylov NOCONV at maxdim 2", flush=True)
+    bonds, sites, model, (Lenv, Ld), (Renv, Rd) = _physical_envs(ctx, L, site, 2, 7, t, U, 24)
+    left, right = bonds[site - 1], bonds[site + 1]
+    bl, br = T.Bond(left), T.Bond(right)
+    xk, xo, xt, xd = T.center_layout(bl, br, 2)
+    xs = keyed(xk, random_blocks(xk, xd, 57))
+    nrm = np.sqrt(sum(np.sum(np.abs(a) ** 2) for a in xs))
+    xs = [a / nrm for a in xs]
+    x_d = dev(pack(xs, xo, xt))
+    rc, info = ctx.krylov_expm(model, site, 2, bl, br, T.Blocks(Ld[0], Ld[1], Lenv.data_ptr(), Ld[2]),
+                               T.Blocks(Rd[0], Rd[1], Renv.data_ptr(), Rd[2]),
+                               T.Blocks(xk, xo, x_d.data_ptr(), xt), -0.3j, tol=1e-12, maxdim=2, check=False)
+    assert rc == -6 and info["iters"] == 2 and not info["converged"]
+    ys = unpack(host(x_d), xo, xd)
+    full = [R.expand_site("A" if k < site else ("C" if k == site else "B"), sites[k - 1], bonds[k - 1],
+                          bonds[k], k) for k in range(1, L + 1)]
+    Lf = D.empty_env()
+    for k in range(1, site):
+        Lf = D.left_env_update(Lf, full[k - 1], k, t, U)
+    Rf = D.empty_env()
+    for k in range(L, site + 1, -1):
+        Rf = D.right_env_update(Rf, full[k - 1], k, t, U)
+    v = R.expand_theta(theta_dict(xk, xs), left, right, site)
+    ref, rinfo = D.lanczos_expm(lambda z: D.heff2(Lf, Rf, z, site, t, U), v, -0.3j, tol=1e-12, maxdim=2)
+    assert rinfo["iters"] == 2 and not rinfo["converged"]
+    got = R.expand_theta(theta_dict(xk, ys), left, right, site)
+    assert np.abs(got - ref).max() < 1e-12
+
+
+def test_nomem_from_a_capped_allocator():
+    """A device allocator that refuses large requests makes the call that
+    needs the memory return NOMEM (-4); the context stays usable."""
+    import ctypes
+    print("capped allocator: NOMEM", flush=True)
+    stream = torch_stream_handle()
+    cap = 4 << 20
+    refused = []
+
+    def alloc(n, user):
+        if n > cap:
+            refused.append(n)
+            return None
+        return torch.cuda.caching_allocator_alloc(int(n), 0, int(stream))
+
+    def free(p, user):
+        torch.cuda.caching_allocator_delete(int(p))
+
+    cbs = (T._ALLOC_FN(alloc), T._FREE_FN(free))
+    c = T.Context(0, stream=stream, allocator=cbs)
+    try:
+        keep, (bl, br, xk, xo, xt, lk, lo, lt, rk, ro, rt) = _apply_case(c, 413)
+        c.synchronize()
+        x_d, L_d, R_d, _ = keep
+        assert 42 * 16 * xt > cap
+        rc, _ = c.krylov_expm(T.Model(8), 3, 2, bl, br, T.Blocks(lk, lo, L_d.data_ptr(), lt),
+                              T.Blocks(rk, ro, R_d.data_ptr(), rt), T.Blocks(xk, xo, x_d.data_ptr(), xt),
+                              -0.025j, tol=1e-12, maxdim=40, check=False)
+        assert rc == -4 and refused
+        keep, _ = _apply_case(c, 414)    # small requests still succeed
+        c.synchronize()
+        assert np.isfinite(host(keep[3])).all()
+    finally:
+        c.close()

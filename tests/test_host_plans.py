@@ -168,3 +168,17 @@ def test_invalid_inputs_return_errors():
     with pytest.raises(T.TdvpError) as e:
         T.heff_plan(model, 8, 2, left, right, L_, R_, T.Blocks(xk, xo, size=xt))
     assert e.value.code == -1
+
+
+def test_split_sectors_match_the_oracle_sector_matrices():
+    """The coupled sectors the split reports (and orders its singular values
+    by) are those of the oracle's per-sector view of a two-site tensor, with
+    the same matrix sizes."""
+    from oracle import reduced as R
+    left = synth.sector_profile(60, 3, parity=1)
+    right = synth.sector_profile(60, 4, parity=1)
+    got = T.split_sectors(T.Bond(left), T.Bond(right))
+    ref = R.sector_matrices({}, left, right)
+    assert [(q, tj) for q, tj, _, _ in got] == sorted(ref)
+    for q, tj, r, c in got:
+        assert ref[(q, tj)][0].shape == (r, c)

@@ -479,8 +479,9 @@ def test_synthetic_profile_shape():
 
 
 def test_sector_restricted_block_equals_full_dense():
-    """The restricted evaluation of one output block equals that block of the
-    full dense effective Hamiltonian (checked by expanding the block back)."""
+    """The restricted evaluation of one output block, directly and by
+    inclusion-exclusion over three smaller restrictions, equals that block of
+    the full dense effective Hamiltonian (checked by expanding the block back)."""
     from oracle import sampled as S
     site, t, U = 3, 1.0, 4.0
     left = synth.sector_profile(40, 71, parity=0)
@@ -512,6 +513,7 @@ def test_sector_restricted_block_equals_full_dense():
     for j in rng.choice(len(keys), size=6, replace=False):
         key = keys[j]
         blk, _ = S.heff2_block(left, right, Lenv, Renv, theta, key, site, t, U)
+        cross = S.heff2_block_cross(left, right, Lenv, Renv, theta, key, site, t, U)
         ia, ib = key[0], key[4]
         ref_blk = np.zeros_like(blk)
         for x in range(left[ia][2]):
@@ -521,6 +523,7 @@ def test_sector_restricted_block_equals_full_dense():
                 tree = R.expand_theta({key: e}, left, right, site)
                 ref_blk[x, y] = np.vdot(tree, full)
         assert np.abs(blk - ref_blk).max() < 1e-12 * max(1.0, np.abs(ref_blk).max())
+        assert np.abs(cross - ref_blk).max() < 1e-12 * max(1.0, np.abs(ref_blk).max())
 
 
 def _theta_keys(left, right):
