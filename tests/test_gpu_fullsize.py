@@ -192,16 +192,19 @@ def test_fullsize_longest_k_chain_block(p4096):
 
 
 def test_fullsize_split_k_chains_match_the_oracle(p16384):
-    """chi = 16384 (>= 1e11 flops per apply): the default launch splits the
-    longest K chains into pieces summed by a second kernel.  The blocks whose
-    bits differ from an unsplit launch are the split ones; there must be some,
-    the two launches must agree to rounding, and the cheapest split block with
-    a long chain must match the oracle."""
+    """chi = 16384: K chains split on request (tdvp_ctx_set_split with a cap of
+    0.1 x the mean work per resident workgroup, pieces >= 64 deep) and summed by
+    the second kernel.  The default rule splits no tile at this shape (no tile
+    reaches its cap), so the split launch is forced here.  The blocks whose bits
+    differ from an unsplit launch are the split ones; there must be some, the
+    two launches must agree to rounding, and the cheapest split block with a
+    long chain must match the oracle."""
     p = p16384
     ctx = p["ctx"]
-    y_split = _apply(p, p["dev"]["x"])
-    ctx.set_split(0.0, 128)
+    ctx.set_split(0.1, 64)
     try:
+        y_split = _apply(p, p["dev"]["x"])
+        ctx.set_split(0.0, 128)
         y_plain = _apply(p, p["dev"]["x"])
     finally:
         ctx.set_split()
