@@ -53,7 +53,8 @@
  * Device memory.  Every device buffer the library itself needs (workspaces,
  * the Krylov basis, program arrays, the blocks of a library-owned MPS) comes
  * from the allocator given to tdvp_ctx_create (dev_alloc / dev_free with the
- * caller's `user` pointer), or from hipMalloc / hipFree when none is given.
+ * caller's `user` pointer), or from hipMalloc / hipFree when none is given
+ * (tdvp_env_update_noalloc excepted: it uses a static device array).
  * The library may release a buffer while work that used it is still queued
  * on the context stream: the allocator must order reuse on that stream (a
  * stream-ordered caching allocator bound to the context stream, such as
@@ -309,6 +310,25 @@ int tdvp_tridiag_expm(int32_t n, const double* alpha, const double* beta, double
 int tdvp_env_update(tdvp_ctx* ctx, const tdvp_model* model, int32_t site, int32_t direction,
                     const tdvp_bond* bond_in, const tdvp_bond* bond_out, const tdvp_blocks* env_in,
                     const tdvp_blocks* tensor, tdvp_blocks* env_out);
+/* Allocation-free variant, for callers that cannot allocate device memory
+ * (code under stream capture, serving loops that forbid hipMalloc): the same
+ * arguments, layouts, results (bit-identical for the same precision and
+ * inputs) and errors as tdvp_env_update, but every device buffer beyond the
+ * caller's inputs and outputs -- the stage-1 products E . op(ket), the
+ * program arrays, the shifts of reduced-precision launches, the partial sums
+ * of split K chains -- lives in one static device array of 64 MiB per device,
+ * held from the first context created on that device until the process ends.
+ * The call allocates no device or pinned host memory (the program arrays are
+ * copied from host memory kept by the context, on the context stream).
+ * Limits: stage-1 products plus partial sums up to 60 MiB (33 MB at a
+ * chi = 4096 bond with Table-S2-shaped sectors), program arrays up to about
+ * 4 MiB; beyond them TDVP_E_NOMEM with nothing launched.  Every call on a
+ * device shares its array and overwrites it: calls that overlap on one device
+ * (other contexts, streams or threads) race.  Split-BF16 products need the
+ * all-64x64 tiling (the default tile mode).  Does not synchronise. */
+int tdvp_env_update_noalloc(tdvp_ctx* ctx, const tdvp_model* model, int32_t site, int32_t direction,
+                            const tdvp_bond* bond_in, const tdvp_bond* bond_out, const tdvp_blocks* env_in,
+                            const tdvp_blocks* tensor, tdvp_blocks* env_out);
 /* Host-side plan of the same update (no GPU): terms as tdvp_env_term, flop
  * count as tdvp_heff_plan.  Two-call pattern on *nterms. */
 int tdvp_env_plan(const tdvp_model* model, int32_t site, int32_t direction, const tdvp_bond* bond_in,

@@ -94,6 +94,7 @@ def _load():
         "tdvp_krylov_expm": [P, P, I32, I32, P, P, P, P, P, D, D, D, I32, P],
         "tdvp_tridiag_expm": [I32, P, P, D, D, D, P],
         "tdvp_env_update": [P, P, I32, I32, P, P, P, P, P],
+        "tdvp_env_update_noalloc": [P, P, I32, I32, P, P, P, P, P],
         "tdvp_env_plan": [P, I32, I32, P, P, P, P, P, P, P, P],
         "tdvp_mps_create": [P, P, P, P, P],
         "tdvp_mps_create_neel": [P, P, I32, P],
@@ -370,6 +371,10 @@ class Context:
     def env_update(self, model, site, direction, bond_in, bond_out, env_in, tensor, env_out):
         _check(lib.tdvp_env_update(self.h, model.ref, site, direction, bond_in.ref, bond_out.ref, env_in.ref,
                                    tensor.ref, env_out.ref), self.h)
+
+    def env_update_noalloc(self, model, site, direction, bond_in, bond_out, env_in, tensor, env_out):
+        _check(lib.tdvp_env_update_noalloc(self.h, model.ref, site, direction, bond_in.ref, bond_out.ref,
+                                           env_in.ref, tensor.ref, env_out.ref), self.h)
 
 
 class MPS:

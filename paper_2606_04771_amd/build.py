@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtdvp.so")
 SOURCES = ["symm.cpp", "plan.cpp", "common.cpp", "capi_host.cpp", "tridiag.cpp", "capi_dev.cpp",
-           "krylov.cpp", "sweep.cpp", "gemm.hip", "vec.hip"]
+           "krylov.cpp", "sweep.cpp", "gemm.hip", "vec.hip", "noalloc.hip"]
 # host sources that launch kernels or use HIP device types are compiled as HIP
 HIP_CPP = ("capi_dev.cpp", "krylov.cpp", "sweep.cpp")
 ARCH = "gfx950"

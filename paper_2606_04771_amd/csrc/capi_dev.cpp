@@ -177,12 +177,9 @@ std::shared_ptr<Program> heff_program(tdvp_ctx* ctx, const tdvp_model& m, int si
 // products E . op(ket) into scratch (buffer 3), stage 2 contracts them (or the
 // ket directly) with op(bra)^ into the output environment.
 // Buffers: 1 = env_in, 2 = tensor, 3 = scratch.
-struct EnvPrograms {
-  std::shared_ptr<Program> s1, s2;
-  int64_t scratch = 0;
-};
+namespace {
 
-EnvPrograms env_programs(tdvp_ctx* ctx, const tdvp_model& m, int site, int dir, const EnvInputs& in, int& rc) {
+Hasher env_hash(tdvp_ctx* ctx, const tdvp_model& m, int site, int dir, const EnvInputs& in) {
   Hasher hs;
   hs.add(2);
   hs.addd(m.t);
@@ -196,16 +193,14 @@ EnvPrograms env_programs(tdvp_ctx* ctx, const tdvp_model& m, int site, int dir, 
   hs.blocks(in.eout);
   hs.addd(ctx->split_alpha);
   hs.add((uint64_t)ctx->split_kmin);
-  rc = TDVP_OK;
-  EnvPrograms ep;
-  auto p1 = cache_get(ctx, hs.h, hs.sig);
-  auto p2 = cache_get(ctx, hs.h ^ 0x5555555555555555ull, hs.sig);
-  if (p1 && p2) {
-    ep.s1 = p1;
-    ep.s2 = p2;
-    ep.scratch = p1->aux;
-    return ep;
-  }
+  return hs;
+}
+
+constexpr uint64_t kStage2Key = 0x5555555555555555ull;
+
+// Host side of the two stages (term lists, tiles); nothing on the device.
+EnvPrograms build_env_programs(tdvp_ctx* ctx, const tdvp_model& m, int site, int dir, const EnvInputs& in,
+                               const Hasher& hs) {
   std::vector<ETerm> terms;
   double flops = 0;
   plan_env(m, site, dir, in.bin, in.bout, in.ein, in.ten, in.eout, terms, flops);
@@ -282,14 +277,55 @@ EnvPrograms env_programs(tdvp_ctx* ctx, const tdvp_model& m, int site, int dir, 
     s2->outs.push_back(ob);
   }
   s2->finalize();
-  rc = upload(ctx, *s1);
-  if (!rc) rc = upload(ctx, *s2);
-  if (rc) return ep;
-  cache_put(ctx, hs.h, s1);
-  cache_put(ctx, hs.h ^ 0x5555555555555555ull, s2);
+  EnvPrograms ep;
   ep.s1 = s1;
   ep.s2 = s2;
   ep.scratch = so;
+  return ep;
+}
+
+}  // namespace
+
+EnvPrograms env_programs(tdvp_ctx* ctx, const tdvp_model& m, int site, int dir, const EnvInputs& in, int& rc) {
+  const Hasher hs = env_hash(ctx, m, site, dir, in);
+  rc = TDVP_OK;
+  EnvPrograms ep;
+  auto p1 = cache_get(ctx, hs.h, hs.sig);
+  auto p2 = cache_get(ctx, hs.h ^ kStage2Key, hs.sig);
+  if (p1 && p2) {
+    ep.s1 = p1;
+    ep.s2 = p2;
+    ep.scratch = p1->aux;
+    return ep;
+  }
+  ep = build_env_programs(ctx, m, site, dir, in, hs);
+  rc = upload(ctx, *ep.s1);
+  if (!rc) rc = upload(ctx, *ep.s2);
+  if (rc) return EnvPrograms{};
+  cache_put(ctx, hs.h, ep.s1);
+  cache_put(ctx, hs.h ^ kStage2Key, ep.s2);
+  return ep;
+}
+
+EnvPrograms env_programs_host(tdvp_ctx* ctx, const tdvp_model& m, int site, int dir, const EnvInputs& in) {
+  const Hasher hs = env_hash(ctx, m, site, dir, in);
+  EnvPrograms ep;
+  // the device cache holds the same host description of uploaded programs
+  auto p1 = cache_get(ctx, hs.h, hs.sig);
+  auto p2 = cache_get(ctx, hs.h ^ kStage2Key, hs.sig);
+  if (!(p1 && p2)) {
+    p1 = cache_get(ctx->host_cache, hs.h, hs.sig);
+    p2 = cache_get(ctx->host_cache, hs.h ^ kStage2Key, hs.sig);
+  }
+  if (p1 && p2) {
+    ep.s1 = p1;
+    ep.s2 = p2;
+    ep.scratch = p1->aux;
+    return ep;
+  }
+  ep = build_env_programs(ctx, m, site, dir, in, hs);
+  cache_put(ctx->host_cache, hs.h, ep.s1);
+  cache_put(ctx->host_cache, hs.h ^ kStage2Key, ep.s2);
   return ep;
 }
 
@@ -369,6 +405,19 @@ int tdvp_ctx_create(tdvp_ctx** out, int32_t device, void* hip_stream, int32_t pr
       return set_error(nullptr, e == hipErrorOutOfMemory ? TDVP_E_NOMEM : TDVP_E_HIP, "context flag buffer");
     }
     for (auto& ev : c->ev) (void)hipEventCreate(&ev);
+    // device address of the static scratch of the allocation-free entry point
+    // (once per device, with the device current) and the event that orders
+    // reuse of its host staging
+    if (int rc = noalloc_init(c)) {
+      std::string msg = c->err;
+      for (auto& ev : c->ev)
+        if (ev) (void)hipEventDestroy(ev);
+      if (c->own_stream) (void)hipStreamDestroy(c->stream);
+      if (c->host_small) (void)hipHostFree(c->host_small);
+      delete c;
+      return set_error(nullptr, rc, msg);
+    }
+    (void)hipEventCreateWithFlags(&c->na_copied, hipEventDisableTiming);
     const char* gr = std::getenv("TDVP_GRAPH");
     c->graphs = !(gr && std::atoi(gr) == 0);
     const char* v = std::getenv("TDVP_VERBOSE");
@@ -394,6 +443,7 @@ void tdvp_ctx_destroy(tdvp_ctx* ctx) {
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->host_small) (void)hipHostFree(ctx->host_small);
   if (ctx->upload_done) (void)hipEventDestroy(ctx->upload_done);
+  if (ctx->na_copied) (void)hipEventDestroy(ctx->na_copied);
   for (auto& ev : ctx->ev)
     if (ev) (void)hipEventDestroy(ev);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);

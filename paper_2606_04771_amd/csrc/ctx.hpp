@@ -195,6 +195,12 @@ struct tdvp_ctx {
   // program cache (structural hash -> program; a hit is confirmed by
   // comparing the full structural signature the hash was taken of)
   std::list<std::pair<uint64_t, std::shared_ptr<tdvp::Program>>> cache;
+  // host-only programs of the allocation-free entry point (never uploaded:
+  // their arrays are copied into the static scratch at every call)
+  std::list<std::pair<uint64_t, std::shared_ptr<tdvp::Program>>> host_cache;
+  void* scratch = nullptr;   // device address of the static scratch on `device`
+  std::vector<char> na_stage;          // host staging of its program arrays
+  hipEvent_t na_copied = nullptr;      // recorded after the last copy out of na_stage
   hipEvent_t ev[8] = {};
   std::shared_ptr<const tdvp::Allocator> alloc = std::make_shared<tdvp::Allocator>();
   // splitting of long K chains in effective-Hamiltonian programs
@@ -219,6 +225,10 @@ int upload(tdvp_ctx* ctx, Program& p);
 // Cache lookup by hash; a hit counts only if the stored signature equals sig.
 std::shared_ptr<Program> cache_get(tdvp_ctx* ctx, uint64_t key, const std::vector<uint64_t>& sig);
 void cache_put(tdvp_ctx* ctx, uint64_t key, std::shared_ptr<Program> p);
+// The same on another list (programs kept on the host only).
+typedef std::list<std::pair<uint64_t, std::shared_ptr<Program>>> ProgCache;
+std::shared_ptr<Program> cache_get(ProgCache& c, uint64_t key, const std::vector<uint64_t>& sig);
+void cache_put(ProgCache& c, uint64_t key, std::shared_ptr<Program> p);
 // Device flag of non-finite outputs (allocated on first use, zeroed).
 int bad_flag(tdvp_ctx* ctx, int** flag);
 // Reads and clears the flag (synchronises the context stream).
@@ -233,6 +243,27 @@ inline void use_alloc(tdvp_ctx* ctx, std::initializer_list<DeviceBuffer*> bufs) 
 int launch_gemm(tdvp_ctx* ctx, const Program& p, const Bufs& bufs, double* C, int precision);
 // The same with the program's active tiling, no autotuning.
 int launch_gemm_tiles(tdvp_ctx* ctx, const Program& p, const Bufs& bufs, double* C, int precision);
+// Device copies of a program's arrays (the program's own after upload(), or
+// copies the caller placed elsewhere).
+struct DevArrays {
+  const DevTerm* terms;
+  const DevOut* outs;
+  const DevRed* reds;
+  const int64_t* shift_meta;
+};
+// Workspaces of a launch given by the caller instead of the context's
+// grow-only buffers: partial slots of split chains (partial_slot_bytes) and
+// the shifts of reduced-precision launches (shift_bytes).
+struct LaunchWs {
+  double2* part;
+  double* shift;
+};
+size_t partial_slot_bytes(int nslots);
+inline size_t shift_bytes(int nblocks) { return sizeof(double) * 2 * (size_t)(nblocks + 1); }
+// Active tiling of p (d_tiles: its device copy) on the given arrays and
+// workspaces; allocates nothing.
+int launch_gemm_ws(tdvp_ctx* ctx, const Program& p, const DevArrays& a, const DevTile* d_tiles, const Bufs& bufs,
+                   double* C, int precision, const LaunchWs& ws);
 
 // Lanczos vector kernels (complex128 vectors of n elements).
 int vec_dots(tdvp_ctx* ctx, const double* V, int64_t stride, int nv, const double* w, int64_t n,

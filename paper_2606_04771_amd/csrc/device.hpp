@@ -18,6 +18,21 @@ std::shared_ptr<Program> heff_program(tdvp_ctx* ctx, const tdvp_model& m, int si
 int env_update_dev(tdvp_ctx* ctx, const tdvp_model& m, int site, int dir, const EnvInputs& in,
                    double* flops = nullptr);
 
+// The two grouped-GEMM stages of an environment update; scratch = complex
+// elements of the stage-1 products.
+struct EnvPrograms {
+  std::shared_ptr<Program> s1, s2;
+  int64_t scratch = 0;
+};
+// Uploaded and cached (device memory from the context's allocator).
+EnvPrograms env_programs(tdvp_ctx* ctx, const tdvp_model& m, int site, int dir, const EnvInputs& in, int& rc);
+// Host description only (cached on the host; no device memory touched).
+EnvPrograms env_programs_host(tdvp_ctx* ctx, const tdvp_model& m, int site, int dir, const EnvInputs& in);
+
+// Address of the static scratch on the current device (taken once per device
+// by the first context created there).  Errors: HIP.
+int noalloc_init(tdvp_ctx* ctx);
+
 struct KrylovResult {
   int iters = 0;
   int converged = 0;

@@ -572,18 +572,18 @@ __global__ __launch_bounds__(64 * WM * WN) void block_gemm(Bufs bufs, double* __
 
 template <typename T, int WM, int WN>
 void launch_one(tdvp_ctx* ctx, bool heff, int ntiles, const Bufs& bufs, double* C, double2* part,
-                const DevTile* tiles, const Program& p) {
+                const DevTile* tiles, const DevArrays& a) {
   const dim3 g(ntiles), b(64 * WM * WN);
   if (bufs.shift) {
     if (heff)
-      hipLaunchKernelGGL((heff_gemm<T, WM, WN, true>), g, b, 0, ctx->stream, bufs, C, part, tiles, p.d_outs, p.d_terms);
+      hipLaunchKernelGGL((heff_gemm<T, WM, WN, true>), g, b, 0, ctx->stream, bufs, C, part, tiles, a.outs, a.terms);
     else
-      hipLaunchKernelGGL((block_gemm<T, WM, WN, true>), g, b, 0, ctx->stream, bufs, C, part, tiles, p.d_outs, p.d_terms);
+      hipLaunchKernelGGL((block_gemm<T, WM, WN, true>), g, b, 0, ctx->stream, bufs, C, part, tiles, a.outs, a.terms);
   } else {
     if (heff)
-      hipLaunchKernelGGL((heff_gemm<T, WM, WN, false>), g, b, 0, ctx->stream, bufs, C, part, tiles, p.d_outs, p.d_terms);
+      hipLaunchKernelGGL((heff_gemm<T, WM, WN, false>), g, b, 0, ctx->stream, bufs, C, part, tiles, a.outs, a.terms);
     else
-      hipLaunchKernelGGL((block_gemm<T, WM, WN, false>), g, b, 0, ctx->stream, bufs, C, part, tiles, p.d_outs, p.d_terms);
+      hipLaunchKernelGGL((block_gemm<T, WM, WN, false>), g, b, 0, ctx->stream, bufs, C, part, tiles, a.outs, a.terms);
   }
 }
 
@@ -964,23 +964,30 @@ int upload(tdvp_ctx* ctx, Program& p) {
   return TDVP_OK;
 }
 
-std::shared_ptr<Program> cache_get(tdvp_ctx* ctx, uint64_t key, const std::vector<uint64_t>& sig) {
-  for (auto it = ctx->cache.begin(); it != ctx->cache.end(); ++it)
+std::shared_ptr<Program> cache_get(ProgCache& c, uint64_t key, const std::vector<uint64_t>& sig) {
+  for (auto it = c.begin(); it != c.end(); ++it)
     if (it->first == key && it->second->sig == sig) {
       auto p = it->second;
-      ctx->cache.splice(ctx->cache.begin(), ctx->cache, it);
+      c.splice(c.begin(), c, it);
       return p;
     }
   return nullptr;
 }
 
-void cache_put(tdvp_ctx* ctx, uint64_t key, std::shared_ptr<Program> p) {
-  ctx->cache.emplace_front(key, std::move(p));
-  while (ctx->cache.size() > 24) ctx->cache.pop_back();
+void cache_put(ProgCache& c, uint64_t key, std::shared_ptr<Program> p) {
+  c.emplace_front(key, std::move(p));
+  while (c.size() > 24) c.pop_back();
 }
 
-static int launch_core(tdvp_ctx* ctx, const Program& p, int ntiles, int n64, const DevTile* d_tiles,
-                       const Bufs& bufs, double* C, int precision);
+std::shared_ptr<Program> cache_get(tdvp_ctx* ctx, uint64_t key, const std::vector<uint64_t>& sig) {
+  return cache_get(ctx->cache, key, sig);
+}
+
+void cache_put(tdvp_ctx* ctx, uint64_t key, std::shared_ptr<Program> p) { cache_put(ctx->cache, key, std::move(p)); }
+
+static int launch_core(tdvp_ctx* ctx, const Program& p, const DevArrays& a, int ntiles, int n64,
+                       const DevTile* d_tiles, const Bufs& bufs, double* C, int precision, const LaunchWs* ws);
+static DevArrays arrays_of(const Program& p) { return DevArrays{p.d_terms, p.d_outs, p.d_reds, p.d_shift_meta}; }
 
 // Autotuner step: which tiling this launch uses, with its events.  Every
 // candidate is launched kTuneRounds times, each bracketed by events; at the
@@ -1055,7 +1062,7 @@ static int launch_per_block(tdvp_ctx* ctx, const Program& p, const Bufs& bufs, d
   const DevTile* base = (const DevTile*)p.d_by_out;
   for (size_t b = 0; b + 1 < p.blk_begin.size(); ++b) {
     const int n = p.blk_begin[b + 1] - p.blk_begin[b];
-    int rc = launch_core(ctx, p, n, n, base + p.blk_begin[b], bufs, C, precision);
+    int rc = launch_core(ctx, p, arrays_of(p), n, n, base + p.blk_begin[b], bufs, C, precision, nullptr);
     if (rc) return rc;
   }
   return TDVP_OK;
@@ -1074,24 +1081,38 @@ int launch_gemm(tdvp_ctx* ctx, const Program& p, const Bufs& bufs, double* C, in
   if (v >= 0) {   // the chosen (or measured) tiling replaces the active one
     const Program::Tiling& a = p.alt[v];
     if (ev0) TDVP_HIP(ctx, hipEventRecord(*ev0, ctx->stream));
-    int rc = launch_core(ctx, p, (int)a.tiles.size(), a.n64, a.d_tiles, bufs, C, precision);
+    int rc = launch_core(ctx, p, arrays_of(p), (int)a.tiles.size(), a.n64, a.d_tiles, bufs, C, precision, nullptr);
     if (ev1) TDVP_HIP(ctx, hipEventRecord(*ev1, ctx->stream));
     return rc;
   }
-  return launch_core(ctx, p, (int)p.tiles.size(), p.n64, p.d_tiles, bufs, C, precision);
+  return launch_core(ctx, p, arrays_of(p), (int)p.tiles.size(), p.n64, p.d_tiles, bufs, C, precision, nullptr);
 }
 
 int launch_gemm_tiles(tdvp_ctx* ctx, const Program& p, const Bufs& bufs, double* C, int precision) {
-  return launch_core(ctx, p, (int)p.tiles.size(), p.n64, p.d_tiles, bufs, C, precision);
+  return launch_core(ctx, p, arrays_of(p), (int)p.tiles.size(), p.n64, p.d_tiles, bufs, C, precision, nullptr);
 }
 
-static int launch_core(tdvp_ctx* ctx, const Program& p, int ntiles, int n64, const DevTile* d_tiles,
-                       const Bufs& bufs, double* C, int precision) {
+int launch_gemm_ws(tdvp_ctx* ctx, const Program& p, const DevArrays& a, const DevTile* d_tiles, const Bufs& bufs,
+                   double* C, int precision, const LaunchWs& ws) {
+  return launch_core(ctx, p, a, (int)p.tiles.size(), p.n64, d_tiles, bufs, C, precision, &ws);
+}
+
+size_t partial_slot_bytes(int nslots) { return sizeof(double2) * (size_t)nslots * kSlotDim * kSlotDim; }
+
+// ws == nullptr: partial slots and shifts live in the context's grow-only
+// workspaces; otherwise in the caller's (ws->part, ws->shift), which are
+// large enough (checked by the caller).
+static int launch_core(tdvp_ctx* ctx, const Program& p, const DevArrays& arr, int ntiles, int n64,
+                       const DevTile* d_tiles, const Bufs& bufs, double* C, int precision, const LaunchWs* ws) {
   if (ntiles == 0) return TDVP_OK;
   double2* part = nullptr;
   if (p.nslots > 0) {
-    TDVP_HIP(ctx, ctx->ws_part.ensure(sizeof(double2) * (size_t)p.nslots * kSlotDim * kSlotDim));
-    part = (double2*)ctx->ws_part.p;
+    if (ws) {
+      part = ws->part;
+    } else {
+      TDVP_HIP(ctx, ctx->ws_part.ensure(partial_slot_bytes(p.nslots)));
+      part = (double2*)ctx->ws_part.p;
+    }
   }
   if (precision == TDVP_BF16X3 && ntiles > n64) {
     // the split-BF16 kernel exists for 64x64 tiles only: take the program's
@@ -1099,7 +1120,7 @@ static int launch_core(tdvp_ctx* ctx, const Program& p, int ntiles, int n64, con
     const Program::Tiling* t64 = nullptr;
     for (const auto& a : p.alt)
       if (a.mode == 2) t64 = &a;
-    if (!t64 || !t64->d_tiles)
+    if (ws || !t64 || !t64->d_tiles)
       return set_error(ctx, TDVP_E_INVALID, "split-BF16 products need 64x64 tiles (tile mode 2)");
     ntiles = (int)t64->tiles.size();
     n64 = t64->n64;
@@ -1113,10 +1134,15 @@ static int launch_core(tdvp_ctx* ctx, const Program& p, int ntiles, int n64, con
   if (int rc = bad_flag(ctx, &bf.bad)) return rc;
   if (precision != TDVP_FP64 && p.nshift[0] + p.nshift[1] > 0) {
     const int nb = p.nshift[0] + p.nshift[1];
-    TDVP_HIP(ctx, ctx->ws_shift.ensure(sizeof(double) * 2 * (size_t)(nb + 1)));
-    double* out = (double*)ctx->ws_shift.p;
-    double2* partial = (double2*)ctx->ws_shift.p + 1;
-    hipLaunchKernelGGL(env_shift_parts, dim3(nb), dim3(256), 0, ctx->stream, bufs, (const int64_t*)p.d_shift_meta,
+    double* out;
+    if (ws) {
+      out = ws->shift;
+    } else {
+      TDVP_HIP(ctx, ctx->ws_shift.ensure(shift_bytes(nb)));
+      out = (double*)ctx->ws_shift.p;
+    }
+    double2* partial = (double2*)out + 1;
+    hipLaunchKernelGGL(env_shift_parts, dim3(nb), dim3(256), 0, ctx->stream, bufs, arr.shift_meta,
                        p.nshift[0], partial);
     hipLaunchKernelGGL(env_shift_final, dim3(1), dim3(64), 0, ctx->stream, (const double2*)partial, p.nshift[0],
                        p.nshift[1], out);
@@ -1126,25 +1152,25 @@ static int launch_core(tdvp_ctx* ctx, const Program& p, int ntiles, int n64, con
     if (precision == TDVP_BF16X3) {
       const dim3 g(n64), bl(256);
       if (bf.shift) {
-        if (heff) hipLaunchKernelGGL((heff_gemm_b3<true>), g, bl, 0, ctx->stream, bf, C, part, d_tiles, p.d_outs, p.d_terms);
-        else hipLaunchKernelGGL((block_gemm_b3<true>), g, bl, 0, ctx->stream, bf, C, part, d_tiles, p.d_outs, p.d_terms);
+        if (heff) hipLaunchKernelGGL((heff_gemm_b3<true>), g, bl, 0, ctx->stream, bf, C, part, d_tiles, arr.outs, arr.terms);
+        else hipLaunchKernelGGL((block_gemm_b3<true>), g, bl, 0, ctx->stream, bf, C, part, d_tiles, arr.outs, arr.terms);
       } else {
-        if (heff) hipLaunchKernelGGL((heff_gemm_b3<false>), g, bl, 0, ctx->stream, bf, C, part, d_tiles, p.d_outs, p.d_terms);
-        else hipLaunchKernelGGL((block_gemm_b3<false>), g, bl, 0, ctx->stream, bf, C, part, d_tiles, p.d_outs, p.d_terms);
+        if (heff) hipLaunchKernelGGL((heff_gemm_b3<false>), g, bl, 0, ctx->stream, bf, C, part, d_tiles, arr.outs, arr.terms);
+        else hipLaunchKernelGGL((block_gemm_b3<false>), g, bl, 0, ctx->stream, bf, C, part, d_tiles, arr.outs, arr.terms);
       }
     } else if (precision == TDVP_FP32) {
-      launch_one<float, 2, 2>(ctx, heff, n64, bf, C, part, d_tiles, p);
+      launch_one<float, 2, 2>(ctx, heff, n64, bf, C, part, d_tiles, arr);
     } else {
-      launch_one<double, 2, 2>(ctx, heff, n64, bf, C, part, d_tiles, p);
+      launch_one<double, 2, 2>(ctx, heff, n64, bf, C, part, d_tiles, arr);
     }
   }
   if (n32 > 0) {   // 32x32 tiles (optional tile modes; never under BF16X3, see above)
-    if (precision != TDVP_FP64) launch_one<float, 1, 1>(ctx, heff, n32, bf, C, part, t32, p);
-    else launch_one<double, 1, 1>(ctx, heff, n32, bf, C, part, t32, p);
+    if (precision != TDVP_FP64) launch_one<float, 1, 1>(ctx, heff, n32, bf, C, part, t32, arr);
+    else launch_one<double, 1, 1>(ctx, heff, n32, bf, C, part, t32, arr);
   }
   if (!p.reds.empty())
     hipLaunchKernelGGL(reduce_parts, dim3((unsigned)p.reds.size()), dim3(256), 0, ctx->stream, bf, C,
-                       (const double2*)part, p.d_reds, p.d_outs, p.d_terms);
+                       (const double2*)part, arr.reds, arr.outs, arr.terms);
   TDVP_HIP(ctx, hipGetLastError());
   return TDVP_OK;
 }
