@@ -37,7 +37,35 @@ import sys
 import time
 
 METRIC = "H_eff·Θ TFLOP/s + s/sweep at L=60 χ=4096; mixed vs FP64 at ≤1e-4 obs err"
-PEAK = {"fp64": 78.6, "fp32": 157.3}
+# MI355X dense matrix-core peaks (TFLOP/s).  Split-BF16 products issue six
+# bf16 slice products per logical real product, so their logical-flop
+# ceiling is the bf16 peak / 6.
+BF16_PEAK = 2516.0
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": BF16_PEAK / 6}
+
+
+def rooflines(by_prec):
+    """Fraction of each precision's matrix-core ceiling reached by the H_eff
+    applies (logical flops: 8 per complex multiply-add)."""
+    out = {}
+    for name, r in by_prec.items():
+        if name not in PEAK or "tflops" not in r:
+            continue
+        out[name] = {"achieved": r["tflops"], "peak": PEAK[name], "unit": "TFLOP/s",
+                     "frac": r["tflops"] / PEAK[name]}
+        if name == "bf16x3":
+            out[name]["bf16_issue_frac"] = 6 * r["tflops"] / BF16_PEAK
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def pack(blocks, keys, offs, total):
@@ -144,6 +172,7 @@ def large_heff(args, T, torch, stream, ctx, model, late=False):
         res[name] = {"ms_per_apply": 1e3 * dt, "tflops": flops / dt / 1e12}
         print(f"bench: chi={chi} H_eff {name} {1e3 * dt:.2f} ms, {flops / dt / 1e12:.2f} TFLOP/s",
               file=sys.stderr, flush=True)
+    res["roofline_by_precision"] = rooflines({k: res[k] for k in ("fp64", "fp32", "bf16x3")})
     if not late:
         os.environ["TDVP_PER_BLOCK"] = "1"
         try:
@@ -322,11 +351,14 @@ def main():
 
         run = dict(dt=0.05, eps_tol=1e-4, chi_cap=chi, krylov_tol=1e-10, krylov_maxdim=40)
         mps = new_mps(ctx)
-        other = None
+        # the other precision rungs, each from the same initial state on its own context
+        others = []
         if not args.no_mixed:
-            octx = T.Context(0, stream=stream.cuda_stream, precision=T.FP32 if prec == T.FP64 else T.FP64)
-            other = new_mps(octx)
-        infos, oinfos, cmp = [], [], []
+            rungs = [("fp32", T.FP32), ("bf16x3", T.BF16X3)] if prec == T.FP64 else [("fp64", T.FP64)]
+            for name, p_ in rungs:
+                octx = T.Context(0, stream=stream.cuda_stream, precision=p_)
+                others.append({"name": name, "ctx": octx, "mps": new_mps(octx), "infos": [], "cmp": []})
+        infos = []
         t_sw = 0.0
         for st in range(args.warmup + args.steps):
             timed = st >= args.warmup
@@ -342,18 +374,20 @@ def main():
                 infos.append(info)
             print(f"bench: {'timed' if timed else 'warmup'} sweep {st + 1}: {info['seconds']:.2f} s",
                   file=sys.stderr, flush=True)
-            if other is not None:
+            for o in others:
+                other = o["mps"]
                 oinfo = other.sweep(run["dt"], eps_tol=run["eps_tol"], chi_cap=run["chi_cap"],
                                     krylov_tol=run["krylov_tol"], krylov_maxdim=run["krylov_maxdim"])
-                oinfos.append(oinfo)
+                o["infos"].append(oinfo)
                 ov = mps.overlap(other)
                 n1, n2 = mps.overlap(mps).real, other.overlap(other).real
                 sz1, dc1, _ = mps.measure()
                 sz2, dc2, _ = other.measure()
-                cmp.append({"state_err": float(np.sqrt(max(n1 + n2 - 2 * ov.real, 0.0))),
-                            "d_sz": float(np.abs(sz1 - sz2).max()), "d_docc": float(np.abs(dc1 - dc2).max())})
-                print(f"bench: other-precision sweep {st + 1}: {oinfo['seconds']:.2f} s, |psi-phi| "
-                      f"{cmp[-1]['state_err']:.2e}, max|dSz| {cmp[-1]['d_sz']:.2e}", file=sys.stderr, flush=True)
+                o["cmp"].append({"state_err": float(np.sqrt(max(n1 + n2 - 2 * ov.real, 0.0))),
+                                 "d_sz": float(np.abs(sz1 - sz2).max()), "d_docc": float(np.abs(dc1 - dc2).max())})
+                print(f"bench: {o['name']} sweep {st + 1}: {oinfo['seconds']:.2f} s, |psi-phi| "
+                      f"{o['cmp'][-1]['state_err']:.2e}, max|dSz| {o['cmp'][-1]['d_sz']:.2e}",
+                      file=sys.stderr, flush=True)
         # one-site sweeps on the saturated state (bond dimensions fixed)
         one = []
         for st in range(args.one_site_steps):
@@ -382,10 +416,11 @@ def main():
                     "krylov_iters_per_sweep": float(np.mean([i["krylov_iters"] for i in one])),
                     "note": "one-site TDVP sweeps continuing from the saturated two-site state "
                             "(QR gauge moves instead of SVD splits; bond dimensions fixed)"}
-        if other is not None:
-            tail = oinfos[args.warmup:] or oinfos
-            mixed = {
-                "precision": "fp32" if prec == T.FP64 else "fp64",
+        for o in others:
+            tail = o["infos"][args.warmup:] or o["infos"]
+            cmp = o["cmp"]
+            rec = {
+                "precision": o["name"],
                 "s_per_sweep": float(np.mean([i["seconds"] for i in tail])),
                 "sweep_phase_s": {k: float(np.mean([i[k] for i in tail])) for k in
                                   ("t_lanczos", "t_svd", "t_env")},
@@ -393,11 +428,15 @@ def main():
                 "state_err_after_all": cmp[-1]["state_err"],
                 "max_obs_err": max(max(c["d_sz"], c["d_docc"]) for c in cmp),
                 "sweeps_compared": len(cmp),
-                "note": "both runs start from the same seeded random MPS; errors are |psi_64 - psi_mixed| and "
+                "note": "both runs start from the same seeded random MPS; errors are |psi_ref - psi_rung| and "
                         "max over sites of |d<S^z>|, |d<n_up n_dn>| after each sweep",
             }
-            other.close()
-            octx.close()
+            if mixed is None:
+                mixed = rec
+            else:
+                mixed.setdefault("other_rungs", []).append(rec)
+            o["mps"].close()
+            o["ctx"].close()
         mps.close()
 
     # ---- CPU baseline: the oracle on sampled output blocks ------------------------
@@ -442,6 +481,7 @@ def main():
                 break
         t_cpu = time.time() - t0
         cpu = {"value": done_f / t_cpu / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
+               "cpu_model": cpu_model(),
                "sample": f"{n_blocks} output blocks of the chi=4096 middle-bond H_eff apply, each evaluated by "
                          f"the dense oracle on the sector-restricted expanded problem ({t_cpu:.1f} s); rate = "
                          f"algorithmic flops of those blocks / oracle time"}
@@ -465,7 +505,8 @@ def main():
                    "L": L, "chi": chi, "precision": args.prec},
         "heff": {"flops_per_apply": flops, "ms_per_apply": 1e3 * t_apply,
                  "blocks": len(xk), "terms": len(terms), "theta_elems": int(xt),
-                 "env_chain_s": t_env_chain, "by_precision": heff_by_prec},
+                 "env_chain_s": t_env_chain, "by_precision": heff_by_prec,
+                 "roofline_by_precision": rooflines(heff_by_prec)},
         "roofline": {"bound": "mfma", "achieved": heff_tflops, "peak": PEAK[args.prec], "unit": "TFLOP/s",
                      "frac": heff_tflops / PEAK[args.prec], "traffic": measured_traffic(args.prec),
                      "kernel": "heff_gemm<double, 2, 2>" if prec == T.FP64 else "heff_gemm<float, 2, 2>"},

@@ -95,9 +95,10 @@ enum {
 
 /* Arithmetic of the block contractions (effective-Hamiltonian applies and
  * environment updates).  TDVP_FP32: FP32 operands and accumulation.
- * TDVP_BF16X3: each operand value split into three bfloat16 slices, the six
- * leading slice products of every real product accumulated in FP32 (about
- * FP32 accuracy on the bfloat16 matrix cores).  In both reduced modes the
+ * TDVP_BF16X3: each operand value split into three bfloat16 slices (once per
+ * operand buffer and launch, into a workspace of 16 bytes per complex
+ * element), the six leading slice products of every real product
+ * accumulated in FP32 (about FP32 accuracy on the bfloat16 matrix cores).  In both reduced modes the
  * block-Hamiltonian environment channels are shifted by their mean diagonal
  * and the shift is added back exactly.  Lanczos scalars, reorthogonalisation,
  * the small exponential, the SVD/QR splits and all local terms stay in FP64 in
@@ -217,6 +218,30 @@ int tdvp_ctx_set_precision(tdvp_ctx* ctx, int32_t precision);
  * applies and environment updates alike.  Applies to programs built
  * afterwards.  Errors: INVALID. */
 int tdvp_ctx_set_split(tdvp_ctx* ctx, double alpha, int32_t kmin);
+/* Storage of the Krylov basis (the memory side of supplementary section
+ * S2.3, where float32 halves the memory of the largest runs): TDVP_FP64
+ * (default) or TDVP_FP32 (complex64 basis vectors, half the memory).  With
+ * FP32 storage the recurrence keeps an FP64 copy of the current vector (the
+ * operator input), and the Lanczos scalars, the operator applies and the
+ * working vector stay FP64; the re-orthogonalisation and the final
+ * combination read the rounded basis (relative error of the result about
+ * 1e-7).  Applies to later Krylov exponentials (tdvp_krylov_expm and the
+ * sweeps).  Errors: INVALID. */
+int tdvp_ctx_set_krylov_storage(tdvp_ctx* ctx, int32_t precision);
+/* Host staging in sweeps (supplementary section S2.3 stores the state on the
+ * CPU and keeps only the tensors being worked on in GPU memory): with enable
+ * = 1, tdvp_sweep moves every MPS tensor and environment that the next bond
+ * update does not read to pinned host memory after each bond (copies on the
+ * context stream; the device memory goes back to the allocator) and brings
+ * those of the next bond back before it.  Results are bit-identical to an
+ * unstaged sweep.  Calls that read the whole chain (measure, overlap,
+ * site_read, tdvp_sweep1) bring everything back first.  Errors: INVALID. */
+int tdvp_ctx_set_host_staging(tdvp_ctx* ctx, int32_t enable);
+/* Device memory held through the context's allocator (by the context and the
+ * MPS made with it): *live_bytes now, *peak_bytes the high-water mark since
+ * the last reset; reset_peak = 1 then sets the mark to the live value.
+ * Host-only query (no device call).  Errors: INVALID. */
+int tdvp_ctx_memory(tdvp_ctx* ctx, int64_t* live_bytes, int64_t* peak_bytes, int32_t reset_peak);
 /* Graph replay of Lanczos iterations (enable 1, the default unless the
  * environment variable TDVP_GRAPH is 0, or 0).  With it on, each Krylov
  * exponential of an effective Hamiltonian records one iteration (apply, two
@@ -324,8 +349,9 @@ int tdvp_env_update(tdvp_ctx* ctx, const tdvp_model* model, int32_t site, int32_
  * chi = 4096 bond with Table-S2-shaped sectors), program arrays up to about
  * 4 MiB; beyond them TDVP_E_NOMEM with nothing launched.  Every call on a
  * device shares its array and overwrites it: calls that overlap on one device
- * (other contexts, streams or threads) race.  Split-BF16 products need the
- * all-64x64 tiling (the default tile mode).  Does not synchronise. */
+ * (other contexts, streams or threads) race.  Split-BF16 precision is not
+ * available here (TDVP_E_INVALID): its operand slices need a workspace of
+ * the size of the operands.  Does not synchronise. */
 int tdvp_env_update_noalloc(tdvp_ctx* ctx, const tdvp_model* model, int32_t site, int32_t direction,
                             const tdvp_bond* bond_in, const tdvp_bond* bond_out, const tdvp_blocks* env_in,
                             const tdvp_blocks* tensor, tdvp_blocks* env_out);

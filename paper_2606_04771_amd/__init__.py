@@ -80,6 +80,9 @@ def _load():
     sig = {
         "tdvp_ctx_create": [C.POINTER(C.c_void_p), I32, P, I32, P, P, P],
         "tdvp_ctx_set_split": [P, D, I32],
+        "tdvp_ctx_set_krylov_storage": [P, I32],
+        "tdvp_ctx_set_host_staging": [P, I32],
+        "tdvp_ctx_memory": [P, P, P, I32],
         "tdvp_split_sectors": [P, P, P, P, P, P, P],
         "tdvp_split": [P, P, P, P, I32, P, P, P, P],
         "tdvp_ctx_destroy": [P],
@@ -326,6 +329,20 @@ class Context:
 
     def set_graphs(self, enable):
         _check(lib.tdvp_ctx_set_graphs(self.h, int(bool(enable))), self.h)
+
+    def set_krylov_storage(self, precision):
+        """Krylov basis storage: FP64 (default) or FP32 (complex64 basis vectors)."""
+        _check(lib.tdvp_ctx_set_krylov_storage(self.h, int(precision)), self.h)
+
+    def set_host_staging(self, enable):
+        """Sweeps keep inactive MPS tensors and environments in pinned host memory."""
+        _check(lib.tdvp_ctx_set_host_staging(self.h, int(bool(enable))), self.h)
+
+    def memory(self, reset_peak=False):
+        """(live, peak) device bytes held through the context's allocator."""
+        live, peak = C.c_int64(), C.c_int64()
+        _check(lib.tdvp_ctx_memory(self.h, C.byref(live), C.byref(peak), int(bool(reset_peak))), self.h)
+        return live.value, peak.value
 
     def set_split(self, alpha=-1.0, kmin=128):
         """K-chain splitting of effective-Hamiltonian launches (alpha < 0: size rule)."""

@@ -374,7 +374,7 @@ int tdvp_ctx_create(tdvp_ctx** out, int32_t device, void* hip_stream, int32_t pr
       c->alloc = al;
       c->pool->al = al;
       for (DeviceBuffer* b : {&c->ws_scratch, &c->ws_krylov, &c->ws_small, &c->ws_vec, &c->ws_theta, &c->ws_svd,
-                              &c->ws_lanczos, &c->ws_part, &c->ws_shift, &c->ws_compact, &c->ws_flag})
+                              &c->ws_lanczos, &c->ws_part, &c->ws_shift, &c->ws_compact, &c->ws_flag, &c->ws_slices})
         b->al = al;
     }
     if (const char* e = std::getenv("TDVP_SPLIT_ALPHA")) c->split_alpha = std::atof(e);
@@ -455,6 +455,29 @@ int tdvp_ctx_set_precision(tdvp_ctx* ctx, int32_t precision) {
   if (precision != TDVP_FP64 && precision != TDVP_FP32 && precision != TDVP_BF16X3)
     return set_error(ctx, TDVP_E_INVALID, "unknown precision");
   ctx->precision = precision;
+  return TDVP_OK;
+}
+
+int tdvp_ctx_set_krylov_storage(tdvp_ctx* ctx, int32_t precision) {
+  if (!ctx) return set_error(nullptr, TDVP_E_INVALID, "null ctx");
+  if (precision != TDVP_FP64 && precision != TDVP_FP32)
+    return set_error(ctx, TDVP_E_INVALID, "Krylov basis storage must be TDVP_FP64 or TDVP_FP32");
+  ctx->krylov_fp32 = precision == TDVP_FP32;
+  return TDVP_OK;
+}
+
+int tdvp_ctx_set_host_staging(tdvp_ctx* ctx, int32_t enable) {
+  if (!ctx) return set_error(nullptr, TDVP_E_INVALID, "null ctx");
+  ctx->host_staging = enable != 0;
+  return TDVP_OK;
+}
+
+int tdvp_ctx_memory(tdvp_ctx* ctx, int64_t* live_bytes, int64_t* peak_bytes, int32_t reset_peak) {
+  if (!ctx) return set_error(nullptr, TDVP_E_INVALID, "null ctx");
+  std::lock_guard<std::mutex> lk(ctx->alloc->mu);
+  if (live_bytes) *live_bytes = (int64_t)ctx->alloc->live;
+  if (peak_bytes) *peak_bytes = (int64_t)ctx->alloc->peak;
+  if (reset_peak) ctx->alloc->peak = ctx->alloc->live;
   return TDVP_OK;
 }
 

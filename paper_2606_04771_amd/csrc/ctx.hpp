@@ -9,6 +9,7 @@
 #include <map>
 #include <string>
 #include <initializer_list>
+#include <mutex>
 #include <unordered_map>
 #include <vector>
 
@@ -76,6 +77,10 @@ struct Allocator {
   void* user = nullptr;
   hipError_t get(void** p, size_t n) const;
   void put(void* p) const;
+  // bytes held (live) and the high-water mark since the last reset (peak)
+  mutable std::mutex mu;
+  mutable std::unordered_map<void*, size_t> held;
+  mutable size_t live = 0, peak = 0;
 };
 
 // Device memory for program arrays, recycled by size class.  Every use of a
@@ -106,6 +111,9 @@ struct Program {
   std::vector<int64_t> shift_meta;
   int nshift[2] = {0, 0};
   double flops = 0.0;
+  // element range [blo, bhi) of each buffer read as a GEMM operand (the part
+  // that split-BF16 launches slice); empty when blo == bhi
+  int64_t blo[kMaxBufs] = {}, bhi[kMaxBufs] = {};
   int64_t aux = 0;          // scratch elements needed by the program's outputs
   int tile_mode = 0;        // 0: per output block the better of 64x64 / 32x32; 1: all 32x32; 2: all 64x64
   int n64 = 0;              // tiles[0, n64) are 64x64 (four waves), the rest 32x32 (one wave)
@@ -176,6 +184,7 @@ struct tdvp_ctx {
   tdvp::DeviceBuffer ws_lanczos;   // partial sums of the graph-replayed Lanczos iteration
   tdvp::DeviceBuffer ws_part;   // partial tiles of split K chains
   tdvp::DeviceBuffer ws_shift;  // diagonal shifts of reduced-precision launches
+  tdvp::DeviceBuffer ws_slices; // split-BF16 operand records
   tdvp::DeviceBuffer ws_compact;  // compact copy of a non-contiguous Krylov start vector
   void* solver = nullptr;       // rocblas handle for the eigensolver (created on first use)
   // side streams (default priority) with their own solver handles, for
@@ -207,6 +216,11 @@ struct tdvp_ctx {
   // (tdvp_ctx_set_split): alpha < 0 means the size rule
   double split_alpha = -1.0;
   int split_kmin = 128;
+  // Krylov basis storage (tdvp_ctx_set_krylov_storage): complex64 when set
+  bool krylov_fp32 = false;
+  // sweeps keep inactive MPS tensors and environments in pinned host memory
+  // (tdvp_ctx_set_host_staging)
+  bool host_staging = false;
   // device flag set by launches that wrote non-finite values (in ws_flag)
   tdvp::DeviceBuffer ws_flag;
 };
@@ -265,20 +279,24 @@ inline size_t shift_bytes(int nblocks) { return sizeof(double) * 2 * (size_t)(nb
 int launch_gemm_ws(tdvp_ctx* ctx, const Program& p, const DevArrays& a, const DevTile* d_tiles, const Bufs& bufs,
                    double* C, int precision, const LaunchWs& ws);
 
-// Lanczos vector kernels (complex128 vectors of n elements).
+// Lanczos vector kernels (complex128 vectors of n elements).  Basis vectors V
+// (stride in elements) are complex128, or complex64 when v32 is set; the
+// other vectors and every scalar are FP64.
 int vec_dots(tdvp_ctx* ctx, const double* V, int64_t stride, int nv, const double* w, int64_t n,
-             double* d_out /* 2*nv doubles, device */);
+             double* d_out /* 2*nv doubles, device */, bool v32 = false);
 int vec_subtract_combo(tdvp_ctx* ctx, double* w, const double* V, int64_t stride, int nv,
-                       const double* d_coef /* 2*nv */, int64_t n, double* d_norm2 /* or null */);
+                       const double* d_coef /* 2*nv */, int64_t n, double* d_norm2 /* or null */, bool v32 = false);
 int vec_scale_copy(tdvp_ctx* ctx, double* dst, const double* src, double s, int64_t n);
 int vec_combo(tdvp_ctx* ctx, double* out, const double* V, int64_t stride, int nv, const double* d_coef,
-              int64_t n);
+              int64_t n, bool v32 = false);
 int vec_norm2(tdvp_ctx* ctx, const double* x, int64_t n, double* d_out);
 size_t lanczos_partial_bytes(int64_t n, int maxdim);
 int vec_lanczos_orth_it(tdvp_ctx* ctx, double* W, const double* V, int64_t stride, int maxdim, int64_t n,
-                        const int* d_j, double* c1, double* c2, double* d_norm2, void* partial_buf);
+                        const int* d_j, double* c1, double* c2, double* d_norm2, void* partial_buf, bool v32 = false);
 int vec_lanczos_advance_it(tdvp_ctx* ctx, double* V, int64_t stride, double* x, const double* W, int64_t n,
-                           const double* d_b2, int* d_j, int maxdim);
+                           const double* d_b2, int* d_j, int maxdim, bool v32 = false);
+// complex64 basis slot from a complex128 vector
+int vec_store_basis32(tdvp_ctx* ctx, double* V32, const double* x, int64_t n);
 int vec_set_index(tdvp_ctx* ctx, int* d_j, int v);
 int vec_check_finite(tdvp_ctx* ctx, const double* x, int64_t n, int* d_flag);
 int vec_pad_matrix(tdvp_ctx* ctx, double* A, int64_t n, int64_t g, double v, double* d_scale);

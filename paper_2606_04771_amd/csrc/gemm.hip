@@ -286,34 +286,81 @@ __device__ __forceinline__ void gemm_body(const Bufs& bufs, double* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Split-BF16 products (Ozaki-style): every staged operand value (after its
-// coefficient, in FP64) is cut into three bfloat16 slices v = v1 + v2 + v3
-// (each the round-to-nearest of the remainder, through FP32), and each real
-// product keeps the six slice products with slice indices summing to at most
-// four, accumulated in FP32 on v_mfma_f32_16x16x32_bf16.  Lane layout of that
-// instruction: A[i][k] for i = lane % 16 and k = 8 (lane / 16) .. +7 (one
-// 16-byte vector), B[k][j] likewise with j = lane % 16, D as the FP32 16x16x4
-// one.  LDS keeps, per slice and real/imaginary plane, rows of K = 32
-// contiguous values.
+// Split-BF16 products (Ozaki-style).  Every operand value a (real and
+// imaginary parts separately) is cut into three bfloat16 slices
+// a = a1 + a2 + a3 (each the round-to-nearest of the remainder, in FP32), and
+// each real product keeps the six slice products whose slice indices sum to
+// at most four, accumulated in FP32 on v_mfma_f32_16x16x32_bf16.  Lane layout
+// of that instruction: A[i][k] for i = lane % 16 and k = 8 (lane / 16) .. +7
+// (one 16-byte vector), B[k][j] likewise with j = lane % 16, D as the FP32
+// 16x16x4 one.
+//
+// The slicing is done once per operand buffer and launch by a streaming
+// kernel (slice_records), not per tile: each complex element becomes one
+// 16-byte record, dword s (s = 0, 1, 2) holding slice s of the real part in
+// its low and of the imaginary part in its high half (dword 3 zero).  The
+// energy shift of the block-Hamiltonian environment blocks is applied to
+// their diagonals in the records (slice_fix_diag).  The tile loop only loads
+// records, regroups their halves into per-slice LDS rows of K = 32
+// contiguous values (conjugation = a sign flip of the imaginary halves) and
+// issues matrix instructions.  The term coefficient multiplies a term group's
+// FP32 partial sum when the coefficient changes along the K chain.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int TKB = 32, PADB = 8;
 
-__device__ __forceinline__ void slice3(double v, __bf16& s1, __bf16& s2, __bf16& s3) {
+struct Slices {
+  const uint4* p[kMaxBufs];   // records of buffer b, p[b][e - lo[b]] for element e
+  int64_t lo[kMaxBufs];
+};
+
+__device__ __forceinline__ uint32_t bf16_bits(float f) {
+  return (uint32_t)__builtin_bit_cast(unsigned short, (__bf16)f);
+}
+__device__ __forceinline__ float bf16_value(uint32_t bits) { return __uint_as_float(bits << 16); }
+
+__device__ __forceinline__ void slice3_bits(double v, uint32_t& s1, uint32_t& s2, uint32_t& s3) {
   const float f = (float)v;
-  s1 = (__bf16)f;
-  const float r1 = f - (float)s1;
-  s2 = (__bf16)r1;
-  s3 = (__bf16)(r1 - (float)s2);
+  s1 = bf16_bits(f);
+  const float r1 = f - bf16_value(s1);
+  s2 = bf16_bits(r1);
+  s3 = bf16_bits(r1 - bf16_value(s2));
 }
 
-__device__ __forceinline__ bf16x8 neg8(bf16x8 v) {
-#pragma unroll
-  for (int q = 0; q < 8; ++q) v[q] = -v[q];
-  return v;
+__device__ __forceinline__ uint4 make_record(double2 v) {
+  uint32_t r1, r2, r3, i1, i2, i3;
+  slice3_bits(v.x, r1, r2, r3);
+  slice3_bits(v.y, i1, i2, i3);
+  return make_uint4(r1 | (i1 << 16), r2 | (i2 << 16), r3 | (i3 << 16), 0u);
 }
+
+__global__ __launch_bounds__(256) void slice_records(const double2* __restrict__ src, uint4* __restrict__ dst,
+                                                     int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
+    dst[e] = make_record(src[e]);
+}
+
+// Records of the diagonals of the listed blocks (meta: offset, dimension,
+// weight triplets) re-made from E - shift: one workgroup per block.  Only
+// elements inside the sliced range [lo, hi) have records (a listed block that
+// no product reads may lie outside it).
+__global__ __launch_bounds__(256) void slice_fix_diag(const double2* __restrict__ E, uint4* __restrict__ dst,
+                                                      int64_t lo, int64_t hi, const int64_t* __restrict__ meta,
+                                                      const double* __restrict__ shift) {
+  const int64_t off = meta[3 * blockIdx.x], d = meta[3 * blockIdx.x + 1];
+  const double e0 = *shift;
+  for (int64_t i = threadIdx.x; i < d; i += 256) {
+    const int64_t e = off + i * (d + 1);
+    if (e < lo || e >= hi) continue;
+    double2 v = E[e];
+    v.x -= e0;
+    dst[e - lo] = make_record(v);
+  }
+}
+
+__device__ __forceinline__ uint32_t rec_word(const uint4& r, int s) { return s == 0 ? r.x : s == 1 ? r.y : r.z; }
 
 template <bool SH>
-__device__ __forceinline__ void gemm_body_b3(const Bufs& bufs, double* __restrict__ Cbase,
+__device__ __forceinline__ void gemm_body_b3(const Bufs& bufs, const Slices& sl, double* __restrict__ Cbase,
                                              double2* __restrict__ part, const DevTile* __restrict__ tiles,
                                              const DevOut* __restrict__ outs, const DevTerm* __restrict__ terms) {
   constexpr int TM = 64, TN = 64;
@@ -331,55 +378,76 @@ __device__ __forceinline__ void gemm_body_b3(const Bufs& bufs, double* __restric
     rv[i] = tl.m0 + wm * 32 + i * 16 < ob.M;
     cv[i] = tl.n0 + wn * 32 + i * 16 < ob.N;
   }
-  acc_t accr[2][2], acci[2][2];
+  // accr/acci: the tile's sum; tr/ti: the partial sum of the current group of
+  // consecutive terms with one coefficient (ccur)
+  acc_t accr[2][2], acci[2][2], tr[2][2], ti[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       accr[i][j] = acc_t{0, 0, 0, 0};
       acci[i][j] = acc_t{0, 0, 0, 0};
+      tr[i][j] = acc_t{0, 0, 0, 0};
+      ti[i][j] = acc_t{0, 0, 0, 0};
     }
+  auto flush = [&](double c) {
+    const float cf = (float)c;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        accr[i][j] += cf * tr[i][j];
+        acci[i][j] += cf * ti[i][j];
+        tr[i][j] = acc_t{0, 0, 0, 0};
+        ti[i][j] = acc_t{0, 0, 0, 0};
+      }
+  };
   // staging: this thread owns row sr of the A and B tiles and 8 consecutive k
   const int sr = tid % 64, kg = tid / 64;
   int t = tl.t0, k0 = tl.k0;
+  double ccur = before(t, k0, tl.t1, tl.k1) ? terms[t].coef : 0.0;
   while (before(t, k0, tl.t1, tl.k1)) {
     const DevTerm tm = terms[t];
+    if (tm.coef != ccur) {   // uniform: a new coefficient group
+      flush(ccur);
+      ccur = tm.coef;
+    }
     {
-      const double2* A = reinterpret_cast<const double2*>(bufs.p[tm.a_buf]) + tm.a_off;
-      const double2* B = reinterpret_cast<const double2*>(bufs.p[tm.b_buf]) + tm.b_off;
-      const bool ta = tm.ops & 1, ca = tm.ops & 2, tb = tm.ops & 4, cb = tm.ops & 8;
-      const double c = tm.coef;
-      bf16x8 a[3][2], b[3][2];
+      const uint4* A = sl.p[tm.a_buf] + (tm.a_off - sl.lo[tm.a_buf]);
+      const uint4* B = sl.p[tm.b_buf] + (tm.b_off - sl.lo[tm.b_buf]);
+      const bool ta = tm.ops & 1, tb = tm.ops & 4;
+      const uint32_t sa = (tm.ops & 2) ? 0x80008000u : 0u, sb = (tm.ops & 8) ? 0x80008000u : 0u;
       const int gm = tl.m0 + sr, gn = tl.n0 + sr;
+      uint4 ra[8], rb[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int gk = k0 + 8 * kg + q;
-        double2 va = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
-        if (gm < ob.M && gk < tm.K) {
-          va = ta ? A[(int64_t)gk + (int64_t)gm * tm.lda] : A[(int64_t)gm + (int64_t)gk * tm.lda];
-          if (SH && (tm.ops & 16) && gm == gk) va.x -= bufs.shift[0];
-        }
-        if (gn < ob.N && gk < tm.K) {
-          vb = tb ? B[(int64_t)gn + (int64_t)gk * tm.ldb] : B[(int64_t)gk + (int64_t)gn * tm.ldb];
-          if (SH && (tm.ops & 32) && gn == gk) vb.x -= bufs.shift[1];
-        }
-        __bf16 s1, s2, s3;
-        slice3(c * va.x, s1, s2, s3);
-        a[0][0][q] = s1; a[1][0][q] = s2; a[2][0][q] = s3;
-        slice3(ca ? -c * va.y : c * va.y, s1, s2, s3);
-        a[0][1][q] = s1; a[1][1][q] = s2; a[2][1][q] = s3;
-        slice3(vb.x, s1, s2, s3);
-        b[0][0][q] = s1; b[1][0][q] = s2; b[2][0][q] = s3;
-        slice3(cb ? -vb.y : vb.y, s1, s2, s3);
-        b[0][1][q] = s1; b[1][1][q] = s2; b[2][1][q] = s3;
+        ra[q] = make_uint4(0u, 0u, 0u, 0u);
+        rb[q] = make_uint4(0u, 0u, 0u, 0u);
+        if (gm < ob.M && gk < tm.K) ra[q] = ta ? A[(int64_t)gk + (int64_t)gm * tm.lda] : A[(int64_t)gm + (int64_t)gk * tm.lda];
+        if (gn < ob.N && gk < tm.K) rb[q] = tb ? B[(int64_t)gn + (int64_t)gk * tm.ldb] : B[(int64_t)gk + (int64_t)gn * tm.ldb];
       }
 #pragma unroll
-      for (int sl = 0; sl < 3; ++sl)
+      for (int s = 0; s < 3; ++s) {
+        uint4 are, aim, bre, bim;
+        uint32_t* pare = reinterpret_cast<uint32_t*>(&are);
+        uint32_t* paim = reinterpret_cast<uint32_t*>(&aim);
+        uint32_t* pbre = reinterpret_cast<uint32_t*>(&bre);
+        uint32_t* pbim = reinterpret_cast<uint32_t*>(&bim);
 #pragma unroll
-        for (int p = 0; p < 2; ++p) {
-          *reinterpret_cast<bf16x8*>(&As[sl][p][sr][8 * kg]) = a[sl][p];
-          *reinterpret_cast<bf16x8*>(&Bs[sl][p][sr][8 * kg]) = b[sl][p];
+        for (int j = 0; j < 4; ++j) {
+          const uint32_t a0 = rec_word(ra[2 * j], s), a1 = rec_word(ra[2 * j + 1], s);
+          const uint32_t b0 = rec_word(rb[2 * j], s), b1 = rec_word(rb[2 * j + 1], s);
+          pare[j] = (a0 & 0xffffu) | (a1 << 16);
+          paim[j] = ((a0 >> 16) | (a1 & 0xffff0000u)) ^ sa;
+          pbre[j] = (b0 & 0xffffu) | (b1 << 16);
+          pbim[j] = ((b0 >> 16) | (b1 & 0xffff0000u)) ^ sb;
         }
+        *reinterpret_cast<uint4*>(&As[s][0][sr][8 * kg]) = are;
+        *reinterpret_cast<uint4*>(&As[s][1][sr][8 * kg]) = aim;
+        *reinterpret_cast<uint4*>(&Bs[s][0][sr][8 * kg]) = bre;
+        *reinterpret_cast<uint4*>(&Bs[s][1][sr][8 * kg]) = bim;
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -387,29 +455,31 @@ __device__ __forceinline__ void gemm_body_b3(const Bufs& bufs, double* __restric
       if (!rv[i]) continue;
       bf16x8 ar[3], ai[3], nai[3];
 #pragma unroll
-      for (int sl = 0; sl < 3; ++sl) {
-        ar[sl] = *reinterpret_cast<const bf16x8*>(&As[sl][0][wm * 32 + i * 16 + li][8 * lk]);
-        ai[sl] = *reinterpret_cast<const bf16x8*>(&As[sl][1][wm * 32 + i * 16 + li][8 * lk]);
-        nai[sl] = neg8(ai[sl]);
+      for (int s = 0; s < 3; ++s) {
+        ar[s] = *reinterpret_cast<const bf16x8*>(&As[s][0][wm * 32 + i * 16 + li][8 * lk]);
+        ai[s] = *reinterpret_cast<const bf16x8*>(&As[s][1][wm * 32 + i * 16 + li][8 * lk]);
+        const uint4 u = *reinterpret_cast<const uint4*>(&ai[s]);
+        const uint4 nu = make_uint4(u.x ^ 0x80008000u, u.y ^ 0x80008000u, u.z ^ 0x80008000u, u.w ^ 0x80008000u);
+        nai[s] = *reinterpret_cast<const bf16x8*>(&nu);
       }
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         if (!cv[j]) continue;
         bf16x8 br[3], bi[3];
 #pragma unroll
-        for (int sl = 0; sl < 3; ++sl) {
-          br[sl] = *reinterpret_cast<const bf16x8*>(&Bs[sl][0][wn * 32 + j * 16 + li][8 * lk]);
-          bi[sl] = *reinterpret_cast<const bf16x8*>(&Bs[sl][1][wn * 32 + j * 16 + li][8 * lk]);
+        for (int s = 0; s < 3; ++s) {
+          br[s] = *reinterpret_cast<const bf16x8*>(&Bs[s][0][wn * 32 + j * 16 + li][8 * lk]);
+          bi[s] = *reinterpret_cast<const bf16x8*>(&Bs[s][1][wn * 32 + j * 16 + li][8 * lk]);
         }
-        // slice pairs (0,0) (0,1) (1,0) (0,2) (1,1) (2,0), smallest last
+        // slice pairs (0,0) (0,1) (1,0) (0,2) (1,1) (2,0), smallest first
 #pragma unroll
         for (int pp = 5; pp >= 0; --pp) {
           const int x = pp == 0 ? 0 : pp == 1 ? 0 : pp == 2 ? 1 : pp == 3 ? 0 : pp == 4 ? 1 : 2;
           const int y = pp == 0 ? 0 : pp == 1 ? 1 : pp == 2 ? 0 : pp == 3 ? 2 : pp == 4 ? 1 : 0;
-          accr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar[x], br[y], accr[i][j], 0, 0, 0);
-          acci[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar[x], bi[y], acci[i][j], 0, 0, 0);
-          accr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nai[x], bi[y], accr[i][j], 0, 0, 0);
-          acci[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[x], br[y], acci[i][j], 0, 0, 0);
+          tr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar[x], br[y], tr[i][j], 0, 0, 0);
+          ti[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar[x], bi[y], ti[i][j], 0, 0, 0);
+          tr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nai[x], bi[y], tr[i][j], 0, 0, 0);
+          ti[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[x], br[y], ti[i][j], 0, 0, 0);
         }
       }
     }
@@ -420,6 +490,7 @@ __device__ __forceinline__ void gemm_body_b3(const Bufs& bufs, double* __restric
       ++t;
     }
   }
+  flush(ccur);
 
   if (tl.slot >= 0) {
     double2* P = part + (int64_t)tl.slot * kSlotDim * kSlotDim;
@@ -466,18 +537,18 @@ __device__ __forceinline__ void gemm_body_b3(const Bufs& bufs, double* __restric
 }
 
 template <bool SH>
-__global__ __launch_bounds__(256) void heff_gemm_b3(Bufs bufs, double* __restrict__ C, double2* __restrict__ part,
-                                                    const DevTile* __restrict__ tiles,
+__global__ __launch_bounds__(256) void heff_gemm_b3(Bufs bufs, Slices sl, double* __restrict__ C,
+                                                    double2* __restrict__ part, const DevTile* __restrict__ tiles,
                                                     const DevOut* __restrict__ outs,
                                                     const DevTerm* __restrict__ terms) {
-  gemm_body_b3<SH>(bufs, C, part, tiles, outs, terms);
+  gemm_body_b3<SH>(bufs, sl, C, part, tiles, outs, terms);
 }
 template <bool SH>
-__global__ __launch_bounds__(256) void block_gemm_b3(Bufs bufs, double* __restrict__ C, double2* __restrict__ part,
-                                                     const DevTile* __restrict__ tiles,
+__global__ __launch_bounds__(256) void block_gemm_b3(Bufs bufs, Slices sl, double* __restrict__ C,
+                                                     double2* __restrict__ part, const DevTile* __restrict__ tiles,
                                                      const DevOut* __restrict__ outs,
                                                      const DevTerm* __restrict__ terms) {
-  gemm_body_b3<SH>(bufs, C, part, tiles, outs, terms);
+  gemm_body_b3<SH>(bufs, sl, C, part, tiles, outs, terms);
 }
 
 // Diagonal shifts of a reduced-precision launch: out[s] = sum_b w_b tr(E_b) /
@@ -590,13 +661,32 @@ void launch_one(tdvp_ctx* ctx, bool heff, int ntiles, const Bufs& bufs, double* 
 }  // namespace
 
 hipError_t Allocator::get(void** p, size_t n) const {
-  if (!alloc_fn) return hipMalloc(p, n);
-  *p = alloc_fn(n, user);
-  return *p ? hipSuccess : hipErrorOutOfMemory;
+  hipError_t e;
+  if (!alloc_fn) {
+    e = hipMalloc(p, n);
+  } else {
+    *p = alloc_fn(n, user);
+    e = *p ? hipSuccess : hipErrorOutOfMemory;
+  }
+  if (e == hipSuccess && *p) {
+    std::lock_guard<std::mutex> lk(mu);
+    held[*p] = n;
+    live += n;
+    peak = std::max(peak, live);
+  }
+  return e;
 }
 
 void Allocator::put(void* p) const {
   if (!p) return;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = held.find(p);
+    if (it != held.end()) {
+      live -= it->second;
+      held.erase(it);
+    }
+  }
   if (free_fn) free_fn(p, user);
   else (void)hipFree(p);
 }
@@ -703,6 +793,31 @@ void Program::finalize() {
   tiles.clear();
   reds.clear();
   nslots = 0;
+  // operand ranges per buffer (the elements a launch can read through GEMM terms)
+  for (int b = 0; b < kMaxBufs; ++b) blo[b] = bhi[b] = 0;
+  bool seen[kMaxBufs] = {};
+  auto widen = [&](int b, int64_t lo, int64_t hi) {
+    if (b < 0 || b >= kMaxBufs) return;
+    if (!seen[b]) {
+      blo[b] = lo;
+      bhi[b] = hi;
+      seen[b] = true;
+    } else {
+      blo[b] = std::min(blo[b], lo);
+      bhi[b] = std::max(bhi[b], hi);
+    }
+  };
+  for (const DevOut& ob : outs)
+    for (int t = ob.t_begin; t < ob.t_end; ++t) {
+      const DevTerm& d = terms[t];
+      if (d.K <= 0 || ob.M <= 0 || ob.N <= 0) continue;
+      const int64_t ea = (d.ops & 1) ? (int64_t)(d.K - 1) + (int64_t)(ob.M - 1) * d.lda
+                                     : (int64_t)(ob.M - 1) + (int64_t)(d.K - 1) * d.lda;
+      const int64_t eb = (d.ops & 4) ? (int64_t)(ob.N - 1) + (int64_t)(d.K - 1) * d.ldb
+                                     : (int64_t)(d.K - 1) + (int64_t)(ob.N - 1) * d.ldb;
+      widen(d.a_buf, d.a_off, d.a_off + ea + 1);
+      widen(d.b_buf, d.b_off, d.b_off + eb + 1);
+    }
   tile_mode = default_tile_mode();
   const double thr = tile_threshold();
   // Splitting of long K chains, so that no work item runs much longer than
@@ -1132,6 +1247,22 @@ static int launch_core(tdvp_ctx* ctx, const Program& p, const DevArrays& arr, in
   Bufs bf = bufs;
   bf.shift = nullptr;
   if (int rc = bad_flag(ctx, &bf.bad)) return rc;
+  Slices sl{};
+  uint4* slice_base = nullptr;
+  if (precision == TDVP_BF16X3 && n64 > 0) {
+    if (ws) return set_error(ctx, TDVP_E_INVALID, "split-BF16 products need the context's operand-slice workspace");
+    size_t nrec = 0;
+    for (int b = 0; b < kMaxBufs; ++b) nrec += (size_t)(p.bhi[b] - p.blo[b]);
+    TDVP_HIP(ctx, ctx->ws_slices.ensure(sizeof(uint4) * std::max<size_t>(nrec, 1)));
+    slice_base = (uint4*)ctx->ws_slices.p;
+    size_t cur = 0;
+    for (int b = 0; b < kMaxBufs; ++b) {
+      if (p.bhi[b] <= p.blo[b]) continue;
+      sl.p[b] = slice_base + cur;
+      sl.lo[b] = p.blo[b];
+      cur += (size_t)(p.bhi[b] - p.blo[b]);
+    }
+  }
   if (precision != TDVP_FP64 && p.nshift[0] + p.nshift[1] > 0) {
     const int nb = p.nshift[0] + p.nshift[1];
     double* out;
@@ -1148,15 +1279,32 @@ static int launch_core(tdvp_ctx* ctx, const Program& p, const DevArrays& arr, in
                        p.nshift[1], out);
     bf.shift = out;
   }
+  if (slice_base) {   // operand records, once per buffer; shifted diagonals re-made from E - shift
+    for (int b = 0; b < kMaxBufs; ++b) {
+      if (!sl.p[b]) continue;
+      const int64_t n = p.bhi[b] - p.blo[b];
+      const unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
+      hipLaunchKernelGGL(slice_records, dim3(g), dim3(256), 0, ctx->stream,
+                         reinterpret_cast<const double2*>(bufs.p[b]) + p.blo[b], const_cast<uint4*>(sl.p[b]), n);
+    }
+    for (int s = 0; s < 2 && bf.shift; ++s) {
+      const int b = 1 + s;
+      const int nb = p.nshift[s];
+      if (nb == 0 || !sl.p[b]) continue;
+      hipLaunchKernelGGL(slice_fix_diag, dim3(nb), dim3(256), 0, ctx->stream,
+                         reinterpret_cast<const double2*>(bufs.p[b]), const_cast<uint4*>(sl.p[b]), p.blo[b], p.bhi[b],
+                         arr.shift_meta + 3 * (s ? p.nshift[0] : 0), (const double*)bf.shift + s);
+    }
+  }
   if (n64 > 0) {
     if (precision == TDVP_BF16X3) {
       const dim3 g(n64), bl(256);
       if (bf.shift) {
-        if (heff) hipLaunchKernelGGL((heff_gemm_b3<true>), g, bl, 0, ctx->stream, bf, C, part, d_tiles, arr.outs, arr.terms);
-        else hipLaunchKernelGGL((block_gemm_b3<true>), g, bl, 0, ctx->stream, bf, C, part, d_tiles, arr.outs, arr.terms);
+        if (heff) hipLaunchKernelGGL((heff_gemm_b3<true>), g, bl, 0, ctx->stream, bf, sl, C, part, d_tiles, arr.outs, arr.terms);
+        else hipLaunchKernelGGL((block_gemm_b3<true>), g, bl, 0, ctx->stream, bf, sl, C, part, d_tiles, arr.outs, arr.terms);
       } else {
-        if (heff) hipLaunchKernelGGL((heff_gemm_b3<false>), g, bl, 0, ctx->stream, bf, C, part, d_tiles, arr.outs, arr.terms);
-        else hipLaunchKernelGGL((block_gemm_b3<false>), g, bl, 0, ctx->stream, bf, C, part, d_tiles, arr.outs, arr.terms);
+        if (heff) hipLaunchKernelGGL((heff_gemm_b3<false>), g, bl, 0, ctx->stream, bf, sl, C, part, d_tiles, arr.outs, arr.terms);
+        else hipLaunchKernelGGL((block_gemm_b3<false>), g, bl, 0, ctx->stream, bf, sl, C, part, d_tiles, arr.outs, arr.terms);
       }
     } else if (precision == TDVP_FP32) {
       launch_one<float, 2, 2>(ctx, heff, n64, bf, C, part, d_tiles, arr);

@@ -87,14 +87,22 @@ int krylov_core(tdvp_ctx* ctx, int64_t n, double* x, const std::function<int(con
   out = KrylovResult();
   if (n == 0) return TDVP_OK;
   const int64_t stride = n;
-  // basis v_0..v_{maxdim-1}, w, and the fixed operator input of the graph
+  // basis v_0..v_{maxdim-1} (complex128, or complex64 with the FP32 basis
+  // storage), w, and the FP64 operator input Xg: the current basis vector,
+  // which the graph reads from a fixed address and which the complex64 basis
+  // keeps in full precision (the recurrence itself stays in FP64; only the
+  // re-orthogonalisation and the final combination read the rounded copies)
+  const bool v32 = ctx->krylov_fp32;
   const bool try_graph = capturable && ctx->graphs && maxdim > 1;
-  TDVP_HIP(ctx, ctx->ws_krylov.ensure(sizeof(double) * 2 * (size_t)stride * (maxdim + (try_graph ? 2 : 1))));
+  const bool own_x = try_graph || v32;
+  const size_t vbytes = (v32 ? sizeof(float) : sizeof(double)) * 2 * (size_t)stride * maxdim;
+  const size_t vpad = (vbytes + 255) & ~(size_t)255;
+  TDVP_HIP(ctx, ctx->ws_krylov.ensure(vpad + sizeof(double) * 2 * (size_t)stride * (own_x ? 2 : 1)));
   TDVP_HIP(ctx, ctx->ws_small.ensure(1 << 16));
   if (try_graph) TDVP_HIP(ctx, ctx->ws_lanczos.ensure(lanczos_partial_bytes(n, maxdim)));
   double* V = (double*)ctx->ws_krylov.p;
-  double* W = V + 2 * stride * maxdim;
-  double* Xg = try_graph ? W + 2 * stride : nullptr;
+  double* W = (double*)((char*)ctx->ws_krylov.p + vpad);
+  double* Xg = own_x ? W + 2 * stride : nullptr;
   double* d_small = (double*)ctx->ws_small.p;
   double* h_small = (double*)ctx->host_small;
   double* d_c1 = d_small;          // 2*64
@@ -107,8 +115,9 @@ int krylov_core(tdvp_ctx* ctx, int64_t n, double* x, const std::function<int(con
 
   // v0 = x / |x|
   int rc;
-  TDVP_HIP(ctx, hipMemcpyAsync(V, x, sizeof(double) * 2 * n, hipMemcpyDeviceToDevice, ctx->stream));
-  if ((rc = vec_norm2(ctx, V, n, d_nrm))) return rc;
+  double* x0 = v32 ? Xg : V;   // FP64 copy of v0
+  TDVP_HIP(ctx, hipMemcpyAsync(x0, x, sizeof(double) * 2 * n, hipMemcpyDeviceToDevice, ctx->stream));
+  if ((rc = vec_norm2(ctx, x0, n, d_nrm))) return rc;
   TDVP_HIP(ctx, hipMemcpyAsync(h_small, d_nrm, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
   if (h_small[1] != 0.0 || !std::isfinite(h_small[0]))
@@ -119,25 +128,29 @@ int krylov_core(tdvp_ctx* ctx, int64_t n, double* x, const std::function<int(con
     out.converged = 1;
     return TDVP_OK;
   }
-  if ((rc = vec_scale_copy(ctx, V, V, 1.0 / nrm, n))) return rc;
+  if ((rc = vec_scale_copy(ctx, x0, x0, 1.0 / nrm, n))) return rc;
+  if (v32 && (rc = vec_store_basis32(ctx, V, x0, n))) return rc;
 
   std::vector<double> alpha, beta;
   std::vector<std::complex<double>> y;
   for (int j = 0; j < maxdim; ++j) {
-    double* vj = V + 2 * stride * j;
+    // FP64 operator input of this iteration: the basis slot itself, or Xg
+    // (always Xg with the complex64 basis, where it holds v_j in FP64)
+    double* vj = v32 ? Xg : V + 2 * stride * j;
     // from the second iteration on (workspaces sized), once the operator can
     // be recorded: capture one iteration and replay it from here on
     if (try_graph && !replay && j >= 1 && capturable()) {
       if ((rc = vec_set_index(ctx, d_j, j))) return rc;
-      TDVP_HIP(ctx, hipMemcpyAsync(Xg, vj, sizeof(double) * 2 * n, hipMemcpyDeviceToDevice, ctx->stream));
+      if (!v32) TDVP_HIP(ctx, hipMemcpyAsync(Xg, vj, sizeof(double) * 2 * n, hipMemcpyDeviceToDevice, ctx->stream));
       bool ok = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
       if (ok) {
         int crc = op(Xg, W);
-        if (!crc) crc = vec_lanczos_orth_it(ctx, W, V, stride, maxdim, n, d_j, d_c1, d_c2, d_nrm, ctx->ws_lanczos.p);
+        if (!crc)
+          crc = vec_lanczos_orth_it(ctx, W, V, stride, maxdim, n, d_j, d_c1, d_c2, d_nrm, ctx->ws_lanczos.p, v32);
         if (!crc && hipMemcpyAsync(h_small, d_small, 258 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream) !=
                         hipSuccess)
           crc = TDVP_E_HIP;
-        if (!crc) crc = vec_lanczos_advance_it(ctx, V, stride, Xg, W, n, d_nrm, d_j, maxdim);
+        if (!crc) crc = vec_lanczos_advance_it(ctx, V, stride, Xg, W, n, d_nrm, d_j, maxdim, v32);
         hipGraph_t g = nullptr;
         const hipError_t e = hipStreamEndCapture(ctx->stream, &g);
         graph.graph = g;
@@ -161,10 +174,10 @@ int krylov_core(tdvp_ctx* ctx, int64_t n, double* x, const std::function<int(con
       if ((rc = op(vj, W))) return rc;
       out.heff_flops += flops_per_apply;
       // two passes of classical Gram-Schmidt against v_0..v_j
-      if ((rc = vec_dots(ctx, V, stride, j + 1, W, n, d_c1))) return rc;
-      if ((rc = vec_subtract_combo(ctx, W, V, stride, j + 1, d_c1, n, nullptr))) return rc;
-      if ((rc = vec_dots(ctx, V, stride, j + 1, W, n, d_c2))) return rc;
-      if ((rc = vec_subtract_combo(ctx, W, V, stride, j + 1, d_c2, n, d_nrm))) return rc;
+      if ((rc = vec_dots(ctx, V, stride, j + 1, W, n, d_c1, v32))) return rc;
+      if ((rc = vec_subtract_combo(ctx, W, V, stride, j + 1, d_c1, n, nullptr, v32))) return rc;
+      if ((rc = vec_dots(ctx, V, stride, j + 1, W, n, d_c2, v32))) return rc;
+      if ((rc = vec_subtract_combo(ctx, W, V, stride, j + 1, d_c2, n, d_nrm, v32))) return rc;
       TDVP_HIP(ctx, hipMemcpyAsync(h_small, d_small, 258 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     }
     TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -192,16 +205,16 @@ int krylov_core(tdvp_ctx* ctx, int64_t n, double* x, const std::function<int(con
       }
       TDVP_HIP(ctx, hipMemcpyAsync(d_y, h_small + 512, sizeof(double) * 2 * (j + 1), hipMemcpyHostToDevice,
                                    ctx->stream));
-      if ((rc = vec_combo(ctx, x, V, stride, j + 1, d_y, n))) return rc;
+      if ((rc = vec_combo(ctx, x, V, stride, j + 1, d_y, n, v32))) return rc;
       TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
       if (!out.converged) return set_error(ctx, TDVP_E_NOCONV, "Krylov tolerance not reached within maxdim");
       return TDVP_OK;
     }
     beta.push_back(b);
     if (!replay) {   // v_{j+1} = w / |w| by the replayed iteration's own kernel (same rounding)
-      double* vn = V + 2 * stride * (j + 1);
+      double* vn = v32 ? Xg : V + 2 * stride * (j + 1);
       if ((rc = vec_set_index(ctx, d_j, j))) return rc;
-      if ((rc = vec_lanczos_advance_it(ctx, V, stride, vn, W, n, d_nrm, d_j, maxdim))) return rc;
+      if ((rc = vec_lanczos_advance_it(ctx, V, stride, vn, W, n, d_nrm, d_j, maxdim, v32))) return rc;
     }
   }
   return TDVP_OK;

@@ -26,6 +26,14 @@ namespace tdvp {
 struct Tensor {
   Blocks blk;
   DeviceBuffer buf;
+  // Host staging: while `staged`, the data lives in the pinned host buffer
+  // `host` (grow-only), the device buffer is given back and blk.data is null.
+  void* host = nullptr;
+  size_t host_cap = 0;
+  bool staged = false;
+  ~Tensor() {
+    if (host) (void)hipHostFree(host);
+  }
 };
 
 }  // namespace tdvp
@@ -48,10 +56,12 @@ double now() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// New contents are about to be written on the device: any staged copy is stale.
 int set_site_layout(tdvp_ctx* ctx, Tensor& t, const Bond& l, const Bond& r) {
   layout_site(l, r, t.blk);
   TDVP_HIP(ctx, t.buf.ensure(sizeof(double) * 2 * (size_t)std::max<int64_t>(t.blk.size, 1)));
   t.blk.data = t.buf.p;
+  t.staged = false;
   return TDVP_OK;
 }
 
@@ -59,6 +69,51 @@ int set_env_layout(tdvp_ctx* ctx, Tensor& t, const Bond& b) {
   layout_env(b, t.blk);
   TDVP_HIP(ctx, t.buf.ensure(sizeof(double) * 2 * (size_t)std::max<int64_t>(t.blk.size, 1)));
   t.blk.data = t.buf.p;
+  t.staged = false;
+  return TDVP_OK;
+}
+
+// Host staging (paper section S2.3 keeps only the active tensors on the GPU):
+// copy a tensor to pinned host memory on the context stream and give its
+// device memory back (the allocator orders reuse after the copy: torch's is
+// stream-ordered, hipFree waits for the device).
+int stage_out(tdvp_ctx* ctx, Tensor& t) {
+  if (t.staged || !t.buf.p) return TDVP_OK;
+  const size_t bytes = sizeof(double) * 2 * (size_t)std::max<int64_t>(t.blk.size, 1);
+  if (t.host_cap < bytes) {
+    if (t.host) {   // an earlier copy from this buffer may still be queued
+      TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+      TDVP_HIP(ctx, hipHostFree(t.host));
+      t.host = nullptr;
+      t.host_cap = 0;
+    }
+    TDVP_HIP(ctx, hipHostMalloc(&t.host, bytes));
+    t.host_cap = bytes;
+  }
+  TDVP_HIP(ctx, hipMemcpyAsync(t.host, t.buf.p, bytes, hipMemcpyDeviceToHost, ctx->stream));
+  t.buf.release();
+  t.blk.data = nullptr;
+  t.staged = true;
+  return TDVP_OK;
+}
+
+// Back to device memory (stream-ordered copy).
+int stage_in(tdvp_ctx* ctx, Tensor& t) {
+  if (!t.staged) return TDVP_OK;
+  const size_t bytes = sizeof(double) * 2 * (size_t)std::max<int64_t>(t.blk.size, 1);
+  TDVP_HIP(ctx, t.buf.ensure(bytes));
+  TDVP_HIP(ctx, hipMemcpyAsync(t.buf.p, t.host, bytes, hipMemcpyHostToDevice, ctx->stream));
+  t.blk.data = t.buf.p;
+  t.staged = false;
+  return TDVP_OK;
+}
+
+// Every tensor of the MPS on the device (calls that read the whole chain).
+int unstage_all(tdvp_ctx* ctx, const tdvp_mps* m) {
+  for (auto* v : {&m->site, &m->Lenv, &m->Renv})
+    for (auto& t : *v)
+      if (t)
+        if (int rc = stage_in(ctx, *t)) return rc;
   return TDVP_OK;
 }
 
@@ -1086,6 +1141,7 @@ int tdvp_mps_site_layout(const tdvp_mps* m, int32_t k, int32_t* nblocks, int32_t
 
 int tdvp_mps_site_read(tdvp_ctx* ctx, const tdvp_mps* m, int32_t k, void* host_dst) {
   if (!ctx || !m || !host_dst || k < 1 || k > m->L) return set_error(ctx, TDVP_E_INVALID, "bad arguments");
+  if (int rc = stage_in(ctx, *m->site[k - 1])) return rc;
   const Blocks& b = m->site[k - 1]->blk;
   TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
   TDVP_HIP(ctx, hipMemcpy(host_dst, b.data, sizeof(double) * 2 * b.size, hipMemcpyDeviceToHost));
@@ -1120,9 +1176,27 @@ int tdvp_sweep(tdvp_ctx* ctx, tdvp_mps* m, double dt, const tdvp_trunc* tr, tdvp
                    now() - tb, b.t_lanczos - a.t_lanczos, b.t_svd - a.t_svd, b.t_env - a.t_env);
       std::fflush(stderr);
     };
+    // host staging: the tensors of the bond being updated come to the device
+    // before it, and those the next bond does not read go back to host memory
+    // after it (a left-to-right step leaves L_{i-1}, R_{i+1} and A_i behind,
+    // a right-to-left one R_{i+1}, L_{i-1} and B_{i+1})
+    const bool staging = ctx->host_staging;
+    auto bring = [&](int i) -> int {
+      if (!staging) return TDVP_OK;
+      for (Tensor* t : {m->Lenv[i - 1].get(), m->Renv[i + 1].get(), m->site[i - 1].get(), m->site[i].get()})
+        if (int r = stage_in(ctx, *t)) return r;
+      return TDVP_OK;
+    };
+    auto park = [&](std::initializer_list<Tensor*> ts) -> int {
+      if (!staging) return TDVP_OK;
+      for (Tensor* t : ts)
+        if (int r = stage_out(ctx, *t)) return r;
+      return TDVP_OK;
+    };
     for (int i = 1; i <= L - 1; ++i) {
       double tb = now();
       tdvp_sweep_info before = inf;
+      if ((rc = bring(i))) return rc;
       if ((rc = merge(ctx, m, i, th))) return rc;
       if ((rc = check_finite(ctx, th, "merge", i))) return rc;
       if ((rc = timed(inf.t_lanczos, [&] {
@@ -1146,11 +1220,13 @@ int tdvp_sweep(tdvp_ctx* ctx, tdvp_mps* m, double dt, const tdvp_trunc* tr, tdvp
              })))
           return rc;
       }
+      if (i < L - 1 && (rc = park({m->Lenv[i - 1].get(), m->Renv[i + 1].get(), m->site[i - 1].get()}))) return rc;
       vlog("L->R", i, tb, before, inf, th.size);
     }
     for (int i = L - 1; i >= 1; --i) {
       double tb = now();
       tdvp_sweep_info before = inf;
+      if ((rc = bring(i))) return rc;
       if ((rc = merge(ctx, m, i, th))) return rc;
       if ((rc = timed(inf.t_lanczos, [&] {
              return evolve(ctx, m, i, 2, th, m->Lenv[i - 1]->blk, m->Renv[i + 1]->blk, -tau, *tr, &inf);
@@ -1169,6 +1245,7 @@ int tdvp_sweep(tdvp_ctx* ctx, tdvp_mps* m, double dt, const tdvp_trunc* tr, tdvp
              })))
           return rc;
       }
+      if (i > 1 && (rc = park({m->Renv[i + 1].get(), m->Lenv[i - 1].get(), m->site[i].get()}))) return rc;
       vlog("R->L", i, tb, before, inf, th.size);
     }
     TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -1206,6 +1283,7 @@ int tdvp_mps_measure(tdvp_ctx* ctx, const tdvp_mps* m, double* sz, double* docc,
     TDVP_HIP(ctx, hipSetDevice(ctx->device));
     const int L = m->L;
     int rc;
+    if ((rc = unstage_all(ctx, m))) return rc;
     // sector-diagonal layout of N on bond k
     auto nlayout = [](const Bond& b, Blocks& nb) {
       nb = Blocks();
@@ -1339,6 +1417,8 @@ int tdvp_mps_overlap(tdvp_ctx* ctx, const tdvp_mps* bra, const tdvp_mps* ket, do
     if (bra->L != ket->L) return set_error(ctx, TDVP_E_SHAPE, "chains of different length");
     if (bra->fragment || ket->fragment) return set_error(ctx, TDVP_E_INVALID, "a split result is not a chain");
     TDVP_HIP(ctx, hipSetDevice(ctx->device));
+    if (int r0 = unstage_all(ctx, bra)) return r0;
+    if (int r0 = unstage_all(ctx, ket)) return r0;
     const int L = ket->L;
     int rc;
     // environment layout on bond k: blocks keyed by the ket's sector index
@@ -1924,6 +2004,7 @@ int tdvp_sweep1(tdvp_ctx* ctx, tdvp_mps* m, double dt, const tdvp_trunc* tr, tdv
     if (m->fragment) return set_error(ctx, TDVP_E_INVALID, "a split result is not a chain");
     if (tr->krylov_maxdim < 1 || tr->krylov_maxdim > 64) return set_error(ctx, TDVP_E_INVALID, "bad krylov_maxdim");
     TDVP_HIP(ctx, hipSetDevice(ctx->device));
+    if (int r0 = unstage_all(ctx, m)) return r0;   // one-site sweeps keep every tensor on the device
     tdvp_sweep_info inf{};
     double t0 = now();
     const int L = m->L;

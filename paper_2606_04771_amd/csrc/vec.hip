@@ -137,6 +137,16 @@ __global__ __launch_bounds__(NT) void k_reflect_back(double2* __restrict__ G, in
   }
 }
 
+// Krylov basis vectors are stored as complex128 (double2) or, to halve the
+// basis memory, complex64 (float2); they are read and combined in FP64.
+__device__ __forceinline__ double2 ldv(const double2* p) { return *p; }
+__device__ __forceinline__ double2 ldv(const float2* p) {
+  const float2 v = *p;
+  return make_double2((double)v.x, (double)v.y);
+}
+__device__ __forceinline__ void stv(double2* p, double2 v) { *p = v; }
+__device__ __forceinline__ void stv(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
+
 int nblocks_for(int64_t n) {
   int64_t g = (n + NT * 4 - 1) / (NT * 4);
   if (g < 1) g = 1;
@@ -146,7 +156,8 @@ int nblocks_for(int64_t n) {
 
 // partial[k * G + g] = sum_{i in chunk g} conj(V_k[i]) w[i]: for k = blockIdx.y,
 // or, with d_j (index read on the device), for every k <= *d_j in turn
-__global__ __launch_bounds__(NT) void k_dots_partial(const double2* __restrict__ V, int64_t stride,
+template <typename VT>
+__global__ __launch_bounds__(NT) void k_dots_partial(const VT* __restrict__ V, int64_t stride,
                                                      const double2* __restrict__ w, int64_t n,
                                                      double2* __restrict__ partial, const int* __restrict__ d_j) {
   const int g = blockIdx.x, G = gridDim.x;
@@ -154,10 +165,10 @@ __global__ __launch_bounds__(NT) void k_dots_partial(const double2* __restrict__
   int64_t chunk = (n + G - 1) / G;
   int64_t lo = (int64_t)g * chunk, hi = lo + chunk < n ? lo + chunk : n;
   for (int k = kb; k < ke; ++k) {
-    const double2* v = V + (int64_t)k * stride;
+    const VT* v = V + (int64_t)k * stride;
     double re = 0.0, im = 0.0;
     for (int64_t i = lo + threadIdx.x; i < hi; i += NT) {
-      double2 a = v[i], b = w[i];
+      double2 a = ldv(v + i), b = w[i];
       re += a.x * b.x + a.y * b.y;
       im += a.x * b.y - a.y * b.x;
     }
@@ -185,7 +196,8 @@ __global__ __launch_bounds__(NT) void k_reduce(const double2* __restrict__ parti
 }
 
 // w -= sum_k c_k V_k ; optional partial |w|^2; with d_j, nv = *d_j + 1
-__global__ __launch_bounds__(NT) void k_sub_combo(double2* __restrict__ w, const double2* __restrict__ V,
+template <typename VT>
+__global__ __launch_bounds__(NT) void k_sub_combo(double2* __restrict__ w, const VT* __restrict__ V,
                                                   int64_t stride, int nv, const double* __restrict__ coef,
                                                   int64_t n, double2* __restrict__ partial,
                                                   const int* __restrict__ d_j) {
@@ -200,7 +212,7 @@ __global__ __launch_bounds__(NT) void k_sub_combo(double2* __restrict__ w, const
   for (int64_t i = lo + threadIdx.x; i < hi; i += NT) {
     double2 x = w[i];
     for (int k = 0; k < nv; ++k) {
-      double2 v = V[(int64_t)k * stride + i];
+      double2 v = ldv(V + (int64_t)k * stride + i);
       double cr = c[2 * k], ci = c[2 * k + 1];
       x.x -= cr * v.x - ci * v.y;
       x.y -= cr * v.y + ci * v.x;
@@ -215,7 +227,8 @@ __global__ __launch_bounds__(NT) void k_sub_combo(double2* __restrict__ w, const
   }
 }
 
-__global__ __launch_bounds__(NT) void k_combo(double2* __restrict__ out, const double2* __restrict__ V,
+template <typename VT>
+__global__ __launch_bounds__(NT) void k_combo(double2* __restrict__ out, const VT* __restrict__ V,
                                               int64_t stride, int nv, const double* __restrict__ coef,
                                               int64_t n) {
   __shared__ double c[2 * kMaxV];
@@ -224,7 +237,7 @@ __global__ __launch_bounds__(NT) void k_combo(double2* __restrict__ out, const d
   for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
     double2 x = make_double2(0.0, 0.0);
     for (int k = 0; k < nv; ++k) {
-      double2 v = V[(int64_t)k * stride + i];
+      double2 v = ldv(V + (int64_t)k * stride + i);
       double cr = c[2 * k], ci = c[2 * k + 1];
       x.x += cr * v.x - ci * v.y;
       x.y += cr * v.y + ci * v.x;
@@ -242,21 +255,27 @@ __global__ __launch_bounds__(NT) void k_scale_copy(double2* __restrict__ dst, co
 }
 
 // Next Lanczos vector w / sqrt(b2) into basis slot *d_j + 1 (when it exists)
-// and into the fixed operator input x; b2 = |w|^2 from the device.
-__global__ __launch_bounds__(NT) void k_advance(double2* __restrict__ V, int64_t stride, double2* __restrict__ x,
+// and into the fixed operator input x (FP64); b2 = |w|^2 from the device.
+template <typename VT>
+__global__ __launch_bounds__(NT) void k_advance(VT* __restrict__ V, int64_t stride, double2* __restrict__ x,
                                                 const double2* __restrict__ w, int64_t n,
                                                 const double* __restrict__ b2, const int* __restrict__ d_j,
                                                 int maxdim) {
   const double q = *b2;
   const double s = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
   const int j = *d_j;
-  double2* dst = j + 1 < maxdim ? V + (int64_t)(j + 1) * stride : nullptr;
+  VT* dst = j + 1 < maxdim ? V + (int64_t)(j + 1) * stride : nullptr;
   for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
     double2 v = w[i];
     v = make_double2(s * v.x, s * v.y);
     x[i] = v;
-    if (dst) dst[i] = v;
+    if (dst) stv(dst + i, v);
   }
+}
+
+// basis slot 0 (complex64) from an FP64 vector
+__global__ __launch_bounds__(NT) void k_store32(float2* __restrict__ dst, const double2* __restrict__ src, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) stv(dst + i, src[i]);
 }
 
 __global__ void k_set_index(int* __restrict__ d_j, int v, int add) {
@@ -361,21 +380,25 @@ int grid_1d(int64_t n) {
 }  // namespace
 
 int vec_dots(tdvp_ctx* ctx, const double* V, int64_t stride, int nv, const double* w, int64_t n,
-             double* d_out) {
+             double* d_out, bool v32) {
   if (nv <= 0) return TDVP_OK;
   int G = nblocks_for(n);
   size_t need = sizeof(double2) * (size_t)G * nv;
   TDVP_HIP(ctx, ctx->ws_vec.ensure(need));
   double2* partial = (double2*)ctx->ws_vec.p;
-  hipLaunchKernelGGL(k_dots_partial, dim3(G, nv), dim3(NT), 0, ctx->stream, (const double2*)V, stride,
-                     (const double2*)w, n, partial, (const int*)nullptr);
+  if (v32)
+    hipLaunchKernelGGL(k_dots_partial<float2>, dim3(G, nv), dim3(NT), 0, ctx->stream, (const float2*)V, stride,
+                       (const double2*)w, n, partial, (const int*)nullptr);
+  else
+    hipLaunchKernelGGL(k_dots_partial<double2>, dim3(G, nv), dim3(NT), 0, ctx->stream, (const double2*)V, stride,
+                       (const double2*)w, n, partial, (const int*)nullptr);
   hipLaunchKernelGGL(k_reduce, dim3(nv), dim3(NT), 0, ctx->stream, partial, G, d_out, (const int*)nullptr);
   TDVP_HIP(ctx, hipGetLastError());
   return TDVP_OK;
 }
 
 int vec_subtract_combo(tdvp_ctx* ctx, double* w, const double* V, int64_t stride, int nv, const double* d_coef,
-                       int64_t n, double* d_norm2) {
+                       int64_t n, double* d_norm2, bool v32) {
   if (nv > kMaxV) return TDVP_E_INVALID;
   int G = nblocks_for(n);
   double2* partial = nullptr;
@@ -383,8 +406,12 @@ int vec_subtract_combo(tdvp_ctx* ctx, double* w, const double* V, int64_t stride
     TDVP_HIP(ctx, ctx->ws_vec.ensure(sizeof(double2) * (size_t)G));
     partial = (double2*)ctx->ws_vec.p;
   }
-  hipLaunchKernelGGL(k_sub_combo, dim3(G), dim3(NT), 0, ctx->stream, (double2*)w, (const double2*)V, stride, nv,
-                     d_coef, n, partial, (const int*)nullptr);
+  if (v32)
+    hipLaunchKernelGGL(k_sub_combo<float2>, dim3(G), dim3(NT), 0, ctx->stream, (double2*)w, (const float2*)V, stride,
+                       nv, d_coef, n, partial, (const int*)nullptr);
+  else
+    hipLaunchKernelGGL(k_sub_combo<double2>, dim3(G), dim3(NT), 0, ctx->stream, (double2*)w, (const double2*)V,
+                       stride, nv, d_coef, n, partial, (const int*)nullptr);
   if (d_norm2)
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(NT), 0, ctx->stream, partial, G, d_norm2, (const int*)nullptr);
   TDVP_HIP(ctx, hipGetLastError());
@@ -399,10 +426,14 @@ int vec_scale_copy(tdvp_ctx* ctx, double* dst, const double* src, double s, int6
 }
 
 int vec_combo(tdvp_ctx* ctx, double* out, const double* V, int64_t stride, int nv, const double* d_coef,
-              int64_t n) {
+              int64_t n, bool v32) {
   if (nv > kMaxV) return TDVP_E_INVALID;
-  hipLaunchKernelGGL(k_combo, dim3(grid_1d(n)), dim3(NT), 0, ctx->stream, (double2*)out, (const double2*)V,
-                     stride, nv, d_coef, n);
+  if (v32)
+    hipLaunchKernelGGL(k_combo<float2>, dim3(grid_1d(n)), dim3(NT), 0, ctx->stream, (double2*)out, (const float2*)V,
+                       stride, nv, d_coef, n);
+  else
+    hipLaunchKernelGGL(k_combo<double2>, dim3(grid_1d(n)), dim3(NT), 0, ctx->stream, (double2*)out,
+                       (const double2*)V, stride, nv, d_coef, n);
   TDVP_HIP(ctx, hipGetLastError());
   return TDVP_OK;
 }
@@ -417,17 +448,25 @@ size_t lanczos_partial_bytes(int64_t n, int maxdim) {
 // two classical Gram-Schmidt passes of W against V_0..V_j: coefficients to
 // c1 and c2 (2 * maxdim doubles each), |W|^2 after the second pass to d_norm2
 int vec_lanczos_orth_it(tdvp_ctx* ctx, double* W, const double* V, int64_t stride, int maxdim, int64_t n,
-                        const int* d_j, double* c1, double* c2, double* d_norm2, void* partial_buf) {
+                        const int* d_j, double* c1, double* c2, double* d_norm2, void* partial_buf, bool v32) {
   if (maxdim > kMaxV) return TDVP_E_INVALID;
   const int G = nblocks_for(n);
   double2* partial = (double2*)partial_buf;
   double* cs[2] = {c1, c2};
   for (int pass = 0; pass < 2; ++pass) {
-    hipLaunchKernelGGL(k_dots_partial, dim3(G), dim3(NT), 0, ctx->stream, (const double2*)V, stride,
-                       (const double2*)W, n, partial, d_j);
+    if (v32)
+      hipLaunchKernelGGL(k_dots_partial<float2>, dim3(G), dim3(NT), 0, ctx->stream, (const float2*)V, stride,
+                         (const double2*)W, n, partial, d_j);
+    else
+      hipLaunchKernelGGL(k_dots_partial<double2>, dim3(G), dim3(NT), 0, ctx->stream, (const double2*)V, stride,
+                         (const double2*)W, n, partial, d_j);
     hipLaunchKernelGGL(k_reduce, dim3(maxdim), dim3(NT), 0, ctx->stream, partial, G, cs[pass], d_j);
-    hipLaunchKernelGGL(k_sub_combo, dim3(G), dim3(NT), 0, ctx->stream, (double2*)W, (const double2*)V, stride, 0,
-                       (const double*)cs[pass], n, pass == 1 ? partial : nullptr, d_j);
+    if (v32)
+      hipLaunchKernelGGL(k_sub_combo<float2>, dim3(G), dim3(NT), 0, ctx->stream, (double2*)W, (const float2*)V,
+                         stride, 0, (const double*)cs[pass], n, pass == 1 ? partial : nullptr, d_j);
+    else
+      hipLaunchKernelGGL(k_sub_combo<double2>, dim3(G), dim3(NT), 0, ctx->stream, (double2*)W, (const double2*)V,
+                         stride, 0, (const double*)cs[pass], n, pass == 1 ? partial : nullptr, d_j);
   }
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(NT), 0, ctx->stream, partial, G, d_norm2, (const int*)nullptr);
   TDVP_HIP(ctx, hipGetLastError());
@@ -436,10 +475,20 @@ int vec_lanczos_orth_it(tdvp_ctx* ctx, double* W, const double* V, int64_t strid
 
 // x = V_{j+1} = W / sqrt(b2) (the basis slot only while j + 1 < maxdim), then j += 1
 int vec_lanczos_advance_it(tdvp_ctx* ctx, double* V, int64_t stride, double* x, const double* W, int64_t n,
-                           const double* d_b2, int* d_j, int maxdim) {
-  hipLaunchKernelGGL(k_advance, dim3(grid_1d(n)), dim3(NT), 0, ctx->stream, (double2*)V, stride, (double2*)x,
-                     (const double2*)W, n, d_b2, (const int*)d_j, maxdim);
+                           const double* d_b2, int* d_j, int maxdim, bool v32) {
+  if (v32)
+    hipLaunchKernelGGL(k_advance<float2>, dim3(grid_1d(n)), dim3(NT), 0, ctx->stream, (float2*)V, stride,
+                       (double2*)x, (const double2*)W, n, d_b2, (const int*)d_j, maxdim);
+  else
+    hipLaunchKernelGGL(k_advance<double2>, dim3(grid_1d(n)), dim3(NT), 0, ctx->stream, (double2*)V, stride,
+                       (double2*)x, (const double2*)W, n, d_b2, (const int*)d_j, maxdim);
   hipLaunchKernelGGL(k_set_index, dim3(1), dim3(64), 0, ctx->stream, d_j, 1, 1);
+  TDVP_HIP(ctx, hipGetLastError());
+  return TDVP_OK;
+}
+
+int vec_store_basis32(tdvp_ctx* ctx, double* V32, const double* x, int64_t n) {
+  hipLaunchKernelGGL(k_store32, dim3(grid_1d(n)), dim3(NT), 0, ctx->stream, (float2*)V32, (const double2*)x, n);
   TDVP_HIP(ctx, hipGetLastError());
   return TDVP_OK;
 }
