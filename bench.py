@@ -189,6 +189,54 @@ def large_heff(args, T, torch, stream, ctx, model, late=False):
     return res
 
 
+def u1_heff(args, T, torch, stream, ctx, model, chi):
+    """H_eff.Theta of the abelian U(1) x U(1) variant at the middle bond of
+    L = 60 with the same full-state bond dimension: sectors (N, 2S^z) around
+    half filling (synth.u1_profile), environments and Theta complex normal;
+    FP64 and FP32 block products."""
+    import numpy as np
+    import synth
+    site = 30
+    left = synth.u1_profile(chi, 7919 * (site - 1), site - 1)
+    right = synth.u1_profile(chi, 7919 * (site + 1), site + 1)
+    bl, br = T.Bond(left), T.Bond(right)
+    xk, xo, xt, xd = T.center_layout(bl, br, 2, abelian=True)
+    lk, lo, lt, ld = T.env_layout(bl, abelian=True)
+    rk, ro, rt, rd = T.env_layout(br, abelian=True)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(args.seed + 71)
+    draw = lambda n: torch.randn(max(n, 1), dtype=torch.complex128, device="cuda", generator=gen)
+    x_d, L_d, R_d = draw(xt), draw(lt), draw(rt)
+    y_d = torch.zeros_like(x_d)
+    torch.cuda.synchronize()
+    Lb = T.Blocks(lk, lo, L_d.data_ptr(), lt)
+    Rb = T.Blocks(rk, ro, R_d.data_ptr(), rt)
+    xb = T.Blocks(xk, xo, x_d.data_ptr(), xt)
+    yb = T.Blocks(xk, xo, y_d.data_ptr(), xt)
+    _, flops = T.heff_plan(model, site, 2, bl, br, Lb, Rb, xb, abelian=True)
+    res = {"workload": f"chi={chi} L=60 middle bond, U(1)xU(1) sectors (N, 2Sz) around half filling",
+           "sectors": len(left), "blocks": len(xk), "theta_elems": int(xt), "flops_per_apply": flops}
+    for name, p, warm, reps in (("fp64", T.FP64, 10, 10), ("fp32", T.FP32, 5, 10)):
+        ctx.set_precision(p)
+        for _ in range(warm):
+            ctx.heff_apply(model, site, 2, bl, br, Lb, Rb, xb, yb, abelian=True)
+        ctx.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            ctx.heff_apply(model, site, 2, bl, br, Lb, Rb, xb, yb, abelian=True)
+        b.record(stream)
+        ctx.synchronize()
+        dt = a.elapsed_time(b) * 1e-3 / reps
+        res[name] = {"ms_per_apply": 1e3 * dt, "tflops": flops / dt / 1e12}
+        print(f"bench: U(1)xU(1) chi={chi} H_eff {name} {1e3 * dt:.2f} ms, {flops / dt / 1e12:.2f} TFLOP/s",
+              file=sys.stderr, flush=True)
+    ctx.set_precision(T.FP64 if args.prec == "fp64" else T.FP32)
+    del x_d, y_d, L_d, R_d
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -204,6 +252,10 @@ def main():
     ap.add_argument("--one-site-steps", type=int, default=2, help="one-site sweeps timed after the two-site ones")
     ap.add_argument("--no-large", action="store_true", help="skip the chi=16384 grouped-vs-per-block measurement")
     ap.add_argument("--no-late", action="store_true", help="skip the chi~62000 H_eff throughput measurement")
+    ap.add_argument("--no-abelian", action="store_true", help="skip the U(1)xU(1) H_eff measurement")
+    ap.add_argument("--krylov-probe", type=int, default=0,
+                    help="only run Krylov exponentials of exactly this many iterations at the middle bond "
+                         "(Lanczos vector-kernel profile)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB three times (reference for the HBM byte counters)")
@@ -305,6 +357,34 @@ def main():
         d = np.array([a.elapsed_time(b) * 1e-3 for a, b in evs])
         return d, y_d.cpu().numpy()
 
+    if args.krylov_probe:
+        # Lanczos vector kernels at a fixed size: exponentials of exactly
+        # krylov_probe iterations (tol 0) on the middle-bond problem, graph
+        # replay on; the per-kernel durations come from a kernel trace of
+        # this mode.
+        m = args.krylov_probe
+        ctx.set_precision(T.FP64)
+        t_it = []
+        for rep in range(4):
+            x_d.copy_(dev(pack(xs, xk, xo, xt)))
+            torch.cuda.synchronize()
+            t0 = time.time()
+            rc, info = ctx.krylov_expm(model, site, 2, left, right, Lb, Rb, xb, -0.025j, tol=0.0, maxdim=m,
+                                       check=False)
+            t_it.append((time.time() - t0) / max(info["iters"], 1))
+            print(f"bench: krylov probe {rep}: {info['iters']} iterations ({info['graph_iters']} replayed), "
+                  f"{1e3 * t_it[-1]:.3f} ms per iteration", file=sys.stderr, flush=True)
+        n = int(xt)
+        # algorithmic HBM bytes of the two Gram-Schmidt passes of iteration j
+        # (16 B per complex element): dots read v_0..v_j and w, the update
+        # reads w and v_0..v_j and writes w
+        per_it = [2 * ((j + 2) + (j + 3)) * 16 * n for j in range(m - 1)]
+        print(json.dumps({"krylov_probe": {"iterations": m, "theta_elems": n, "ms_per_iteration":
+                                           1e3 * float(np.median(t_it[1:])),
+                                           "gs_bytes_per_iteration_mean": float(np.mean(per_it))}}), flush=True)
+        ctx.close()
+        return
+
     heff_by_prec = {}
     ys = {}
     for name, p in (("fp64", T.FP64), ("fp32", T.FP32), ("bf16x3", T.BF16X3)):
@@ -329,6 +409,10 @@ def main():
     late = None
     if not args.no_late:
         late = large_heff(args, T, torch, stream, ctx, model, late=True)
+    abelian = None
+    if not args.no_abelian:
+        abelian = u1_heff(args, T, torch, stream, ctx, model, chi)
+        abelian["su2_over_u1_time"] = heff_by_prec["fp64"]["ms_per_apply"] / abelian["fp64"]["ms_per_apply"]
 
     # ---- full sweeps: the step at the working precision, and the mixed path
     # (FP32 block products, FP64 Lanczos / SVD) from the same initial state ----
@@ -514,6 +598,7 @@ def main():
         "mixed": mixed,
         "large_blocks": large,
         "late_time_blocks": late,
+        "u1xu1_heff": abelian,
     }
     line.update(sweep)
     print(json.dumps(line), flush=True)

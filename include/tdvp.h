@@ -438,6 +438,45 @@ int tdvp_split(tdvp_ctx* ctx, const tdvp_bond* left, const tdvp_bond* right, con
  * support. */
 int tdvp_sweep1(tdvp_ctx* ctx, tdvp_mps* mps, double dt, const tdvp_trunc* trunc, tdvp_sweep_info* info);
 
+/* ---- abelian U(1) x U(1) variant ---------------------------------------------
+ * The paper's comparison symmetry (Table 1, Table S1: the same quench with
+ * only the U(1) charge and spin symmetries): the same operations on the same
+ * grouped-GEMM kernels and Lanczos core, with every recoupling coefficient a
+ * plain local matrix element.  Conventions:
+ *   bonds: tdvp_bond with q[i] = 2 S^z and tj[i] = N (particle number) of
+ *     everything left of the bond; N - 2 S^z even, |2 S^z| <= N.
+ *   local states s = n_up + 2 n_dn: 0 = |0>, 1 = |up>, 2 = |dn>,
+ *     3 = |up dn> = c+_up c+_dn |0> (Jordan-Wigner mode order 1up, 1dn, 2up..).
+ *   keys: one-site (ia, s, ib); two-site (ia, s1, s2, ib); blocks d_a x d_b,
+ *     the full tensor restricted to the sector pair (no Clebsch-Gordan factor).
+ *   environments: keys (iout, w, iin), w = 0 the block Hamiltonian, w = 1..4
+ *     one component each of the doublet edge operators of the U(1) x SU(2)
+ *     environments above: w = 1, 2 the components kappa = +1/2, -1/2 of D+,
+ *     w = 3, 4 those of D- (left block: c+_up P, (-1)^k c_dn P, c+_dn P,
+ *     -(-1)^k c_up P on its last site k; right block: the partners
+ *     Q^w on its first site), so that a left block's environment is the
+ *     full <Phi'| O |Phi> cut into sector blocks.
+ * Same Hamiltonian (particle-hole symmetric interaction), memory layout,
+ * ownership, synchronisation and errors as the U(1) x SU(2) calls. */
+int tdvp_u1_center_layout(const tdvp_bond* left, const tdvp_bond* right, int32_t nsites, int32_t* nblocks,
+                          int32_t* keys, int64_t* offsets, int64_t* total);
+int tdvp_u1_env_layout(const tdvp_bond* bond, int32_t* nblocks, int32_t* keys, int64_t* offsets, int64_t* total);
+int tdvp_u1_heff_plan(const tdvp_model* model, int32_t site, int32_t nsites, const tdvp_bond* left,
+                      const tdvp_bond* right, const tdvp_blocks* Lenv, const tdvp_blocks* Renv, const tdvp_blocks* x,
+                      int64_t* nterms, tdvp_term* terms, double* flops);
+int tdvp_u1_env_plan(const tdvp_model* model, int32_t site, int32_t direction, const tdvp_bond* bond_in,
+                     const tdvp_bond* bond_out, const tdvp_blocks* env_in, const tdvp_blocks* tensor,
+                     const tdvp_blocks* env_out, int64_t* nterms, tdvp_env_term* terms, double* flops);
+int tdvp_u1_heff_apply(tdvp_ctx* ctx, const tdvp_model* model, int32_t site, int32_t nsites, const tdvp_bond* left,
+                       const tdvp_bond* right, const tdvp_blocks* Lenv, const tdvp_blocks* Renv, const tdvp_blocks* x,
+                       tdvp_blocks* y);
+int tdvp_u1_krylov_expm(tdvp_ctx* ctx, const tdvp_model* model, int32_t site, int32_t nsites, const tdvp_bond* left,
+                        const tdvp_bond* right, const tdvp_blocks* Lenv, const tdvp_blocks* Renv, tdvp_blocks* x,
+                        double tau_re, double tau_im, double tol, int32_t maxdim, tdvp_krylov_info* info);
+int tdvp_u1_env_update(tdvp_ctx* ctx, const tdvp_model* model, int32_t site, int32_t direction,
+                       const tdvp_bond* bond_in, const tdvp_bond* bond_out, const tdvp_blocks* env_in,
+                       const tdvp_blocks* tensor, tdvp_blocks* env_out);
+
 /* Site-resolved observables of the quench (the local densities the paper
  * follows in time, main text results section): for every site k in 1..L,
  * sz[k-1] = <S^z_k> = (<n_k,up> - <n_k,down>)/2 and docc[k-1] =

@@ -99,6 +99,13 @@ def _load():
         "tdvp_env_update": [P, P, I32, I32, P, P, P, P, P],
         "tdvp_env_update_noalloc": [P, P, I32, I32, P, P, P, P, P],
         "tdvp_env_plan": [P, I32, I32, P, P, P, P, P, P, P, P],
+        "tdvp_u1_center_layout": [P, P, I32, P, P, P, P],
+        "tdvp_u1_env_layout": [P, P, P, P, P],
+        "tdvp_u1_heff_plan": [P, I32, I32, P, P, P, P, P, P, P, P],
+        "tdvp_u1_env_plan": [P, I32, I32, P, P, P, P, P, P, P, P],
+        "tdvp_u1_heff_apply": [P, P, I32, I32, P, P, P, P, P, P],
+        "tdvp_u1_krylov_expm": [P, P, I32, I32, P, P, P, P, P, D, D, D, I32, P],
+        "tdvp_u1_env_update": [P, P, I32, I32, P, P, P, P, P],
         "tdvp_mps_create": [P, P, P, P, P],
         "tdvp_mps_create_neel": [P, P, I32, P],
         "tdvp_mps_destroy": [P],
@@ -205,51 +212,57 @@ class Blocks:
         return len(self.offsets)
 
 
-def center_layout(left, right, nsites):
-    """Canonical blocks of a centre tensor: (keys, offsets, total, dims)."""
+def center_layout(left, right, nsites, abelian=False):
+    """Canonical blocks of a centre tensor: (keys, offsets, total, dims).
+    abelian: the U(1) x U(1) variant (bonds (2Sz, N, d); two-site keys
+    (ia, s1, s2, ib))."""
+    f = lib.tdvp_u1_center_layout if abelian else lib.tdvp_center_layout
     n = C.c_int32()
     tot = C.c_int64()
-    _check(lib.tdvp_center_layout(left.ref, right.ref, nsites, C.byref(n), None, None, C.byref(tot)))
-    kl = 5 if nsites == 2 else 3
+    _check(f(left.ref, right.ref, nsites, C.byref(n), None, None, C.byref(tot)))
+    kl = (4 if abelian else 5) if nsites == 2 else 3
     keys = np.zeros((n.value, kl), np.int32)
     offs = np.zeros(n.value, np.int64)
-    _check(lib.tdvp_center_layout(left.ref, right.ref, nsites, C.byref(n), _ptr(keys), _ptr(offs), C.byref(tot)))
+    _check(f(left.ref, right.ref, nsites, C.byref(n), _ptr(keys), _ptr(offs), C.byref(tot)))
     dims = [(left.sectors[k[0]][2], right.sectors[k[-1]][2]) for k in keys]
     return keys, offs, tot.value, dims
 
 
-def env_layout(bond):
+def env_layout(bond, abelian=False):
+    f = lib.tdvp_u1_env_layout if abelian else lib.tdvp_env_layout
     n = C.c_int32()
     tot = C.c_int64()
-    _check(lib.tdvp_env_layout(bond.ref, C.byref(n), None, None, C.byref(tot)))
+    _check(f(bond.ref, C.byref(n), None, None, C.byref(tot)))
     keys = np.zeros((n.value, 3), np.int32)
     offs = np.zeros(n.value, np.int64)
-    _check(lib.tdvp_env_layout(bond.ref, C.byref(n), _ptr(keys), _ptr(offs), C.byref(tot)))
+    _check(f(bond.ref, C.byref(n), _ptr(keys), _ptr(offs), C.byref(tot)))
     dims = [(bond.sectors[k[0]][2], bond.sectors[k[2]][2]) for k in keys]
     return keys, offs, tot.value, dims
 
 
-def heff_plan(model, site, nsites, left, right, Lenv, Renv, x):
+def heff_plan(model, site, nsites, left, right, Lenv, Renv, x, abelian=False):
     """Host-side term list of one H_eff apply: structured array with fields
     kind, out, in_, env, coef; and the algorithmic flop count."""
+    f = lib.tdvp_u1_heff_plan if abelian else lib.tdvp_heff_plan
     nt = C.c_int64(0)
     fl = C.c_double()
-    _check(lib.tdvp_heff_plan(model.ref, site, nsites, left.ref, right.ref, Lenv.ref, Renv.ref, x.ref,
-                              C.byref(nt), None, C.byref(fl)))
+    _check(f(model.ref, site, nsites, left.ref, right.ref, Lenv.ref, Renv.ref, x.ref, C.byref(nt), None,
+             C.byref(fl)))
     arr = (_Term * nt.value)()
-    _check(lib.tdvp_heff_plan(model.ref, site, nsites, left.ref, right.ref, Lenv.ref, Renv.ref, x.ref,
-                              C.byref(nt), arr, C.byref(fl)))
+    _check(f(model.ref, site, nsites, left.ref, right.ref, Lenv.ref, Renv.ref, x.ref, C.byref(nt), arr,
+             C.byref(fl)))
     return [(t.kind, t.out, t.in_, t.env, t.coef) for t in arr], fl.value
 
 
-def env_plan(model, site, direction, bond_in, bond_out, env_in, tensor, env_out):
+def env_plan(model, site, direction, bond_in, bond_out, env_in, tensor, env_out, abelian=False):
+    f = lib.tdvp_u1_env_plan if abelian else lib.tdvp_env_plan
     nt = C.c_int64(0)
     fl = C.c_double()
-    _check(lib.tdvp_env_plan(model.ref, site, direction, bond_in.ref, bond_out.ref, env_in.ref, tensor.ref,
-                             env_out.ref, C.byref(nt), None, C.byref(fl)))
+    _check(f(model.ref, site, direction, bond_in.ref, bond_out.ref, env_in.ref, tensor.ref, env_out.ref,
+             C.byref(nt), None, C.byref(fl)))
     arr = (_EnvTerm * nt.value)()
-    _check(lib.tdvp_env_plan(model.ref, site, direction, bond_in.ref, bond_out.ref, env_in.ref, tensor.ref,
-                             env_out.ref, C.byref(nt), arr, C.byref(fl)))
+    _check(f(model.ref, site, direction, bond_in.ref, bond_out.ref, env_in.ref, tensor.ref, env_out.ref,
+             C.byref(nt), arr, C.byref(fl)))
     return [(t.kind, t.out, t.bra, t.ket, t.env, t.coef) for t in arr], fl.value
 
 
@@ -369,25 +382,26 @@ class Context:
     def synchronize(self):
         _check(lib.tdvp_ctx_synchronize(self.h), self.h)
 
-    def heff_apply(self, model, site, nsites, left, right, Lenv, Renv, x, y):
-        _check(lib.tdvp_heff_apply(self.h, model.ref, site, nsites, left.ref, right.ref, Lenv.ref, Renv.ref,
-                                   x.ref, y.ref), self.h)
+    def heff_apply(self, model, site, nsites, left, right, Lenv, Renv, x, y, abelian=False):
+        f = lib.tdvp_u1_heff_apply if abelian else lib.tdvp_heff_apply
+        _check(f(self.h, model.ref, site, nsites, left.ref, right.ref, Lenv.ref, Renv.ref, x.ref, y.ref), self.h)
 
     def krylov_expm(self, model, site, nsites, left, right, Lenv, Renv, x, tau, tol=1e-12, maxdim=40,
-                    check=True):
+                    check=True, abelian=False):
         info = _KrylovInfo()
-        rc = lib.tdvp_krylov_expm(self.h, model.ref, site, nsites, left.ref, right.ref, Lenv.ref, Renv.ref,
-                                  x.ref, float(np.real(tau)), float(np.imag(tau)), float(tol), int(maxdim),
-                                  C.byref(info))
+        f = lib.tdvp_u1_krylov_expm if abelian else lib.tdvp_krylov_expm
+        rc = f(self.h, model.ref, site, nsites, left.ref, right.ref, Lenv.ref, Renv.ref, x.ref,
+               float(np.real(tau)), float(np.imag(tau)), float(tol), int(maxdim), C.byref(info))
         if check:
             _check(rc, self.h)
         return rc, {"iters": info.iters, "converged": bool(info.converged), "err": info.err_est,
                     "norm": info.norm_in, "alpha": list(info.alpha[:info.iters]),
                     "beta": list(info.beta[:info.iters]), "graph_iters": info.graph_iters}
 
-    def env_update(self, model, site, direction, bond_in, bond_out, env_in, tensor, env_out):
-        _check(lib.tdvp_env_update(self.h, model.ref, site, direction, bond_in.ref, bond_out.ref, env_in.ref,
-                                   tensor.ref, env_out.ref), self.h)
+    def env_update(self, model, site, direction, bond_in, bond_out, env_in, tensor, env_out, abelian=False):
+        f = lib.tdvp_u1_env_update if abelian else lib.tdvp_env_update
+        _check(f(self.h, model.ref, site, direction, bond_in.ref, bond_out.ref, env_in.ref, tensor.ref,
+                 env_out.ref), self.h)
 
     def env_update_noalloc(self, model, site, direction, bond_in, bond_out, env_in, tensor, env_out):
         _check(lib.tdvp_env_update_noalloc(self.h, model.ref, site, direction, bond_in.ref, bond_out.ref,

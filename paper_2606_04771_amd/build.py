@@ -13,10 +13,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtdvp.so")
-SOURCES = ["symm.cpp", "plan.cpp", "common.cpp", "capi_host.cpp", "tridiag.cpp", "capi_dev.cpp",
+SOURCES = ["symm.cpp", "plan.cpp", "abelian.cpp", "common.cpp", "capi_host.cpp", "tridiag.cpp", "capi_dev.cpp",
+           "capi_u1.cpp",
            "krylov.cpp", "sweep.cpp", "gemm.hip", "vec.hip", "noalloc.hip"]
 # host sources that launch kernels or use HIP device types are compiled as HIP
-HIP_CPP = ("capi_dev.cpp", "krylov.cpp", "sweep.cpp")
+HIP_CPP = ("capi_dev.cpp", "capi_u1.cpp", "krylov.cpp", "sweep.cpp")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

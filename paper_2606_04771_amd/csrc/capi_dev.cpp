@@ -91,11 +91,13 @@ std::shared_ptr<Program> heff_program(tdvp_ctx* ctx, const tdvp_model& m, int si
   hs.blocks(y);
   hs.addd(ctx->split_alpha);
   hs.add((uint64_t)ctx->split_kmin);
+  hs.add((uint64_t)in.sym);
   rc = TDVP_OK;
   if (auto p = cache_get(ctx, hs.h, hs.sig)) return p;
   std::vector<HTerm> terms;
   double flops = 0;
-  plan_heff(m, site, nsites, in.l, in.r, in.Le, in.Re, in.x, terms, flops);
+  if (in.sym == 1) u1_plan_heff(m, site, nsites, in.l, in.r, in.Le, in.Re, in.x, terms, flops);
+  else plan_heff(m, site, nsites, in.l, in.r, in.Le, in.Re, in.x, terms, flops);
   std::stable_sort(terms.begin(), terms.end(), [](const HTerm& a, const HTerm& b) { return a.out < b.out; });
   auto p = std::make_shared<Program>();
   p->flops = flops;
@@ -163,7 +165,7 @@ std::shared_ptr<Program> heff_program(tdvp_ctx* ctx, const tdvp_model& m, int si
       if (k[1] != 0 || k[0] != k[2] || E[s]->rows[i] != E[s]->cols[i]) continue;
       p->shift_meta.push_back(E[s]->off[i]);
       p->shift_meta.push_back(E[s]->rows[i]);
-      p->shift_meta.push_back(B[s]->tj[k[0]] + 1);
+      p->shift_meta.push_back(in.sym == 1 ? 1 : B[s]->tj[k[0]] + 1);   // multiplet weight
       p->nshift[s]++;
     }
   p->finalize();
@@ -193,6 +195,7 @@ Hasher env_hash(tdvp_ctx* ctx, const tdvp_model& m, int site, int dir, const Env
   hs.blocks(in.eout);
   hs.addd(ctx->split_alpha);
   hs.add((uint64_t)ctx->split_kmin);
+  hs.add((uint64_t)in.sym);
   return hs;
 }
 
@@ -203,7 +206,8 @@ EnvPrograms build_env_programs(tdvp_ctx* ctx, const tdvp_model& m, int site, int
                                const Hasher& hs) {
   std::vector<ETerm> terms;
   double flops = 0;
-  plan_env(m, site, dir, in.bin, in.bout, in.ein, in.ten, in.eout, terms, flops);
+  if (in.sym == 1) u1_plan_env(m, site, dir, in.bin, in.bout, in.ein, in.ten, in.eout, terms, flops);
+  else plan_env(m, site, dir, in.bin, in.bout, in.ein, in.ten, in.eout, terms, flops);
   std::stable_sort(terms.begin(), terms.end(), [](const ETerm& a, const ETerm& b) { return a.out < b.out; });
   const Blocks &E = in.ein, &T = in.ten, &O = in.eout;
   // stage 1: one output per distinct (env, ket) pair

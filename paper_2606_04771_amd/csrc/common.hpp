@@ -30,9 +30,11 @@ int guarded(const tdvp_ctx* ctx, F&& f) {
   }
 }
 
+// sym: 0 = U(1) x SU(2) reduced tensors, 1 = the abelian U(1) x U(1) variant
 struct HeffInputs {
   Bond l, r;
   Blocks Le, Re, x;
+  int sym = 0;
 };
 int load_heff_inputs(HeffInputs& in, const tdvp_model* model, int site, int nsites, const tdvp_bond* left,
                      const tdvp_bond* right, const tdvp_blocks* Lenv, const tdvp_blocks* Renv,
@@ -41,9 +43,18 @@ int load_heff_inputs(HeffInputs& in, const tdvp_model* model, int site, int nsit
 struct EnvInputs {
   Bond bin, bout;
   Blocks ein, ten, eout;
+  int sym = 0;
 };
 int load_env_inputs(EnvInputs& in, const tdvp_model* model, int site, int dir, const tdvp_bond* bond_in,
                     const tdvp_bond* bond_out, const tdvp_blocks* env_in, const tdvp_blocks* tensor,
                     const tdvp_blocks* env_out, std::string& err);
+
+// The abelian U(1) x U(1) variant (bond q = 2 S^z, tj = N of the left block).
+int u1_load_heff_inputs(HeffInputs& in, const tdvp_model* model, int site, int nsites, const tdvp_bond* left,
+                        const tdvp_bond* right, const tdvp_blocks* Lenv, const tdvp_blocks* Renv,
+                        const tdvp_blocks* x, std::string& err);
+int u1_load_env_inputs(EnvInputs& in, const tdvp_model* model, int site, int dir, const tdvp_bond* bond_in,
+                       const tdvp_bond* bond_out, const tdvp_blocks* env_in, const tdvp_blocks* tensor,
+                       const tdvp_blocks* env_out, std::string& err);
 
 }  // namespace tdvp

@@ -402,31 +402,40 @@ __device__ __forceinline__ void gemm_body_b3(const Bufs& bufs, const Slices& sl,
         ti[i][j] = acc_t{0, 0, 0, 0};
       }
   };
-  // staging: this thread owns row sr of the A and B tiles and 8 consecutive k
+  // staging: this thread owns row sr of the A and B tiles and 8 consecutive k;
+  // the records of the next K step are loaded into registers while the
+  // matrix instructions of the current one run
   const int sr = tid % 64, kg = tid / 64;
   int t = tl.t0, k0 = tl.k0;
-  double ccur = before(t, k0, tl.t1, tl.k1) ? terms[t].coef : 0.0;
+  uint4 ra[8], rb[8];
+  auto load_records = [&](const DevTerm& tm, int kk0) {
+    const uint4* A = sl.p[tm.a_buf] + (tm.a_off - sl.lo[tm.a_buf]);
+    const uint4* B = sl.p[tm.b_buf] + (tm.b_off - sl.lo[tm.b_buf]);
+    const bool ta = tm.ops & 1, tb = tm.ops & 4;
+    const int gm = tl.m0 + sr, gn = tl.n0 + sr;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int gk = kk0 + 8 * kg + q;
+      ra[q] = make_uint4(0u, 0u, 0u, 0u);
+      rb[q] = make_uint4(0u, 0u, 0u, 0u);
+      if (gm < ob.M && gk < tm.K) ra[q] = ta ? A[(int64_t)gk + (int64_t)gm * tm.lda] : A[(int64_t)gm + (int64_t)gk * tm.lda];
+      if (gn < ob.N && gk < tm.K) rb[q] = tb ? B[(int64_t)gn + (int64_t)gk * tm.ldb] : B[(int64_t)gk + (int64_t)gn * tm.ldb];
+    }
+  };
+  DevTerm cur;
+  double ccur = 0.0;
+  if (before(t, k0, tl.t1, tl.k1)) {
+    cur = terms[t];
+    ccur = cur.coef;
+    load_records(cur, k0);
+  }
   while (before(t, k0, tl.t1, tl.k1)) {
-    const DevTerm tm = terms[t];
-    if (tm.coef != ccur) {   // uniform: a new coefficient group
+    if (cur.coef != ccur) {   // uniform: a new coefficient group
       flush(ccur);
-      ccur = tm.coef;
+      ccur = cur.coef;
     }
     {
-      const uint4* A = sl.p[tm.a_buf] + (tm.a_off - sl.lo[tm.a_buf]);
-      const uint4* B = sl.p[tm.b_buf] + (tm.b_off - sl.lo[tm.b_buf]);
-      const bool ta = tm.ops & 1, tb = tm.ops & 4;
-      const uint32_t sa = (tm.ops & 2) ? 0x80008000u : 0u, sb = (tm.ops & 8) ? 0x80008000u : 0u;
-      const int gm = tl.m0 + sr, gn = tl.n0 + sr;
-      uint4 ra[8], rb[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int gk = k0 + 8 * kg + q;
-        ra[q] = make_uint4(0u, 0u, 0u, 0u);
-        rb[q] = make_uint4(0u, 0u, 0u, 0u);
-        if (gm < ob.M && gk < tm.K) ra[q] = ta ? A[(int64_t)gk + (int64_t)gm * tm.lda] : A[(int64_t)gm + (int64_t)gk * tm.lda];
-        if (gn < ob.N && gk < tm.K) rb[q] = tb ? B[(int64_t)gn + (int64_t)gk * tm.ldb] : B[(int64_t)gk + (int64_t)gn * tm.ldb];
-      }
+      const uint32_t sa = (cur.ops & 2) ? 0x80008000u : 0u, sb = (cur.ops & 8) ? 0x80008000u : 0u;
 #pragma unroll
       for (int s = 0; s < 3; ++s) {
         uint4 are, aim, bre, bim;
@@ -450,6 +459,26 @@ __device__ __forceinline__ void gemm_body_b3(const Bufs& bufs, const Slices& sl,
       }
     }
     __syncthreads();
+    int tn = t, kn = k0 + TKB;
+    if (kn >= cur.K) {
+      kn = 0;
+      ++tn;
+    }
+    const bool more = before(tn, kn, tl.t1, tl.k1);
+    DevTerm nxt;
+    if (more) {
+      nxt = (tn == t) ? cur : terms[tn];   // the term is reloaded only when it changes
+      load_records(nxt, kn);
+    }
+    // B fragments of both column blocks once, then A per row block
+    bf16x8 br[2][3], bi[2][3];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        br[j][s] = *reinterpret_cast<const bf16x8*>(&Bs[s][0][wn * 32 + j * 16 + li][8 * lk]);
+        bi[j][s] = *reinterpret_cast<const bf16x8*>(&Bs[s][1][wn * 32 + j * 16 + li][8 * lk]);
+      }
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       if (!rv[i]) continue;
@@ -465,30 +494,22 @@ __device__ __forceinline__ void gemm_body_b3(const Bufs& bufs, const Slices& sl,
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         if (!cv[j]) continue;
-        bf16x8 br[3], bi[3];
-#pragma unroll
-        for (int s = 0; s < 3; ++s) {
-          br[s] = *reinterpret_cast<const bf16x8*>(&Bs[s][0][wn * 32 + j * 16 + li][8 * lk]);
-          bi[s] = *reinterpret_cast<const bf16x8*>(&Bs[s][1][wn * 32 + j * 16 + li][8 * lk]);
-        }
         // slice pairs (0,0) (0,1) (1,0) (0,2) (1,1) (2,0), smallest first
 #pragma unroll
         for (int pp = 5; pp >= 0; --pp) {
           const int x = pp == 0 ? 0 : pp == 1 ? 0 : pp == 2 ? 1 : pp == 3 ? 0 : pp == 4 ? 1 : 2;
           const int y = pp == 0 ? 0 : pp == 1 ? 1 : pp == 2 ? 0 : pp == 3 ? 2 : pp == 4 ? 1 : 0;
-          tr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar[x], br[y], tr[i][j], 0, 0, 0);
-          ti[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar[x], bi[y], ti[i][j], 0, 0, 0);
-          tr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nai[x], bi[y], tr[i][j], 0, 0, 0);
-          ti[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[x], br[y], ti[i][j], 0, 0, 0);
+          tr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar[x], br[j][y], tr[i][j], 0, 0, 0);
+          ti[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar[x], bi[j][y], ti[i][j], 0, 0, 0);
+          tr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nai[x], bi[j][y], tr[i][j], 0, 0, 0);
+          ti[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[x], br[j][y], ti[i][j], 0, 0, 0);
         }
       }
     }
     __syncthreads();
-    k0 += TKB;
-    if (k0 >= tm.K) {
-      k0 = 0;
-      ++t;
-    }
+    t = tn;
+    k0 = kn;
+    if (more) cur = nxt;
   }
   flush(ccur);
 

@@ -95,4 +95,17 @@ void plan_env(const tdvp_model& m, int site, int dir, const Bond& bin, const Bon
               const Blocks& ein, const Blocks& ten, const Blocks& eout, std::vector<ETerm>& terms,
               double& flops);
 
+// The abelian U(1) x U(1) variant (abelian.cpp): bond sectors (q = 2 S^z,
+// tj = N), local states s = 0..3, keys (ia, s, ib) and (ia, s1, s2, ib),
+// environment channels w = 0..4.
+int u1_load_bond(Bond& b, const tdvp_bond* in, std::string& err);
+int u1_load_center(Blocks& B, const tdvp_blocks* in, const Bond& l, const Bond& r, int nsites, std::string& err);
+int u1_load_env(Blocks& B, const tdvp_blocks* in, const Bond& b, std::string& err);
+void u1_layout_center(const Bond& l, const Bond& r, int nsites, Blocks& out);
+void u1_layout_env(const Bond& b, Blocks& out);
+void u1_plan_heff(const tdvp_model& m, int site, int nsites, const Bond& l, const Bond& r, const Blocks& Le,
+                  const Blocks& Re, const Blocks& x, std::vector<HTerm>& terms, double& flops);
+void u1_plan_env(const tdvp_model& m, int site, int dir, const Bond& bin, const Bond& bout, const Blocks& ein,
+                 const Blocks& ten, const Blocks& eout, std::vector<ETerm>& terms, double& flops);
+
 }  // namespace tdvp

@@ -223,3 +223,27 @@ def random_mps(L, chi, seed, center=1, profile_seed=None, bonds_only=False):
                 raw[key] = raw[key] / nrm
         sites[k - 1] = raw
     return bonds, sites
+
+
+def u1_profile(chi, seed, nsites, spread=2.0, window=6, big=None):
+    """Sectors [(sz2, N, d)] of a U(1) x U(1) bond with `nsites` sites to its
+    left at half filling: N within +-window of nsites (0 <= N <= 2 nsites),
+    2 S^z within +-window, N - 2 S^z even, |2 S^z| <= N; degeneracies
+    proportional to exp(-((N - nsites)^2 + (2 S^z)^2) / (2 spread^2)) with a
+    +-10 % log-normal jitter, rounded (largest remainder) to sum to chi.
+    big: optionally raise the first sector's degeneracy to this value (a
+    block spanning several tiles with a ragged tail)."""
+    rng = _rng(seed, 5, chi, nsites)
+    labels = [(sz, n) for n in range(max(0, nsites - window), min(2 * nsites, nsites + window) + 1)
+              for sz in range(-window, window + 1) if (n - sz) % 2 == 0 and abs(sz) <= n]
+    w = np.array([np.exp(-((n - nsites) ** 2 + sz ** 2) / (2 * spread ** 2)) for sz, n in labels])
+    w = w * np.exp(0.1 * rng.standard_normal(len(w)))
+    target = w * chi / w.sum()
+    d = np.floor(target).astype(np.int64)
+    rem = chi - int(d.sum())
+    for i in np.argsort(-(target - d), kind="stable")[:rem]:
+        d[i] += 1
+    out = [(sz, n, int(di)) for (sz, n), di in zip(labels, d) if di > 0]
+    if big is not None and out:
+        out[0] = (out[0][0], out[0][1], int(big))
+    return out
