@@ -52,7 +52,7 @@ def rooflines(by_prec):
         if name not in PEAK or "tflops" not in r:
             continue
         out[name] = {"achieved": r["tflops"], "peak": PEAK[name], "unit": "TFLOP/s",
-                     "frac": r["tflops"] / PEAK[name]}
+                     "frac": r["tflops"] / PEAK[name], "traffic": measured_traffic(name)}
         if name == "bf16x3":
             out[name]["bf16_issue_frac"] = 6 * r["tflops"] / BF16_PEAK
     return out
@@ -78,14 +78,15 @@ def pack(blocks, keys, offs, total):
 
 
 def measured_traffic(prec):
-    """HBM bytes per FP64 H_eff launch from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads
-    for a plain copy of known size), or None when the kernel sources changed
-    since the counters were taken."""
+    """HBM bytes per H_eff launch of the given precision's kernel at the
+    chi = 4096 middle bond, from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a
+    plain copy of known size), or None when the kernel sources changed since
+    the counters were taken."""
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
-    path = os.path.join(here, "profiles", "heff_gemm_fp64_chi4096_traffic.json")
-    if prec != "fp64" or not os.path.exists(path):
+    path = os.path.join(here, "profiles", f"heff_gemm_{prec}_chi4096_traffic.json")
+    if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     h = hashlib.sha256()

@@ -438,6 +438,19 @@ int tdvp_split(tdvp_ctx* ctx, const tdvp_bond* left, const tdvp_bond* right, con
  * support. */
 int tdvp_sweep1(tdvp_ctx* ctx, tdvp_mps* mps, double dt, const tdvp_trunc* trunc, tdvp_sweep_info* info);
 
+/* One time step of the adaptive two-/one-site scheme (supplementary section
+ * S2.2: two-site TDVP lets the bond dimension grow; once it has saturated,
+ * one-site TDVP continues without SVDs).  *mode (in/out, host): 0 = the step
+ * is a two-site sweep (tdvp_sweep with trunc), after which *mode becomes 1
+ * if the largest full-state bond dimension has reached switch_frac x
+ * trunc->chi_cap (switch_frac <= 0: never); 1 = the step is a one-site sweep
+ * (tdvp_sweep1).  The caller owns the mode, so runs that must switch at the
+ * same step (two precisions compared step by step) can share one.  info as
+ * for the sweep taken.  Errors: INVALID (null argument, bad mode), else those
+ * of the sweep taken. */
+int tdvp_step(tdvp_ctx* ctx, tdvp_mps* mps, double dt, const tdvp_trunc* trunc, double switch_frac, int32_t* mode,
+              tdvp_sweep_info* info);
+
 /* ---- abelian U(1) x U(1) variant ---------------------------------------------
  * The paper's comparison symmetry (Table 1, Table S1: the same quench with
  * only the U(1) charge and spin symmetries): the same operations on the same

@@ -116,6 +116,7 @@ def _load():
         "tdvp_mps_measure": [P, P, P, P, P],
         "tdvp_mps_overlap": [P, P, P, P],
         "tdvp_sweep1": [P, P, D, P, P],
+        "tdvp_step": [P, P, D, P, D, P, P],
     }
     for name, args in sig.items():
         if not hasattr(lib, name):
@@ -466,6 +467,17 @@ class MPS:
         info = _SweepInfo()
         _check(lib.tdvp_sweep(self.ctx.h, self.h, float(dt), C.byref(tr), C.byref(info)), self.ctx.h)
         return {f: getattr(info, f) for f, _ in _SweepInfo._fields_}
+
+    def step(self, dt, mode, eps_tol=1e-4, chi_cap=4096, krylov_tol=1e-12, krylov_maxdim=40, switch=0.97):
+        """One time step of the adaptive scheme: mode 0 = two-site sweep (then
+        1 once the largest bond reaches switch x chi_cap), 1 = one-site sweep.
+        Returns (info, new mode)."""
+        tr = _Trunc(float(eps_tol), int(chi_cap), 0, float(krylov_tol), int(krylov_maxdim))
+        info = _SweepInfo()
+        m = C.c_int32(int(mode))
+        _check(lib.tdvp_step(self.ctx.h, self.h, float(dt), C.byref(tr), float(switch), C.byref(m), C.byref(info)),
+               self.ctx.h)
+        return {f: getattr(info, f) for f, _ in _SweepInfo._fields_}, m.value
 
     def sweep1(self, dt, krylov_tol=1e-12, krylov_maxdim=40):
         """One time step of one-site TDVP (bond dimensions fixed)."""

@@ -2057,6 +2057,24 @@ int tdvp_sweep1(tdvp_ctx* ctx, tdvp_mps* m, double dt, const tdvp_trunc* tr, tdv
   });
 }
 
+// One time step of the adaptive scheme: two-site sweeps while the bond
+// dimension grows, one-site sweeps once the largest bond has reached
+// switch_frac of the cap (the mode is the caller's, so several runs can be
+// kept on the same schedule).
+int tdvp_step(tdvp_ctx* ctx, tdvp_mps* m, double dt, const tdvp_trunc* tr, double switch_frac, int32_t* mode,
+              tdvp_sweep_info* info) {
+  if (!ctx || !m || !tr || !mode) return set_error(ctx, TDVP_E_INVALID, "null argument");
+  if (*mode != 0 && *mode != 1) return set_error(ctx, TDVP_E_INVALID, "mode must be 0 (two-site) or 1 (one-site)");
+  if (std::isnan(switch_frac)) return set_error(ctx, TDVP_E_INVALID, "bad switch fraction");
+  if (*mode == 1) return tdvp_sweep1(ctx, m, dt, tr, info);
+  tdvp_sweep_info inf{};
+  int rc = tdvp_sweep(ctx, m, dt, tr, &inf);
+  if (info) *info = inf;
+  if (rc) return rc;
+  if (switch_frac > 0.0 && (double)inf.max_chi >= switch_frac * (double)tr->chi_cap) *mode = 1;
+  return TDVP_OK;
+}
+
 // ---------------------------------------------------------------------------
 // The two-site split as a call of its own (supplementary sections S2.2 and
 // S2.4: per coupled sector of the bond, an SVD of the merged tensor, whole

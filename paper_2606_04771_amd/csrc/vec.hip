@@ -154,27 +154,42 @@ int nblocks_for(int64_t n) {
   return (int)g;
 }
 
-// partial[k * G + g] = sum_{i in chunk g} conj(V_k[i]) w[i]: for k = blockIdx.y,
-// or, with d_j (index read on the device), for every k <= *d_j in turn
+// partial[k * G + g] = sum_{i in chunk g} conj(V_k[i]) w[i] for every k < nv,
+// or, with d_j (index read on the device), every k <= *d_j.  The vectors go
+// in groups of kDotGroup, so each element of w is read once per group (not
+// once per vector); every k keeps its own summation order.
+constexpr int kDotGroup = 8;
 template <typename VT>
 __global__ __launch_bounds__(NT) void k_dots_partial(const VT* __restrict__ V, int64_t stride,
                                                      const double2* __restrict__ w, int64_t n,
-                                                     double2* __restrict__ partial, const int* __restrict__ d_j) {
+                                                     double2* __restrict__ partial, const int* __restrict__ d_j,
+                                                     int nv) {
   const int g = blockIdx.x, G = gridDim.x;
-  const int kb = d_j ? 0 : (int)blockIdx.y, ke = d_j ? *d_j + 1 : (int)blockIdx.y + 1;
+  const int ke = d_j ? *d_j + 1 : nv;
   int64_t chunk = (n + G - 1) / G;
   int64_t lo = (int64_t)g * chunk, hi = lo + chunk < n ? lo + chunk : n;
-  for (int k = kb; k < ke; ++k) {
-    const VT* v = V + (int64_t)k * stride;
-    double re = 0.0, im = 0.0;
+  for (int kb = 0; kb < ke; kb += kDotGroup) {
+    const int nk = ke - kb < kDotGroup ? ke - kb : kDotGroup;
+    double re[kDotGroup], im[kDotGroup];
+#pragma unroll
+    for (int q = 0; q < kDotGroup; ++q) re[q] = im[q] = 0.0;
     for (int64_t i = lo + threadIdx.x; i < hi; i += NT) {
-      double2 a = ldv(v + i), b = w[i];
-      re += a.x * b.x + a.y * b.y;
-      im += a.x * b.y - a.y * b.x;
+      const double2 b = w[i];
+#pragma unroll
+      for (int q = 0; q < kDotGroup; ++q) {
+        if (q < nk) {
+          const double2 a = ldv(V + (int64_t)(kb + q) * stride + i);
+          re[q] += a.x * b.x + a.y * b.y;
+          im[q] += a.x * b.y - a.y * b.x;
+        }
+      }
     }
-    block_sum2(re, im);
-    if (threadIdx.x == 0) partial[(int64_t)k * G + g] = make_double2(re, im);
-    __syncthreads();   // block_sum2's shared slots are reused by the next k
+    for (int q = 0; q < nk; ++q) {
+      double r = re[q], m = im[q];
+      block_sum2(r, m);
+      if (threadIdx.x == 0) partial[(int64_t)(kb + q) * G + g] = make_double2(r, m);
+      __syncthreads();   // block_sum2's shared slots are reused by the next vector
+    }
   }
 }
 
@@ -387,11 +402,11 @@ int vec_dots(tdvp_ctx* ctx, const double* V, int64_t stride, int nv, const doubl
   TDVP_HIP(ctx, ctx->ws_vec.ensure(need));
   double2* partial = (double2*)ctx->ws_vec.p;
   if (v32)
-    hipLaunchKernelGGL(k_dots_partial<float2>, dim3(G, nv), dim3(NT), 0, ctx->stream, (const float2*)V, stride,
-                       (const double2*)w, n, partial, (const int*)nullptr);
+    hipLaunchKernelGGL(k_dots_partial<float2>, dim3(G), dim3(NT), 0, ctx->stream, (const float2*)V, stride,
+                       (const double2*)w, n, partial, (const int*)nullptr, nv);
   else
-    hipLaunchKernelGGL(k_dots_partial<double2>, dim3(G, nv), dim3(NT), 0, ctx->stream, (const double2*)V, stride,
-                       (const double2*)w, n, partial, (const int*)nullptr);
+    hipLaunchKernelGGL(k_dots_partial<double2>, dim3(G), dim3(NT), 0, ctx->stream, (const double2*)V, stride,
+                       (const double2*)w, n, partial, (const int*)nullptr, nv);
   hipLaunchKernelGGL(k_reduce, dim3(nv), dim3(NT), 0, ctx->stream, partial, G, d_out, (const int*)nullptr);
   TDVP_HIP(ctx, hipGetLastError());
   return TDVP_OK;
@@ -456,10 +471,10 @@ int vec_lanczos_orth_it(tdvp_ctx* ctx, double* W, const double* V, int64_t strid
   for (int pass = 0; pass < 2; ++pass) {
     if (v32)
       hipLaunchKernelGGL(k_dots_partial<float2>, dim3(G), dim3(NT), 0, ctx->stream, (const float2*)V, stride,
-                         (const double2*)W, n, partial, d_j);
+                         (const double2*)W, n, partial, d_j, 0);
     else
       hipLaunchKernelGGL(k_dots_partial<double2>, dim3(G), dim3(NT), 0, ctx->stream, (const double2*)V, stride,
-                         (const double2*)W, n, partial, d_j);
+                         (const double2*)W, n, partial, d_j, 0);
     hipLaunchKernelGGL(k_reduce, dim3(maxdim), dim3(NT), 0, ctx->stream, partial, G, cs[pass], d_j);
     if (v32)
       hipLaunchKernelGGL(k_sub_combo<float2>, dim3(G), dim3(NT), 0, ctx->stream, (double2*)W, (const float2*)V,

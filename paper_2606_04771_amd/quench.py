@@ -4,9 +4,10 @@ products side by side, comparing the site-resolved <S^z_i> (= (<n_up> -
 <n_down>)/2) and <n_up n_down> after every time step.
 
 Two-site sweeps let the bond dimension grow (truncation: discarded weight
-eps_tol, cap chi in full-state units); once it has saturated the driver
-switches to one-site sweeps (the adaptive scheme of supplementary section
-S2.2), the two precisions switching at the same step.
+eps_tol, cap chi in full-state units); once it has saturated the library's
+adaptive step (tdvp_step) switches to one-site sweeps (supplementary section
+S2.2), the full-precision run deciding for both so that they switch at the
+same step.
 
     python -m paper_2606_04771_amd.quench --L 60 --chi 4096 --t-end 6 --out quench.jsonl
 
@@ -16,10 +17,6 @@ import argparse
 import json
 import sys
 import time
-
-
-def chi_full(bond):
-    return sum(d * (tj + 1) for _, tj, d in bond)
 
 
 def main(argv=None):
@@ -47,18 +44,20 @@ def main(argv=None):
         runs[name] = (ctx, T.MPS.neel(ctx, model, complete=False))
     out = open(a.out, "w") if a.out else None
     nsteps = int(round(a.t_end / a.dt))
-    one_site = False
+    mode = 0                      # 0: two-site sweeps, 1: one-site (set by the library's rule)
+    switch = 0.0 if a.no_switch else a.switch
     worst = {"d_sz": 0.0, "d_docc": 0.0, "state_err": 0.0}
     tot = {"fp64": 0.0, "fp32": 0.0}
     for n in range(1, nsteps + 1):
-        rec = {"t": round(n * a.dt, 10), "kind": "one-site" if one_site else "two-site"}
+        rec = {"t": round(n * a.dt, 10), "kind": "one-site" if mode else "two-site"}
         obs = {}
+        next_mode = mode
         for name, (ctx, mps) in runs.items():
             t0 = time.time()
-            if one_site:
-                info = mps.sweep1(a.dt, krylov_tol=a.krylov_tol, krylov_maxdim=40)
-            else:
-                info = mps.sweep(a.dt, eps_tol=a.eps, chi_cap=a.chi, krylov_tol=a.krylov_tol, krylov_maxdim=40)
+            info, m = mps.step(a.dt, mode, eps_tol=a.eps, chi_cap=a.chi, krylov_tol=a.krylov_tol,
+                               krylov_maxdim=40, switch=switch)
+            if name == "fp64":
+                next_mode = m
             ctx.synchronize()
             rec[f"s_{name}"] = time.time() - t0
             tot[name] += rec[f"s_{name}"]
@@ -80,10 +79,7 @@ def main(argv=None):
         if out:
             out.write(line + "\n")
             out.flush()
-        if not one_site and not a.no_switch:
-            big = max(chi_full(m64.bond(k)) for k in range(1, a.L))
-            if big >= a.switch * a.chi:
-                one_site = True
+        mode = next_mode
     summary = {"summary": True, "L": a.L, "U": a.U, "chi_cap": a.chi, "dt": a.dt, "t_end": a.t_end,
                "eps_tol": a.eps, "max_obs_err": max(worst["d_sz"], worst["d_docc"]), **worst,
                "seconds_fp64": tot["fp64"], "seconds_fp32": tot["fp32"],

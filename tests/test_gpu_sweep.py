@@ -291,3 +291,40 @@ def test_host_staged_sweeps_are_bit_identical():
     for i in (1, 2, 3, 5, 6):
         assert np.array_equal(a[i], b[i])
     assert b[4] < a[4]
+
+
+def test_adaptive_step_switches_to_one_site():
+    """tdvp_step: two-site sweeps while the bonds grow; once the largest bond
+    reaches the switch fraction of the cap the mode turns to one-site and the
+    bonds stay fixed; the states equal those of explicit tdvp_sweep /
+    tdvp_sweep1 calls on the same schedule, bit for bit."""
+    L, dt, cap = 8, 0.05, 12
+    model = T.Model(L, 1.0, 4.0)
+    stream = torch_stream_handle()
+    c = T.Context(0, stream=stream)
+    try:
+        a = T.MPS.neel(c, model)
+        b = T.MPS.neel(c, model)
+        mode, modes = 0, []
+        for n in range(8):
+            info, new_mode = a.step(dt, mode, eps_tol=1e-12, chi_cap=cap, krylov_tol=1e-12, switch=0.75)
+            if mode == 0:
+                ib = b.sweep(dt, eps_tol=1e-12, chi_cap=cap, krylov_tol=1e-12)
+                assert new_mode == (1 if ib["max_chi"] >= 0.75 * cap else 0)
+            else:
+                bonds_before = [a.bond(k) for k in range(L + 1)]
+                b.sweep1(dt, krylov_tol=1e-12)
+                assert new_mode == 1
+            modes.append(mode)
+            mode = new_mode
+            for k in range(1, L + 1):
+                ka, oa, da = a.site(k)
+                kb, ob, db = b.site(k)
+                assert np.array_equal(ka, kb) and np.array_equal(da, db)
+        print(f"modes {modes}", flush=True)
+        assert modes[0] == 0 and modes[-1] == 1
+        assert [a.bond(k) for k in range(L + 1)] == bonds_before
+        a.close()
+        b.close()
+    finally:
+        c.close()
