@@ -1,7 +1,8 @@
 """Neel-quench driver: the L-site Fermi-Hubbard chain from the Neel state,
-evolved by symmetric second-order TDVP in full precision and with FP32 block
-products side by side, comparing the site-resolved <S^z_i> (= (<n_up> -
-<n_down>)/2) and <n_up n_down> after every time step.
+evolved by symmetric second-order TDVP in full precision and with reduced-
+precision block products (FP32, split-BF16) side by side, comparing the
+site-resolved <S^z_i> (= (<n_up> - <n_down>)/2) and <n_up n_down> after every
+time step.
 
 Two-site sweeps let the bond dimension grow (truncation: discarded weight
 eps_tol, cap chi in full-state units); once it has saturated the library's
@@ -12,7 +13,8 @@ same step.
     python -m paper_2606_04771_amd.quench --L 60 --chi 4096 --t-end 6 --out quench.jsonl
 
 Each step prints one JSON line (time, sweep kind, seconds per precision,
-largest bond, max |d<S^z>|, max |d<n_up n_dn>|, |psi_64 - psi_32|)."""
+largest bond, and per reduced precision max |d<S^z>|, max |d<n_up n_dn>|,
+|psi_64 - psi_reduced|)."""
 import argparse
 import json
 import sys
@@ -34,20 +36,24 @@ def main(argv=None):
     ap.add_argument("--switch", type=float, default=0.97,
                     help="switch to one-site sweeps once the largest bond reaches this fraction of the cap")
     ap.add_argument("--no-switch", action="store_true")
+    ap.add_argument("--rungs", default="fp32",
+                    help="comma-separated reduced precisions run beside FP64: fp32, bf16x3")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
 
     model = T.Model(a.L, 1.0, a.U)
+    rungs = [r for r in a.rungs.split(",") if r]
+    precs = {"fp64": T.FP64, "fp32": T.FP32, "bf16x3": T.BF16X3}
     runs = {}
-    for name, prec in (("fp64", T.FP64), ("fp32", T.FP32)):
-        ctx = T.Context(0, precision=prec)
+    for name in ["fp64"] + rungs:
+        ctx = T.Context(0, precision=precs[name])
         runs[name] = (ctx, T.MPS.neel(ctx, model, complete=False))
     out = open(a.out, "w") if a.out else None
     nsteps = int(round(a.t_end / a.dt))
     mode = 0                      # 0: two-site sweeps, 1: one-site (set by the library's rule)
     switch = 0.0 if a.no_switch else a.switch
-    worst = {"d_sz": 0.0, "d_docc": 0.0, "state_err": 0.0}
-    tot = {"fp64": 0.0, "fp32": 0.0}
+    worst = {r: {"d_sz": 0.0, "d_docc": 0.0, "state_err": 0.0} for r in rungs}
+    tot = {name: 0.0 for name in runs}
     for n in range(1, nsteps + 1):
         rec = {"t": round(n * a.dt, 10), "kind": "one-site" if mode else "two-site"}
         obs = {}
@@ -64,16 +70,20 @@ def main(argv=None):
             rec[f"chi_{name}"] = int(info["max_chi"])
             rec[f"disc_{name}"] = float(info["max_discarded"])
             obs[name] = mps.measure()
-        m64, m32 = runs["fp64"][1], runs["fp32"][1]
-        ov = m64.overlap(m32)
-        n1, n2 = m64.overlap(m64).real, m32.overlap(m32).real
-        rec["state_err"] = float(np.sqrt(max(n1 + n2 - 2 * ov.real, 0.0)))
-        rec["d_sz"] = float(np.abs(obs["fp64"][0] - obs["fp32"][0]).max())
-        rec["d_docc"] = float(np.abs(obs["fp64"][1] - obs["fp32"][1]).max())
+        m64 = runs["fp64"][1]
+        n1 = m64.overlap(m64).real
+        for r in rungs:
+            mr = runs[r][1]
+            ov = m64.overlap(mr)
+            n2 = mr.overlap(mr).real
+            e = {"state_err": float(np.sqrt(max(n1 + n2 - 2 * ov.real, 0.0))),
+                 "d_sz": float(np.abs(obs["fp64"][0] - obs[r][0]).max()),
+                 "d_docc": float(np.abs(obs["fp64"][1] - obs[r][1]).max())}
+            for k, v in e.items():
+                rec[f"{k}_{r}"] = v
+                worst[r][k] = max(worst[r][k], v)
         rec["sz_mid"] = float(obs["fp64"][0][a.L // 2 - 1])
         rec["docc_mid"] = float(obs["fp64"][1][a.L // 2 - 1])
-        for k in worst:
-            worst[k] = max(worst[k], rec[k])
         line = json.dumps(rec)
         print(line, flush=True)
         if out:
@@ -81,9 +91,10 @@ def main(argv=None):
             out.flush()
         mode = next_mode
     summary = {"summary": True, "L": a.L, "U": a.U, "chi_cap": a.chi, "dt": a.dt, "t_end": a.t_end,
-               "eps_tol": a.eps, "max_obs_err": max(worst["d_sz"], worst["d_docc"]), **worst,
-               "seconds_fp64": tot["fp64"], "seconds_fp32": tot["fp32"],
-               "s_per_sweep_fp64": tot["fp64"] / nsteps, "s_per_sweep_fp32": tot["fp32"] / nsteps}
+               "eps_tol": a.eps,
+               "max_obs_err": {r: max(worst[r]["d_sz"], worst[r]["d_docc"]) for r in rungs},
+               "max_state_err": {r: worst[r]["state_err"] for r in rungs},
+               "seconds": tot, "s_per_sweep": {k: v / nsteps for k, v in tot.items()}}
     print(json.dumps(summary), flush=True)
     if out:
         out.write(json.dumps(summary) + "\n")
