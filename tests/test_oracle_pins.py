@@ -639,3 +639,74 @@ def test_tied_multiplets_follow_the_tie_rule():
         assert _kept_labels(Um, ops) == {x: n for x, n in kept.items() if n}
     kept1, _ = R.truncate_multiplets(svals, 0.0, 1)
     assert {x: n for x, n in kept1.items() if n} == {first: 1}
+
+
+# ---- abelian U(1) x U(1) expansion (oracle.abelian) --------------------------
+def _u1_chain(L, seed, chi):
+    """Bonds of a U(1) x U(1) chain (vacuum, profiles, total (N, 2Sz) = (L, 0))
+    and random blocks for every allowed (a, s, b) key of each site."""
+    from oracle import abelian as A
+    bonds = [[(0, 0, 1)]] + [synth.u1_profile(chi, seed + k, k, window=2) for k in range(1, L)] + [[(0, L, 1)]]
+    sites = []
+    for k in range(1, L + 1):
+        left, right = bonds[k - 1], bonds[k]
+        keys = [(a, s, b) for a in range(len(left)) for s in range(4) for b in range(len(right))
+                if left[a][1] + A.LOCAL_N[s] == right[b][1] and left[a][0] + A.LOCAL_SZ2[s] == right[b][0]]
+        dims = [(left[a][2], right[b][2]) for a, _, b in keys]
+        sites.append(synth.block_data(keys, dims, seed + 100 + k))
+    return bonds, sites
+
+
+def test_abelian_expansion_has_the_labelled_charges():
+    """A random U(1) x U(1) chain expanded by oracle.abelian and contracted
+    to a state vector is an eigenvector of the total particle number (L) and
+    of 2 S^z (0), built from the Jordan-Wigner operators of oracle.fermions;
+    and the left block of every bond k, contracted separately, has on each
+    sector's columns exactly that sector's (N, 2S^z)."""
+    from oracle import abelian as A
+    L = 6
+    bonds, sites = _u1_chain(L, 400, 9)
+    full = [A.expand_site(sites[k - 1], bonds[k - 1], bonds[k]) for k in range(1, L + 1)]
+    psi = D.mps_state(full)
+    assert np.linalg.norm(psi) > 1e-3
+    c = {(i, s): F.annihilator(i, s, L) for i in range(1, L + 1) for s in (0, 1)}
+    N = sum(c[(i, s)].T @ c[(i, s)] for i in range(1, L + 1) for s in (0, 1))
+    Sz2 = sum(c[(i, 0)].T @ c[(i, 0)] - c[(i, 1)].T @ c[(i, 1)] for i in range(1, L + 1))
+    assert np.abs(N @ psi - L * psi).max() < 1e-12 * np.abs(psi).max()
+    assert np.abs(Sz2 @ psi).max() < 1e-12 * np.abs(psi).max()
+    for k in range(1, L):
+        Phi = D.left_block_basis(full[:k])            # [(s_1..s_k), b]
+        ck = {(i, s): F.annihilator(i, s, k) for i in range(1, k + 1) for s in (0, 1)}
+        Nk = sum(ck[(i, s)].T @ ck[(i, s)] for i in range(1, k + 1) for s in (0, 1)).toarray()
+        Sk = sum(ck[(i, 0)].T @ ck[(i, 0)] - ck[(i, 1)].T @ ck[(i, 1)] for i in range(1, k + 1)).toarray()
+        off, _ = A.offsets(bonds[k])
+        for (sz2, n, d), o in zip(bonds[k], off):
+            cols = Phi[:, o:o + d]
+            assert np.abs(Nk @ cols - n * cols).max() < 1e-12 * max(np.abs(cols).max(), 1.0)
+            assert np.abs(Sk @ cols - sz2 * cols).max() < 1e-12 * max(np.abs(cols).max(), 1.0)
+
+
+def test_abelian_environments_live_on_their_channel_blocks():
+    """Environments of the expanded chain, built by the oracle's dense
+    updates, are zero outside the blocks the abelian channel labels allow:
+    cutting them into oracle.abelian's (out, w, in) blocks and expanding
+    again reproduces them exactly, left and right, every channel."""
+    from oracle import abelian as A
+    L, t, U = 6, 1.0, 4.0
+    bonds, sites = _u1_chain(L, 500, 10)
+    full = [A.expand_site(sites[k - 1], bonds[k - 1], bonds[k]) for k in range(1, L + 1)]
+    dw = {0: (0, 0), 1: (1, 1), 2: (-1, 1), 3: (1, -1), 4: (-1, -1)}   # (dN, d2Sz) of each channel
+    def keys(bond):
+        return [(io, w, ii) for w in range(5) for ii in range(len(bond)) for io in range(len(bond))
+                if bond[io][1] == bond[ii][1] + dw[w][0] and bond[io][0] == bond[ii][0] + dw[w][1]]
+    Lf = D.empty_env()
+    for k in range(1, L):
+        Lf = D.left_env_update(Lf, full[k - 1], k, t, U)
+        back = A.expand_env(A.restrict_env(Lf, bonds[k], keys(bonds[k])), bonds[k])
+        assert all(np.array_equal(back[w], Lf[w]) for w in range(3))
+        assert max(np.abs(Lf[w]).max() for w in (1, 2)) > 0
+    Rf = D.empty_env()
+    for k in range(L, 1, -1):
+        Rf = D.right_env_update(Rf, full[k - 1], k, t, U)
+        back = A.expand_env(A.restrict_env(Rf, bonds[k - 1], keys(bonds[k - 1])), bonds[k - 1])
+        assert all(np.array_equal(back[w], Rf[w]) for w in range(3))
