@@ -125,7 +125,10 @@ struct Program {
   struct Tiling {
     std::vector<DevTile> tiles;
     int n64 = 0;
-    int mode = 0;
+    int mode = 0;             // 0, 1, 2 as tile_mode; 3: the all-64x64 tiles in a persistent launch;
+                              // 4: the all-32x32 tiles as FP64 wave tiles
+    bool persistent = false;  // a fixed grid takes the tiles from a device counter
+    bool wave = false;        // one 32x32 tile per wave (FP64 only)
     DevTile* d_tiles = nullptr;
   };
   std::vector<Tiling> alt;            // candidates (index 0 = the active tiling as built)
@@ -149,7 +152,7 @@ struct Program {
   // tile the outputs, split long K chains, order work items by decreasing cost
   void finalize();
   // tiling of the outputs for a tile mode (no K-chain splitting), ordered for the XCDs
-  void tile_only(int mode, Tiling& out) const;
+  void tile_only(int mode, Tiling& out, int per = 1) const;   // per: tiles per workgroup
 };
 
 // Grow-only device buffer; memory comes from its allocator (set by the owner

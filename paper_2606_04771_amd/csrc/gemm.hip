@@ -162,13 +162,14 @@ constexpr int kSlotDim = 64;
 template <typename T, int WM, int WN, bool SH>
 __device__ __forceinline__ void gemm_body(const Bufs& bufs, double* __restrict__ Cbase,
                                           double2* __restrict__ part, const DevTile* __restrict__ tiles,
-                                          const DevOut* __restrict__ outs, const DevTerm* __restrict__ terms) {
+                                          const DevOut* __restrict__ outs, const DevTerm* __restrict__ terms,
+                                          int tile) {
   typedef Shape<T, WM, WN> S;
   typedef Mfma<T> F;
   constexpr int TK = S::TK;
   __shared__ T As[2][TK][S::TM + PAD];
   __shared__ T Bs[2][TK][S::TN + PAD];
-  const DevTile tl = tiles[blockIdx.x];
+  const DevTile tl = tiles[tile];
   const DevOut ob = outs[tl.out];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
@@ -276,6 +277,202 @@ __device__ __forceinline__ void gemm_body(const Bufs& bufs, double* __restrict__
             double c = dt.coef;
             if (SH && (dt.ops & 16)) c *= bufs.shift[0];
             if (SH && (dt.ops & 32)) c *= bufs.shift[1];
+            vr += c * x.x;
+            vi += (dt.ops & 2) ? -c * x.y : c * x.y;
+          }
+          if (bufs.bad && !(isfinite(vr) && isfinite(vi))) *bufs.bad = 1;
+          C[(int64_t)row + (int64_t)col * ob.ldc] = make_double2(vr, vi);
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 wave tiles: one 32x32 output tile per wave, four independent waves per
+// workgroup, operands loaded by each lane straight into the registers the
+// matrix instruction reads (no LDS staging, no barriers), two K steps of 4
+// ahead of the one being multiplied.  A wave whose tile is a ragged edge
+// spends its time only on its own 16x16 sub-blocks, and no wave waits for
+// another.  Every output element sees the same products in the same order as
+// in gemm_body<double, WM, WN> (K steps of 4 with lane group l / 16 holding
+// k + l / 16, the term coefficient and conjugations applied to the same
+// values, the same matrix instruction sequence per 16x16 sub-block), so the
+// results are bit-identical to every other FP64 tiling.
+struct WPos {
+  int t, k;   // term, K offset (a multiple of 4) inside it
+};
+
+template <int MR, int MC>
+struct WStage {
+  double2 a[MR], b[MC];
+  double c;
+  bool ca, cb;
+};
+
+// Steps of a chain: K offsets 0, 4, ... below K of every term in [t0, t1).
+__device__ __forceinline__ int wave_steps(const DevTerm* __restrict__ terms, int t0, int t1) {
+  int n = 0;
+  for (int t = t0; t < t1; ++t) n += (terms[t].K + 3) >> 2;
+  return n;
+}
+
+// First step at or after p (terms with K = 0 have none); p.t == t1 at the end.
+__device__ __forceinline__ void wave_settle(const DevTerm* __restrict__ terms, WPos& p, int t1) {
+  while (p.t < t1 && p.k >= terms[p.t].K) {
+    p.k = 0;
+    ++p.t;
+  }
+}
+
+// The next step, or p itself when p is the chain's last step (the loads of the
+// pipeline's lookahead then re-read valid data that is never used).
+__device__ __forceinline__ void wave_next(const DevTerm* __restrict__ terms, WPos& p, int t1) {
+  WPos q{p.t, p.k + 4};
+  wave_settle(terms, q, t1);
+  if (q.t < t1) p = q;
+}
+
+// Lanes outside the block load this zero instead of an operand element, so
+// that every load is issued unconditionally and its value is used as loaded.
+// Both addresses are global-memory pointers (a select of generic pointers
+// would turn the loads into flat ones, which the scalar loads' waits then
+// also wait for).
+__device__ const double2 kZero2 = {0.0, 0.0};
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef const __attribute__((address_space(1))) double2* gptr2;
+#else
+typedef const double2* gptr2;   // the host pass only parses the device code
+#endif
+
+template <int MR, int MC>
+__device__ __forceinline__ void wave_load(WStage<MR, MC>& s, const DevTerm* __restrict__ terms, const WPos& p,
+                                          const Bufs& bufs, int m0, int n0, int M, int N, int li, int lk) {
+  const DevTerm& tm = terms[p.t];
+  s.c = tm.coef;
+  s.ca = tm.ops & 2;
+  s.cb = tm.ops & 8;
+  const gptr2 A = (gptr2)(reinterpret_cast<const double2*>(bufs.p[tm.a_buf]) + tm.a_off);
+  const gptr2 B = (gptr2)(reinterpret_cast<const double2*>(bufs.p[tm.b_buf]) + tm.b_off);
+  const gptr2 Z = (gptr2)&kZero2;
+  const bool ta = tm.ops & 1, tb = tm.ops & 4;
+  const int k = p.k + lk;
+  // element (row, k) of A at row * sa_r + k * sa_k, (k, col) of B at k * sb_k + col * sb_c
+  const int64_t sa_r = ta ? tm.lda : 1, sa_k = ta ? 1 : tm.lda;
+  const int64_t sb_k = tb ? tm.ldb : 1, sb_c = tb ? 1 : tm.ldb;
+  const bool kin = k < tm.K;
+#pragma unroll
+  for (int i = 0; i < MR; ++i) {
+    const int gm = m0 + i * 16 + li;
+    const gptr2 at = A + ((int64_t)gm * sa_r + (int64_t)k * sa_k);
+    s.a[i] = *((kin && gm < M) ? at : Z);
+  }
+#pragma unroll
+  for (int j = 0; j < MC; ++j) {
+    const int gn = n0 + j * 16 + li;
+    const gptr2 at = B + ((int64_t)k * sb_k + (int64_t)gn * sb_c);
+    s.b[j] = *((kin && gn < N) ? at : Z);
+  }
+}
+
+template <int MR, int MC>
+__device__ __forceinline__ void wave_mma(const WStage<MR, MC>& s, f64x4 (&accr)[2][2], f64x4 (&acci)[2][2]) {
+  double ar[MR], ai[MR], nai[MR], br[MC], bi[MC];
+#pragma unroll
+  for (int i = 0; i < MR; ++i) {
+    ar[i] = s.c * s.a[i].x;
+    ai[i] = s.ca ? -s.c * s.a[i].y : s.c * s.a[i].y;
+    nai[i] = -ai[i];
+  }
+#pragma unroll
+  for (int j = 0; j < MC; ++j) {
+    br[j] = s.b[j].x;
+    bi[j] = s.cb ? -s.b[j].y : s.b[j].y;
+  }
+#pragma unroll
+  for (int i = 0; i < MR; ++i)
+#pragma unroll
+    for (int j = 0; j < MC; ++j) {
+      accr[i][j] = Mfma<double>::op(ar[i], br[j], accr[i][j]);
+      accr[i][j] = Mfma<double>::op(nai[i], bi[j], accr[i][j]);
+      acci[i][j] = Mfma<double>::op(ar[i], bi[j], acci[i][j]);
+      acci[i][j] = Mfma<double>::op(ai[i], br[j], acci[i][j]);
+    }
+}
+
+// The K chain of one wave tile with MR x MC of its 16x16 sub-blocks inside
+// the output: three register stages, loads two steps ahead of the products.
+template <int MR, int MC>
+__device__ __forceinline__ void wave_chain(const Bufs& bufs, const DevTerm* __restrict__ terms, const DevTile& tl,
+                                           const DevOut& ob, int li, int lk, f64x4 (&accr)[2][2],
+                                           f64x4 (&acci)[2][2]) {
+  const int t1 = tl.t1;
+  const int n = wave_steps(terms, tl.t0, t1);
+  if (n == 0) return;
+  WPos p{tl.t0, 0};
+  wave_settle(terms, p, t1);
+  WStage<MR, MC> s0, s1, s2;
+  wave_load(s0, terms, p, bufs, tl.m0, tl.n0, ob.M, ob.N, li, lk);
+  wave_next(terms, p, t1);
+  wave_load(s1, terms, p, bufs, tl.m0, tl.n0, ob.M, ob.N, li, lk);
+  wave_next(terms, p, t1);
+  int i = 0;
+  for (; i + 3 <= n; i += 3) {   // steps i, i+1, i+2 are all in the chain
+    wave_load(s2, terms, p, bufs, tl.m0, tl.n0, ob.M, ob.N, li, lk);
+    wave_next(terms, p, t1);
+    wave_mma(s0, accr, acci);
+    wave_load(s0, terms, p, bufs, tl.m0, tl.n0, ob.M, ob.N, li, lk);
+    wave_next(terms, p, t1);
+    wave_mma(s1, accr, acci);
+    wave_load(s1, terms, p, bufs, tl.m0, tl.n0, ob.M, ob.N, li, lk);
+    wave_next(terms, p, t1);
+    wave_mma(s2, accr, acci);
+  }
+  if (i < n) wave_mma(s0, accr, acci);
+  if (i + 1 < n) wave_mma(s1, accr, acci);
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void heff_gemm_wave(Bufs bufs, double* __restrict__ Cbase,
+                                                      const DevTile* __restrict__ tiles, int ntiles,
+                                                      const DevOut* __restrict__ outs,
+                                                      const DevTerm* __restrict__ terms) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int tile = blockIdx.x * 4 + wave;
+  if (tile >= ntiles) return;   // whole waves only: nothing below synchronises the workgroup
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const DevTile tl = tiles[tile];
+  const DevOut ob = outs[tl.out];
+  f64x4 accr[2][2], acci[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      accr[i][j] = f64x4{0, 0, 0, 0};
+      acci[i][j] = f64x4{0, 0, 0, 0};
+    }
+  // whole chains only (wave tiles are never split): terms [t0, t1) from K = 0
+  const bool r2 = tl.m0 + 16 < ob.M, c2 = tl.n0 + 16 < ob.N;
+  if (r2 && c2) wave_chain<2, 2>(bufs, terms, tl, ob, li, lk, accr, acci);
+  else if (r2) wave_chain<2, 1>(bufs, terms, tl, ob, li, lk, accr, acci);
+  else if (c2) wave_chain<1, 2>(bufs, terms, tl, ob, li, lk, accr, acci);
+  else wave_chain<1, 1>(bufs, terms, tl, ob, li, lk, accr, acci);
+  // direct (local) terms and the store, as in gemm_body
+  double2* C = reinterpret_cast<double2*>(Cbase) + ob.c_off;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int row = tl.m0 + i * 16 + Mfma<double>::row(r, lk);
+        int col = tl.n0 + j * 16 + li;
+        if (row < ob.M && col < ob.N) {
+          double vr = accr[i][j][r], vi = acci[i][j][r];
+          for (int d = ob.d_begin; d < ob.d_end; ++d) {
+            const DevTerm dt = terms[d];
+            if (dt.ops & 48) continue;   // shift compensation: reduced-precision launches only
+            const int64_t idx = (dt.ops & 1) ? (int64_t)col + (int64_t)row * dt.lda
+                                             : (int64_t)row + (int64_t)col * dt.lda;
+            const double2 x = (reinterpret_cast<const double2*>(bufs.p[dt.a_buf]) + dt.a_off)[idx];
+            const double c = dt.coef;
             vr += c * x.x;
             vi += (dt.ops & 2) ? -c * x.y : c * x.y;
           }
@@ -651,7 +848,7 @@ __global__ __launch_bounds__(64 * WM * WN) void heff_gemm(Bufs bufs, double* __r
                                                          const DevTile* __restrict__ tiles,
                                                          const DevOut* __restrict__ outs,
                                                          const DevTerm* __restrict__ terms) {
-  gemm_body<T, WM, WN, SH>(bufs, C, part, tiles, outs, terms);
+  gemm_body<T, WM, WN, SH>(bufs, C, part, tiles, outs, terms, blockIdx.x);
 }
 template <typename T, int WM, int WN, bool SH>
 __global__ __launch_bounds__(64 * WM * WN) void block_gemm(Bufs bufs, double* __restrict__ C,
@@ -659,7 +856,58 @@ __global__ __launch_bounds__(64 * WM * WN) void block_gemm(Bufs bufs, double* __
                                                           const DevTile* __restrict__ tiles,
                                                           const DevOut* __restrict__ outs,
                                                           const DevTerm* __restrict__ terms) {
-  gemm_body<T, WM, WN, SH>(bufs, C, part, tiles, outs, terms);
+  gemm_body<T, WM, WN, SH>(bufs, C, part, tiles, outs, terms, blockIdx.x);
+}
+
+// Persistent form of the effective-Hamiltonian launch: a grid of as many
+// workgroups as fit on the device at once takes the (cost-ordered) tiles from
+// a device counter, one at a time, until none is left.  Every workgroup ends
+// when the counter passes the tile count, so the grid drains by itself.
+template <typename T, int WM, int WN, bool SH>
+__global__ __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(3)))
+void heff_gemm_persistent(Bufs bufs, double* __restrict__ C,
+                                                                    double2* __restrict__ part,
+                                                                    const DevTile* __restrict__ tiles,
+                                                                    const DevOut* __restrict__ outs,
+                                                                    const DevTerm* __restrict__ terms, int ntiles,
+                                                                    int* __restrict__ counter) {
+  __shared__ int next;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+    __syncthreads();
+    const int tile = next;
+    if (tile >= ntiles) return;
+    gemm_body<T, WM, WN, SH>(bufs, C, part, tiles, outs, terms, tile);
+    __syncthreads();   // every thread has read `next` before it is overwritten
+  }
+}
+
+__global__ void reset_counter(int* __restrict__ counter) {
+  if (threadIdx.x == 0) *counter = 0;
+}
+
+// Workgroups of heff_gemm_persistent<T, 2, 2, SH> resident at once on the device.
+template <typename T, bool SH>
+int resident_groups(tdvp_ctx* ctx) {
+  static int cached[64] = {};
+  const int dev = ctx->device < 64 ? ctx->device : 0;
+  if (cached[dev]) return cached[dev];
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, heff_gemm_persistent<T, 2, 2, SH>, 256, 0) !=
+          hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess ||
+      per_cu < 1 || cus < 1)
+    return 256;
+  return cached[dev] = per_cu * cus;
+}
+
+template <typename T, bool SH>
+void launch_persistent(tdvp_ctx* ctx, int ntiles, const Bufs& bufs, double* C, double2* part, const DevTile* tiles,
+                       const DevArrays& a, int* counter) {
+  const int g = std::max(1, std::min(ntiles, resident_groups<T, SH>(ctx)));
+  hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, ctx->stream, counter);
+  hipLaunchKernelGGL((heff_gemm_persistent<T, 2, 2, SH>), dim3(g), dim3(256), 0, ctx->stream, bufs, C, part, tiles,
+                     a.outs, a.terms, ntiles, counter);
 }
 
 template <typename T, int WM, int WN>
@@ -763,12 +1011,12 @@ double tile_threshold() {
 constexpr int kXcds = 8;
 
 template <typename Item>
-static std::vector<Item> xcd_order(const std::vector<Item>& items) {
+static std::vector<Item> xcd_order(const std::vector<Item>& items, int per = 1) {
   static const bool on = [] {
     const char* e = std::getenv("TDVP_XCD");
     return !(e && std::atoi(e) == 0);
   }();
-  if (!on || items.size() < 2 * kXcds) return items;
+  if (!on || items.size() < 2 * (size_t)kXcds * per) return items;
   std::map<int, double> gcost;
   for (const Item& it : items) gcost[it.t.out] += it.cost;
   std::vector<std::pair<double, int>> groups;
@@ -785,22 +1033,25 @@ static std::vector<Item> xcd_order(const std::vector<Item>& items) {
   }
   std::vector<Item> q[kXcds];
   for (const Item& it : items) q[home[it.t.out]].push_back(it);   // stays cost-ordered
+  // `per` consecutive items make one workgroup (wave tiles: four), so the
+  // queues are interleaved `per` items at a time
   std::vector<Item> out;
   out.reserve(items.size());
   size_t pos[kXcds] = {};
   while (out.size() < items.size()) {
-    for (int x = 0; x < kXcds && out.size() < items.size(); ++x) {
-      int src = x;
-      if (pos[src] >= q[src].size()) {   // empty queue: borrow from the fullest one
-        size_t best = 0;
-        for (int y = 0; y < kXcds; ++y)
-          if (q[y].size() - pos[y] > best) {
-            best = q[y].size() - pos[y];
-            src = y;
-          }
+    for (int x = 0; x < kXcds && out.size() < items.size(); ++x)
+      for (int r = 0; r < per && out.size() < items.size(); ++r) {
+        int src = x;
+        if (pos[src] >= q[src].size()) {   // empty queue: borrow from the fullest one
+          size_t best = 0;
+          for (int y = 0; y < kXcds; ++y)
+            if (q[y].size() - pos[y] > best) {
+              best = q[y].size() - pos[y];
+              src = y;
+            }
+        }
+        out.push_back(q[src][pos[src]++]);
       }
-      out.push_back(q[src][pos[src]++]);
-    }
   }
   return out;
 }
@@ -976,10 +1227,28 @@ void Program::finalize() {
         tile_only(mode, a);
         alt.push_back(a);
       }
+    // the all-64x64 tiles once more, launched as a persistent grid, and the
+    // all-32x32 tiles as wave tiles
+    const size_t nbase = alt.size();
+    for (size_t v = 0; v < nbase; ++v) {
+      if (alt[v].mode == 2) {
+        Tiling a = alt[v];
+        a.mode = 3;
+        a.persistent = true;
+        alt.push_back(a);
+      }
+      if (alt[v].mode == 1) {
+        Tiling a;
+        tile_only(1, a, 4);
+        a.mode = 4;
+        a.wave = true;
+        alt.push_back(a);
+      }
+    }
   }
 }
 
-void Program::tile_only(int mode, Tiling& out) const {
+void Program::tile_only(int mode, Tiling& out, int per) const {
   struct It {
     DevTile t;
     double cost;
@@ -1006,8 +1275,8 @@ void Program::tile_only(int mode, Tiling& out) const {
   out.tiles.clear();
   out.n64 = (int)t64.size();
   out.mode = mode;
-  for (const It& it : xcd_order(t64)) out.tiles.push_back(it.t);
-  for (const It& it : xcd_order(t32)) out.tiles.push_back(it.t);
+  for (const It& it : xcd_order(t64, per)) out.tiles.push_back(it.t);
+  for (const It& it : xcd_order(t32, per)) out.tiles.push_back(it.t);
 }
 
 DeviceBuffer::~DeviceBuffer() { release(); }
@@ -1122,7 +1391,8 @@ std::shared_ptr<Program> cache_get(tdvp_ctx* ctx, uint64_t key, const std::vecto
 void cache_put(tdvp_ctx* ctx, uint64_t key, std::shared_ptr<Program> p) { cache_put(ctx->cache, key, std::move(p)); }
 
 static int launch_core(tdvp_ctx* ctx, const Program& p, const DevArrays& a, int ntiles, int n64,
-                       const DevTile* d_tiles, const Bufs& bufs, double* C, int precision, const LaunchWs* ws);
+                       const DevTile* d_tiles, const Bufs& bufs, double* C, int precision, const LaunchWs* ws,
+                       bool persistent = false, bool wave = false);
 static DevArrays arrays_of(const Program& p) { return DevArrays{p.d_terms, p.d_outs, p.d_reds, p.d_shift_meta}; }
 
 // Autotuner step: which tiling this launch uses, with its events.  Every
@@ -1213,11 +1483,23 @@ int launch_gemm(tdvp_ctx* ctx, const Program& p, const Bufs& bufs, double* C, in
   // FP64 launches only: there every tiling gives identical results, while the
   // reduced-precision kernels differ between 64x64 and 32x32 tiles
   hipEvent_t *ev0 = nullptr, *ev1 = nullptr;
-  const int v = precision == TDVP_FP64 ? tune_pick(ctx, p, ev0, ev1) : -1;
+  int v = precision == TDVP_FP64 ? tune_pick(ctx, p, ev0, ev1) : -1;
+  // measurement and test hook, read at every launch: TDVP_FORCE_TILING=m runs
+  // the candidate of mode m (0-2 tilings, 3 the persistent launch, 4 wave
+  // tiles) instead
+  if (const char* f = std::getenv("TDVP_FORCE_TILING")) {
+    const int m = std::atoi(f);
+    for (int c = 0; c < (int)p.alt.size(); ++c)
+      if (p.alt[c].mode == m && (precision == TDVP_FP64 || !(p.alt[c].persistent || p.alt[c].wave))) {
+        v = c;
+        ev0 = ev1 = nullptr;
+      }
+  }
   if (v >= 0) {   // the chosen (or measured) tiling replaces the active one
     const Program::Tiling& a = p.alt[v];
     if (ev0) TDVP_HIP(ctx, hipEventRecord(*ev0, ctx->stream));
-    int rc = launch_core(ctx, p, arrays_of(p), (int)a.tiles.size(), a.n64, a.d_tiles, bufs, C, precision, nullptr);
+    int rc = launch_core(ctx, p, arrays_of(p), (int)a.tiles.size(), a.n64, a.d_tiles, bufs, C, precision, nullptr,
+                         a.persistent, a.wave);
     if (ev1) TDVP_HIP(ctx, hipEventRecord(*ev1, ctx->stream));
     return rc;
   }
@@ -1239,7 +1521,8 @@ size_t partial_slot_bytes(int nslots) { return sizeof(double2) * (size_t)nslots 
 // workspaces; otherwise in the caller's (ws->part, ws->shift), which are
 // large enough (checked by the caller).
 static int launch_core(tdvp_ctx* ctx, const Program& p, const DevArrays& arr, int ntiles, int n64,
-                       const DevTile* d_tiles, const Bufs& bufs, double* C, int precision, const LaunchWs* ws) {
+                       const DevTile* d_tiles, const Bufs& bufs, double* C, int precision, const LaunchWs* ws,
+                       bool persistent, bool wave) {
   if (ntiles == 0) return TDVP_OK;
   double2* part = nullptr;
   if (p.nslots > 0) {
@@ -1329,13 +1612,24 @@ static int launch_core(tdvp_ctx* ctx, const Program& p, const DevArrays& arr, in
       }
     } else if (precision == TDVP_FP32) {
       launch_one<float, 2, 2>(ctx, heff, n64, bf, C, part, d_tiles, arr);
+    } else if (persistent && heff && !ws) {
+      // the work counter sits in the context's flag buffer, after the non-finite flag
+      int* counter = (int*)ctx->ws_flag.p + 16;
+      if (bf.shift) launch_persistent<double, true>(ctx, n64, bf, C, part, d_tiles, arr, counter);
+      else launch_persistent<double, false>(ctx, n64, bf, C, part, d_tiles, arr, counter);
     } else {
       launch_one<double, 2, 2>(ctx, heff, n64, bf, C, part, d_tiles, arr);
     }
   }
   if (n32 > 0) {   // 32x32 tiles (optional tile modes; never under BF16X3, see above)
-    if (precision != TDVP_FP64) launch_one<float, 1, 1>(ctx, heff, n32, bf, C, part, t32, arr);
-    else launch_one<double, 1, 1>(ctx, heff, n32, bf, C, part, t32, arr);
+    if (precision != TDVP_FP64) {
+      launch_one<float, 1, 1>(ctx, heff, n32, bf, C, part, t32, arr);
+    } else if (wave && heff && p.nslots == 0) {   // four wave tiles per workgroup
+      hipLaunchKernelGGL(heff_gemm_wave, dim3((unsigned)((n32 + 3) / 4)), dim3(256), 0, ctx->stream, bf, C, t32, n32,
+                         arr.outs, arr.terms);
+    } else {
+      launch_one<double, 1, 1>(ctx, heff, n32, bf, C, part, t32, arr);
+    }
   }
   if (!p.reds.empty())
     hipLaunchKernelGGL(reduce_parts, dim3((unsigned)p.reds.size()), dim3(256), 0, ctx->stream, bf, C,

@@ -460,3 +460,37 @@ def test_nomem_from_a_capped_allocator():
         assert np.isfinite(host(keep[3])).all()
     finally:
         c.close()
+
+
+def test_heff_tilings_and_persistent_launch_are_bit_identical(monkeypatch):
+    """Every FP64 candidate of the tiling autotuner -- mixed, all-32x32 and
+    all-64x64 tiles, the all-64x64 tiles in a persistent launch that takes
+    them from a device counter, and the all-32x32 tiles as wave tiles (one
+    per wave, operands loaded straight into registers) -- gives the same bits
+    (each element keeps its summation order whichever workgroup computes it)."""
+    print("FP64 tilings and the persistent launch", flush=True)
+    left, right, bl, br, X, Lx, Rx = _heff_case(4, 2, 500)
+    xk, xo, xt, xd, xs = X
+    lk, lo, lt, ld, Ls = Lx
+    rk, ro, rt, rd, Rs = Rx
+    x_d, L_d, R_d = dev(pack(xs, xo, xt)), dev(pack(Ls, lo, lt)), dev(pack(Rs, ro, rt))
+    c = T.Context(0, stream=torch_stream_handle())
+    outs = {}
+    try:
+        for mode in (2, 3, 0, 1, 4, 3, 4):
+            monkeypatch.setenv("TDVP_FORCE_TILING", str(mode))
+            y_d = torch.full_like(x_d, float("nan"))
+            c.heff_apply(T.Model(8), 4, 2, bl, br, T.Blocks(lk, lo, L_d.data_ptr(), lt),
+                         T.Blocks(rk, ro, R_d.data_ptr(), rt), T.Blocks(xk, xo, x_d.data_ptr(), xt),
+                         T.Blocks(xk, xo, y_d.data_ptr(), xt))
+            c.synchronize()
+            y = host(y_d)
+            assert np.isfinite(y).all()
+            if mode in outs:
+                assert np.array_equal(outs[mode], y)
+            outs[mode] = y
+    finally:
+        monkeypatch.delenv("TDVP_FORCE_TILING", raising=False)
+        c.close()
+    for mode in (3, 0, 1, 4):
+        assert np.array_equal(outs[2], outs[mode]), mode
