@@ -166,7 +166,7 @@ def large_heff(args, T, torch, stream, ctx, model, late=False):
            "theta_gb": round(xt * 16 / 1e9, 2), "env_gb": round((lt + rt) * 16 / 1e9, 2),
            "block_dim_max": int(max(r for r, c in xd)), "flops_per_apply": flops}
     # FP64 warm-up covers the tiling autotuner's measured launches
-    runs = (("fp64", T.FP64, 7, 3), ("fp32", T.FP32, 1, 3), ("bf16x3", T.BF16X3, 1, 3)) if late else \
+    runs = (("fp64", T.FP64, 9, 3), ("fp32", T.FP32, 1, 3), ("bf16x3", T.BF16X3, 1, 3)) if late else \
         (("fp64", T.FP64, 10, 10), ("fp32", T.FP32, 10, 10), ("bf16x3", T.BF16X3, 10, 10))
     for name, p, warm, reps in runs:
         dt = timed(p, warm, reps)
@@ -174,6 +174,14 @@ def large_heff(args, T, torch, stream, ctx, model, late=False):
         print(f"bench: chi={chi} H_eff {name} {1e3 * dt:.2f} ms, {flops / dt / 1e12:.2f} TFLOP/s",
               file=sys.stderr, flush=True)
     res["roofline_by_precision"] = rooflines({k: res[k] for k in ("fp64", "fp32", "bf16x3")})
+    for mode, key in ((2, "fp64_dispatcher_grid"), (3, "fp64_persistent_grid"), (4, "fp64_wave_tiles")):
+        os.environ["TDVP_FORCE_TILING"] = str(mode)
+        try:
+            dt = timed(T.FP64, 2, 3 if late else 10)
+        finally:
+            del os.environ["TDVP_FORCE_TILING"]
+        res[key] = {"ms_per_apply": 1e3 * dt, "tflops": flops / dt / 1e12}
+        print(f"bench: chi={chi} H_eff fp64 tiling mode {mode}, {key}: {1e3 * dt:.2f} ms", file=sys.stderr, flush=True)
     if not late:
         os.environ["TDVP_PER_BLOCK"] = "1"
         try:
@@ -238,6 +246,49 @@ def u1_heff(args, T, torch, stream, ctx, model, chi):
     return res
 
 
+def u1_sweep(args, T, torch, stream, ctx, model, chi, run):
+    """Two-site sweeps of the abelian U(1) x U(1) variant on a seeded random
+    L = 60 MPS at the same full-state bond dimension (synth.u1_random_mps:
+    sectors (2S^z, N) around half filling), with the run parameters of the
+    U(1) x SU(2) sweep; the first sweep is untimed."""
+    import synth
+    L = model.L
+    t0 = time.time()
+    bonds, sites = synth.u1_random_mps(L, chi, args.seed + 200)
+    print(f"bench: U(1)xU(1) random MPS built on the host in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    Tb = [T.Bond(b) for b in bonds]
+    bufs, descs = [], []
+    for k in range(1, L + 1):
+        tk, to, tt, _ = T.center_layout(Tb[k - 1], Tb[k], 1, abelian=True)
+        d = torch.from_numpy(pack(sites[k - 1], tk, to, tt)).to("cuda")
+        bufs.append(d)
+        descs.append(T.Blocks(tk, to, d.data_ptr(), tt))
+    ctx.set_precision(T.FP64)
+    mps = T.MPS.from_blocks(ctx, model, Tb, descs, abelian=True)
+    torch.cuda.synchronize()
+    del bufs, descs
+    ctx.memory(reset_peak=True)
+    infos = []
+    for st in range(2):
+        info = mps.sweep(**run)
+        infos.append(info)
+        print(f"bench: U(1)xU(1) sweep {st + 1}: {info['seconds']:.2f} s (lanczos {info['t_lanczos']:.2f}, "
+              f"svd {info['t_svd']:.2f}, env {info['t_env']:.2f}), chi {info['max_chi']}, "
+              f"krylov {info['krylov_iters']}", file=sys.stderr, flush=True)
+    i = infos[-1]
+    res = {"workload": f"L={L} U(1)xU(1) random MPS, chi={chi}, sectors (2Sz, N) around half filling; "
+                       "dt=0.05, eps_tol=1e-4, chi cap, FP64",
+           "s_per_sweep": i["seconds"], "sweep_phase_s": {k: i[k] for k in ("t_lanczos", "t_svd", "t_env")},
+           "krylov_iters": int(i["krylov_iters"]), "heff_flops": i["heff_flops"],
+           "lanczos_tflops": i["heff_flops"] / i["t_lanczos"] / 1e12 if i["t_lanczos"] > 0 else None,
+           "max_chi": int(i["max_chi"]), "max_discarded": i["max_discarded"],
+           "peak_device_gb": ctx.memory()[1] / 1e9, "sweeps": len(infos), "timed": 1}
+    mps.close()
+    ctx.set_precision(T.FP64 if args.prec == "fp64" else T.FP32)
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,7 +304,7 @@ def main():
     ap.add_argument("--one-site-steps", type=int, default=2, help="one-site sweeps timed after the two-site ones")
     ap.add_argument("--no-large", action="store_true", help="skip the chi=16384 grouped-vs-per-block measurement")
     ap.add_argument("--no-late", action="store_true", help="skip the chi~62000 H_eff throughput measurement")
-    ap.add_argument("--no-abelian", action="store_true", help="skip the U(1)xU(1) H_eff measurement")
+    ap.add_argument("--no-abelian", action="store_true", help="skip the U(1)xU(1) H_eff and sweep measurements")
     ap.add_argument("--krylov-probe", type=int, default=0,
                     help="only run Krylov exponentials of exactly this many iterations at the middle bond "
                          "(Lanczos vector-kernel profile)")
@@ -395,6 +446,18 @@ def main():
                               "tflops": flops / float(np.mean(d)) / 1e12}
         print(f"bench: H_eff apply {name} {heff_by_prec[name]['ms_per_apply']:.3f} ms, "
               f"{heff_by_prec[name]['tflops']:.2f} TFLOP/s", file=sys.stderr, flush=True)
+    # the all-64x64 FP64 tiles on the hardware dispatcher's grid (one workgroup
+    # per tile) and in the persistent launch (resident grid, device work
+    # counter), and the all-32x32 tiles as wave tiles (four per workgroup)
+    for mode, key in ((2, "fp64_dispatcher_grid"), (3, "fp64_persistent_grid"), (4, "fp64_wave_tiles")):
+        os.environ["TDVP_FORCE_TILING"] = str(mode)
+        try:
+            d, _ = time_applies(T.FP64)
+        finally:
+            del os.environ["TDVP_FORCE_TILING"]
+        heff_by_prec["fp64"][key] = {"ms_per_apply": 1e3 * float(np.mean(d)), "tflops": flops / float(np.mean(d)) / 1e12}
+        print(f"bench: H_eff apply FP64 tiling mode {mode}, {key}: {1e3 * float(np.mean(d)):.3f} ms", file=sys.stderr,
+              flush=True)
     ctx.set_precision(prec)
     t_apply = heff_by_prec[args.prec]["ms_per_apply"] * 1e-3
     heff_tflops = heff_by_prec[args.prec]["tflops"]
@@ -443,6 +506,17 @@ def main():
             for name, p_ in rungs:
                 octx = T.Context(0, stream=stream.cuda_stream, precision=p_)
                 others.append({"name": name, "ctx": octx, "mps": new_mps(octx), "infos": [], "cmp": []})
+            if prec == T.FP64:
+                # the memory plan for the largest bonds on the benchmark's bond: inactive
+                # tensors and environments in host memory, complex64 Krylov basis
+                octx = T.Context(0, stream=stream.cuda_stream, precision=T.FP64)
+                octx.set_host_staging(True)
+                octx.set_krylov_storage(T.FP32)
+                others.append({"name": "fp64_host_staged_complex64_krylov", "ctx": octx, "mps": new_mps(octx),
+                               "infos": [], "cmp": []})
+            for o in others:
+                o["ctx"].memory(reset_peak=True)
+        ctx.memory(reset_peak=True)
         infos = []
         t_sw = 0.0
         for st in range(args.warmup + args.steps):
@@ -473,6 +547,7 @@ def main():
                 print(f"bench: {o['name']} sweep {st + 1}: {oinfo['seconds']:.2f} s, |psi-phi| "
                       f"{o['cmp'][-1]['state_err']:.2e}, max|dSz| {o['cmp'][-1]['d_sz']:.2e}",
                       file=sys.stderr, flush=True)
+        sweep_peak = ctx.memory()[1]
         # one-site sweeps on the saturated state (bond dimensions fixed)
         one = []
         for st in range(args.one_site_steps):
@@ -492,6 +567,7 @@ def main():
                 "eig_fallbacks": int(sum(i["eig_fallbacks"] for i in infos)),
                 "max_chi": int(max(i["max_chi"] for i in infos)),
                 "max_discarded": float(max(i["max_discarded"] for i in infos)),
+                "peak_device_gb": sweep_peak / 1e9,
             }
             if one:
                 sweep["one_site"] = {
@@ -506,6 +582,7 @@ def main():
             cmp = o["cmp"]
             rec = {
                 "precision": o["name"],
+                "peak_device_gb": o["ctx"].memory()[1] / 1e9,
                 "s_per_sweep": float(np.mean([i["seconds"] for i in tail])),
                 "sweep_phase_s": {k: float(np.mean([i[k] for i in tail])) for k in
                                   ("t_lanczos", "t_svd", "t_env")},
@@ -523,6 +600,11 @@ def main():
             o["mps"].close()
             o["ctx"].close()
         mps.close()
+
+    abelian_sweep = None
+    if not args.no_abelian and (args.steps > 0 or args.warmup > 0):
+        abelian_sweep = u1_sweep(args, T, torch, stream, ctx, model, chi,
+                                 dict(dt=0.05, eps_tol=1e-4, chi_cap=chi, krylov_tol=1e-10, krylov_maxdim=40))
 
     # ---- CPU baseline: the oracle on sampled output blocks ------------------------
     cpu = None
@@ -600,6 +682,7 @@ def main():
         "large_blocks": large,
         "late_time_blocks": late,
         "u1xu1_heff": abelian,
+        "u1xu1_sweep": abelian_sweep,
     }
     line.update(sweep)
     print(json.dumps(line), flush=True)

@@ -489,13 +489,27 @@ int tdvp_u1_krylov_expm(tdvp_ctx* ctx, const tdvp_model* model, int32_t site, in
 int tdvp_u1_env_update(tdvp_ctx* ctx, const tdvp_model* model, int32_t site, int32_t direction,
                        const tdvp_bond* bond_in, const tdvp_bond* bond_out, const tdvp_blocks* env_in,
                        const tdvp_blocks* tensor, tdvp_blocks* env_out);
+/* U(1) x U(1) MPS, as tdvp_mps_create / tdvp_mps_create_neel with the
+ * conventions above: site keys (ia, s, ib) with s = 0..3; bond 0 the single
+ * sector (0, 0) of dimension 1 and bond L a single sector of dimension 1
+ * (the chain's 2 S^z and N; the Neel state's is (0, L)).  The MPS records its
+ * symmetry, and tdvp_sweep, tdvp_sweep1, tdvp_step, tdvp_mps_measure,
+ * tdvp_mps_overlap and the bond and site queries take either kind: the
+ * two-site split cuts the sector matrices of x = (2 S^z, N) and truncates
+ * single singular values (multiplet dimension 1) by the same rule.
+ * tdvp_split and tdvp_split_sectors are for U(1) x SU(2) only.  Errors as
+ * tdvp_mps_create. */
+int tdvp_u1_mps_create(tdvp_ctx* ctx, const tdvp_model* model, const tdvp_bond* bonds, const tdvp_blocks* sites,
+                       tdvp_mps** out);
+int tdvp_u1_mps_create_neel(tdvp_ctx* ctx, const tdvp_model* model, int32_t complete, tdvp_mps** out);
 
 /* Site-resolved observables of the quench (the local densities the paper
  * follows in time, main text results section): for every site k in 1..L,
  * sz[k-1] = <S^z_k> = (<n_k,up> - <n_k,down>)/2 and docc[k-1] =
  * <n_k,up n_k,down>, normalised by the state norm; *norm2 (optional) receives
  * <psi|psi>.  <n_k> = 1 exactly in the pseudospin-singlet sector, so
- * <n_k,up> = 1/2 + sz.  The MPS must have its centre on site 1 and sites
+ * <n_k,up> = 1/2 + sz there (a U(1) x U(1) state need not be in it).  The
+ * MPS must have its centre on site 1 and sites
  * 2..L right-canonical: the state after tdvp_sweep or tdvp_mps_create.
  * sz and docc are host arrays of L doubles.  Synchronises the stream.
  * Errors: INVALID (null or foreign MPS), NONFINITE (norm not positive). */
@@ -509,8 +523,8 @@ int tdvp_mps_measure(tdvp_ctx* ctx, const tdvp_mps* mps, double* sz, double* doc
  * belong to different contexts on the device of ctx (e.g. one per
  * precision); work runs on ctx's stream, so the caller finishes pending work
  * on the other context's stream first (tdvp_sweep returns synchronised).
- * Synchronises the stream.  Errors: INVALID (null argument or MPS on another
- * device), SHAPE (different L). */
+ * Synchronises the stream.  Errors: INVALID (null argument, MPS on another
+ * device, or of different symmetry), SHAPE (different L). */
 int tdvp_mps_overlap(tdvp_ctx* ctx, const tdvp_mps* bra, const tdvp_mps* ket, double* out);
 
 #ifdef __cplusplus

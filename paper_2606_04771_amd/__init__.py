@@ -108,6 +108,8 @@ def _load():
         "tdvp_u1_env_update": [P, P, I32, I32, P, P, P, P, P],
         "tdvp_mps_create": [P, P, P, P, P],
         "tdvp_mps_create_neel": [P, P, I32, P],
+        "tdvp_u1_mps_create": [P, P, P, P, P],
+        "tdvp_u1_mps_create_neel": [P, P, I32, P],
         "tdvp_mps_destroy": [P],
         "tdvp_mps_bond": [P, I32, P, P, P, P],
         "tdvp_mps_site_layout": [P, I32, P, P, P, P],
@@ -410,25 +412,28 @@ class Context:
 
 
 class MPS:
-    """Library-owned U(1)xSU(2) MPS (right-canonical, centre on site 1)."""
+    """Library-owned MPS (right-canonical, centre on site 1), U(1)xSU(2) or,
+    with abelian=True at creation, U(1)xU(1)."""
 
-    def __init__(self, ctx, handle, model):
-        self.ctx, self.h, self.model = ctx, handle, model
+    def __init__(self, ctx, handle, model, abelian=False):
+        self.ctx, self.h, self.model, self.abelian = ctx, handle, model, abelian
 
     @classmethod
-    def neel(cls, ctx, model, complete=False):
+    def neel(cls, ctx, model, complete=False, abelian=False):
         h = C.c_void_p()
-        _check(lib.tdvp_mps_create_neel(ctx.h, model.ref, int(bool(complete)), C.byref(h)), ctx.h)
-        return cls(ctx, h, model)
+        f = lib.tdvp_u1_mps_create_neel if abelian else lib.tdvp_mps_create_neel
+        _check(f(ctx.h, model.ref, int(bool(complete)), C.byref(h)), ctx.h)
+        return cls(ctx, h, model, abelian)
 
     @classmethod
-    def from_blocks(cls, ctx, model, bonds, sites):
+    def from_blocks(cls, ctx, model, bonds, sites, abelian=False):
         """bonds: L+1 Bond objects; sites: L Blocks (device data, keys (ia, s, ib))."""
         barr = (_Bond * len(bonds))(*[b._s for b in bonds])
         sarr = (_Blocks * len(sites))(*[s._s for s in sites])
         h = C.c_void_p()
-        _check(lib.tdvp_mps_create(ctx.h, model.ref, barr, sarr, C.byref(h)), ctx.h)
-        return cls(ctx, h, model)
+        f = lib.tdvp_u1_mps_create if abelian else lib.tdvp_mps_create
+        _check(f(ctx.h, model.ref, barr, sarr, C.byref(h)), ctx.h)
+        return cls(ctx, h, model, abelian)
 
     def close(self):
         if self.h:

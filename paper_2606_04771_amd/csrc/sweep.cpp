@@ -43,6 +43,7 @@ struct tdvp_mps {
   tdvp_model model{};
   int L = 0;
   bool fragment = false;   // result of tdvp_split: two sites between open bonds, not a chain
+  int sym = 0;             // 0: U(1) x SU(2) sectors (2S^z, 2j); 1: U(1) x U(1) sectors (2S^z, N)
   std::vector<Bond> bonds;                       // 0..L
   std::vector<std::unique_ptr<Tensor>> site;     // site k at index k-1
   std::vector<std::unique_ptr<Tensor>> Lenv, Renv;   // bond 0..L
@@ -56,17 +57,64 @@ double now() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// What the two symmetries differ in, for the chain-level code: the local
+// basis (three U(1) x SU(2) multiplets s = 0..2 with charges kLocQ / kLocTJ,
+// or four occupation states s = n_up + 2 n_dn with (2S^z, N) = kU1Sz / kU1N),
+// the fusion of a bond sector with a local state, the multiplet dimension
+// that weights a reduced singular value (2j + 1, or 1) and the block layouts.
+constexpr int kU1Sz[4] = {0, 1, -1, 0};
+constexpr int kU1N[4] = {0, 1, 1, 2};
+
+inline int nlocal(int sym) { return sym ? 4 : 3; }
+inline int64_t multiplet_dim(int sym, int tj) { return sym ? 1 : tj + 1; }
+
+// Does bond sector (q, tj) fused with local state s contain sector (q2, tj2)?
+inline bool fuses(int sym, int q, int tj, int s, int q2, int tj2) {
+  if (sym) return q + kU1Sz[s] == q2 && tj + kU1N[s] == tj2;
+  return q + kLocQ[s] == q2 && triangle(tj, kLocTJ[s], tj2);
+}
+
+// Every sector of (q, tj) fused with local state s.
+template <class F>
+void for_fused(int sym, int q, int tj, int s, F&& f) {
+  if (sym) {
+    f(q + kU1Sz[s], tj + kU1N[s]);
+    return;
+  }
+  for (int t2 = std::abs(tj - kLocTJ[s]); t2 <= tj + kLocTJ[s]; t2 += 2) f(q + kLocQ[s], t2);
+}
+
+int64_t bond_chi(int sym, const Bond& b) { return sym ? b.chi_su2() : b.chi_full(); }
+
+// Two-site blocks: (ia, s1, 2j_x, s2, ib) for U(1) x SU(2), (ia, s1, s2, ib)
+// for U(1) x U(1).  The middle sector x and the column pair (s2, ib) of a key.
+std::pair<int, int> theta_mid(int sym, const Bond& l, const int* k) {
+  if (sym) return {l.q[k[0]] + kU1Sz[k[1]], l.tj[k[0]] + kU1N[k[1]]};
+  return {l.q[k[0]] + kLocQ[k[1]], k[2]};
+}
+std::pair<int, int> theta_col(int sym, const int* k) { return sym ? std::make_pair(k[2], k[3]) : std::make_pair(k[3], k[4]); }
+
+void site_layout(int sym, const Bond& l, const Bond& r, Blocks& out) {
+  if (sym) u1_layout_center(l, r, 1, out);
+  else layout_site(l, r, out);
+}
+void theta_layout(int sym, const Bond& l, const Bond& r, Blocks& out) {
+  if (sym) u1_layout_center(l, r, 2, out);
+  else layout_center(l, r, 2, out);
+}
+
 // New contents are about to be written on the device: any staged copy is stale.
-int set_site_layout(tdvp_ctx* ctx, Tensor& t, const Bond& l, const Bond& r) {
-  layout_site(l, r, t.blk);
+int set_site_layout(tdvp_ctx* ctx, Tensor& t, const Bond& l, const Bond& r, int sym) {
+  site_layout(sym, l, r, t.blk);
   TDVP_HIP(ctx, t.buf.ensure(sizeof(double) * 2 * (size_t)std::max<int64_t>(t.blk.size, 1)));
   t.blk.data = t.buf.p;
   t.staged = false;
   return TDVP_OK;
 }
 
-int set_env_layout(tdvp_ctx* ctx, Tensor& t, const Bond& b) {
-  layout_env(b, t.blk);
+int set_env_layout(tdvp_ctx* ctx, Tensor& t, const Bond& b, int sym) {
+  if (sym) u1_layout_env(b, t.blk);
+  else layout_env(b, t.blk);
   TDVP_HIP(ctx, t.buf.ensure(sizeof(double) * 2 * (size_t)std::max<int64_t>(t.blk.size, 1)));
   t.blk.data = t.buf.p;
   t.staged = false;
@@ -118,8 +166,8 @@ int unstage_all(tdvp_ctx* ctx, const tdvp_mps* m) {
 }
 
 // environment of the empty block (bond [(0,0,1)]): zero Hamiltonian
-int empty_env(tdvp_ctx* ctx, Tensor& t, const Bond& b) {
-  int rc = set_env_layout(ctx, t, b);
+int empty_env(tdvp_ctx* ctx, Tensor& t, const Bond& b, int sym) {
+  int rc = set_env_layout(ctx, t, b, sym);
   if (rc) return rc;
   TDVP_HIP(ctx, hipMemsetAsync(t.blk.data, 0, sizeof(double) * 2 * std::max<int64_t>(t.blk.size, 1), ctx->stream));
   return TDVP_OK;
@@ -128,12 +176,13 @@ int empty_env(tdvp_ctx* ctx, Tensor& t, const Bond& b) {
 int env_step(tdvp_ctx* ctx, tdvp_mps* m, int site, int dir, double* flops = nullptr) {
   // dir +1: Lenv[site] from Lenv[site-1] and site tensor; -1: Renv[site-1] from Renv[site]
   EnvInputs in;
+  in.sym = m->sym;
   if (dir > 0) {
     in.bin = m->bonds[site - 1];
     in.bout = m->bonds[site];
     in.ein = m->Lenv[site - 1]->blk;
     in.ten = m->site[site - 1]->blk;
-    int rc = set_env_layout(ctx, *m->Lenv[site], in.bout);
+    int rc = set_env_layout(ctx, *m->Lenv[site], in.bout, m->sym);
     if (rc) return rc;
     in.eout = m->Lenv[site]->blk;
   } else {
@@ -141,7 +190,7 @@ int env_step(tdvp_ctx* ctx, tdvp_mps* m, int site, int dir, double* flops = null
     in.bout = m->bonds[site - 1];
     in.ein = m->Renv[site]->blk;
     in.ten = m->site[site - 1]->blk;
-    int rc = set_env_layout(ctx, *m->Renv[site - 1], in.bout);
+    int rc = set_env_layout(ctx, *m->Renv[site - 1], in.bout, m->sym);
     if (rc) return rc;
     in.eout = m->Renv[site - 1]->blk;
   }
@@ -160,7 +209,7 @@ int env_step_sync(tdvp_ctx* ctx, tdvp_mps* m, int site, int dir, tdvp_sweep_info
 // Theta(a, s1, x, s2, b) = X(a, s1, x) Y(x, s2, b) for the bond between i and i+1
 int merge(tdvp_ctx* ctx, tdvp_mps* m, int i, Blocks& th) {
   const Bond &l = m->bonds[i - 1], &c = m->bonds[i], &r = m->bonds[i + 1];
-  layout_center(l, r, 2, th);
+  theta_layout(m->sym, l, r, th);
   TDVP_HIP(ctx, ctx->ws_theta.ensure(sizeof(double) * 2 * (size_t)std::max<int64_t>(th.size, 1)));
   th.data = ctx->ws_theta.p;
   const Blocks &X = m->site[i - 1]->blk, &Y = m->site[i]->blk;
@@ -172,9 +221,11 @@ int merge(tdvp_ctx* ctx, tdvp_mps* m, int i, Blocks& th) {
     ob.ldc = ob.M = (int32_t)th.rows[o];
     ob.N = (int32_t)th.cols[o];
     ob.t_begin = (int32_t)p->terms.size();
-    int ix = c.find(l.q[k[0]] + kLocQ[k[1]], k[2]);
+    const auto x = theta_mid(m->sym, l, k);
+    const auto col = theta_col(m->sym, k);
+    int ix = c.find(x.first, x.second);
     if (ix >= 0) {
-      int a = X.find3(k[0], k[1], ix), b = Y.find3(ix, k[3], k[4]);
+      int a = X.find3(k[0], k[1], ix), b = Y.find3(ix, col.first, col.second);
       if (a >= 0 && b >= 0) {
         DevTerm d{};
         d.coef = 1.0;
@@ -220,6 +271,15 @@ bool eig_divide_conquer() {
     return !(e && std::string(e) == "jacobi");
   }();
   return dc;
+}
+
+// Buckets of at least this padded size are solved by the cyclic Jacobi
+// eigensolver instead (no tridiagonal reduction: a few launches per sweep
+// rather than several per column); read at every split, off by default.
+int64_t eig_jacobi_min() {
+  const char* e = std::getenv("TDVP_EIG_JACOBI_MIN");
+  const long long v = e ? std::atoll(e) : 0;
+  return v > 0 ? (int64_t)v : (int64_t)1 << 40;
 }
 
 int ensure_solver(tdvp_ctx* ctx) {
@@ -320,25 +380,25 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
     if (ctx->verbose >= 2 && hipStreamSynchronize(ctx->stream) == hipSuccess) ph[k] = now();
   };
   const Bond &l = m->bonds[i - 1], &r = m->bonds[i + 1];
+  const int sym = m->sym, nloc = nlocal(sym);
   std::map<std::pair<int, int>, Sector> secs;
   for (int o = 0; o < th.n(); ++o) {
-    const int* k = th.k(o);
-    int qx = l.q[k[0]] + kLocQ[k[1]];
-    Sector& s = secs[{qx, k[2]}];
-    s.q = qx;
-    s.tj = k[2];
+    const auto x = theta_mid(sym, l, th.k(o));
+    Sector& s = secs[x];
+    s.q = x.first;
+    s.tj = x.second;
   }
   for (auto& kv : secs) {   // every fusion partner of x, in a fixed order
     Sector& s = kv.second;
     for (int a = 0; a < l.size(); ++a)
-      for (int s1 = 0; s1 < 3; ++s1)
-        if (l.q[a] + kLocQ[s1] == s.q && triangle(l.tj[a], kLocTJ[s1], s.tj)) {
+      for (int s1 = 0; s1 < nloc; ++s1)
+        if (fuses(sym, l.q[a], l.tj[a], s1, s.q, s.tj)) {
           s.roff[{a, s1}] = s.rows;
           s.rows += l.d[a];
         }
-    for (int s2 = 0; s2 < 3; ++s2)
+    for (int s2 = 0; s2 < nloc; ++s2)
       for (int b = 0; b < r.size(); ++b)
-        if (s.q + kLocQ[s2] == r.q[b] && triangle(s.tj, kLocTJ[s2], r.tj[b])) {
+        if (fuses(sym, s.q, s.tj, s2, r.q[b], r.tj[b])) {
           s.coff[{s2, b}] = s.cols;
           s.cols += r.d[b];
         }
@@ -376,15 +436,19 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
   }
   // M | Gram slots | reflector scratch (n complex per slot) | eigenvalues |
   // off-diagonal workspace | info flags
-  size_t bytes = sizeof(double) * (2 * (size_t)(mtot + gtot) + 2 * (size_t)dtot + 2 * ((size_t)dtot + 8)) +
-                 sizeof(rocblas_int) * (size_t)(nmat + 8) + 4096;
+  // ... | Jacobi residuals | info flags | Jacobi sweep counts
+  size_t bytes = sizeof(double) * (2 * (size_t)(mtot + gtot) + 2 * (size_t)dtot + 2 * ((size_t)dtot + 8) +
+                                   (size_t)(nmat + 8)) +
+                 2 * sizeof(rocblas_int) * (size_t)(nmat + 8) + 4096;
   TDVP_HIP(ctx, ctx->ws_svd.ensure(bytes));
   double* Mbase = (double*)ctx->ws_svd.p;
   double* Gbase = Mbase + 2 * mtot;
   double* Pbase = Gbase + 2 * gtot;
   double* Dbase = Pbase + 2 * dtot;
   double* Ebase = Dbase + dtot + 8;
-  rocblas_int* dinfo = (rocblas_int*)(Ebase + dtot + 8);
+  double* jres = Ebase + dtot + 8;
+  rocblas_int* dinfo = (rocblas_int*)(jres + nmat + 8);
+  rocblas_int* jsweeps = dinfo + nmat + 8;
   int rc;
   Bufs b{};
   // gather Theta blocks into the sector matrices (zeros elsewhere)
@@ -393,9 +457,9 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
     Program p;
     for (int o = 0; o < th.n(); ++o) {
       const int* k = th.k(o);
-      Sector& s = secs[{l.q[k[0]] + kLocQ[k[1]], k[2]}];
+      Sector& s = secs[theta_mid(sym, l, k)];
       DevOut ob{};
-      ob.c_off = s.moff + s.roff.at({k[0], k[1]}) + s.coff.at({k[3], k[4]}) * s.rows;
+      ob.c_off = s.moff + s.roff.at({k[0], k[1]}) + s.coff.at(theta_col(sym, k)) * s.rows;
       ob.ldc = (int32_t)s.rows;
       ob.M = (int32_t)th.rows[o];
       ob.N = (int32_t)th.cols[o];
@@ -488,9 +552,10 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
     // host thread per stream was measured slower)
     struct EigJob {
       int64_t n, cnt, gmax;
-      double *G0, *P0, *D0, *E0;
-      rocblas_int* info;
+      double *G0, *P0, *D0, *E0, *res;
+      rocblas_int *info, *sweeps;
     };
+    const int64_t jmin = eig_jacobi_min();
     std::vector<std::vector<EigJob>> jobs(ctx->nside);
     for (int ob = (int)order.size() - 1; ob >= 0; --ob) {
       int64_t n = order[ob].first;
@@ -505,14 +570,21 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
       int k = (int)(std::min_element(sload.begin(), sload.end()) - sload.begin());
       sload[k] += (double)n;
       jobs[k].push_back(EigJob{n, (int64_t)secv.size(), gmax, Gbase + 2 * s0->goff, Pbase + 2 * s0->doff,
-                               Dbase + s0->doff, Ebase + s0->doff, dinfo + minfo[ob]});
+                               Dbase + s0->doff, Ebase + s0->doff, jres + minfo[ob], dinfo + minfo[ob],
+                               jsweeps + minfo[ob]});
     }
     auto issue = [&](int k) -> int {
       for (const EigJob& jb : jobs[k]) {
         const int64_t n = jb.n;
         rocblas_status st;
         int r;
-        if (dc) {
+        if (n >= jmin) {
+          // cyclic Jacobi: correct on block-structured and padded matrices as they are
+          st = rocsolver_zheevj_strided_batched(
+              (rocblas_handle)ctx->side_solver[k], rocblas_esort_ascending, rocblas_evect_original, rocblas_fill_upper,
+              (rocblas_int)n, (rocblas_double_complex*)jb.G0, (rocblas_int)n, (rocblas_stride)(n * n), 0.0, jb.res,
+              100, jb.sweeps, jb.D0, (rocblas_stride)n, jb.info, (rocblas_int)jb.cnt);
+        } else if (dc) {
           // The divide-and-conquer solver returns non-finite eigenvectors when the
           // tridiagonal form splits exactly, which zero-padded or block-structured
           // Gram matrices force; a dense Householder reflection H G H (same
@@ -613,7 +685,7 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
     Sector& s = kv.second;
     for (int64_t e = 0; e < std::min(s.rows, s.cols); ++e) {   // rank bound
       double lam = std::max(ev[s.doff + s.col0 + s.g - 1 - e], 0.0);   // descending
-      ents.push_back({lam, lam / (s.tj + 1), s.q, s.tj, (int)e, &s});
+      ents.push_back({lam, lam / (double)multiplet_dim(sym, s.tj), s.q, s.tj, (int)e, &s});
       W += lam;
     }
   }
@@ -649,8 +721,8 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
     int64_t chi = 0;
     size_t p = 0;
     for (; p < keep; ++p) {
-      if (p > 0 && chi + ents[p].tj + 1 > tr.chi_cap) break;
-      chi += ents[p].tj + 1;
+      if (p > 0 && chi + multiplet_dim(sym, ents[p].tj) > tr.chi_cap) break;
+      chi += multiplet_dim(sym, ents[p].tj);
     }
     keep = std::max<size_t>(p, 1);
   }
@@ -808,8 +880,8 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
   m->bonds[i] = nb;
   Tensor& TA = *m->site[i - 1];
   Tensor& TB = *m->site[i];
-  rc = set_site_layout(ctx, TA, m->bonds[i - 1], nb);
-  if (!rc) rc = set_site_layout(ctx, TB, nb, m->bonds[i + 1]);
+  rc = set_site_layout(ctx, TA, m->bonds[i - 1], nb, sym);
+  if (!rc) rc = set_site_layout(ctx, TB, nb, m->bonds[i + 1], sym);
   if (rc) return rc;
   // buffers: 0 = eigenvectors (Gbase), 1 = M, 2 = QR isometries
   auto iso_buf = [](const Sector& s) { return s.qr ? 2 : 0; };
@@ -902,6 +974,7 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
 int evolve(tdvp_ctx* ctx, tdvp_mps* m, int site, int nsites, Blocks& x, const Blocks& Le, const Blocks& Re,
            double tau_im, const tdvp_trunc& tr, tdvp_sweep_info* info) {
   HeffInputs in;
+  in.sym = m->sym;
   in.l = m->bonds[site - 1];
   in.r = m->bonds[site + nsites - 1];
   in.Le = Le;
@@ -938,11 +1011,11 @@ int check_finite(tdvp_ctx* ctx, const Blocks& b, const char* what, int bond) {
 
 int build_right_envs(tdvp_ctx* ctx, tdvp_mps* m) {
   int L = m->L;
-  int rc = empty_env(ctx, *m->Renv[L], m->bonds[L]);
+  int rc = empty_env(ctx, *m->Renv[L], m->bonds[L], m->sym);
   if (rc) return rc;
   for (int k = L; k >= 2; --k)
     if ((rc = env_step(ctx, m, k, -1))) return rc;
-  return empty_env(ctx, *m->Lenv[0], m->bonds[0]);
+  return empty_env(ctx, *m->Lenv[0], m->bonds[0], m->sym);
 }
 
 tdvp_mps* new_mps(tdvp_ctx* ctx, const tdvp_model& model) {
@@ -961,27 +1034,24 @@ tdvp_mps* new_mps(tdvp_ctx* ctx, const tdvp_model& model) {
   return m;
 }
 
-// multiplet counts of every (q, tj) in a block of n sites
-std::map<std::pair<int, int>, int64_t> multiplicity(int n) {
+// Sector counts of a block of n sites: multiplets per (2S^z, 2j) (sym 0) or
+// states per (2S^z, N) (sym 1).
+std::map<std::pair<int, int>, int64_t> sector_counts(int sym, int n) {
   std::map<std::pair<int, int>, int64_t> cur{{{0, 0}, 1}};
   for (int s = 0; s < n; ++s) {
     std::map<std::pair<int, int>, int64_t> nxt;
     for (auto& kv : cur)
-      for (int l = 0; l < 3; ++l)
-        for (int tj = std::abs(kv.first.second - kLocTJ[l]); tj <= kv.first.second + kLocTJ[l]; tj += 2)
-          nxt[{kv.first.first + kLocQ[l], tj}] += kv.second;
+      for (int l = 0; l < nlocal(sym); ++l)
+        for_fused(sym, kv.first.first, kv.first.second, l, [&](int q, int tj) { nxt[{q, tj}] += kv.second; });
     cur.swap(nxt);
   }
   return cur;
 }
 
-}  // namespace
-
-}  // namespace tdvp
-
-extern "C" {
-
-int tdvp_mps_create_neel(tdvp_ctx* ctx, const tdvp_model* model, int32_t complete, tdvp_mps** out) {
+// The Neel product state (up on odd sites) at half filling, right-canonical
+// with the centre on site 1; with `complete`, every bond at the full
+// dimension its sectors can have in the chain (zero-weight directions kept).
+int create_neel(tdvp_ctx* ctx, const tdvp_model* model, int32_t complete, int sym, tdvp_mps** out) {
   if (!ctx || !model || !out) return set_error(ctx, TDVP_E_INVALID, "null argument");
   return guarded(ctx, [&]() -> int {
     *out = nullptr;
@@ -989,20 +1059,26 @@ int tdvp_mps_create_neel(tdvp_ctx* ctx, const tdvp_model* model, int32_t complet
     if (L < 2 || L % 2) return set_error(ctx, TDVP_E_INVALID, "the Neel state needs an even L >= 2");
     TDVP_HIP(ctx, hipSetDevice(ctx->device));
     std::unique_ptr<tdvp_mps> m(new_mps(ctx, *model));
+    m->sym = sym;
     auto neel_s = [](int k) { return (k & 1) ? 1 : 2; };   // up on odd sites
+    // sector of the Neel state's first k sites, and the partner a right block
+    // of L - k sites needs for the whole chain to be the Neel state's sector
+    // (2S^z = 0; pseudospin singlet, or N = L)
+    auto neel_label = [&](int k) { return sym ? std::make_pair(k & 1, k) : std::make_pair(k & 1, 0); };
+    auto partner = [&](int q, int tj) { return sym ? std::make_pair(-q, L - tj) : std::make_pair(-q, tj); };
     // bond sectors
     std::vector<std::map<std::pair<int, int>, int64_t>> mult(L + 1);
-    for (int n = 0; n <= L; ++n) mult[n] = multiplicity(n);
+    for (int n = 0; n <= L; ++n) mult[n] = sector_counts(sym, n);
     for (int k = 0; k <= L; ++k) {
       Bond b;
       if (complete) {
         for (auto& kv : mult[k]) {
-          auto it = mult[L - k].find({-kv.first.first, kv.first.second});
+          auto it = mult[L - k].find(partner(kv.first.first, kv.first.second));
           if (it == mult[L - k].end()) continue;
           b.add(kv.first.first, kv.first.second, std::min(kv.second, it->second));
         }
       } else {
-        b.add(k & 1, 0, 1);
+        b.add(neel_label(k).first, neel_label(k).second, 1);
       }
       m->bonds[k] = b;
     }
@@ -1012,11 +1088,12 @@ int tdvp_mps_create_neel(tdvp_ctx* ctx, const tdvp_model* model, int32_t complet
     std::vector<std::vector<double>> host(L);
     for (int k = L; k >= 1; --k) {
       Tensor& T = *m->site[k - 1];
-      int rc = set_site_layout(ctx, T, m->bonds[k - 1], m->bonds[k]);
+      int rc = set_site_layout(ctx, T, m->bonds[k - 1], m->bonds[k], sym);
       if (rc) return rc;
       const Bond &l = m->bonds[k - 1], &r = m->bonds[k];
       host[k - 1].assign(2 * (size_t)T.blk.size, 0.0);
-      int ia_neel = l.find((k - 1) & 1, 0), ib_neel = r.find(k & 1, 0);
+      int ia_neel = l.find(neel_label(k - 1).first, neel_label(k - 1).second);
+      int ib_neel = r.find(neel_label(k).first, neel_label(k).second);
       for (int ia = 0; ia < l.size(); ++ia) {
         // columns of the fused space for row sector ia, in block order
         std::vector<int> blocks;
@@ -1071,29 +1148,37 @@ int tdvp_mps_create_neel(tdvp_ctx* ctx, const tdvp_model* model, int32_t complet
   });
 }
 
-int tdvp_mps_create(tdvp_ctx* ctx, const tdvp_model* model, const tdvp_bond* bonds, const tdvp_blocks* sites,
-                    tdvp_mps** out) {
+// An MPS from caller blocks (right-canonical, centre on site 1).
+int create_from_blocks(tdvp_ctx* ctx, const tdvp_model* model, const tdvp_bond* bonds, const tdvp_blocks* sites,
+                       int sym, tdvp_mps** out) {
   if (!ctx || !model || !out || !bonds || !sites) return set_error(ctx, TDVP_E_INVALID, "null argument");
   return guarded(ctx, [&]() -> int {
     *out = nullptr;
     if (model->L < 2) return set_error(ctx, TDVP_E_INVALID, "L must be >= 2");
     TDVP_HIP(ctx, hipSetDevice(ctx->device));
     std::unique_ptr<tdvp_mps> m(new_mps(ctx, *model));
+    m->sym = sym;
     std::string err;
     for (int k = 0; k <= m->L; ++k) {
-      int rc = load_bond(m->bonds[k], &bonds[k], err);
+      int rc = sym ? u1_load_bond(m->bonds[k], &bonds[k], err) : load_bond(m->bonds[k], &bonds[k], err);
       if (rc) return set_error(ctx, rc, err);
     }
-    if (m->bonds[0].size() != 1 || m->bonds[0].q[0] != 0 || m->bonds[0].tj[0] != 0 || m->bonds[0].d[0] != 1 ||
-        m->bonds[m->L].size() != 1 || m->bonds[m->L].q[0] != 0 || m->bonds[m->L].tj[0] != 0 ||
-        m->bonds[m->L].d[0] != 1)
-      return set_error(ctx, TDVP_E_SECTOR, "boundary bonds must be the single sector (0,0) of dimension 1");
+    const Bond &b0 = m->bonds[0], &bL = m->bonds[m->L];
+    if (b0.size() != 1 || b0.q[0] != 0 || b0.tj[0] != 0 || b0.d[0] != 1)
+      return set_error(ctx, TDVP_E_SECTOR, "bond 0 must be the single sector (0,0) of dimension 1");
+    // U(1) x SU(2): the chain is a pseudospin singlet with S^z = 0; U(1) x U(1):
+    // the last bond's one sector is the chain's (2S^z, N)
+    if (bL.size() != 1 || bL.d[0] != 1 || (!sym && (bL.q[0] != 0 || bL.tj[0] != 0)))
+      return set_error(ctx, TDVP_E_SECTOR,
+                       sym ? "bond L must be a single sector of dimension 1"
+                           : "boundary bonds must be the single sector (0,0) of dimension 1");
     for (int k = 1; k <= m->L; ++k) {
       Blocks src;
-      int rc = load_site(src, &sites[k - 1], m->bonds[k - 1], m->bonds[k], err);
+      int rc = sym ? u1_load_center(src, &sites[k - 1], m->bonds[k - 1], m->bonds[k], 1, err)
+                   : load_site(src, &sites[k - 1], m->bonds[k - 1], m->bonds[k], err);
       if (rc) return set_error(ctx, rc, err);
       if (src.n() && !src.data) return set_error(ctx, TDVP_E_INVALID, "null device data");
-      rc = set_site_layout(ctx, *m->site[k - 1], m->bonds[k - 1], m->bonds[k]);
+      rc = set_site_layout(ctx, *m->site[k - 1], m->bonds[k - 1], m->bonds[k], sym);
       if (rc) return rc;
       TDVP_HIP(ctx, hipMemsetAsync(m->site[k - 1]->blk.data, 0,
                                    sizeof(double) * 2 * std::max<int64_t>(m->site[k - 1]->blk.size, 1), ctx->stream));
@@ -1106,6 +1191,30 @@ int tdvp_mps_create(tdvp_ctx* ctx, const tdvp_model* model, const tdvp_bond* bon
     *out = m.release();
     return TDVP_OK;
   });
+}
+
+}  // namespace
+
+}  // namespace tdvp
+
+extern "C" {
+
+int tdvp_mps_create_neel(tdvp_ctx* ctx, const tdvp_model* model, int32_t complete, tdvp_mps** out) {
+  return create_neel(ctx, model, complete, 0, out);
+}
+
+int tdvp_u1_mps_create_neel(tdvp_ctx* ctx, const tdvp_model* model, int32_t complete, tdvp_mps** out) {
+  return create_neel(ctx, model, complete, 1, out);
+}
+
+int tdvp_mps_create(tdvp_ctx* ctx, const tdvp_model* model, const tdvp_bond* bonds, const tdvp_blocks* sites,
+                    tdvp_mps** out) {
+  return create_from_blocks(ctx, model, bonds, sites, 0, out);
+}
+
+int tdvp_u1_mps_create(tdvp_ctx* ctx, const tdvp_model* model, const tdvp_bond* bonds, const tdvp_blocks* sites,
+                       tdvp_mps** out) {
+  return create_from_blocks(ctx, model, bonds, sites, 1, out);
 }
 
 void tdvp_mps_destroy(tdvp_mps* mps) {
@@ -1172,7 +1281,7 @@ int tdvp_sweep(tdvp_ctx* ctx, tdvp_mps* m, double dt, const tdvp_trunc* tr, tdvp
       if (!ctx->verbose) return;
       std::fprintf(stderr,
                    "[tdvp] %s bond %2d chi=%6lld theta=%9lld krylov=%3d t=%.3fs (lanczos %.3f svd %.3f env %.3f)\n",
-                   dirs, i, (long long)m->bonds[i].chi_full(), (long long)n, b.krylov_iters - a.krylov_iters,
+                   dirs, i, (long long)bond_chi(m->sym, m->bonds[i]), (long long)n, b.krylov_iters - a.krylov_iters,
                    now() - tb, b.t_lanczos - a.t_lanczos, b.t_svd - a.t_svd, b.t_env - a.t_env);
       std::fflush(stderr);
     };
@@ -1250,7 +1359,7 @@ int tdvp_sweep(tdvp_ctx* ctx, tdvp_mps* m, double dt, const tdvp_trunc* tr, tdvp
     }
     TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
     for (int k = 0; k <= L; ++k) {
-      inf.max_chi = std::max(inf.max_chi, m->bonds[k].chi_full());
+      inf.max_chi = std::max(inf.max_chi, bond_chi(m->sym, m->bonds[k]));
       inf.max_chi_su2 = std::max(inf.max_chi_su2, m->bonds[k].chi_su2());
     }
     {
@@ -1274,7 +1383,9 @@ int tdvp_sweep(tdvp_ctx* ctx, tdvp_mps* m, double dt, const tdvp_trunc* tr, tdvp
 // vacuum), and the weight of local multiplet s on site k is
 //   W_s(k) = sum_{a,b} (2j_a+1) tr(T[a,s,b]^dag N_{k-1}[a] T[a,s,b]).
 // S^z is +1/2 on |up>, -1/2 on |down>, 0 on the doublet; in a pseudospin
-// singlet the doublet weight splits evenly between |up,down> and |0>.
+// singlet the doublet weight splits evenly between |up,down> and |0>.  For a
+// U(1) x U(1) chain the dimension factors are 1 and s runs over the four
+// occupation states, |up,down> being s = 3.
 int tdvp_mps_measure(tdvp_ctx* ctx, const tdvp_mps* m, double* sz, double* docc, double* norm2) {
   if (!ctx || !m || !sz || !docc) return set_error(ctx, TDVP_E_INVALID, "null argument");
   return guarded(ctx, [&]() -> int {
@@ -1358,7 +1469,7 @@ int tdvp_mps_measure(tdvp_ctx* ctx, const tdvp_mps* m, double* sz, double* docc,
           const int* key = T.k(o);
           if (key[2] != b) continue;
           DevTerm d{};
-          d.coef = (double)(l.tj[key[0]] + 1) / (double)(r.tj[b] + 1);
+          d.coef = (double)multiplet_dim(m->sym, l.tj[key[0]]) / (double)multiplet_dim(m->sym, r.tj[b]);
           d.a_buf = 1; d.a_off = T.off[o]; d.lda = (int32_t)T.rows[o]; d.ops = 1 | 2;
           d.b_buf = 2; d.b_off = T.off[o]; d.ldb = (int32_t)T.rows[o];
           d.K = (int32_t)T.rows[o];
@@ -1385,16 +1496,18 @@ int tdvp_mps_measure(tdvp_ctx* ctx, const tdvp_mps* m, double* sz, double* docc,
       TDVP_HIP(ctx, hipMemcpyAsync(hp.data(), part.p, sizeof(double) * 2 * T.n(), hipMemcpyDeviceToHost,
                                    ctx->stream));
       TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
-      double W[3] = {0.0, 0.0, 0.0};
+      double W[4] = {0.0, 0.0, 0.0, 0.0};
       for (int o = 0; o < T.n(); ++o) {
         const int* key = T.k(o);
-        W[key[1]] += (double)(l.tj[key[0]] + 1) * hp[2 * o];
+        W[key[1]] += (double)multiplet_dim(m->sym, l.tj[key[0]]) * hp[2 * o];
       }
-      const double nrm = W[0] + W[1] + W[2];
+      const double nrm = W[0] + W[1] + W[2] + W[3];
       if (!std::isfinite(nrm) || nrm <= 0.0)
         return set_error(ctx, TDVP_E_NONFINITE, "state norm not positive and finite at site " + std::to_string(k));
+      // |up> and |down> are s = 1, 2 in both local bases; the double occupancy
+      // is half the pseudospin doublet's weight (s = 0) or the weight of s = 3
       sz[k - 1] = 0.5 * (W[1] - W[2]) / nrm;
-      docc[k - 1] = 0.5 * W[0] / nrm;
+      docc[k - 1] = (m->sym ? W[3] : 0.5 * W[0]) / nrm;
       last_norm = nrm;
       Nin = Nout;
       cur = 1 - cur;
@@ -1408,13 +1521,15 @@ int tdvp_mps_measure(tdvp_ctx* ctx, const tdvp_mps* m, double* sz, double* docc,
 // differ): the mixed overlap environment on bond k, one d_bra x d_ket matrix
 // per sector present in both, obeys
 //   N_k[b] = sum_{a,s} (2j_a+1)/(2j_b+1) bra[a,s,b]^dag N_{k-1}[a] ket[a,s,b]
-// (the same recoupling as the norm), and <bra|ket> = N_L on the vacuum.
+// (the same recoupling as the norm; factors 1 for U(1) x U(1)), and
+// <bra|ket> = N_L on the last bond's one sector.
 int tdvp_mps_overlap(tdvp_ctx* ctx, const tdvp_mps* bra, const tdvp_mps* ket, double* out) {
   if (!ctx || !bra || !ket || !out) return set_error(ctx, TDVP_E_INVALID, "null argument");
   return guarded(ctx, [&]() -> int {
     if (bra->ctx->device != ctx->device || ket->ctx->device != ctx->device)
       return set_error(ctx, TDVP_E_INVALID, "MPS on another device");
     if (bra->L != ket->L) return set_error(ctx, TDVP_E_SHAPE, "chains of different length");
+    if (bra->sym != ket->sym) return set_error(ctx, TDVP_E_INVALID, "chains of different symmetry");
     if (bra->fragment || ket->fragment) return set_error(ctx, TDVP_E_INVALID, "a split result is not a chain");
     TDVP_HIP(ctx, hipSetDevice(ctx->device));
     if (int r0 = unstage_all(ctx, bra)) return r0;
@@ -1521,7 +1636,7 @@ int tdvp_mps_overlap(tdvp_ctx* ctx, const tdvp_mps* bra, const tdvp_mps* ket, do
           int bo = B.find3(ba, key[1], bb);
           if (bo < 0) continue;
           DevTerm d{};
-          d.coef = (double)(kl.tj[key[0]] + 1) / (double)(kr.tj[kb] + 1);
+          d.coef = (double)multiplet_dim(ket->sym, kl.tj[key[0]]) / (double)multiplet_dim(ket->sym, kr.tj[kb]);
           d.a_buf = 2; d.a_off = B.off[bo]; d.lda = (int32_t)B.rows[bo]; d.ops = 1 | 2;
           d.b_buf = 3; d.b_off = t1off[o]; d.ldb = (int32_t)B.rows[bo];
           d.K = (int32_t)B.rows[bo];
@@ -1856,6 +1971,7 @@ int evolve_bond(tdvp_ctx* ctx, tdvp_mps* m, int i, int dir, Blocks& x, double ta
                 tdvp_sweep_info* info) {
   const Blocks& T = m->site[i - 1]->blk;   // A_i (dir +1) or B_i (dir -1)
   HeffInputs in;
+  in.sym = m->sym;
   in.l = m->bonds[i - 1];
   in.r = m->bonds[i];
   in.Le = m->Lenv[i - 1]->blk;
@@ -2043,7 +2159,7 @@ int tdvp_sweep1(tdvp_ctx* ctx, tdvp_mps* m, double dt, const tdvp_trunc* tr, tdv
     }
     TDVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
     for (int k = 0; k <= L; ++k) {
-      inf.max_chi = std::max(inf.max_chi, m->bonds[k].chi_full());
+      inf.max_chi = std::max(inf.max_chi, bond_chi(m->sym, m->bonds[k]));
       inf.max_chi_su2 = std::max(inf.max_chi_su2, m->bonds[k].chi_su2());
     }
     {

@@ -247,3 +247,94 @@ def u1_profile(chi, seed, nsites, spread=2.0, window=6, big=None):
     if big is not None and out:
         out[0] = (out[0][0], out[0][1], int(big))
     return out
+
+
+U1_LOCAL = [(0, 0), (1, 1), (-1, 1), (0, 2)]     # (2 S^z, N) of s = n_up + 2 n_dn
+
+
+def _u1_count(n, sz2, nn):
+    """Number of occupation states of n sites with 2 S^z = sz2 and N = nn."""
+    from math import comb
+    if (nn + sz2) % 2 or nn < 0:
+        return 0
+    nu, nd = (nn + sz2) // 2, (nn - sz2) // 2
+    if nu < 0 or nd < 0 or nu > n or nd > n:
+        return 0
+    return comb(n, nu) * comb(n, nd)
+
+
+def u1_random_mps(L, chi, seed, center=1, spread=2.0, window=6):
+    """Random U(1) x U(1) MPS of L sites at half filling (2 S^z = 0, N = L) in
+    mixed-canonical form with the centre on ``center``, the abelian analogue
+    of ``random_mps``: bond k gets ``u1_profile(chi, ., k)`` capped sector by
+    sector by the state counts of both sides and by the isometry condition of
+    the neighbouring tensor.
+
+    Returns (bonds, sites): bonds[k] = [(sz2, N, d)] for k = 0..L;
+    sites[k-1] = {(ia, s, ib): d_a x d_b complex array}, s = 0..3."""
+    bonds = [None] * (L + 1)
+    bonds[0] = [(0, 0, 1)]
+    bonds[L] = [(0, L, 1)]
+    for k in range(1, L):
+        bond = []
+        for sz2, nn, d in u1_profile(chi, seed + 7919 * k, k, spread=spread, window=window):
+            c = min(d, _u1_count(k, sz2, nn), _u1_count(L - k, -sz2, L - nn))
+            if c > 0:
+                bond.append((sz2, nn, c))
+        bonds[k] = sorted(bond)
+    for k in range(1, center):
+        prev = bonds[k - 1]
+        nb = []
+        for sz2, nn, d in bonds[k]:
+            rows = sum(da for (qa, na, da) in prev for qs, ns in U1_LOCAL if qa + qs == sz2 and na + ns == nn)
+            if min(d, rows) > 0:
+                nb.append((sz2, nn, min(d, rows)))
+        bonds[k] = nb
+    for k in range(L - 1, center - 1, -1):
+        nxt = bonds[k + 1]
+        nb = []
+        for sz2, nn, d in bonds[k]:
+            cols = sum(db for (qb, nb_, db) in nxt for qs, ns in U1_LOCAL if sz2 + qs == qb and nn + ns == nb_)
+            if min(d, cols) > 0:
+                nb.append((sz2, nn, min(d, cols)))
+        bonds[k] = nb
+    sites = [None] * L
+    for k in range(1, L + 1):
+        lb, rb = bonds[k - 1], bonds[k]
+        keys, dims = [], []
+        for ia, (qa, na, da) in enumerate(lb):
+            for s, (qs, ns) in enumerate(U1_LOCAL):
+                for ib, (qb, nb_, db) in enumerate(rb):
+                    if qa + qs == qb and na + ns == nb_:
+                        keys.append((ia, s, ib))
+                        dims.append((da, db))
+        raw = block_data(keys, dims, seed, 300 + k)
+        if k < center:
+            for ib in range(len(rb)):
+                ks = [key for key in keys if key[2] == ib]
+                if not ks:
+                    continue
+                Q, _ = np.linalg.qr(np.concatenate([raw[key] for key in ks], axis=0))
+                r = 0
+                for key in ks:
+                    n = raw[key].shape[0]
+                    raw[key] = Q[r:r + n]
+                    r += n
+        elif k > center:
+            for ia in range(len(lb)):
+                ks = [key for key in keys if key[0] == ia]
+                if not ks:
+                    continue
+                Q, _ = np.linalg.qr(np.concatenate([raw[key] for key in ks], axis=1).conj().T)
+                Q = Q.conj().T
+                c = 0
+                for key in ks:
+                    n = raw[key].shape[1]
+                    raw[key] = Q[:, c:c + n]
+                    c += n
+        else:
+            nrm = np.sqrt(sum(np.sum(np.abs(v) ** 2) for v in raw.values()))
+            for key in raw:
+                raw[key] = raw[key] / nrm
+        sites[k - 1] = raw
+    return bonds, sites

@@ -122,16 +122,22 @@ def _library_mps(ctx, model, bonds, sites):
     return mps
 
 
-@pytest.mark.parametrize("chi_cap,eps,fallback", [(24, 1e-8, False), (40, 1e-3, False), (24, 1e-8, True)])
-def test_truncated_sweeps_match_oracle(ctx, chi_cap, eps, fallback, monkeypatch):
+@pytest.mark.parametrize("chi_cap,eps,solver", [(24, 1e-8, "dc"), (40, 1e-3, "dc"), (24, 1e-8, "fallback"),
+                                                 (24, 1e-8, "jacobi")])
+def test_truncated_sweeps_match_oracle(ctx, chi_cap, eps, solver, monkeypatch):
     """Truncated two-site TDVP from a seeded random reduced MPS (L = 8): the
     library and the dense oracle, which truncates whole degenerate groups of
     singular values by the same rule, give the same state after each sweep.
     With fallback, every split re-solves its Gram matrices unpadded by the
-    Jacobi-based solver (the path taken when the main solver fails)."""
+    Jacobi-based solver (the path taken when the main solver fails); with
+    jacobi, every bucket goes to the cyclic Jacobi eigensolver (the option
+    for large buckets)."""
     import synth
+    fallback = solver == "fallback"
     if fallback:
         monkeypatch.setenv("TDVP_EIG_FORCE_FALLBACK", "1")
+    if solver == "jacobi":
+        monkeypatch.setenv("TDVP_EIG_JACOBI_MIN", "1")
     L, t, U, dt = 8, 1.0, 4.0, 0.05
     bonds, sites = synth.random_mps(L, 48, 17, center=1)
     model = T.Model(L, t, U)

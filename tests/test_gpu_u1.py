@@ -168,3 +168,134 @@ def test_u1_krylov_against_oracle(ctx, nsites, tau):
     print(f"  iters={info['iters']} err={err:.2e}", flush=True)
     assert err < 1e-10
     assert abs(np.linalg.norm(got) - 1.0) < 1e-12
+
+
+# ---- U(1) x U(1) chains: sweeps, observables and overlaps ---------------------
+
+def u1_state(mps, L):
+    """Expand a library U(1) x U(1) MPS (centre on site 1) with the oracle's
+    abelian conventions and contract it to a state vector."""
+    bonds = [mps.bond(k) for k in range(L + 1)]
+    full = []
+    for k in range(1, L + 1):
+        keys, offs, data = mps.site(k)
+        dims = [(bonds[k - 1][kk[0]][2], bonds[k][kk[2]][2]) for kk in keys]
+        full.append(A.expand_site(theta_dict(keys, unpack(data, offs, dims)), bonds[k - 1], bonds[k]))
+    return D.mps_state(full)
+
+
+def u1_library_mps(ctx, model, bonds, sites):
+    Tb = [T.Bond(b) for b in bonds]
+    bufs, descs = [], []
+    for k in range(1, len(sites) + 1):
+        tk, to, tt, _ = T.center_layout(Tb[k - 1], Tb[k], 1, abelian=True)
+        d = dev(pack([sites[k - 1][tuple(int(v) for v in kk)] for kk in tk], to, tt))
+        bufs.append(d)
+        descs.append(T.Blocks(tk, to, d.data_ptr(), tt))
+    mps = T.MPS.from_blocks(ctx, model, Tb, descs, abelian=True)
+    torch.cuda.synchronize()
+    return mps
+
+
+def u1_oracle_mps(bonds, sites):
+    return [A.expand_site(sites[k - 1], bonds[k - 1], bonds[k]) for k in range(1, len(sites) + 1)]
+
+
+def test_u1_neel_mps_is_the_neel_state(ctx):
+    from oracle import fermions as F
+    L = 6
+    for complete in (False, True):
+        mps = T.MPS.neel(ctx, T.Model(L, 1.0, 4.0), complete=complete, abelian=True)
+        assert mps.bond(L) == [(0, L, 1)]
+        psi = u1_state(mps, L)
+        assert abs(abs(np.vdot(F.neel_state(L), psi)) - 1) < 1e-14
+        sz, docc, n2 = mps.measure()
+        assert np.abs(sz - 0.5 * (-1.0) ** np.arange(L)).max() < 1e-14
+        assert np.abs(docc).max() < 1e-14 and abs(n2 - 1) < 1e-14
+        mps.close()
+
+
+@pytest.mark.parametrize("one_site", [False, True])
+def test_u1_complete_basis_sweeps_follow_exact_evolution_L8(ctx, one_site):
+    """L = 8 Neel quench (U/J = 4, dt = 0.05) with every bond at its full
+    U(1) x U(1) dimension, where two-site and one-site TDVP are exact:
+    against the 4^8 state-vector evolution, with the library's own
+    observables (S^z, double occupancy, norm)."""
+    from oracle import fermions as F
+    L, t, U, dt, nsteps = 8, 1.0, 4.0, 0.05, 20
+    mps = T.MPS.neel(ctx, T.Model(L, t, U), complete=True, abelian=True)
+    exact = F.evolve(F.hubbard(L, t, U), F.neel_state(L), np.arange(nsteps + 1) * dt)
+    worst = 0.0
+    for n in range(1, nsteps + 1):
+        if one_site:
+            info = mps.sweep1(dt, krylov_tol=1e-14, krylov_maxdim=50)
+        else:
+            info = mps.sweep(dt, keep_all=True, krylov_tol=1e-14, krylov_maxdim=50)
+        assert info["nonconverged"] == 0
+        if n % 5 == 0 or n == 1:
+            psi = u1_state(mps, L)
+            nu0, nd0, dd0 = F.local_expectations(exact[n], L)
+            nu, nd, dd = F.local_expectations(psi, L)
+            sz, docc, n2 = mps.measure()
+            err = max(abs(1 - abs(np.vdot(exact[n], psi))), np.abs(nu - nu0).max(), np.abs(dd - dd0).max(),
+                      np.abs(sz - 0.5 * (nu0 - nd0)).max(), np.abs(docc - dd0).max(), abs(n2 - 1))
+            print(f"t={n * dt:.2f} err {err:.2e} chi {info['max_chi']} krylov {info['krylov_iters']}", flush=True)
+            worst = max(worst, err)
+    mps.close()
+    assert worst < 1e-10
+
+
+@pytest.mark.parametrize("chi_cap,eps", [(24, 1e-8), (40, 1e-3)])
+def test_u1_truncated_sweeps_match_oracle(ctx, chi_cap, eps):
+    """Truncated two-site TDVP from a seeded random U(1) x U(1) MPS (L = 8):
+    the library's per-sector split keeps single singular values by the same
+    rule as the oracle's plain truncated SVD of the dense two-site matrix, so
+    the states, the discarded weights and the observables agree."""
+    from oracle import fermions as F
+    L, t, U, dt = 8, 1.0, 4.0, 0.05
+    bonds, sites = synth.u1_random_mps(L, 48, 17)
+    mps = u1_library_mps(ctx, T.Model(L, t, U), bonds, sites)
+    ref = u1_oracle_mps(bonds, sites)
+    assert abs(np.linalg.norm(D.mps_state(ref)) - 1) < 1e-12
+    assert abs(np.vdot(D.mps_state(ref), u1_state(mps, L)) - 1) < 1e-12
+    for n in range(3):
+        info = mps.sweep(dt, eps_tol=eps, chi_cap=chi_cap, keep_all=False, krylov_tol=1e-14, krylov_maxdim=50)
+        ref, disc = D.tdvp2_sweep(ref, dt, t, U, tol=1e-14, maxdim=50, keep_all=False, eps_tol=eps, chi_cap=chi_cap)
+        psi, phi = u1_state(mps, L), D.mps_state(ref)
+        ov = abs(np.vdot(phi, psi))
+        nu, nd, dd = F.local_expectations(psi, L)
+        mu, md, de = F.local_expectations(phi, L)
+        sz, docc, n2 = mps.measure()
+        print(f"sweep {n + 1}: 1-|ov| {1 - ov:.2e} chi {info['max_chi']} max disc {info['max_discarded']:.2e} "
+              f"(oracle {max(disc):.2e})", flush=True)
+        assert info["max_chi"] <= chi_cap
+        assert abs(info["max_discarded"] - max(disc)) < 1e-10
+        assert 1 - ov < 1e-10
+        assert max(np.abs(nu - mu).max(), np.abs(nd - md).max(), np.abs(dd - de).max()) < 1e-10
+        assert np.abs(sz - 0.5 * (nu - nd)).max() < 1e-12 and np.abs(docc - dd).max() < 1e-12
+    mps.close()
+
+
+def test_u1_one_site_sweeps_and_overlap_match_oracle(ctx):
+    """One-site TDVP at fixed bond dimensions from a seeded random U(1) x U(1)
+    MPS against the oracle's dense one-site sweep, and the overlap of two
+    such chains against the vdot of their expanded state vectors."""
+    L, t, U, dt = 8, 1.0, 4.0, 0.05
+    bonds, sites = synth.u1_random_mps(L, 48, 23)
+    b2, s2 = synth.u1_random_mps(L, 24, 29)
+    model = T.Model(L, t, U)
+    mps, other = u1_library_mps(ctx, model, bonds, sites), u1_library_mps(ctx, model, b2, s2)
+    ref = u1_oracle_mps(bonds, sites)
+    psi2 = D.mps_state(u1_oracle_mps(b2, s2))
+    assert abs(other.overlap(mps) - np.vdot(psi2, D.mps_state(ref))) < 1e-13
+    for n in range(3):
+        info = mps.sweep1(dt, krylov_tol=1e-14, krylov_maxdim=50)
+        ref = D.tdvp1_sweep(ref, dt, t, U, tol=1e-14, maxdim=50)
+        psi, phi = u1_state(mps, L), D.mps_state(ref)
+        ov = abs(np.vdot(phi, psi))
+        print(f"sweep {n + 1}: 1-|ov| {1 - ov:.2e} krylov {info['krylov_iters']}", flush=True)
+        assert 1 - ov < 1e-10
+        assert mps.bond(4) == [tuple(b) for b in bonds[4]]
+        assert abs(other.overlap(mps) - np.vdot(psi2, psi)) < 1e-12
+    mps.close()
+    other.close()
