@@ -192,6 +192,35 @@ def large_heff(args, T, torch, stream, ctx, model, late=False):
                                             "launches_per_apply": len(xk)}
         print(f"bench: chi={chi} H_eff fp64, one launch per output block: {1e3 * dt:.2f} ms, "
               f"{flops / dt / 1e12:.2f} TFLOP/s", file=sys.stderr, flush=True)
+    if late and args.late_bond:
+        # the other two costs of one bond update at this size, with the memory
+        # plan's complex64 Krylov basis: a fixed-length Krylov exponential
+        # (tol 0) and the split of Theta (operands are random, so only the
+        # times and the device memory are meaningful here)
+        ctx.set_precision(T.FP64)
+        ctx.set_krylov_storage(T.FP32)
+        ctx.memory(reset_peak=True)
+        m = args.late_bond
+        torch.cuda.synchronize()
+        t0 = time.time()
+        rc, info = ctx.krylov_expm(model, site, 2, bl, br, Lbk, Rbk, xb, -0.025j, tol=0.0, maxdim=m, check=False)
+        t_kry = time.time() - t0
+        ctx.set_krylov_storage(T.FP64)
+        print(f"bench: chi={chi} Krylov exponential, {info['iters']} iterations (complex64 basis): {t_kry:.2f} s",
+              file=sys.stderr, flush=True)
+        x_d /= torch.linalg.vector_norm(x_d)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        out, sv, disc = ctx.split(bl, br, xb, +1, eps_tol=1e-8, chi_cap=10 ** 6)
+        t_split = time.time() - t0
+        bond = out.bond(1)
+        out.close()
+        print(f"bench: chi={chi} split: {t_split:.2f} s, {len(sv)} sectors, largest sector matrix side "
+              f"{max(min(len(v), 10 ** 9) for v in sv.values())}", file=sys.stderr, flush=True)
+        res["bond_update"] = {"krylov_iterations": int(info["iters"]), "krylov_s": t_kry,
+                              "krylov_s_per_iteration": t_kry / max(info["iters"], 1), "split_s": t_split,
+                              "split_sectors": len(sv), "kept_reduced_dim": int(sum(d for _, _, d in bond)),
+                              "peak_device_gb": ctx.memory()[1] / 1e9}
     ctx.set_precision(T.FP64 if args.prec == "fp64" else T.FP32)
     del x_d, y_d, L_d, R_d
     torch.cuda.empty_cache()
@@ -304,6 +333,8 @@ def main():
     ap.add_argument("--one-site-steps", type=int, default=2, help="one-site sweeps timed after the two-site ones")
     ap.add_argument("--no-large", action="store_true", help="skip the chi=16384 grouped-vs-per-block measurement")
     ap.add_argument("--no-late", action="store_true", help="skip the chi~62000 H_eff throughput measurement")
+    ap.add_argument("--late-bond", type=int, default=8,
+                    help="Krylov iterations of the timed chi~62000 bond update (Krylov exponential and split; 0: skip)")
     ap.add_argument("--no-abelian", action="store_true", help="skip the U(1)xU(1) H_eff and sweep measurements")
     ap.add_argument("--krylov-probe", type=int, default=0,
                     help="only run Krylov exponentials of exactly this many iterations at the middle bond "
