@@ -1009,6 +1009,17 @@ double tile_threshold() {
 // the per-XCD queues (each still by decreasing cost) are interleaved so that
 // index i runs on XCD i mod 8.  TDVP_XCD=0 keeps the plain cost order.
 constexpr int kXcds = 8;
+constexpr int kCusPerXcd = 32;   // MI355X: 256 compute units in eight XCDs
+
+// Snake order of wave-tile workgroups within each XCD (TDVP_WAVE_SNAKE=0
+// keeps the plain cost order; read when a program is built).
+static bool wave_snake() {
+  static const bool on = [] {
+    const char* e = std::getenv("TDVP_WAVE_SNAKE");
+    return !(e && std::atoi(e) == 0);
+  }();
+  return on;
+}
 
 template <typename Item>
 static std::vector<Item> xcd_order(const std::vector<Item>& items, int per = 1) {
@@ -1033,6 +1044,26 @@ static std::vector<Item> xcd_order(const std::vector<Item>& items, int per = 1) 
   }
   std::vector<Item> q[kXcds];
   for (const Item& it : items) q[home[it.t.out]].push_back(it);   // stays cost-ordered
+  if (per > 1 && wave_snake()) {
+    // Wave tiles: all workgroups are resident at once and an XCD's workgroups
+    // go to its compute units in turn, so in every other round of one
+    // workgroup per compute unit the order is reversed (the unit that took the
+    // heaviest group of one round takes the lightest of the next).
+    for (auto& v : q) {
+      const size_t round = (size_t)kCusPerXcd * per;
+      for (size_t r0 = round; r0 < v.size(); r0 += 2 * round) {
+        const size_t r1 = std::min(v.size(), r0 + round);
+        std::vector<Item> g;   // the round's workgroups (items in runs of `per`), last one first
+        g.reserve(r1 - r0);
+        for (size_t e = r1; e > r0;) {
+          const size_t b = r0 + (e - r0 - 1) / per * per;   // start of the run that ends at e
+          g.insert(g.end(), v.begin() + b, v.begin() + e);
+          e = b;
+        }
+        std::copy(g.begin(), g.end(), v.begin() + r0);
+      }
+    }
+  }
   // `per` consecutive items make one workgroup (wave tiles: four), so the
   // queues are interleaved `per` items at a time
   std::vector<Item> out;
