@@ -58,6 +58,13 @@ def rooflines(by_prec):
     return out
 
 
+def restore_env(name, value):
+    if value is None:
+        os.environ.pop(name, None)
+    else:
+        os.environ[name] = value
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -175,11 +182,12 @@ def large_heff(args, T, torch, stream, ctx, model, late=False):
               file=sys.stderr, flush=True)
     res["roofline_by_precision"] = rooflines({k: res[k] for k in ("fp64", "fp32", "bf16x3")})
     for mode, key in ((2, "fp64_dispatcher_grid"), (3, "fp64_persistent_grid"), (4, "fp64_wave_tiles")):
+        before = os.environ.get("TDVP_FORCE_TILING")
         os.environ["TDVP_FORCE_TILING"] = str(mode)
         try:
             dt = timed(T.FP64, 2, 3 if late else 10)
         finally:
-            del os.environ["TDVP_FORCE_TILING"]
+            restore_env("TDVP_FORCE_TILING", before)
         res[key] = {"ms_per_apply": 1e3 * dt, "tflops": flops / dt / 1e12}
         print(f"bench: chi={chi} H_eff fp64 tiling mode {mode}, {key}: {1e3 * dt:.2f} ms", file=sys.stderr, flush=True)
     if not late:
@@ -481,11 +489,12 @@ def main():
     # per tile) and in the persistent launch (resident grid, device work
     # counter), and the all-32x32 tiles as wave tiles (four per workgroup)
     for mode, key in ((2, "fp64_dispatcher_grid"), (3, "fp64_persistent_grid"), (4, "fp64_wave_tiles")):
+        before = os.environ.get("TDVP_FORCE_TILING")
         os.environ["TDVP_FORCE_TILING"] = str(mode)
         try:
             d, _ = time_applies(T.FP64)
         finally:
-            del os.environ["TDVP_FORCE_TILING"]
+            restore_env("TDVP_FORCE_TILING", before)
         heff_by_prec["fp64"][key] = {"ms_per_apply": 1e3 * float(np.mean(d)), "tflops": flops / float(np.mean(d)) / 1e12}
         print(f"bench: H_eff apply FP64 tiling mode {mode}, {key}: {1e3 * float(np.mean(d)):.3f} ms", file=sys.stderr,
               flush=True)

@@ -305,7 +305,9 @@ template <int MR, int MC>
 struct WStage {
   double2 a[MR], b[MC];
   double c;
+  int k;          // the step's K offset
   bool ca, cb;
+  bool sha, shb;  // reduced precision: the energy shift on the diagonal of A (B)
 };
 
 // Steps of a chain: K offsets 0, 4, ... below K of every term in [t0, t1).
@@ -343,13 +345,16 @@ typedef const __attribute__((address_space(1))) double2* gptr2;
 typedef const double2* gptr2;   // the host pass only parses the device code
 #endif
 
-template <int MR, int MC>
+template <bool SH, int MR, int MC>
 __device__ __forceinline__ void wave_load(WStage<MR, MC>& s, const DevTerm* __restrict__ terms, const WPos& p,
                                           const Bufs& bufs, int m0, int n0, int M, int N, int li, int lk) {
   const DevTerm& tm = terms[p.t];
   s.c = tm.coef;
+  s.k = p.k;
   s.ca = tm.ops & 2;
   s.cb = tm.ops & 8;
+  s.sha = SH && (tm.ops & 16);
+  s.shb = SH && (tm.ops & 32);
   const gptr2 A = (gptr2)(reinterpret_cast<const double2*>(bufs.p[tm.a_buf]) + tm.a_off);
   const gptr2 B = (gptr2)(reinterpret_cast<const double2*>(bufs.p[tm.b_buf]) + tm.b_off);
   const gptr2 Z = (gptr2)&kZero2;
@@ -373,87 +378,104 @@ __device__ __forceinline__ void wave_load(WStage<MR, MC>& s, const DevTerm* __re
   }
 }
 
-template <int MR, int MC>
-__device__ __forceinline__ void wave_mma(const WStage<MR, MC>& s, f64x4 (&accr)[2][2], f64x4 (&acci)[2][2]) {
-  double ar[MR], ai[MR], nai[MR], br[MC], bi[MC];
+// The products of one step.  Values as the LDS-staged kernel stages them:
+// the shift subtracted on the diagonal, then coefficient and conjugation in
+// FP64, then the conversion to T.
+template <typename T, bool SH, int MR, int MC>
+__device__ __forceinline__ void wave_mma(const WStage<MR, MC>& s, typename Mfma<T>::acc_t (&accr)[2][2],
+                                         typename Mfma<T>::acc_t (&acci)[2][2], const int (&gm)[MR],
+                                         const int (&gn)[MC], int lk, double sh0, double sh1) {
+  T ar[MR], ai[MR], nai[MR], br[MC], bi[MC];
+  const int k = s.k + lk;
 #pragma unroll
   for (int i = 0; i < MR; ++i) {
-    ar[i] = s.c * s.a[i].x;
-    ai[i] = s.ca ? -s.c * s.a[i].y : s.c * s.a[i].y;
+    double x = s.a[i].x;
+    if (SH && s.sha && gm[i] == k) x -= sh0;
+    ar[i] = (T)(s.c * x);
+    ai[i] = (T)(s.ca ? -s.c * s.a[i].y : s.c * s.a[i].y);
     nai[i] = -ai[i];
   }
 #pragma unroll
   for (int j = 0; j < MC; ++j) {
-    br[j] = s.b[j].x;
-    bi[j] = s.cb ? -s.b[j].y : s.b[j].y;
+    double x = s.b[j].x;
+    if (SH && s.shb && gn[j] == k) x -= sh1;
+    br[j] = (T)x;
+    bi[j] = (T)(s.cb ? -s.b[j].y : s.b[j].y);
   }
 #pragma unroll
   for (int i = 0; i < MR; ++i)
 #pragma unroll
     for (int j = 0; j < MC; ++j) {
-      accr[i][j] = Mfma<double>::op(ar[i], br[j], accr[i][j]);
-      accr[i][j] = Mfma<double>::op(nai[i], bi[j], accr[i][j]);
-      acci[i][j] = Mfma<double>::op(ar[i], bi[j], acci[i][j]);
-      acci[i][j] = Mfma<double>::op(ai[i], br[j], acci[i][j]);
+      accr[i][j] = Mfma<T>::op(ar[i], br[j], accr[i][j]);
+      accr[i][j] = Mfma<T>::op(nai[i], bi[j], accr[i][j]);
+      acci[i][j] = Mfma<T>::op(ar[i], bi[j], acci[i][j]);
+      acci[i][j] = Mfma<T>::op(ai[i], br[j], acci[i][j]);
     }
 }
 
 // The K chain of one wave tile with MR x MC of its 16x16 sub-blocks inside
 // the output: three register stages, loads two steps ahead of the products.
-template <int MR, int MC>
+template <typename T, bool SH, int MR, int MC>
 __device__ __forceinline__ void wave_chain(const Bufs& bufs, const DevTerm* __restrict__ terms, const DevTile& tl,
-                                           const DevOut& ob, int li, int lk, f64x4 (&accr)[2][2],
-                                           f64x4 (&acci)[2][2]) {
+                                           const DevOut& ob, int li, int lk, typename Mfma<T>::acc_t (&accr)[2][2],
+                                           typename Mfma<T>::acc_t (&acci)[2][2]) {
   const int t1 = tl.t1;
   const int n = wave_steps(terms, tl.t0, t1);
   if (n == 0) return;
+  int gm[MR], gn[MC];
+#pragma unroll
+  for (int i = 0; i < MR; ++i) gm[i] = tl.m0 + i * 16 + li;
+#pragma unroll
+  for (int j = 0; j < MC; ++j) gn[j] = tl.n0 + j * 16 + li;
+  const double sh0 = SH ? bufs.shift[0] : 0.0, sh1 = SH ? bufs.shift[1] : 0.0;
   WPos p{tl.t0, 0};
   wave_settle(terms, p, t1);
   WStage<MR, MC> s0, s1, s2;
-  wave_load(s0, terms, p, bufs, tl.m0, tl.n0, ob.M, ob.N, li, lk);
+  wave_load<SH>(s0, terms, p, bufs, tl.m0, tl.n0, ob.M, ob.N, li, lk);
   wave_next(terms, p, t1);
-  wave_load(s1, terms, p, bufs, tl.m0, tl.n0, ob.M, ob.N, li, lk);
+  wave_load<SH>(s1, terms, p, bufs, tl.m0, tl.n0, ob.M, ob.N, li, lk);
   wave_next(terms, p, t1);
   int i = 0;
   for (; i + 3 <= n; i += 3) {   // steps i, i+1, i+2 are all in the chain
-    wave_load(s2, terms, p, bufs, tl.m0, tl.n0, ob.M, ob.N, li, lk);
+    wave_load<SH>(s2, terms, p, bufs, tl.m0, tl.n0, ob.M, ob.N, li, lk);
     wave_next(terms, p, t1);
-    wave_mma(s0, accr, acci);
-    wave_load(s0, terms, p, bufs, tl.m0, tl.n0, ob.M, ob.N, li, lk);
+    wave_mma<T, SH>(s0, accr, acci, gm, gn, lk, sh0, sh1);
+    wave_load<SH>(s0, terms, p, bufs, tl.m0, tl.n0, ob.M, ob.N, li, lk);
     wave_next(terms, p, t1);
-    wave_mma(s1, accr, acci);
-    wave_load(s1, terms, p, bufs, tl.m0, tl.n0, ob.M, ob.N, li, lk);
+    wave_mma<T, SH>(s1, accr, acci, gm, gn, lk, sh0, sh1);
+    wave_load<SH>(s1, terms, p, bufs, tl.m0, tl.n0, ob.M, ob.N, li, lk);
     wave_next(terms, p, t1);
-    wave_mma(s2, accr, acci);
+    wave_mma<T, SH>(s2, accr, acci, gm, gn, lk, sh0, sh1);
   }
-  if (i < n) wave_mma(s0, accr, acci);
-  if (i + 1 < n) wave_mma(s1, accr, acci);
+  if (i < n) wave_mma<T, SH>(s0, accr, acci, gm, gn, lk, sh0, sh1);
+  if (i + 1 < n) wave_mma<T, SH>(s1, accr, acci, gm, gn, lk, sh0, sh1);
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void heff_gemm_wave(Bufs bufs, double* __restrict__ Cbase,
-                                                      const DevTile* __restrict__ tiles, int ntiles,
-                                                      const DevOut* __restrict__ outs,
-                                                      const DevTerm* __restrict__ terms) {
+template <typename T, bool SH>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void heff_gemm_wave(
+    Bufs bufs, double* __restrict__ Cbase, const DevTile* __restrict__ tiles, int ntiles,
+    const DevOut* __restrict__ outs, const DevTerm* __restrict__ terms) {
+  typedef typename Mfma<T>::acc_t acc_t;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int tile = blockIdx.x * 4 + wave;
   if (tile >= ntiles) return;   // whole waves only: nothing below synchronises the workgroup
   const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
   const DevTile tl = tiles[tile];
   const DevOut ob = outs[tl.out];
-  f64x4 accr[2][2], acci[2][2];
+  acc_t accr[2][2], acci[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      accr[i][j] = f64x4{0, 0, 0, 0};
-      acci[i][j] = f64x4{0, 0, 0, 0};
+      accr[i][j] = acc_t{0, 0, 0, 0};
+      acci[i][j] = acc_t{0, 0, 0, 0};
     }
   // whole chains only (wave tiles are never split): terms [t0, t1) from K = 0
   const bool r2 = tl.m0 + 16 < ob.M, c2 = tl.n0 + 16 < ob.N;
-  if (r2 && c2) wave_chain<2, 2>(bufs, terms, tl, ob, li, lk, accr, acci);
-  else if (r2) wave_chain<2, 1>(bufs, terms, tl, ob, li, lk, accr, acci);
-  else if (c2) wave_chain<1, 2>(bufs, terms, tl, ob, li, lk, accr, acci);
-  else wave_chain<1, 1>(bufs, terms, tl, ob, li, lk, accr, acci);
+  if (r2 && c2) wave_chain<T, SH, 2, 2>(bufs, terms, tl, ob, li, lk, accr, acci);
+  else if (r2) wave_chain<T, SH, 2, 1>(bufs, terms, tl, ob, li, lk, accr, acci);
+  else if (c2) wave_chain<T, SH, 1, 2>(bufs, terms, tl, ob, li, lk, accr, acci);
+  else wave_chain<T, SH, 1, 1>(bufs, terms, tl, ob, li, lk, accr, acci);
   // direct (local) terms and the store, as in gemm_body
   double2* C = reinterpret_cast<double2*>(Cbase) + ob.c_off;
 #pragma unroll
@@ -462,17 +484,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void h
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int row = tl.m0 + i * 16 + Mfma<double>::row(r, lk);
+        int row = tl.m0 + i * 16 + Mfma<T>::row(r, lk);
         int col = tl.n0 + j * 16 + li;
         if (row < ob.M && col < ob.N) {
           double vr = accr[i][j][r], vi = acci[i][j][r];
           for (int d = ob.d_begin; d < ob.d_end; ++d) {
             const DevTerm dt = terms[d];
-            if (dt.ops & 48) continue;   // shift compensation: reduced-precision launches only
+            if (!SH && (dt.ops & 48)) continue;   // compensation of shifts not applied
             const int64_t idx = (dt.ops & 1) ? (int64_t)col + (int64_t)row * dt.lda
                                              : (int64_t)row + (int64_t)col * dt.lda;
             const double2 x = (reinterpret_cast<const double2*>(bufs.p[dt.a_buf]) + dt.a_off)[idx];
-            const double c = dt.coef;
+            double c = dt.coef;
+            if (SH && (dt.ops & 16)) c *= bufs.shift[0];
+            if (SH && (dt.ops & 32)) c *= bufs.shift[1];
             vr += c * x.x;
             vi += (dt.ops & 2) ? -c * x.y : c * x.y;
           }
@@ -1468,8 +1492,10 @@ static int tune_pick(tdvp_ctx* ctx, const Program& p, hipEvent_t*& ev0, hipEvent
   for (int k = 0; k < need; ++k) {
     float ms = 0.0f;
     if (hipEventSynchronize(p.tune_ev[2 * k + 1]) != hipSuccess ||
-        hipEventElapsedTime(&ms, p.tune_ev[2 * k], p.tune_ev[2 * k + 1]) != hipSuccess)
+        hipEventElapsedTime(&ms, p.tune_ev[2 * k], p.tune_ev[2 * k + 1]) != hipSuccess) {
       ms = 1e30f;
+      (void)hipGetLastError();   // a failed timing query ranks the candidate last; it is no launch error
+    }
     tot[k % nv] += ms;
   }
   p.tuned = (int)(std::min_element(tot.begin(), tot.end()) - tot.begin());
@@ -1514,18 +1540,18 @@ int launch_gemm(tdvp_ctx* ctx, const Program& p, const Bufs& bufs, double* C, in
   // FP64 launches only: there every tiling gives identical results, while the
   // reduced-precision kernels differ between 64x64 and 32x32 tiles
   hipEvent_t *ev0 = nullptr, *ev1 = nullptr;
-  int v = precision == TDVP_FP64 ? tune_pick(ctx, p, ev0, ev1) : -1;
+  int v = -1;
   // measurement and test hook, read at every launch: TDVP_FORCE_TILING=m runs
   // the candidate of mode m (0-2 tilings, 3 the persistent launch, 4 wave
-  // tiles) instead
+  // tiles) instead, and the autotuner is left alone
   if (const char* f = std::getenv("TDVP_FORCE_TILING")) {
     const int m = std::atoi(f);
     for (int c = 0; c < (int)p.alt.size(); ++c)
-      if (p.alt[c].mode == m && (precision == TDVP_FP64 || !(p.alt[c].persistent || p.alt[c].wave))) {
+      if (p.alt[c].mode == m && (precision == TDVP_FP64 || !p.alt[c].persistent) &&
+          (precision != TDVP_BF16X3 || !p.alt[c].wave))
         v = c;
-        ev0 = ev1 = nullptr;
-      }
   }
+  if (v < 0 && precision == TDVP_FP64) v = tune_pick(ctx, p, ev0, ev1);
   if (v >= 0) {   // the chosen (or measured) tiling replaces the active one
     const Program::Tiling& a = p.alt[v];
     if (ev0) TDVP_HIP(ctx, hipEventRecord(*ev0, ctx->stream));
@@ -1653,11 +1679,15 @@ static int launch_core(tdvp_ctx* ctx, const Program& p, const DevArrays& arr, in
     }
   }
   if (n32 > 0) {   // 32x32 tiles (optional tile modes; never under BF16X3, see above)
-    if (precision != TDVP_FP64) {
+    if (precision != TDVP_FP64 && wave && heff && p.nslots == 0) {   // FP32 wave tiles
+      const dim3 g((unsigned)((n32 + 3) / 4)), b(256);
+      if (bf.shift) hipLaunchKernelGGL((heff_gemm_wave<float, true>), g, b, 0, ctx->stream, bf, C, t32, n32, arr.outs, arr.terms);
+      else hipLaunchKernelGGL((heff_gemm_wave<float, false>), g, b, 0, ctx->stream, bf, C, t32, n32, arr.outs, arr.terms);
+    } else if (precision != TDVP_FP64) {
       launch_one<float, 1, 1>(ctx, heff, n32, bf, C, part, t32, arr);
     } else if (wave && heff && p.nslots == 0) {   // four wave tiles per workgroup
-      hipLaunchKernelGGL(heff_gemm_wave, dim3((unsigned)((n32 + 3) / 4)), dim3(256), 0, ctx->stream, bf, C, t32, n32,
-                         arr.outs, arr.terms);
+      hipLaunchKernelGGL((heff_gemm_wave<double, false>), dim3((unsigned)((n32 + 3) / 4)), dim3(256), 0, ctx->stream,
+                         bf, C, t32, n32, arr.outs, arr.terms);
     } else {
       launch_one<double, 1, 1>(ctx, heff, n32, bf, C, part, t32, arr);
     }

@@ -494,3 +494,35 @@ def test_heff_tilings_and_persistent_launch_are_bit_identical(monkeypatch):
         c.close()
     for mode in (3, 0, 1, 4):
         assert np.array_equal(outs[2], outs[mode]), mode
+
+
+def test_fp32_tilings_are_bit_identical(monkeypatch):
+    """FP32 block products (energy shift included) on every tiling the FP32
+    launches can take -- mixed, all-32x32 and all-64x64 LDS-staged tiles and
+    the wave tiles -- give the same bits: the products of each element come
+    in the same order, from the same FP32 values."""
+    print("FP32 tilings", flush=True)
+    left, right, bl, br, X, Lx, Rx = _heff_case(4, 2, 501)
+    xk, xo, xt, xd, xs = X
+    lk, lo, lt, ld, Ls = Lx
+    rk, ro, rt, rd, Rs = Rx
+    x_d, L_d, R_d = dev(pack(xs, xo, xt)), dev(pack(Ls, lo, lt)), dev(pack(Rs, ro, rt))
+    c = T.Context(0, stream=torch_stream_handle(), precision=T.FP32)
+    outs = {}
+    try:
+        for mode in (2, 4, 0, 1):
+            monkeypatch.setenv("TDVP_FORCE_TILING", str(mode))
+            y_d = torch.full_like(x_d, float("nan"))
+            c.heff_apply(T.Model(8), 4, 2, bl, br, T.Blocks(lk, lo, L_d.data_ptr(), lt),
+                         T.Blocks(rk, ro, R_d.data_ptr(), rt), T.Blocks(xk, xo, x_d.data_ptr(), xt),
+                         T.Blocks(xk, xo, y_d.data_ptr(), xt))
+            c.synchronize()
+            outs[mode] = host(y_d)
+            assert np.isfinite(outs[mode]).all()
+    finally:
+        monkeypatch.delenv("TDVP_FORCE_TILING", raising=False)
+        c.close()
+    diffs = {m: float(np.abs(outs[m] - outs[2]).max()) for m in (4, 0, 1)}
+    print("  max |difference| to the all-64x64 tiles:", diffs, flush=True)
+    for mode in (4, 0, 1):
+        assert np.array_equal(outs[2], outs[mode]), mode
