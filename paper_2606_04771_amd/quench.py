@@ -12,6 +12,10 @@ same step.
 
     python -m paper_2606_04771_amd.quench --L 60 --chi 4096 --t-end 6 --out quench.jsonl
 
+With --abelian the chain is the U(1) x U(1) one (same conventions, bond
+dimensions counted in states), for the paper's comparison of the two
+symmetries on the same quench.
+
 Each step prints one JSON line (time, sweep kind, seconds per precision,
 largest bond, and per reduced precision max |d<S^z>|, max |d<n_up n_dn>|,
 |psi_64 - psi_reduced|)."""
@@ -38,6 +42,8 @@ def main(argv=None):
     ap.add_argument("--no-switch", action="store_true")
     ap.add_argument("--rungs", default="fp32",
                     help="comma-separated reduced precisions run beside FP64: fp32, bf16x3")
+    ap.add_argument("--abelian", action="store_true",
+                    help="the U(1) x U(1) chain (the paper's comparison symmetry) instead of U(1) x SU(2)")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
 
@@ -47,7 +53,7 @@ def main(argv=None):
     runs = {}
     for name in ["fp64"] + rungs:
         ctx = T.Context(0, precision=precs[name])
-        runs[name] = (ctx, T.MPS.neel(ctx, model, complete=False))
+        runs[name] = (ctx, T.MPS.neel(ctx, model, complete=False, abelian=a.abelian))
     out = open(a.out, "w") if a.out else None
     nsteps = int(round(a.t_end / a.dt))
     mode = 0                      # 0: two-site sweeps, 1: one-site (set by the library's rule)
@@ -90,8 +96,8 @@ def main(argv=None):
             out.write(line + "\n")
             out.flush()
         mode = next_mode
-    summary = {"summary": True, "L": a.L, "U": a.U, "chi_cap": a.chi, "dt": a.dt, "t_end": a.t_end,
-               "eps_tol": a.eps,
+    summary = {"summary": True, "symmetry": "U(1)xU(1)" if a.abelian else "U(1)xSU(2)", "L": a.L, "U": a.U,
+               "chi_cap": a.chi, "dt": a.dt, "t_end": a.t_end, "eps_tol": a.eps,
                "max_obs_err": {r: max(worst[r]["d_sz"], worst[r]["d_docc"]) for r in rungs},
                "max_state_err": {r: worst[r]["state_err"] for r in rungs},
                "seconds": tot, "s_per_sweep": {k: v / nsteps for k, v in tot.items()}}

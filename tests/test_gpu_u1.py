@@ -299,3 +299,42 @@ def test_u1_one_site_sweeps_and_overlap_match_oracle(ctx):
         assert abs(other.overlap(mps) - np.vdot(psi2, psi)) < 1e-12
     mps.close()
     other.close()
+
+
+def test_u1_host_staged_sweeps_and_adaptive_step():
+    """U(1) x U(1) chains with the memory plan (inactive tensors in host
+    memory, FP64 Krylov storage) give bit-identical sweeps, and
+    the library's adaptive step switches to one-site sweeps once the largest
+    bond reaches the given fraction of the cap, on a seeded L = 12 chain."""
+    L, t, U, dt = 12, 1.0, 4.0, 0.05
+    bonds, sites = synth.u1_random_mps(L, 40, 31)
+    model = T.Model(L, t, U)
+    c1 = T.Context(0, stream=torch_stream_handle())
+    c2 = T.Context(0, stream=torch_stream_handle())
+    c2.set_host_staging(True)
+    try:
+        m1, m2 = u1_library_mps(c1, model, bonds, sites), u1_library_mps(c2, model, bonds, sites)
+        for n in range(2):
+            i1 = m1.sweep(dt, eps_tol=1e-8, chi_cap=48, krylov_tol=1e-12, krylov_maxdim=40)
+            i2 = m2.sweep(dt, eps_tol=1e-8, chi_cap=48, krylov_tol=1e-12, krylov_maxdim=40)
+            assert i1["max_chi"] == i2["max_chi"] and i1["krylov_iters"] == i2["krylov_iters"]
+        for k in range(1, L + 1):
+            k1, o1, d1 = m1.site(k)
+            k2, o2, d2 = m2.site(k)
+            assert np.array_equal(k1, k2) and np.array_equal(d1, d2)
+        sz1, dd1, _ = m1.measure()
+        sz2, dd2, _ = m2.measure()
+        assert np.array_equal(sz1, sz2) and np.array_equal(dd1, dd2)
+        # adaptive step: cap 24, switch at 75 % of it
+        mode, modes = 0, []
+        for n in range(4):
+            info, mode = m1.step(dt, mode, eps_tol=1e-8, chi_cap=24, krylov_tol=1e-12, krylov_maxdim=40, switch=0.75)
+            modes.append(mode)
+            assert info["max_chi"] <= 24
+        print("modes", modes, flush=True)
+        assert modes[-1] == 1
+        m1.close()
+        m2.close()
+    finally:
+        c1.close()
+        c2.close()
