@@ -15,7 +15,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtdvp.so")
 SOURCES = ["symm.cpp", "plan.cpp", "abelian.cpp", "common.cpp", "capi_host.cpp", "tridiag.cpp", "capi_dev.cpp",
            "capi_u1.cpp",
-           "krylov.cpp", "sweep.cpp", "gemm.hip", "vec.hip", "noalloc.hip"]
+           "krylov.cpp", "sweep.cpp", "gemm.hip", "vec.hip", "eig.hip", "noalloc.hip"]
 # host sources that launch kernels or use HIP device types are compiled as HIP
 HIP_CPP = ("capi_dev.cpp", "capi_u1.cpp", "krylov.cpp", "sweep.cpp")
 ARCH = "gfx950"

@@ -444,6 +444,7 @@ void tdvp_ctx_destroy(tdvp_ctx* ctx) {
   }
   for (auto& ev : ctx->side_ev)
     if (ev) (void)hipEventDestroy(ev);
+  for (auto& ev : ctx->eig_ev) (void)hipEventDestroy(ev);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->host_small) (void)hipHostFree(ctx->host_small);
   if (ctx->upload_done) (void)hipEventDestroy(ctx->upload_done);

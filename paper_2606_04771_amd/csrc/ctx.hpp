@@ -195,12 +195,13 @@ struct tdvp_ctx {
   // Side streams for concurrent batched eigensolves.  HIP maps streams onto
   // GPU_MAX_HW_QUEUES hardware queues (4 unless set before HIP starts); with
   // 8 queues the split of a chi = 4096 sweep takes ~30 % less time than with 4.
-  static constexpr int kSide = 8;
+  static constexpr int kSide = 16;
   int nside = 8;                      // in use (TDVP_SIDE_STREAMS, 1..kSide)
   bool graphs = true;                 // graph replay of Lanczos iterations
   hipStream_t side[kSide] = {};
   void* side_solver[kSide] = {};
   hipEvent_t side_ev[kSide + 1] = {};
+  std::vector<hipEvent_t> eig_ev;     // cross-stream dependencies of the split's eigensolves
   void* host_small = nullptr;   // pinned host mirror of ws_small
   std::shared_ptr<tdvp::ProgPool> pool = std::make_shared<tdvp::ProgPool>();
   int verbose = 0;
@@ -308,6 +309,28 @@ int vec_pad_matrix(tdvp_ctx* ctx, double* A, int64_t n, int64_t g, double v, dou
 // columns c >= c0 of eigenvectors W -> H W
 int vec_reflect_forward(tdvp_ctx* ctx, hipStream_t st, double* G, int64_t n, int64_t count, double* P);
 int vec_reflect_back(tdvp_ctx* ctx, hipStream_t st, double* G, int64_t n, int64_t count, int64_t c0);
+// Householder reduction of Hermitian n x n matrices to real tridiagonal form,
+// one launch per column index for a whole set of jobs.  A job is `count`
+// consecutive matrices A (full storage, n <= kTrdMaxN, overwritten); d, e (n
+// reals per matrix) receive the diagonal and off-diagonal, V (n^2 complex per
+// matrix) the reflectors, tau (n complex per matrix) their factors; Y: 2n
+// complex per matrix of scratch.  eig_trd_column(k) for k = 0, 1, ... in
+// stream order completes a job once k reaches its n - 1.
+constexpr int64_t kTrdMaxN = 1024;
+constexpr int kTrdMaxJobs = 16;
+struct TrdJob {
+  double *A, *V, *Y, *tau, *d, *e;
+  int n, count;
+};
+struct TrdSet {
+  TrdJob job[kTrdMaxJobs];
+  int njobs;
+};
+int eig_trd_column(tdvp_ctx* ctx, hipStream_t st, const TrdSet& set, int64_t k);
+// Columns c >= c0 of G = Q Zt for each matrix (Zt: real n x n eigenvectors of
+// the tridiagonal form, Q the product of the reflectors in V / tau).
+int eig_trd_back(tdvp_ctx* ctx, hipStream_t st, const double* Zt, const double* V, const double* tau, double* G,
+                 int64_t n, int64_t count, int64_t c0);
 // d_out[2b], d_out[2b+1] = re, im of sum conj(x) y over block b, whose element
 // range is [d_meta[2b], d_meta[2b] + d_meta[2b+1]) (device metadata)
 int vec_block_dots(tdvp_ctx* ctx, const double* x, const double* y, const int64_t* d_meta, int nblocks,

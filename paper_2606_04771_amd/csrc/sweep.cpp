@@ -282,6 +282,17 @@ int64_t eig_jacobi_min() {
   return v > 0 ? (int64_t)v : (int64_t)1 << 40;
 }
 
+// Buckets of padded size in [this, kTrdMaxN] take the in-house Householder
+// tridiagonal reduction (one launch per column for the whole bucket) and the
+// library's tridiagonal divide and conquer per matrix, instead of the batched
+// library solver; read at every split.
+int64_t eig_trd_min() {
+  const char* e = std::getenv("TDVP_EIG_TRD_MIN");
+  if (!e) return 256;
+  const long long v = std::atoll(e);
+  return v > 0 ? (int64_t)v : (int64_t)1 << 40;
+}
+
 int ensure_solver(tdvp_ctx* ctx) {
   if (ctx->solver) return TDVP_OK;
   rocblas_handle h;
@@ -434,12 +445,25 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
       ++nmat;
     }
   }
+  // which buckets the in-house tridiagonal reduction takes, and its storage:
+  // reflectors (n^2 complex), tridiagonal eigenvectors (n^2 real), two
+  // n-vectors of scratch and the reflector factors (n complex) per matrix
+  const bool dc = eig_divide_conquer();
+  const int64_t jmin = eig_jacobi_min(), tmin = eig_trd_min();
+  auto use_trd = [&](int64_t n) { return dc && n < jmin && n >= tmin && n <= kTrdMaxN; };
+  int64_t tsq = 0, tvec = 0;
+  for (auto& bk : buckets)
+    if (use_trd(bk.first)) {
+      tsq += bk.first * bk.first * (int64_t)bk.second.size();
+      tvec += bk.first * (int64_t)bk.second.size();
+    }
   // M | Gram slots | reflector scratch (n complex per slot) | eigenvalues |
-  // off-diagonal workspace | info flags
-  // ... | Jacobi residuals | info flags | Jacobi sweep counts
+  // off-diagonal workspace | Jacobi residuals | info flags | Jacobi sweep
+  // counts | tridiagonal-reduction storage
+  const size_t tri_bytes = sizeof(double) * (3 * (size_t)tsq + 6 * (size_t)tvec);
   size_t bytes = sizeof(double) * (2 * (size_t)(mtot + gtot) + 2 * (size_t)dtot + 2 * ((size_t)dtot + 8) +
                                    (size_t)(nmat + 8)) +
-                 2 * sizeof(rocblas_int) * (size_t)(nmat + 8) + 4096;
+                 2 * sizeof(rocblas_int) * (size_t)(nmat + 8) + 4096 + 256 + tri_bytes;
   TDVP_HIP(ctx, ctx->ws_svd.ensure(bytes));
   double* Mbase = (double*)ctx->ws_svd.p;
   double* Gbase = Mbase + 2 * mtot;
@@ -449,6 +473,8 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
   double* jres = Ebase + dtot + 8;
   rocblas_int* dinfo = (rocblas_int*)(jres + nmat + 8);
   rocblas_int* jsweeps = dinfo + nmat + 8;
+  double* tri = (double*)(((uintptr_t)(jsweeps + nmat + 8) + 255) & ~(uintptr_t)255);
+  double *triV = tri, *triZ = triV + 2 * tsq, *triY = triZ + tsq, *triT = triY + 4 * tvec;
   int rc;
   Bufs b{};
   // gather Theta blocks into the sector matrices (zeros elsewhere)
@@ -544,19 +570,38 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
       minfo.push_back(mi);
       mi += (int64_t)bk.second.size();
     }
-    std::vector<double> sload(ctx->nside, 0.0);
-    const bool dc = eig_divide_conquer();
-    // assign the buckets to side streams (largest first, balancing the summed
-    // padded size: each batched solve is a chain of dependent launches whose
-    // length follows n), then issue them stream by stream (issuing from one
-    // host thread per stream was measured slower)
+    // Schedule.  A bucket is one job: either one batched library solve, or
+    // (in-house reduction) reflection + reduction, one tridiagonal solve per
+    // matrix, back-transformation.  The reductions of all such buckets share
+    // their launches (one per column index, on side stream 0), so a bucket is
+    // reduced after as many launches as it has columns; its tridiagonal
+    // solves (independent chains of small library launches) go to the other
+    // side streams, each waiting for that point by an event, and its
+    // back-transformation waits for all of them.  Host issue order: the
+    // reductions, then the library solves, then the tridiagonal solves and
+    // back-transformations, so that every event is recorded before a wait on
+    // it is issued, and the long reduction chain starts first.  Streams are
+    // chosen by earliest estimated finish, largest work first.  Issuing from
+    // one host thread per stream was measured slower.
+    // Cost estimates in milliseconds, fitted to one MI355X (only their ratios
+    // steer the schedule): library solve of a bucket, the reduction reaching
+    // column n, tridiagonal solve of one matrix, back-transformation.
+    auto cost_lib = [](double n, double cnt) { return 0.4 + 0.03 * n + 0.002 * n * (cnt - 1.0); };
+    auto ready_red = [](double n) { return 0.015 * n; };
+    auto cost_stedc = [](double n) { return 0.5 + 0.004 * n; };
+    auto cost_back = [](double n, double cnt) { return 0.3 + 8e-4 * n * cnt; };
     struct EigJob {
       int64_t n, cnt, gmax;
       double *G0, *P0, *D0, *E0, *res;
       rocblas_int *info, *sweeps;
+      double *tV = nullptr, *tZ = nullptr, *tY = nullptr, *tT = nullptr;   // tridiagonal-reduction storage
+      int home = 0;                   // stream of a library solve / of the back-transformation
+      std::vector<int> stedc_on;      // stream of each matrix's tridiagonal solve
+      int ev_red = -1;                // event index: reduction done
+      std::vector<int> ev_stedc;      // event index per tridiagonal solve off the home stream (-1: home)
     };
-    const int64_t jmin = eig_jacobi_min();
-    std::vector<std::vector<EigJob>> jobs(ctx->nside);
+    int64_t tsq_at = 0, tvec_at = 0;
+    std::vector<EigJob> jobs;         // largest first
     for (int ob = (int)order.size() - 1; ob >= 0; --ob) {
       int64_t n = order[ob].first;
       auto& secv = *order[ob].second;
@@ -567,47 +612,190 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
         secv[q]->iidx = minfo[ob] + (int64_t)q;
         gmax = std::max(gmax, secv[q]->g);
       }
-      int k = (int)(std::min_element(sload.begin(), sload.end()) - sload.begin());
-      sload[k] += (double)n;
-      jobs[k].push_back(EigJob{n, (int64_t)secv.size(), gmax, Gbase + 2 * s0->goff, Pbase + 2 * s0->doff,
-                               Dbase + s0->doff, Ebase + s0->doff, jres + minfo[ob], dinfo + minfo[ob],
-                               jsweeps + minfo[ob]});
-    }
-    auto issue = [&](int k) -> int {
-      for (const EigJob& jb : jobs[k]) {
-        const int64_t n = jb.n;
-        rocblas_status st;
-        int r;
-        if (n >= jmin) {
-          // cyclic Jacobi: correct on block-structured and padded matrices as they are
-          st = rocsolver_zheevj_strided_batched(
-              (rocblas_handle)ctx->side_solver[k], rocblas_esort_ascending, rocblas_evect_original, rocblas_fill_upper,
-              (rocblas_int)n, (rocblas_double_complex*)jb.G0, (rocblas_int)n, (rocblas_stride)(n * n), 0.0, jb.res,
-              100, jb.sweeps, jb.D0, (rocblas_stride)n, jb.info, (rocblas_int)jb.cnt);
-        } else if (dc) {
-          // The divide-and-conquer solver returns non-finite eigenvectors when the
-          // tridiagonal form splits exactly, which zero-padded or block-structured
-          // Gram matrices force; a dense Householder reflection H G H (same
-          // spectrum, eigenvectors H W) removes that structure at O(n^2) cost.
-          if ((r = vec_reflect_forward(ctx, ctx->side[k], jb.G0, n, jb.cnt, jb.P0))) return r;
-          st = rocsolver_zheevd_strided_batched(
-              (rocblas_handle)ctx->side_solver[k], rocblas_evect_original, rocblas_fill_upper, (rocblas_int)n,
-              (rocblas_double_complex*)jb.G0, (rocblas_int)n, (rocblas_stride)(n * n), jb.D0, (rocblas_stride)n,
-              jb.E0, (rocblas_stride)n, jb.info, (rocblas_int)jb.cnt);
-          if (st == rocblas_status_success && (r = vec_reflect_back(ctx, ctx->side[k], jb.G0, n, jb.cnt, n - jb.gmax)))
-            return r;
-        } else {
-          st = rocsolver_zheevdj_strided_batched(
-              (rocblas_handle)ctx->side_solver[k], rocblas_evect_original, rocblas_fill_upper, (rocblas_int)n,
-              (rocblas_double_complex*)jb.G0, (rocblas_int)n, (rocblas_stride)(n * n), jb.D0, (rocblas_stride)n,
-              jb.info, (rocblas_int)jb.cnt);
-        }
-        if (st != rocblas_status_success) return TDVP_E_HIP;
+      EigJob jb{n, (int64_t)secv.size(), gmax, Gbase + 2 * s0->goff, Pbase + 2 * s0->doff,
+                Dbase + s0->doff, Ebase + s0->doff, jres + minfo[ob], dinfo + minfo[ob],
+                jsweeps + minfo[ob]};
+      if (use_trd(n)) {
+        jb.tV = triV + 2 * tsq_at;
+        jb.tZ = triZ + tsq_at;
+        jb.tY = triY + 4 * tvec_at;
+        jb.tT = triT + 2 * tvec_at;
+        tsq_at += n * n * jb.cnt;
+        tvec_at += n * jb.cnt;
       }
+      jobs.push_back(std::move(jb));
+    }
+    std::vector<int> trd_ix;          // in-house jobs, smallest first (the order they complete)
+    for (int j = (int)jobs.size() - 1; j >= 0; --j)
+      if (jobs[j].tV) trd_ix.push_back(j);
+    if ((int)trd_ix.size() > kTrdMaxJobs) return set_error(ctx, TDVP_E_INVALID, "too many eigensolver buckets");
+    // side stream 0 carries the reductions; the rest take everything else
+    // (with one side stream, everything runs on it in issue order)
+    const int s_lo = (!trd_ix.empty() && ctx->nside > 1) ? 1 : 0;
+    std::vector<double> sfree(ctx->nside, 0.0);
+    // (giving the largest bucket's tridiagonal solves streams of their own,
+    // the end of the critical path, was measured slower: 5.8 s against 5.3 s)
+    auto pick = [&](double ready, double cost) {
+      int best = s_lo;
+      for (int k = s_lo + 1; k < ctx->nside; ++k)
+        if (std::max(sfree[k], ready) + cost < std::max(sfree[best], ready) + cost) best = k;
+      return best;
+    };
+    for (EigJob& jb : jobs)
+      if (!jb.tV) {
+        jb.home = pick(0.0, cost_lib((double)jb.n, (double)jb.cnt));
+        sfree[jb.home] += cost_lib((double)jb.n, (double)jb.cnt);
+      }
+    int nev = 0;
+    for (int j : trd_ix) {
+      EigJob& jb = jobs[j];
+      const double ready = ready_red((double)jb.n);
+      jb.ev_red = nev++;
+      double done = ready;
+      for (int64_t q = 0; q < jb.cnt; ++q) {
+        const int k = pick(ready, cost_stedc((double)jb.n));
+        sfree[k] = std::max(sfree[k], ready) + cost_stedc((double)jb.n);
+        done = std::max(done, sfree[k]);
+        jb.stedc_on.push_back(k);
+      }
+      jb.home = jb.stedc_on[0];
+      for (int k : jb.stedc_on) jb.ev_stedc.push_back(k == jb.home ? -1 : nev++);
+      sfree[jb.home] = std::max(sfree[jb.home], done) + cost_back((double)jb.n, (double)jb.cnt);
+    }
+    while ((int)ctx->eig_ev.size() < nev) {
+      hipEvent_t e;
+      TDVP_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      ctx->eig_ev.push_back(e);
+    }
+    // verbose >= 3: a timeline of the phase (start / end of every piece of
+    // work against the phase start, "stream:what@start-end" in ms) and the
+    // host time spent issuing
+    struct Span {
+      int stream;
+      std::string what;
+      hipEvent_t a, b;
+    };
+    std::vector<Span> spans;
+    hipEvent_t t_ref = nullptr;
+    if (ctx->verbose >= 3) {
+      TDVP_HIP(ctx, hipEventCreate(&t_ref));
+      TDVP_HIP(ctx, hipEventRecord(t_ref, ctx->stream));
+    }
+    auto span_open = [&](int k, const std::string& what) -> int {
+      if (!t_ref) return TDVP_OK;
+      spans.push_back(Span{k, what, nullptr, nullptr});
+      TDVP_HIP(ctx, hipEventCreate(&spans.back().a));
+      TDVP_HIP(ctx, hipEventCreate(&spans.back().b));
+      TDVP_HIP(ctx, hipEventRecord(spans.back().a, ctx->side[k]));
       return TDVP_OK;
     };
-    for (int k = 0; k < ctx->nside; ++k)
-      if (int r = issue(k)) return r == TDVP_E_HIP ? set_error(ctx, r, "batched eigensolver failed") : r;
+    auto span_close = [&](int k) -> int {
+      if (t_ref) TDVP_HIP(ctx, hipEventRecord(spans.back().b, ctx->side[k]));
+      return TDVP_OK;
+    };
+    auto fail = [&](rocblas_status st) {
+      return st == rocblas_status_success ? TDVP_OK : set_error(ctx, TDVP_E_HIP, "batched eigensolver failed");
+    };
+    const double t_issue = now();
+    int ec;
+    // 1. the reductions (the tridiagonal divide and conquer fails on split
+    //    tridiagonal forms, so the Gram matrices are reflected first, as for
+    //    the library solver below)
+    if (!trd_ix.empty()) {
+      TrdSet set{};
+      int64_t nmax = 0;
+      for (int j : trd_ix) {
+        EigJob& jb = jobs[j];
+        if ((ec = vec_reflect_forward(ctx, ctx->side[0], jb.G0, jb.n, jb.cnt, jb.P0))) return ec;
+        set.job[set.njobs++] = TrdJob{jb.G0, jb.tV, jb.tY, jb.tT, jb.D0, jb.E0, (int)jb.n, (int)jb.cnt};
+        nmax = std::max(nmax, jb.n);
+      }
+      if ((ec = span_open(0, "reduce"))) return ec;
+      size_t next = 0;
+      for (int64_t k = 0; k < nmax; ++k) {
+        if ((ec = eig_trd_column(ctx, ctx->side[0], set, k))) return ec;
+        for (; next < trd_ix.size() && jobs[trd_ix[next]].n == k + 1; ++next)
+          TDVP_HIP(ctx, hipEventRecord(ctx->eig_ev[jobs[trd_ix[next]].ev_red], ctx->side[0]));
+      }
+      if ((ec = span_close(0))) return ec;
+    }
+    // 2. the library solves
+    for (const EigJob& jb : jobs) {
+      if (jb.tV) continue;
+      const int k = jb.home;
+      const int64_t n = jb.n;
+      if ((ec = span_open(k, "lib" + std::to_string(n) + "x" + std::to_string(jb.cnt)))) return ec;
+      if (n >= jmin) {
+        // cyclic Jacobi: correct on block-structured and padded matrices as they are
+        if ((ec = fail(rocsolver_zheevj_strided_batched(
+                 (rocblas_handle)ctx->side_solver[k], rocblas_esort_ascending, rocblas_evect_original,
+                 rocblas_fill_upper, (rocblas_int)n, (rocblas_double_complex*)jb.G0, (rocblas_int)n,
+                 (rocblas_stride)(n * n), 0.0, jb.res, 100, jb.sweeps, jb.D0, (rocblas_stride)n, jb.info,
+                 (rocblas_int)jb.cnt))))
+          return ec;
+      } else if (dc) {
+        // The divide-and-conquer solver returns non-finite eigenvectors when the
+        // tridiagonal form splits exactly, which zero-padded or block-structured
+        // Gram matrices force; a dense Householder reflection H G H (same
+        // spectrum, eigenvectors H W) removes that structure at O(n^2) cost.
+        if ((ec = vec_reflect_forward(ctx, ctx->side[k], jb.G0, n, jb.cnt, jb.P0))) return ec;
+        if ((ec = fail(rocsolver_zheevd_strided_batched(
+                 (rocblas_handle)ctx->side_solver[k], rocblas_evect_original, rocblas_fill_upper, (rocblas_int)n,
+                 (rocblas_double_complex*)jb.G0, (rocblas_int)n, (rocblas_stride)(n * n), jb.D0, (rocblas_stride)n,
+                 jb.E0, (rocblas_stride)n, jb.info, (rocblas_int)jb.cnt))))
+          return ec;
+        if ((ec = vec_reflect_back(ctx, ctx->side[k], jb.G0, n, jb.cnt, n - jb.gmax))) return ec;
+      } else {
+        if ((ec = fail(rocsolver_zheevdj_strided_batched(
+                 (rocblas_handle)ctx->side_solver[k], rocblas_evect_original, rocblas_fill_upper, (rocblas_int)n,
+                 (rocblas_double_complex*)jb.G0, (rocblas_int)n, (rocblas_stride)(n * n), jb.D0, (rocblas_stride)n,
+                 jb.info, (rocblas_int)jb.cnt))))
+          return ec;
+      }
+      if ((ec = span_close(k))) return ec;
+    }
+    // 3. per in-house bucket, in the order the reduction completes them: the
+    //    tridiagonal solves, then the eigenvectors of the needed columns
+    //    mapped back through both reflections on the home stream
+    for (int j : trd_ix) {
+      const EigJob& jb = jobs[j];
+      const int64_t n = jb.n;
+      for (int64_t q = 0; q < jb.cnt; ++q) {
+        const int k = jb.stedc_on[q];
+        TDVP_HIP(ctx, hipStreamWaitEvent(ctx->side[k], ctx->eig_ev[jb.ev_red], 0));
+        if ((ec = span_open(k, "tri" + std::to_string(n)))) return ec;
+        if ((ec = fail(rocsolver_dstedc((rocblas_handle)ctx->side_solver[k], rocblas_evect_tridiagonal,
+                                       (rocblas_int)n, jb.D0 + q * n, jb.E0 + q * n, jb.tZ + q * n * n,
+                                       (rocblas_int)n, jb.info + q))))
+          return ec;
+        if ((ec = span_close(k))) return ec;
+        if (jb.ev_stedc[q] >= 0) TDVP_HIP(ctx, hipEventRecord(ctx->eig_ev[jb.ev_stedc[q]], ctx->side[k]));
+      }
+      const int k = jb.home;
+      for (int e : jb.ev_stedc)
+        if (e >= 0) TDVP_HIP(ctx, hipStreamWaitEvent(ctx->side[k], ctx->eig_ev[e], 0));
+      if ((ec = span_open(k, "back" + std::to_string(n)))) return ec;
+      if ((ec = eig_trd_back(ctx, ctx->side[k], jb.tZ, jb.tV, jb.tT, jb.G0, n, jb.cnt, n - jb.gmax))) return ec;
+      if ((ec = vec_reflect_back(ctx, ctx->side[k], jb.G0, n, jb.cnt, n - jb.gmax))) return ec;
+      if ((ec = span_close(k))) return ec;
+    }
+    if (t_ref) {
+      const double host_ms = 1e3 * (now() - t_issue);
+      TDVP_HIP(ctx, hipDeviceSynchronize());
+      std::string line;
+      for (Span& x : spans) {
+        float a = 0.f, b = 0.f;
+        TDVP_HIP(ctx, hipEventElapsedTime(&a, t_ref, x.a));
+        TDVP_HIP(ctx, hipEventElapsedTime(&b, t_ref, x.b));
+        char buf[128];
+        std::snprintf(buf, sizeof buf, " %d:%s@%.1f-%.1f", x.stream, x.what.c_str(), a, b);
+        line += buf;
+        (void)hipEventDestroy(x.a);
+        (void)hipEventDestroy(x.b);
+      }
+      (void)hipEventDestroy(t_ref);
+      std::fprintf(stderr, "[tdvp]   eig bond %d: issue %.2f ms;%s\n", i, host_ms, line.c_str());
+    }
     for (int k = 0; k < ctx->nside; ++k) {
       TDVP_HIP(ctx, hipEventRecord(ctx->side_ev[k], ctx->side[k]));
       TDVP_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->side_ev[k], 0));

@@ -96,9 +96,14 @@ def _check_split(ctx, left, right, blocks, direction, eps, cap, keep_all=False, 
         mps.close()
 
 
+@pytest.mark.parametrize("solver", ["trd", "library"])
 @pytest.mark.parametrize("direction,eps,cap", [(1, 1e-4, 4096), (-1, 1e-4, 4096), (1, 1e-8, 2048)])
-def test_split_at_the_chi4096_middle_bond(ctx, direction, eps, cap):
-    print(f"split chi=4096 middle bond direction={direction} eps={eps} cap={cap}", flush=True)
+def test_split_at_the_chi4096_middle_bond(ctx, direction, eps, cap, solver, monkeypatch):
+    """With trd the Gram matrices of 256 and more go through the in-house
+    tridiagonal reduction (the default), with library through the batched
+    library solver."""
+    monkeypatch.setenv("TDVP_EIG_TRD_MIN", "256" if solver == "trd" else "0")
+    print(f"split chi=4096 middle bond direction={direction} eps={eps} cap={cap} eigensolver {solver}", flush=True)
     bonds = synth.random_bonds(60, 4096, 0, center=30)
     left, right = bonds[29], bonds[31]
     keys = [tuple(int(v) for v in k) for k in T.center_layout(T.Bond(left), T.Bond(right), 2)[0]]
@@ -142,8 +147,10 @@ def test_split_isometry_with_a_spread_spectrum(ctx, direction):
     _check_split(ctx, left, right, blocks, direction, 1e-10, 10 ** 6)
 
 
-def test_split_keep_all_is_exact(ctx):
-    print("split keep_all", flush=True)
+@pytest.mark.parametrize("trd_min", ["256", "1"])
+def test_split_keep_all_is_exact(ctx, trd_min, monkeypatch):
+    monkeypatch.setenv("TDVP_EIG_TRD_MIN", trd_min)
+    print(f"split keep_all, tridiagonal reduction from n={trd_min}", flush=True)
     left = synth.sector_profile(200, 41, parity=0)
     right = synth.sector_profile(200, 42, parity=0)
     blocks = _spread_theta(left, right, 1e-3, 9)

@@ -54,11 +54,16 @@ def test_neel_mps_is_the_neel_state(ctx):
         mps.close()
 
 
-def test_complete_basis_sweeps_follow_exact_evolution_L8(ctx):
+@pytest.mark.parametrize("solver", ["library", "trd"])
+def test_complete_basis_sweeps_follow_exact_evolution_L8(ctx, solver, monkeypatch):
     """Config: L = 8, U/J = 4, half filling, Neel start, complete bases,
     dt = 0.05; compared with the 4^8 state vector.  The Lanczos tolerance is
     1e-14 so that ~1000 exponentials stay within 1e-10 (at 1e-12 the drift of
-    the densities reaches 2.4e-10 by t = 2, the accumulated tolerance)."""
+    the densities reaches 2.4e-10 by t = 2, the accumulated tolerance).  With
+    trd every Gram matrix goes through the in-house tridiagonal reduction;
+    with library through the batched library solver."""
+    monkeypatch.setenv("TDVP_EIG_TRD_MIN", "1" if solver == "trd" else "0")
+    print(f"complete-basis L=8 exact evolution, eigensolver {solver}", flush=True)
     L, t, U, dt, nsteps = 8, 1.0, 4.0, 0.05, 40
     model = T.Model(L, t, U)
     mps = T.MPS.neel(ctx, model, complete=True)
@@ -123,7 +128,7 @@ def _library_mps(ctx, model, bonds, sites):
 
 
 @pytest.mark.parametrize("chi_cap,eps,solver", [(24, 1e-8, "dc"), (40, 1e-3, "dc"), (24, 1e-8, "fallback"),
-                                                 (24, 1e-8, "jacobi")])
+                                                 (24, 1e-8, "jacobi"), (24, 1e-8, "trd"), (40, 1e-3, "trd")])
 def test_truncated_sweeps_match_oracle(ctx, chi_cap, eps, solver, monkeypatch):
     """Truncated two-site TDVP from a seeded random reduced MPS (L = 8): the
     library and the dense oracle, which truncates whole degenerate groups of
@@ -131,13 +136,16 @@ def test_truncated_sweeps_match_oracle(ctx, chi_cap, eps, solver, monkeypatch):
     With fallback, every split re-solves its Gram matrices unpadded by the
     Jacobi-based solver (the path taken when the main solver fails); with
     jacobi, every bucket goes to the cyclic Jacobi eigensolver (the option
-    for large buckets)."""
+    for large buckets); with trd, every bucket goes through the in-house
+    tridiagonal reduction, with dc through the batched library solver."""
     import synth
+    print(f"truncated sweeps chi_cap={chi_cap} eps={eps} eigensolver {solver}", flush=True)
     fallback = solver == "fallback"
     if fallback:
         monkeypatch.setenv("TDVP_EIG_FORCE_FALLBACK", "1")
     if solver == "jacobi":
         monkeypatch.setenv("TDVP_EIG_JACOBI_MIN", "1")
+    monkeypatch.setenv("TDVP_EIG_TRD_MIN", "1" if solver == "trd" else "0")
     L, t, U, dt = 8, 1.0, 4.0, 0.05
     bonds, sites = synth.random_mps(L, 48, 17, center=1)
     model = T.Model(L, t, U)
