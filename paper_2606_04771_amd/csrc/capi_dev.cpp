@@ -378,7 +378,8 @@ int tdvp_ctx_create(tdvp_ctx** out, int32_t device, void* hip_stream, int32_t pr
       c->alloc = al;
       c->pool->al = al;
       for (DeviceBuffer* b : {&c->ws_scratch, &c->ws_krylov, &c->ws_small, &c->ws_vec, &c->ws_theta, &c->ws_svd,
-                              &c->ws_lanczos, &c->ws_part, &c->ws_shift, &c->ws_compact, &c->ws_flag, &c->ws_slices})
+                              &c->ws_lanczos, &c->ws_part, &c->ws_shift, &c->ws_compact, &c->ws_flag, &c->ws_slices,
+                              &c->ws_trd})
         b->al = al;
     }
     if (const char* e = std::getenv("TDVP_SPLIT_ALPHA")) c->split_alpha = std::atof(e);

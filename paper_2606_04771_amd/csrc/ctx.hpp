@@ -189,6 +189,7 @@ struct tdvp_ctx {
   tdvp::DeviceBuffer ws_shift;  // diagonal shifts of reduced-precision launches
   tdvp::DeviceBuffer ws_slices; // split-BF16 operand records
   tdvp::DeviceBuffer ws_compact;  // compact copy of a non-contiguous Krylov start vector
+  tdvp::DeviceBuffer ws_trd;      // job table of the split's tridiagonal reductions
   void* solver = nullptr;       // rocblas handle for the eigensolver (created on first use)
   // side streams (default priority) with their own solver handles, for
   // independent eigensolves; joined back to `stream` by events
@@ -304,11 +305,12 @@ int vec_store_basis32(tdvp_ctx* ctx, double* V32, const double* x, int64_t n);
 int vec_set_index(tdvp_ctx* ctx, int* d_j, int v);
 int vec_check_finite(tdvp_ctx* ctx, const double* x, int64_t n, int* d_flag);
 int vec_pad_matrix(tdvp_ctx* ctx, double* A, int64_t n, int64_t g, double v, double* d_scale);
-// G -> H G H for count consecutive n x n Hermitian matrices (H = I - u u^H, a
-// fixed dense reflector of size n; P: count * n complex scratch), and back:
-// columns c >= c0 of eigenvectors W -> H W
-int vec_reflect_forward(tdvp_ctx* ctx, hipStream_t st, double* G, int64_t n, int64_t count, double* P);
-int vec_reflect_back(tdvp_ctx* ctx, hipStream_t st, double* G, int64_t n, int64_t count, int64_t c0);
+// G -> H G H for count n x n Hermitian matrices of leading dimension ld
+// (ld^2 apart; ld <= 0: n) (H = I - u u^H, a fixed dense reflector of size n;
+// P: count * n complex scratch), and back: columns c >= c0 of eigenvectors W -> H W
+int vec_reflect_forward(tdvp_ctx* ctx, hipStream_t st, double* G, int64_t n, int64_t count, double* P,
+                        int64_t ld = 0);
+int vec_reflect_back(tdvp_ctx* ctx, hipStream_t st, double* G, int64_t n, int64_t count, int64_t c0, int64_t ld = 0);
 // Householder reduction of Hermitian n x n matrices to real tridiagonal form,
 // one launch per column index for a whole set of jobs.  A job is `count`
 // consecutive matrices A (full storage, n <= kTrdMaxN, overwritten); d, e (n
@@ -317,20 +319,24 @@ int vec_reflect_back(tdvp_ctx* ctx, hipStream_t st, double* G, int64_t n, int64_
 // complex per matrix of scratch.  eig_trd_column(k) for k = 0, 1, ... in
 // stream order completes a job once k reaches its n - 1.
 constexpr int64_t kTrdMaxN = 1024;
-constexpr int kTrdMaxJobs = 16;
+constexpr int kTrdMaxJobs = 48;
 struct TrdJob {
   double *A, *V, *Y, *tau, *d, *e;
-  int n, count;
+  int n, count, lda;   // A: leading dimension lda, matrices lda^2 apart; V, Y, tau, d, e packed by n
 };
 struct TrdSet {
   TrdJob job[kTrdMaxJobs];
   int njobs;
 };
-int eig_trd_column(tdvp_ctx* ctx, hipStream_t st, const TrdSet& set, int64_t k);
+// The set's job table goes to device memory `table` (kTrdMaxJobs TrdJob
+// entries) once, in stream order; every column launch reads it there.
+int eig_trd_upload(tdvp_ctx* ctx, hipStream_t st, const TrdSet& set, void* table);
+int eig_trd_column(tdvp_ctx* ctx, hipStream_t st, const TrdSet& set, const void* table, int64_t k);
 // Columns c >= c0 of G = Q Zt for each matrix (Zt: real n x n eigenvectors of
-// the tridiagonal form, Q the product of the reflectors in V / tau).
+// the tridiagonal form, Q the product of the reflectors in V / tau; G of
+// leading dimension ld, matrices ld^2 apart).
 int eig_trd_back(tdvp_ctx* ctx, hipStream_t st, const double* Zt, const double* V, const double* tau, double* G,
-                 int64_t n, int64_t count, int64_t c0);
+                 int64_t n, int64_t count, int64_t c0, int64_t ld);
 // d_out[2b], d_out[2b+1] = re, im of sum conj(x) y over block b, whose element
 // range is [d_meta[2b], d_meta[2b] + d_meta[2b+1]) (device metadata)
 int vec_block_dots(tdvp_ctx* ctx, const double* x, const double* y, const int64_t* d_meta, int nblocks,

@@ -71,15 +71,16 @@ __device__ __forceinline__ double2 group_total(double a, double b, double* red) 
 template <int RB>
 __device__ __forceinline__ void trd_column(double2* __restrict__ A, double2* __restrict__ V, double2* __restrict__ Y,
                                            double2* __restrict__ tau, double* __restrict__ dg,
-                                           double* __restrict__ eg, const int n, const int k, const int mat_,
-                                           const int rb_, double2* lds, double* red, double2* part) {
+                                           double* __restrict__ eg, const int n, const int lda, const int k,
+                                           const int mat_, const int rb_, double2* lds, double* red,
+                                           double2* part) {
   double2* vp = lds;           // v_{k-1} on rows [k, n)
   double2* wp = lds + n;       // w_{k-1} on rows [k, n)
   double2* vc = lds + 2 * n;   // column k on rows [k, n), then v_k on rows [k+1, n)
   constexpr int S = (int)(kTrdMaxN / kTrdThreads);   // rows of [k, n) per thread
   const int tid = threadIdx.x;
   const int64_t mat = mat_, nn = (int64_t)n * n;
-  double2* Am = A + mat * nn;
+  double2* Am = A + mat * lda * (int64_t)lda;
   double2* Vm = V + mat * nn;
   const double2* yprev = Y + (2 * mat + ((k + 1) & 1)) * n;
   double2* ynext = Y + (2 * mat + (k & 1)) * n;
@@ -97,7 +98,7 @@ __device__ __forceinline__ void trd_column(double2* __restrict__ A, double2* __r
     const int r = k + tid + j * kTrdThreads;
     vv[j] = ww[j] = cc[j] = make_double2(0.0, 0.0);
     if (r < n) {
-      cc[j] = Am[r + (int64_t)k * n];
+      cc[j] = Am[r + (int64_t)k * lda];
       if (k > 0) {
         vv[j] = Vm[r + (int64_t)(k - 1) * n];
         ww[j] = yprev[r];
@@ -179,7 +180,7 @@ __device__ __forceinline__ void trd_column(double2* __restrict__ A, double2* __r
         const double2 vq = vp[c], wq = wp[c];
         a.x -= (vr.x * wq.x + vr.y * wq.y) + (wr.x * vq.x + wr.y * vq.y);
         a.y -= (vr.y * wq.x - vr.x * wq.y) + (wr.y * vq.x - wr.x * vq.y);
-        Am[rown + (int64_t)c * n] = a;
+        Am[rown + (int64_t)c * lda] = a;
       }
       const double2 x = vc[c];
       accr += a.x * x.x - a.y * x.y;
@@ -190,7 +191,7 @@ __device__ __forceinline__ void trd_column(double2* __restrict__ A, double2* __r
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int c = c0 + u * NCG;
-        a[u] = c < n ? Am[rown + (int64_t)c * n] : make_double2(0.0, 0.0);
+        a[u] = c < n ? Am[rown + (int64_t)c * lda] : make_double2(0.0, 0.0);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -214,18 +215,18 @@ __device__ __forceinline__ void trd_column(double2* __restrict__ A, double2* __r
 
 // One launch: column k of every job of the set with n > k.  The workgroups
 // are numbered job by job, matrix by matrix, row block by row block.
-__global__ __launch_bounds__(kTrdThreads) void k_trd_multi(TrdSet set, int k) {
+__global__ __launch_bounds__(kTrdThreads) void k_trd_multi(const TrdJob* __restrict__ jobs, int njobs, int k) {
   extern __shared__ double2 lds[];
   __shared__ double red[2 * (kTrdThreads / 64)];
   __shared__ double2 part[kTrdThreads];
   int blk = (int)blockIdx.x;
-  for (int j = 0; j < set.njobs; ++j) {
-    const TrdJob& jb = set.job[j];
+  for (int j = 0; j < njobs; ++j) {
+    const TrdJob jb = jobs[j];
     if (k >= jb.n) continue;
     const int nrb = max(1, (jb.n - k - 1 + kTrdRows - 1) / kTrdRows);
     if (blk < nrb * jb.count) {
-      trd_column<kTrdRows>((double2*)jb.A, (double2*)jb.V, (double2*)jb.Y, (double2*)jb.tau, jb.d, jb.e, jb.n, k,
-                           blk / nrb, blk % nrb, lds, red, part);
+      trd_column<kTrdRows>((double2*)jb.A, (double2*)jb.V, (double2*)jb.Y, (double2*)jb.tau, jb.d, jb.e, jb.n,
+                           jb.lda, k, blk / nrb, blk % nrb, lds, red, part);
       return;
     }
     blk -= nrb * jb.count;
@@ -239,7 +240,7 @@ template <int NR>
 __global__ __launch_bounds__(kTrdThreads) void k_trd_back(const double* __restrict__ Zt,
                                                            const double2* __restrict__ V,
                                                            const double2* __restrict__ tau, double2* __restrict__ G,
-                                                           int n, int c0) {
+                                                           int n, int c0, int ld) {
   const int lane = threadIdx.x & 63;
   const int c = c0 + (int)blockIdx.x * (kTrdThreads / 64) + (int)(threadIdx.x >> 6);
   if (c >= n) return;   // whole wave; no workgroup barrier below
@@ -292,25 +293,32 @@ __global__ __launch_bounds__(kTrdThreads) void k_trd_back(const double* __restri
 #pragma unroll
   for (int j = 0; j < NR; ++j) {
     const int r = lane + 64 * j;
-    if (r < n) G[mo + r + (int64_t)c * n] = make_double2(zr[j], zi[j]);
+    if (r < n) G[(int64_t)blockIdx.y * ld * ld + r + (int64_t)c * ld] = make_double2(zr[j], zi[j]);
   }
 }
 
 template <int NR>
 void launch_back(hipStream_t st, const double* Zt, const double* V, const double* tau, double* G, int n, int count,
-                 int c0) {
+                 int c0, int ld) {
   const int cols = n - c0, per = kTrdThreads / 64;
   hipLaunchKernelGGL(k_trd_back<NR>, dim3((unsigned)((cols + per - 1) / per), (unsigned)count), dim3(kTrdThreads), 0,
-                     st, Zt, (const double2*)V, (const double2*)tau, (double2*)G, n, c0);
+                     st, Zt, (const double2*)V, (const double2*)tau, (double2*)G, n, c0, ld);
 }
 
 }  // namespace
 
-int eig_trd_column(tdvp_ctx* ctx, hipStream_t st, const TrdSet& set, int64_t k) {
+int eig_trd_upload(tdvp_ctx* ctx, hipStream_t st, const TrdSet& set, void* table) {
+  if (set.njobs <= 0) return TDVP_OK;
+  if (set.njobs > kTrdMaxJobs) return set_error(ctx, TDVP_E_INVALID, "tridiagonal reduction: too many jobs");
+  TDVP_HIP(ctx, hipMemcpyAsync(table, set.job, sizeof(TrdJob) * (size_t)set.njobs, hipMemcpyHostToDevice, st));
+  return TDVP_OK;
+}
+
+int eig_trd_column(tdvp_ctx* ctx, hipStream_t st, const TrdSet& set, const void* table, int64_t k) {
   int64_t blocks = 0, nmax = 0;
   for (int j = 0; j < set.njobs; ++j) {
     const TrdJob& jb = set.job[j];
-    if (jb.n <= 0 || jb.n > kTrdMaxN || jb.count <= 0)
+    if (jb.n <= 0 || jb.n > kTrdMaxN || jb.count <= 0 || jb.lda < jb.n)
       return set_error(ctx, TDVP_E_INVALID, "tridiagonal reduction: size out of range");
     nmax = std::max<int64_t>(nmax, jb.n);
     if (k < jb.n) blocks += (int64_t)jb.count * std::max<int64_t>(1, (jb.n - k - 1 + kTrdRows - 1) / kTrdRows);
@@ -319,23 +327,23 @@ int eig_trd_column(tdvp_ctx* ctx, hipStream_t st, const TrdSet& set, int64_t k) 
     return set_error(ctx, TDVP_E_INVALID, "tridiagonal reduction: too many jobs");
   if (blocks == 0) return TDVP_OK;
   hipLaunchKernelGGL(k_trd_multi, dim3((unsigned)blocks), dim3(kTrdThreads), sizeof(double2) * 3 * (size_t)nmax, st,
-                     set, (int)k);
+                     (const TrdJob*)table, set.njobs, (int)k);
   TDVP_HIP(ctx, hipGetLastError());
   return TDVP_OK;
 }
 
 int eig_trd_back(tdvp_ctx* ctx, hipStream_t st, const double* Zt, const double* V, const double* tau, double* G,
-                 int64_t n, int64_t count, int64_t c0) {
+                 int64_t n, int64_t count, int64_t c0, int64_t ld) {
   if (n <= 0 || count <= 0 || c0 >= n) return TDVP_OK;
-  if (n > kTrdMaxN || count > 65535 || c0 < 0)
+  if (n > kTrdMaxN || count > 65535 || c0 < 0 || ld < n)
     return set_error(ctx, TDVP_E_INVALID, "tridiagonal back-transformation: size out of range");
-  const int ni = (int)n, ci = (int)count, c0i = (int)c0;
-  if (n <= 64) launch_back<1>(st, Zt, V, tau, G, ni, ci, c0i);
-  else if (n <= 128) launch_back<2>(st, Zt, V, tau, G, ni, ci, c0i);
-  else if (n <= 256) launch_back<4>(st, Zt, V, tau, G, ni, ci, c0i);
-  else if (n <= 512) launch_back<8>(st, Zt, V, tau, G, ni, ci, c0i);
-  else if (n <= 768) launch_back<12>(st, Zt, V, tau, G, ni, ci, c0i);
-  else launch_back<16>(st, Zt, V, tau, G, ni, ci, c0i);
+  const int ni = (int)n, ci = (int)count, c0i = (int)c0, ldi = (int)ld;
+  if (n <= 64) launch_back<1>(st, Zt, V, tau, G, ni, ci, c0i, ldi);
+  else if (n <= 128) launch_back<2>(st, Zt, V, tau, G, ni, ci, c0i, ldi);
+  else if (n <= 256) launch_back<4>(st, Zt, V, tau, G, ni, ci, c0i, ldi);
+  else if (n <= 512) launch_back<8>(st, Zt, V, tau, G, ni, ci, c0i, ldi);
+  else if (n <= 768) launch_back<12>(st, Zt, V, tau, G, ni, ci, c0i, ldi);
+  else launch_back<16>(st, Zt, V, tau, G, ni, ci, c0i, ldi);
   TDVP_HIP(ctx, hipGetLastError());
   return TDVP_OK;
 }

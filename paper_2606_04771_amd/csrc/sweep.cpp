@@ -450,13 +450,29 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
   // n-vectors of scratch and the reflector factors (n complex) per matrix
   const bool dc = eig_divide_conquer();
   const int64_t jmin = eig_jacobi_min(), tmin = eig_trd_min();
-  auto use_trd = [&](int64_t n) { return dc && n < jmin && n >= tmin && n <= kTrdMaxN; };
+  // (each of their matrices is reduced at its own size g, not the bucket's
+  // padded size; at most kTrdMaxJobs matrices, the largest buckets first)
+  int64_t trd_lo = std::max<int64_t>(tmin, 1);
+  {
+    int64_t cnt = 0;
+    for (auto it = buckets.rbegin(); it != buckets.rend(); ++it) {
+      const int64_t n = it->first;
+      if (!(dc && n < jmin && n >= tmin && n <= kTrdMaxN)) continue;
+      if (cnt + (int64_t)it->second.size() > kTrdMaxJobs) {
+        trd_lo = n + 1;
+        break;
+      }
+      cnt += (int64_t)it->second.size();
+    }
+  }
+  auto use_trd = [&](int64_t n) { return dc && n < jmin && n >= trd_lo && n <= kTrdMaxN; };
   int64_t tsq = 0, tvec = 0;
   for (auto& bk : buckets)
-    if (use_trd(bk.first)) {
-      tsq += bk.first * bk.first * (int64_t)bk.second.size();
-      tvec += bk.first * (int64_t)bk.second.size();
-    }
+    if (use_trd(bk.first))
+      for (Sector* sp : bk.second) {
+        tsq += sp->g * sp->g;
+        tvec += sp->g;
+      }
   // M | Gram slots | reflector scratch (n complex per slot) | eigenvalues |
   // off-diagonal workspace | Jacobi residuals | info flags | Jacobi sweep
   // counts | tridiagonal-reduction storage
@@ -594,6 +610,7 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
       int64_t n, cnt, gmax;
       double *G0, *P0, *D0, *E0, *res;
       rocblas_int *info, *sweeps;
+      int64_t ld = 0;                 // leading dimension of the matrices (their slot size)
       double *tV = nullptr, *tZ = nullptr, *tY = nullptr, *tT = nullptr;   // tridiagonal-reduction storage
       int home = 0;                   // stream of a library solve / of the back-transformation
       std::vector<int> stedc_on;      // stream of each matrix's tridiagonal solve
@@ -612,29 +629,42 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
         secv[q]->iidx = minfo[ob] + (int64_t)q;
         gmax = std::max(gmax, secv[q]->g);
       }
+      if (use_trd(n)) {
+        // one job per matrix, at its own size (the padding is not touched)
+        for (size_t q = 0; q < secv.size(); ++q) {
+          Sector* sp = secv[q];
+          const int64_t g = sp->g;
+          sp->col0 = 0;
+          EigJob jb{g, 1, g, Gbase + 2 * sp->goff, Pbase + 2 * sp->doff, Dbase + sp->doff, Ebase + sp->doff,
+                    jres + sp->iidx, dinfo + sp->iidx, jsweeps + sp->iidx};
+          jb.ld = n;
+          jb.tV = triV + 2 * tsq_at;
+          jb.tZ = triZ + tsq_at;
+          jb.tY = triY + 4 * tvec_at;
+          jb.tT = triT + 2 * tvec_at;
+          tsq_at += g * g;
+          tvec_at += g;
+          jobs.push_back(std::move(jb));
+        }
+        continue;
+      }
       EigJob jb{n, (int64_t)secv.size(), gmax, Gbase + 2 * s0->goff, Pbase + 2 * s0->doff,
                 Dbase + s0->doff, Ebase + s0->doff, jres + minfo[ob], dinfo + minfo[ob],
                 jsweeps + minfo[ob]};
-      if (use_trd(n)) {
-        jb.tV = triV + 2 * tsq_at;
-        jb.tZ = triZ + tsq_at;
-        jb.tY = triY + 4 * tvec_at;
-        jb.tT = triT + 2 * tvec_at;
-        tsq_at += n * n * jb.cnt;
-        tvec_at += n * jb.cnt;
-      }
+      jb.ld = n;
       jobs.push_back(std::move(jb));
     }
     std::vector<int> trd_ix;          // in-house jobs, smallest first (the order they complete)
-    for (int j = (int)jobs.size() - 1; j >= 0; --j)
+    for (int j = 0; j < (int)jobs.size(); ++j)
       if (jobs[j].tV) trd_ix.push_back(j);
+    std::stable_sort(trd_ix.begin(), trd_ix.end(), [&](int a, int b) { return jobs[a].n < jobs[b].n; });
     if ((int)trd_ix.size() > kTrdMaxJobs) return set_error(ctx, TDVP_E_INVALID, "too many eigensolver buckets");
     // side stream 0 carries the reductions; the rest take everything else
     // (with one side stream, everything runs on it in issue order)
     const int s_lo = (!trd_ix.empty() && ctx->nside > 1) ? 1 : 0;
     std::vector<double> sfree(ctx->nside, 0.0);
-    // (giving the largest bucket's tridiagonal solves streams of their own,
-    // the end of the critical path, was measured slower: 5.8 s against 5.3 s)
+    // (giving the largest matrices' tridiagonal solves streams of their own,
+    // the end of the critical path, was measured no faster)
     auto pick = [&](double ready, double cost) {
       int best = s_lo;
       for (int k = s_lo + 1; k < ctx->nside; ++k)
@@ -706,19 +736,22 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
       int64_t nmax = 0;
       for (int j : trd_ix) {
         EigJob& jb = jobs[j];
-        if ((ec = vec_reflect_forward(ctx, ctx->side[0], jb.G0, jb.n, jb.cnt, jb.P0))) return ec;
-        set.job[set.njobs++] = TrdJob{jb.G0, jb.tV, jb.tY, jb.tT, jb.D0, jb.E0, (int)jb.n, (int)jb.cnt};
+        if ((ec = vec_reflect_forward(ctx, ctx->side[0], jb.G0, jb.n, jb.cnt, jb.P0, jb.ld))) return ec;
+        set.job[set.njobs++] = TrdJob{jb.G0, jb.tV, jb.tY, jb.tT, jb.D0, jb.E0, (int)jb.n, (int)jb.cnt, (int)jb.ld};
         nmax = std::max(nmax, jb.n);
       }
+      TDVP_HIP(ctx, ctx->ws_trd.ensure(sizeof(TrdJob) * kTrdMaxJobs));
+      if ((ec = eig_trd_upload(ctx, ctx->side[0], set, ctx->ws_trd.p))) return ec;
       if ((ec = span_open(0, "reduce"))) return ec;
       size_t next = 0;
       for (int64_t k = 0; k < nmax; ++k) {
-        if ((ec = eig_trd_column(ctx, ctx->side[0], set, k))) return ec;
+        if ((ec = eig_trd_column(ctx, ctx->side[0], set, ctx->ws_trd.p, k))) return ec;
         for (; next < trd_ix.size() && jobs[trd_ix[next]].n == k + 1; ++next)
           TDVP_HIP(ctx, hipEventRecord(ctx->eig_ev[jobs[trd_ix[next]].ev_red], ctx->side[0]));
       }
       if ((ec = span_close(0))) return ec;
     }
+    const double t_issue_red = now();
     // 2. the library solves
     for (const EigJob& jb : jobs) {
       if (jb.tV) continue;
@@ -754,6 +787,7 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
       }
       if ((ec = span_close(k))) return ec;
     }
+    const double t_issue_lib = now();
     // 3. per in-house bucket, in the order the reduction completes them: the
     //    tridiagonal solves, then the eigenvectors of the needed columns
     //    mapped back through both reflections on the home stream
@@ -775,8 +809,8 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
       for (int e : jb.ev_stedc)
         if (e >= 0) TDVP_HIP(ctx, hipStreamWaitEvent(ctx->side[k], ctx->eig_ev[e], 0));
       if ((ec = span_open(k, "back" + std::to_string(n)))) return ec;
-      if ((ec = eig_trd_back(ctx, ctx->side[k], jb.tZ, jb.tV, jb.tT, jb.G0, n, jb.cnt, n - jb.gmax))) return ec;
-      if ((ec = vec_reflect_back(ctx, ctx->side[k], jb.G0, n, jb.cnt, n - jb.gmax))) return ec;
+      if ((ec = eig_trd_back(ctx, ctx->side[k], jb.tZ, jb.tV, jb.tT, jb.G0, n, jb.cnt, n - jb.gmax, jb.ld))) return ec;
+      if ((ec = vec_reflect_back(ctx, ctx->side[k], jb.G0, n, jb.cnt, n - jb.gmax, jb.ld))) return ec;
       if ((ec = span_close(k))) return ec;
     }
     if (t_ref) {
@@ -794,7 +828,8 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
         (void)hipEventDestroy(x.b);
       }
       (void)hipEventDestroy(t_ref);
-      std::fprintf(stderr, "[tdvp]   eig bond %d: issue %.2f ms;%s\n", i, host_ms, line.c_str());
+      std::fprintf(stderr, "[tdvp]   eig bond %d: issue %.2f ms (reductions %.2f, library %.2f);%s\n", i, host_ms,
+                   1e3 * (t_issue_red - t_issue), 1e3 * (t_issue_lib - t_issue_red), line.c_str());
     }
     for (int k = 0; k < ctx->nside; ++k) {
       TDVP_HIP(ctx, hipEventRecord(ctx->side_ev[k], ctx->side[k]));
@@ -862,9 +897,12 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
     if (hinfo[q] != 0)
       return set_error(ctx, TDVP_E_NOCONV, "eigensolver info " + std::to_string(hinfo[q]) + " at bond " +
                                                std::to_string(i));
-  for (int64_t q = 0; q < dtot; ++q)
-    if (!std::isfinite(ev[q]))
-      return set_error(ctx, TDVP_E_NONFINITE, "non-finite Gram eigenvalue at bond " + std::to_string(i));
+  for (auto& kv : secs) {   // the eigenvalues each sector uses (the padding's are not all computed)
+    const Sector& s = kv.second;
+    for (int64_t q = 0; q < s.g; ++q)
+      if (!std::isfinite(ev[s.doff + s.col0 + q]))
+        return set_error(ctx, TDVP_E_NONFINITE, "non-finite Gram eigenvalue at bond " + std::to_string(i));
+  }
   // truncation: whole multiplets by descending full-state singular value
   struct Ent { double w, sfull; int q, tj, idx; Sector* s; };
   std::vector<Ent> ents;

@@ -45,7 +45,8 @@ __device__ __forceinline__ void block_sum2(double& a, double& b) {
 }
 
 // ---- Householder reflection H = I - u u^H (|u|^2 = 2) of batched Hermitian
-// n x n matrices: G -> H G H before an eigensolve, eigenvectors W -> H W after.
+// n x n matrices (leading dimension ld, consecutive matrices ld^2 apart):
+// G -> H G H before an eigensolve, eigenvectors W -> H W after.
 // The spectrum is unchanged; a dense u removes exact block structure (zero
 // padding, decoupled sectors) that would split the tridiagonal form.
 __device__ __forceinline__ double2 reflector_u(int64_t i, int64_t n) {
@@ -56,16 +57,16 @@ __device__ __forceinline__ double2 reflector_u(int64_t i, int64_t n) {
 }
 
 // p = G u, one workgroup per 64 rows of one matrix (blockIdx.y)
-__global__ __launch_bounds__(NT) void k_reflect_p(const double2* __restrict__ G, int64_t n,
+__global__ __launch_bounds__(NT) void k_reflect_p(const double2* __restrict__ G, int64_t n, int64_t ld,
                                                   double2* __restrict__ P) {
   __shared__ double2 part[4][64];
-  const double2* A = G + (int64_t)blockIdx.y * n * n;
+  const double2* A = G + (int64_t)blockIdx.y * ld * ld;
   const int64_t r = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
   const int cg = threadIdx.x >> 6;
   double re = 0.0, im = 0.0;
   if (r < n)
     for (int64_t c = cg; c < n; c += 4) {
-      const double2 a = A[r + c * n], u = reflector_u(c, n);
+      const double2 a = A[r + c * ld], u = reflector_u(c, n);
       re += a.x * u.x - a.y * u.y;
       im += a.x * u.y + a.y * u.x;
     }
@@ -102,24 +103,25 @@ __global__ __launch_bounds__(NT) void k_reflect_w(double2* __restrict__ P, int64
 }
 
 // G -= u w^H + w u^H over all count matrices
-__global__ __launch_bounds__(NT) void k_reflect_update(double2* __restrict__ G, int64_t n, int64_t count,
+__global__ __launch_bounds__(NT) void k_reflect_update(double2* __restrict__ G, int64_t n, int64_t ld, int64_t count,
                                                        const double2* __restrict__ W) {
   const int64_t nn = n * n, total = nn * count;
   for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
     const int64_t m = e / nn, rc = e - m * nn, c = rc / n, r = rc - c * n;
     const double2 ur = reflector_u(r, n), uc = reflector_u(c, n);
     const double2 wr = W[m * n + r], wc = W[m * n + c];
-    double2 a = G[e];
+    double2& g = G[m * ld * ld + r + c * ld];
+    double2 a = g;
     // u_r conj(w_c) + w_r conj(u_c)
     a.x -= (ur.x * wc.x + ur.y * wc.y) + (wr.x * uc.x + wr.y * uc.y);
     a.y -= (ur.y * wc.x - ur.x * wc.y) + (wr.y * uc.x - wr.x * uc.y);
-    G[e] = a;
+    g = a;
   }
 }
 
 // columns c >= c0 of each matrix: W_c -= u (u^H W_c); one workgroup per column
-__global__ __launch_bounds__(NT) void k_reflect_back(double2* __restrict__ G, int64_t n, int64_t c0) {
-  double2* w = G + (int64_t)blockIdx.y * n * n + (c0 + blockIdx.x) * n;
+__global__ __launch_bounds__(NT) void k_reflect_back(double2* __restrict__ G, int64_t n, int64_t ld, int64_t c0) {
+  double2* w = G + (int64_t)blockIdx.y * ld * ld + (c0 + blockIdx.x) * ld;
   double re = 0.0, im = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += NT) {
     const double2 u = reflector_u(i, n), v = w[i];
@@ -556,20 +558,23 @@ int vec_scale_cols_rsqrt(tdvp_ctx* ctx, double* A, int64_t ld, int64_t rows, int
   return TDVP_OK;
 }
 
-int vec_reflect_forward(tdvp_ctx* ctx, hipStream_t st, double* G, int64_t n, int64_t count, double* P) {
+int vec_reflect_forward(tdvp_ctx* ctx, hipStream_t st, double* G, int64_t n, int64_t count, double* P, int64_t ld) {
   if (n <= 1 || count <= 0) return TDVP_OK;
+  if (ld <= 0) ld = n;
   hipLaunchKernelGGL(k_reflect_p, dim3((unsigned)((n + 63) / 64), (unsigned)count), dim3(NT), 0, st,
-                     (const double2*)G, n, (double2*)P);
+                     (const double2*)G, n, ld, (double2*)P);
   hipLaunchKernelGGL(k_reflect_w, dim3((unsigned)count), dim3(NT), 0, st, (double2*)P, n);
-  hipLaunchKernelGGL(k_reflect_update, dim3(grid_1d(n * n * count)), dim3(NT), 0, st, (double2*)G, n, count,
+  hipLaunchKernelGGL(k_reflect_update, dim3(grid_1d(n * n * count)), dim3(NT), 0, st, (double2*)G, n, ld, count,
                      (const double2*)P);
   TDVP_HIP(ctx, hipGetLastError());
   return TDVP_OK;
 }
 
-int vec_reflect_back(tdvp_ctx* ctx, hipStream_t st, double* G, int64_t n, int64_t count, int64_t c0) {
+int vec_reflect_back(tdvp_ctx* ctx, hipStream_t st, double* G, int64_t n, int64_t count, int64_t c0, int64_t ld) {
   if (n <= 1 || count <= 0 || c0 >= n) return TDVP_OK;
-  hipLaunchKernelGGL(k_reflect_back, dim3((unsigned)(n - c0), (unsigned)count), dim3(NT), 0, st, (double2*)G, n, c0);
+  if (ld <= 0) ld = n;
+  hipLaunchKernelGGL(k_reflect_back, dim3((unsigned)(n - c0), (unsigned)count), dim3(NT), 0, st, (double2*)G, n, ld,
+                     c0);
   TDVP_HIP(ctx, hipGetLastError());
   return TDVP_OK;
 }
