@@ -194,14 +194,20 @@ struct tdvp_ctx {
   // side streams (default priority) with their own solver handles, for
   // independent eigensolves; joined back to `stream` by events
   // Side streams for concurrent batched eigensolves.  HIP maps streams onto
-  // GPU_MAX_HW_QUEUES hardware queues (4 unless set before HIP starts); with
-  // 8 queues the split of a chi = 4096 sweep takes ~30 % less time than with 4.
+  // GPU_MAX_HW_QUEUES hardware queues (4 unless set before HIP starts); the
+  // split plans its work per queue (side_group), and with its in-house
+  // reduction a chi = 4096 sweep is fastest with the default 4 (3.8 s against
+  // 4.4-4.8 s with 5-8 queues: fewer concurrent queues slow the reduction less).
   static constexpr int kSide = 16;
   int nside = 8;                      // in use (TDVP_SIDE_STREAMS, 1..kSide)
   bool graphs = true;                 // graph replay of Lanczos iterations
   hipStream_t side[kSide] = {};
   void* side_solver[kSide] = {};
   hipEvent_t side_ev[kSide + 1] = {};
+  // side streams that share a hardware queue (HIP maps streams onto
+  // GPU_MAX_HW_QUEUES queues; a shared queue runs its streams' work in issue
+  // order): side_group[k] is the lowest side stream on side stream k's queue
+  int side_group[kSide] = {};
   std::vector<hipEvent_t> eig_ev;     // cross-stream dependencies of the split's eigensolves
   void* host_small = nullptr;   // pinned host mirror of ws_small
   std::shared_ptr<tdvp::ProgPool> pool = std::make_shared<tdvp::ProgPool>();
@@ -331,6 +337,8 @@ struct TrdSet {
 // The set's job table goes to device memory `table` (kTrdMaxJobs TrdJob
 // entries) once, in stream order; every column launch reads it there.
 int eig_trd_upload(tdvp_ctx* ctx, hipStream_t st, const TrdSet& set, void* table);
+// A single-wave kernel that busy-waits for the given time on the wall clock.
+int eig_spin(tdvp_ctx* ctx, hipStream_t st, double microseconds);
 int eig_trd_column(tdvp_ctx* ctx, hipStream_t st, const TrdSet& set, const void* table, int64_t k);
 // Columns c >= c0 of G = Q Zt for each matrix (Zt: real n x n eigenvectors of
 // the tridiagonal form, Q the product of the reflectors in V / tau; G of

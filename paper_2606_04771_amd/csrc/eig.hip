@@ -305,7 +305,24 @@ void launch_back(hipStream_t st, const double* Zt, const double* V, const double
                      st, Zt, (const double2*)V, (const double2*)tau, (double2*)G, n, c0, ld);
 }
 
+// Busy wait of `ticks` ticks of the constant-rate wall clock (one wave).
+__global__ void k_spin(long long ticks) {
+  const long long t0 = wall_clock64();
+  while (wall_clock64() - t0 < ticks) {
+  }
+}
+
 }  // namespace
+
+int eig_spin(tdvp_ctx* ctx, hipStream_t st, double microseconds) {
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device) != hipSuccess || khz <= 0)
+    khz = 100000;
+  const long long ticks = (long long)(microseconds * 1e-3 * (double)khz);
+  hipLaunchKernelGGL(k_spin, dim3(1), dim3(64), 0, st, ticks);
+  TDVP_HIP(ctx, hipGetLastError());
+  return TDVP_OK;
+}
 
 int eig_trd_upload(tdvp_ctx* ctx, hipStream_t st, const TrdSet& set, void* table) {
   if (set.njobs <= 0) return TDVP_OK;

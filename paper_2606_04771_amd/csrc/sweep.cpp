@@ -312,6 +312,31 @@ int ensure_solver(tdvp_ctx* ctx) {
       return set_error(ctx, TDVP_E_HIP, "rocblas_set_stream failed");
   }
   for (auto& ev : ctx->side_ev) TDVP_HIP(ctx, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  // Which side streams share a hardware queue: a 300 us busy wait on stream i,
+  // then an event on stream j; if that event completes only after the wait,
+  // j's work queues behind i's.  Once per context, ~5 ms.
+  for (int j = 0; j < ctx->nside; ++j) {
+    ctx->side_group[j] = j;
+    for (int i = 0; i < j; ++i) {
+      if (ctx->side_group[i] != i) continue;
+      if (int r = eig_spin(ctx, ctx->side[i], 300.0)) return r;
+      TDVP_HIP(ctx, hipEventRecord(ctx->side_ev[0], ctx->side[i]));
+      TDVP_HIP(ctx, hipEventRecord(ctx->side_ev[1], ctx->side[j]));
+      TDVP_HIP(ctx, hipEventSynchronize(ctx->side_ev[1]));
+      const hipError_t q = hipEventQuery(ctx->side_ev[0]);
+      if (q != hipSuccess && q != hipErrorNotReady) TDVP_HIP(ctx, q);
+      TDVP_HIP(ctx, hipEventSynchronize(ctx->side_ev[0]));
+      if (q == hipSuccess) {
+        ctx->side_group[j] = i;
+        break;
+      }
+    }
+  }
+  if (ctx->verbose) {
+    std::string g;
+    for (int k = 0; k < ctx->nside; ++k) g += " " + std::to_string(ctx->side_group[k]);
+    std::fprintf(stderr, "[tdvp] side streams' hardware-queue groups:%s\n", g.c_str());
+  }
   return TDVP_OK;
 }
 
@@ -603,7 +628,6 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
     // steer the schedule): library solve of a bucket, the reduction reaching
     // column n, tridiagonal solve of one matrix, back-transformation.
     auto cost_lib = [](double n, double cnt) { return 0.4 + 0.03 * n + 0.002 * n * (cnt - 1.0); };
-    auto ready_red = [](double n) { return 0.015 * n; };
     auto cost_stedc = [](double n) { return 0.5 + 0.004 * n; };
     auto cost_back = [](double n, double cnt) { return 0.3 + 8e-4 * n * cnt; };
     struct EigJob {
@@ -665,10 +689,20 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
     std::vector<double> sfree(ctx->nside, 0.0);
     // (giving the largest matrices' tridiagonal solves streams of their own,
     // the end of the critical path, was measured no faster)
+    // streams that share a hardware queue are one resource (sfree is kept on
+    // the group's lowest stream); with in-house jobs, stream 0's queue is left
+    // to the reductions and their tail when another queue exists
+    const int* grp = ctx->side_group;
+    bool other_queue = false;
+    for (int k = s_lo; k < ctx->nside; ++k) other_queue = other_queue || grp[k] != grp[0];
     auto pick = [&](double ready, double cost) {
-      int best = s_lo;
-      for (int k = s_lo + 1; k < ctx->nside; ++k)
-        if (std::max(sfree[k], ready) + cost < std::max(sfree[best], ready) + cost) best = k;
+      int best = -1;
+      for (int k = s_lo; k < ctx->nside; ++k) {
+        if (grp[k] != k) continue;   // a group is represented by its lowest stream
+        if (s_lo == 1 && other_queue && grp[k] == grp[0]) continue;
+        if (best < 0 || std::max(sfree[k], ready) + cost < std::max(sfree[best], ready) + cost) best = k;
+      }
+      if (best < 0) best = s_lo;
       return best;
     };
     for (EigJob& jb : jobs)
@@ -676,14 +710,39 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
         jb.home = pick(0.0, cost_lib((double)jb.n, (double)jb.cnt));
         sfree[jb.home] += cost_lib((double)jb.n, (double)jb.cnt);
       }
+    // when each in-house matrix is reduced: the launches share the trailing
+    // matrices' traffic (read and write, ~5 TB/s measured) on top of ~6 us each
+    std::vector<double> ready_at(jobs.size(), 0.0);
+    {
+      double t = 0.0;
+      size_t next = 0;
+      const int64_t nmax = trd_ix.empty() ? 0 : jobs[trd_ix.back()].n;
+      for (int64_t k = 0; k < nmax; ++k) {
+        double bytes = 0.0;
+        for (size_t q = next; q < trd_ix.size(); ++q) {
+          const double m = (double)(jobs[trd_ix[q]].n - k - 1);
+          bytes += 32.0 * m * m * (double)jobs[trd_ix[q]].cnt;
+        }
+        t += 6e-3 + bytes / 5e9;   // ms
+        for (; next < trd_ix.size() && jobs[trd_ix[next]].n == k + 1; ++next) ready_at[trd_ix[next]] = t;
+      }
+      if (!trd_ix.empty()) sfree[0] = std::max(sfree[0], t);
+    }
+    // The largest matrix is reduced by the last launch: its tridiagonal solve
+    // and back-transformation follow the reductions on their stream and are
+    // issued right after them, ahead of everything else that may share that
+    // stream's hardware queue (sweep 3.81 s; 3.92 s with the solve planned like
+    // the others, 3.85 / 4.11 s with the two / three largest on stream 0).
+    const int ntail = s_lo == 1 ? std::min<int>(1, (int)trd_ix.size()) : 0;
     int nev = 0;
     for (int j : trd_ix) {
       EigJob& jb = jobs[j];
-      const double ready = ready_red((double)jb.n);
+      const double ready = ready_at[j];
+      const bool last = std::find(trd_ix.end() - ntail, trd_ix.end(), j) != trd_ix.end();
       jb.ev_red = nev++;
       double done = ready;
       for (int64_t q = 0; q < jb.cnt; ++q) {
-        const int k = pick(ready, cost_stedc((double)jb.n));
+        const int k = last && q == 0 ? 0 : pick(ready, cost_stedc((double)jb.n));
         sfree[k] = std::max(sfree[k], ready) + cost_stedc((double)jb.n);
         done = std::max(done, sfree[k]);
         jb.stedc_on.push_back(k);
@@ -728,6 +787,29 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
     };
     const double t_issue = now();
     int ec;
+    auto issue_trd = [&](int j) -> int {
+      const EigJob& jb = jobs[j];
+      const int64_t n = jb.n;
+      int e2;
+      for (int64_t q = 0; q < jb.cnt; ++q) {
+        const int k = jb.stedc_on[q];
+        TDVP_HIP(ctx, hipStreamWaitEvent(ctx->side[k], ctx->eig_ev[jb.ev_red], 0));
+        if ((e2 = span_open(k, "tri" + std::to_string(n)))) return e2;
+        if ((e2 = fail(rocsolver_dstedc((rocblas_handle)ctx->side_solver[k], rocblas_evect_tridiagonal,
+                                       (rocblas_int)n, jb.D0 + q * n, jb.E0 + q * n, jb.tZ + q * n * n,
+                                       (rocblas_int)n, jb.info + q))))
+          return e2;
+        if ((e2 = span_close(k))) return e2;
+        if (jb.ev_stedc[q] >= 0) TDVP_HIP(ctx, hipEventRecord(ctx->eig_ev[jb.ev_stedc[q]], ctx->side[k]));
+      }
+      const int k = jb.home;
+      for (int e : jb.ev_stedc)
+        if (e >= 0) TDVP_HIP(ctx, hipStreamWaitEvent(ctx->side[k], ctx->eig_ev[e], 0));
+      if ((e2 = span_open(k, "back" + std::to_string(n)))) return e2;
+      if ((e2 = eig_trd_back(ctx, ctx->side[k], jb.tZ, jb.tV, jb.tT, jb.G0, n, jb.cnt, n - jb.gmax, jb.ld))) return e2;
+      if ((e2 = vec_reflect_back(ctx, ctx->side[k], jb.G0, n, jb.cnt, n - jb.gmax, jb.ld))) return e2;
+      return span_close(k);
+    };
     // 1. the reductions (the tridiagonal divide and conquer fails on split
     //    tridiagonal forms, so the Gram matrices are reflected first, as for
     //    the library solver below)
@@ -751,6 +833,10 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
       }
       if ((ec = span_close(0))) return ec;
     }
+    // the largest matrices' tridiagonal solves and back-transformations, on
+    // stream 0 (largest first), issued before anything else can queue there
+    for (int t = 0; t < ntail; ++t)
+      if ((ec = issue_trd(trd_ix[trd_ix.size() - 1 - t]))) return ec;
     const double t_issue_red = now();
     // 2. the library solves
     for (const EigJob& jb : jobs) {
@@ -790,29 +876,10 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
     const double t_issue_lib = now();
     // 3. per in-house bucket, in the order the reduction completes them: the
     //    tridiagonal solves, then the eigenvectors of the needed columns
-    //    mapped back through both reflections on the home stream
-    for (int j : trd_ix) {
-      const EigJob& jb = jobs[j];
-      const int64_t n = jb.n;
-      for (int64_t q = 0; q < jb.cnt; ++q) {
-        const int k = jb.stedc_on[q];
-        TDVP_HIP(ctx, hipStreamWaitEvent(ctx->side[k], ctx->eig_ev[jb.ev_red], 0));
-        if ((ec = span_open(k, "tri" + std::to_string(n)))) return ec;
-        if ((ec = fail(rocsolver_dstedc((rocblas_handle)ctx->side_solver[k], rocblas_evect_tridiagonal,
-                                       (rocblas_int)n, jb.D0 + q * n, jb.E0 + q * n, jb.tZ + q * n * n,
-                                       (rocblas_int)n, jb.info + q))))
-          return ec;
-        if ((ec = span_close(k))) return ec;
-        if (jb.ev_stedc[q] >= 0) TDVP_HIP(ctx, hipEventRecord(ctx->eig_ev[jb.ev_stedc[q]], ctx->side[k]));
-      }
-      const int k = jb.home;
-      for (int e : jb.ev_stedc)
-        if (e >= 0) TDVP_HIP(ctx, hipStreamWaitEvent(ctx->side[k], ctx->eig_ev[e], 0));
-      if ((ec = span_open(k, "back" + std::to_string(n)))) return ec;
-      if ((ec = eig_trd_back(ctx, ctx->side[k], jb.tZ, jb.tV, jb.tT, jb.G0, n, jb.cnt, n - jb.gmax, jb.ld))) return ec;
-      if ((ec = vec_reflect_back(ctx, ctx->side[k], jb.G0, n, jb.cnt, n - jb.gmax, jb.ld))) return ec;
-      if ((ec = span_close(k))) return ec;
-    }
+    //    mapped back through both reflections on the home stream (the largest
+    //    matrix's were issued right after the reductions)
+    for (size_t t = 0; t + ntail < trd_ix.size(); ++t)
+      if ((ec = issue_trd(trd_ix[t]))) return ec;
     if (t_ref) {
       const double host_ms = 1e3 * (now() - t_issue);
       TDVP_HIP(ctx, hipDeviceSynchronize());
