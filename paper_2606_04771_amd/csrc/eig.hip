@@ -22,6 +22,7 @@
 
 #include "common.hpp"
 #include "ctx.hpp"
+#include "eig.hpp"
 
 namespace tdvp {
 
@@ -68,7 +69,7 @@ __device__ __forceinline__ double2 group_total(double a, double b, double* red) 
 //   tau  tau_k (complex), d / e: diagonal / off-diagonal of T (real)
 // Launch k writes only columns > k of A, rows it owns, so the column every
 // workgroup reads (k) is never written in the same launch.
-template <int RB>
+template <int RB, int S>
 __device__ __forceinline__ void trd_column(double2* __restrict__ A, double2* __restrict__ V, double2* __restrict__ Y,
                                            double2* __restrict__ tau, double* __restrict__ dg,
                                            double* __restrict__ eg, const int n, const int lda, const int k,
@@ -77,7 +78,7 @@ __device__ __forceinline__ void trd_column(double2* __restrict__ A, double2* __r
   double2* vp = lds;           // v_{k-1} on rows [k, n)
   double2* wp = lds + n;       // w_{k-1} on rows [k, n)
   double2* vc = lds + 2 * n;   // column k on rows [k, n), then v_k on rows [k+1, n)
-  constexpr int S = (int)(kTrdMaxN / kTrdThreads);   // rows of [k, n) per thread
+  // S: rows of [k, n) per thread (n <= 256 S)
   const int tid = threadIdx.x;
   const int64_t mat = mat_, nn = (int64_t)n * n;
   double2* Am = A + mat * lda * (int64_t)lda;
@@ -215,6 +216,7 @@ __device__ __forceinline__ void trd_column(double2* __restrict__ A, double2* __r
 
 // One launch: column k of every job of the set with n > k.  The workgroups
 // are numbered job by job, matrix by matrix, row block by row block.
+template <int S>
 __global__ __launch_bounds__(kTrdThreads) void k_trd_multi(const TrdJob* __restrict__ jobs, int njobs, int k) {
   extern __shared__ double2 lds[];
   __shared__ double red[2 * (kTrdThreads / 64)];
@@ -225,7 +227,7 @@ __global__ __launch_bounds__(kTrdThreads) void k_trd_multi(const TrdJob* __restr
     if (k >= jb.n) continue;
     const int nrb = max(1, (jb.n - k - 1 + kTrdRows - 1) / kTrdRows);
     if (blk < nrb * jb.count) {
-      trd_column<kTrdRows>((double2*)jb.A, (double2*)jb.V, (double2*)jb.Y, (double2*)jb.tau, jb.d, jb.e, jb.n,
+      trd_column<kTrdRows, S>((double2*)jb.A, (double2*)jb.V, (double2*)jb.Y, (double2*)jb.tau, jb.d, jb.e, jb.n,
                            jb.lda, k, blk / nrb, blk % nrb, lds, red, part);
       return;
     }
@@ -314,6 +316,26 @@ __global__ void k_spin(long long ticks) {
 
 }  // namespace
 
+int64_t eig_trd_max_n(tdvp_ctx* ctx) {
+  // the large variant's LDS: 3 n complex values plus the kernel's own
+  // reduction arrays; launches beyond 64 KB are allowed explicitly once
+  static int64_t cached[64];
+  const int dev = ctx->device;
+  if (dev < 0 || dev >= 64) return kTrdMaxN;
+  if (cached[dev]) return cached[dev];
+  int lim = 0;
+  int64_t r = kTrdMaxN;
+  const size_t need = sizeof(double2) * 3 * (size_t)kTrdMaxNLarge;
+  if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+      (size_t)lim >= need + sizeof(double2) * (kTrdThreads + 8) &&
+      hipFuncSetAttribute((const void*)k_trd_multi<(int)(kTrdMaxNLarge / kTrdThreads)>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)need) == hipSuccess)
+    r = kTrdMaxNLarge;
+  (void)hipGetLastError();
+  cached[dev] = r;
+  return r;
+}
+
 int eig_spin(tdvp_ctx* ctx, hipStream_t st, double microseconds) {
   int khz = 0;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device) != hipSuccess || khz <= 0)
@@ -335,7 +357,7 @@ int eig_trd_column(tdvp_ctx* ctx, hipStream_t st, const TrdSet& set, const void*
   int64_t blocks = 0, nmax = 0;
   for (int j = 0; j < set.njobs; ++j) {
     const TrdJob& jb = set.job[j];
-    if (jb.n <= 0 || jb.n > kTrdMaxN || jb.count <= 0 || jb.lda < jb.n)
+    if (jb.n <= 0 || jb.n > kTrdMaxNLarge || jb.count <= 0 || jb.lda < jb.n)
       return set_error(ctx, TDVP_E_INVALID, "tridiagonal reduction: size out of range");
     nmax = std::max<int64_t>(nmax, jb.n);
     if (k < jb.n) blocks += (int64_t)jb.count * std::max<int64_t>(1, (jb.n - k - 1 + kTrdRows - 1) / kTrdRows);
@@ -343,8 +365,15 @@ int eig_trd_column(tdvp_ctx* ctx, hipStream_t st, const TrdSet& set, const void*
   if (set.njobs > kTrdMaxJobs || blocks > INT32_MAX)
     return set_error(ctx, TDVP_E_INVALID, "tridiagonal reduction: too many jobs");
   if (blocks == 0) return TDVP_OK;
-  hipLaunchKernelGGL(k_trd_multi, dim3((unsigned)blocks), dim3(kTrdThreads), sizeof(double2) * 3 * (size_t)nmax, st,
-                     (const TrdJob*)table, set.njobs, (int)k);
+  const size_t lds = sizeof(double2) * 3 * (size_t)nmax;
+  if (nmax <= kTrdMaxN) {
+    hipLaunchKernelGGL(k_trd_multi<(int)(kTrdMaxN / kTrdThreads)>, dim3((unsigned)blocks), dim3(kTrdThreads), lds, st,
+                       (const TrdJob*)table, set.njobs, (int)k);
+  } else {
+    if (nmax > eig_trd_max_n(ctx)) return set_error(ctx, TDVP_E_INVALID, "tridiagonal reduction: size out of range");
+    hipLaunchKernelGGL(k_trd_multi<(int)(kTrdMaxNLarge / kTrdThreads)>, dim3((unsigned)blocks), dim3(kTrdThreads),
+                       lds, st, (const TrdJob*)table, set.njobs, (int)k);
+  }
   TDVP_HIP(ctx, hipGetLastError());
   return TDVP_OK;
 }
@@ -352,7 +381,7 @@ int eig_trd_column(tdvp_ctx* ctx, hipStream_t st, const TrdSet& set, const void*
 int eig_trd_back(tdvp_ctx* ctx, hipStream_t st, const double* Zt, const double* V, const double* tau, double* G,
                  int64_t n, int64_t count, int64_t c0, int64_t ld) {
   if (n <= 0 || count <= 0 || c0 >= n) return TDVP_OK;
-  if (n > kTrdMaxN || count > 65535 || c0 < 0 || ld < n)
+  if (n > kTrdMaxNLarge || count > 65535 || c0 < 0 || ld < n)
     return set_error(ctx, TDVP_E_INVALID, "tridiagonal back-transformation: size out of range");
   const int ni = (int)n, ci = (int)count, c0i = (int)c0, ldi = (int)ld;
   if (n <= 64) launch_back<1>(st, Zt, V, tau, G, ni, ci, c0i, ldi);
@@ -360,7 +389,8 @@ int eig_trd_back(tdvp_ctx* ctx, hipStream_t st, const double* Zt, const double* 
   else if (n <= 256) launch_back<4>(st, Zt, V, tau, G, ni, ci, c0i, ldi);
   else if (n <= 512) launch_back<8>(st, Zt, V, tau, G, ni, ci, c0i, ldi);
   else if (n <= 768) launch_back<12>(st, Zt, V, tau, G, ni, ci, c0i, ldi);
-  else launch_back<16>(st, Zt, V, tau, G, ni, ci, c0i, ldi);
+  else if (n <= 1024) launch_back<16>(st, Zt, V, tau, G, ni, ci, c0i, ldi);
+  else launch_back<24>(st, Zt, V, tau, G, ni, ci, c0i, ldi);
   TDVP_HIP(ctx, hipGetLastError());
   return TDVP_OK;
 }

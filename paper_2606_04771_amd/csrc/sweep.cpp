@@ -18,6 +18,7 @@
 #include <numeric>
 
 #include "device.hpp"
+#include "eig.hpp"
 
 using namespace tdvp;
 
@@ -477,12 +478,13 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
   const int64_t jmin = eig_jacobi_min(), tmin = eig_trd_min();
   // (each of their matrices is reduced at its own size g, not the bucket's
   // padded size; at most kTrdMaxJobs matrices, the largest buckets first)
+  const int64_t trd_max = eig_trd_max_n(ctx);
   int64_t trd_lo = std::max<int64_t>(tmin, 1);
   {
     int64_t cnt = 0;
     for (auto it = buckets.rbegin(); it != buckets.rend(); ++it) {
       const int64_t n = it->first;
-      if (!(dc && n < jmin && n >= tmin && n <= kTrdMaxN)) continue;
+      if (!(dc && n < jmin && n >= tmin && n <= trd_max)) continue;
       if (cnt + (int64_t)it->second.size() > kTrdMaxJobs) {
         trd_lo = n + 1;
         break;
@@ -490,7 +492,7 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
       cnt += (int64_t)it->second.size();
     }
   }
-  auto use_trd = [&](int64_t n) { return dc && n < jmin && n >= trd_lo && n <= kTrdMaxN; };
+  auto use_trd = [&](int64_t n) { return dc && n < jmin && n >= trd_lo && n <= trd_max; };
   int64_t tsq = 0, tvec = 0;
   for (auto& bk : buckets)
     if (use_trd(bk.first))

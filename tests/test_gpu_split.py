@@ -157,6 +157,20 @@ def test_split_keep_all_is_exact(ctx, trd_min, monkeypatch):
     _check_split(ctx, left, right, blocks, 1, 0.0, 10 ** 6, keep_all=True)
 
 
+@pytest.mark.parametrize("trd_min", ["256", "0"])
+def test_split_with_gram_matrices_above_1024(ctx, trd_min, monkeypatch):
+    """Few large sectors (chi = 3600 profiles over |2S^z|, 2j <= 2): Gram
+    sides up to 1288, so the in-house reduction's large variant (more rows
+    per thread, more LDS) runs beside the 1024 and 768 buckets; against the
+    oracle, and through the library solver for comparison."""
+    monkeypatch.setenv("TDVP_EIG_TRD_MIN", trd_min)
+    print(f"split with Gram sides up to 1288, tridiagonal reduction from n={trd_min}", flush=True)
+    left = synth.sector_profile(3600, 31, parity=1, qmax=2, tjmax=2)
+    right = synth.sector_profile(3600, 32, parity=1, qmax=2, tjmax=2)
+    blocks = _spread_theta(left, right, 1e-4, 11)
+    _check_split(ctx, left, right, blocks, 1, 1e-10, 10 ** 6)
+
+
 def test_split_rejects_non_finite_theta(ctx):
     print("split with a NaN in theta", flush=True)
     left = synth.sector_profile(60, 43, parity=0)
