@@ -508,12 +508,20 @@ def main():
 
     # ---- larger, more uneven blocks: chi = 16384 with log-normal sector dimensions,
     # grouped launch against one launch per output block ------------------------------
+    # (each on a context of its own, closed afterwards, so that the sweeps below
+    # start from the state a sweep-only run has: with the chi ~ 62 000 apply
+    # and bond update run on the sweep's context, its splits took ~15 % longer)
     large = None
     if not args.no_large:
-        large = large_heff(args, T, torch, stream, ctx, model)
+        lctx = T.Context(0, stream=stream.cuda_stream, precision=prec)
+        large = large_heff(args, T, torch, stream, lctx, model)
+        lctx.close()
     late = None
     if not args.no_late:
-        late = large_heff(args, T, torch, stream, ctx, model, late=True)
+        lctx = T.Context(0, stream=stream.cuda_stream, precision=prec)
+        late = large_heff(args, T, torch, stream, lctx, model, late=True)
+        lctx.close()
+        torch.cuda.empty_cache()
     abelian = None
     if not args.no_abelian:
         abelian = u1_heff(args, T, torch, stream, ctx, model, chi)
