@@ -2,16 +2,18 @@
 // section S2.2: the SVD of each symmetry sector's two-site matrix, done here
 // through the eigendecomposition of its Gram matrix).
 //
-// A batch of `count` Hermitian n x n matrices (column-major, full storage,
-// stride n^2) is reduced to real symmetric tridiagonal form T = Q^H A Q by
-// Householder reflectors Q = H_0 H_1 ... H_{n-2}, H_k = I - tau_k v_k v_k^H
-// (the reduction of Golub and Van Loan, section 8.3.1, in LAPACK's complex
-// convention: beta = e_k real, v_k(k+1) = 1).  Each column is ONE launch for
-// the whole batch: every workgroup of a matrix recomputes the column's
-// reflector from the previous column's rank-2 update (O(n) redundant work),
-// then applies that update to its own rows of the trailing matrix and forms
-// its rows of y_k = tau_k A v_k in the same pass.  A library solver launches
-// about ten small dependent kernels per column for the same reduction.
+// Hermitian matrices (column-major, full storage, each n x n with its own
+// leading dimension) are reduced to real symmetric tridiagonal form
+// T = Q^H A Q by Householder reflectors Q = H_0 H_1 ... H_{n-2},
+// H_k = I - tau_k v_k v_k^H (the reduction of Golub and Van Loan, section
+// 8.3.1, in LAPACK's complex convention: beta = e_k real, v_k(k+1) = 1).
+// Column k of every matrix of a set (all the large Gram matrices of one
+// split, of different sizes) is ONE launch: every workgroup of a matrix
+// recomputes the column's reflector from the previous column's rank-2 update
+// (O(n) redundant work), then applies that update to its own rows of the
+// trailing matrix and forms its rows of y_k = tau_k A v_k in the same pass.
+// A library solver launches about ten small dependent kernels per column for
+// the same reduction.
 //
 // The tridiagonal eigenproblem is left to a library tridiagonal solver; the
 // eigenvectors of A are then Q Z, applied by one launch: one wave per output
@@ -58,9 +60,10 @@ __device__ __forceinline__ double2 group_total(double a, double b, double* red) 
   return make_double2(x, y);
 }
 
-// Column k of the reduction, for every matrix of the batch (blockIdx.y) and
-// the rows [k + 1 + RB * blockIdx.x, ...) of its trailing matrix.
-//   A    the matrices; on entry to launch k the trailing block [k, n)^2 holds
+// Column k of the reduction for matrix `mat_` of a job (RB rows of its
+// trailing matrix per workgroup: block rb_ holds rows k + 1 + RB rb_ ...).
+//   A    the matrices (leading dimension lda, lda^2 apart); on entry to
+//        launch k the trailing block [k, n)^2 holds
 //        A_k + v_{k-1} w_{k-1}^H + w_{k-1} v_{k-1}^H (the last rank-2 update
 //        not yet applied), rows/columns < k are no longer read
 //   V    reflector store: column k receives v_k on rows [k+1, n)
