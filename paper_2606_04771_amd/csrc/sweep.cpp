@@ -613,17 +613,18 @@ int split(tdvp_ctx* ctx, tdvp_mps* m, int i, const Blocks& th, int dir, const td
       minfo.push_back(mi);
       mi += (int64_t)bk.second.size();
     }
-    // Schedule.  A bucket is one job: either one batched library solve, or
-    // (in-house reduction) reflection + reduction, one tridiagonal solve per
-    // matrix, back-transformation.  The reductions of all such buckets share
-    // their launches (one per column index, on side stream 0), so a bucket is
-    // reduced after as many launches as it has columns; its tridiagonal
-    // solves (independent chains of small library launches) go to the other
-    // side streams, each waiting for that point by an event, and its
-    // back-transformation waits for all of them.  Host issue order: the
-    // reductions, then the library solves, then the tridiagonal solves and
+    // Schedule.  A job is either one batched library solve of a bucket, or
+    // (in-house path) one matrix: reflection + reduction, its tridiagonal
+    // solve, back-transformation.  The reductions of all in-house matrices
+    // share their launches (one per column index, on side stream 0), so a
+    // matrix is reduced after as many launches as it has columns; its
+    // tridiagonal solve (a chain of small library launches) goes to another
+    // hardware queue, waiting for that point by an event, and its
+    // back-transformation follows it.  Host issue order: the reductions (then
+    // the largest matrix's solve and back-transformation on stream 0), the
+    // library solves, then the other tridiagonal solves and
     // back-transformations, so that every event is recorded before a wait on
-    // it is issued, and the long reduction chain starts first.  Streams are
+    // it is issued and the long reduction chain starts first.  Queues are
     // chosen by earliest estimated finish, largest work first.  Issuing from
     // one host thread per stream was measured slower.
     // Cost estimates in milliseconds, fitted to one MI355X (only their ratios
