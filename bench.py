@@ -617,6 +617,12 @@ def main():
                 "max_chi": int(max(i["max_chi"] for i in infos)),
                 "max_discarded": float(max(i["max_discarded"] for i in infos)),
                 "peak_device_gb": sweep_peak / 1e9,
+                "split_eigensolver": {
+                    "in_house_reduction_from": os.environ.get("TDVP_EIG_TRD_MIN", "256"),
+                    "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES", ""),
+                    "note": "Gram matrices of buckets >= in_house_reduction_from: in-house Householder reduction "
+                            "(one launch per column for all of a split's matrices), library tridiagonal divide "
+                            "and conquer, in-house back-transformation; smaller ones: library batched solver"},
             }
             if one:
                 sweep["one_site"] = {
